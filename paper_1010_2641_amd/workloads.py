@@ -1,0 +1,258 @@
+"""Seeded synthetic inputs for the direct scattering sum.
+
+This module only builds inputs: atom sites, displacement fields, per-atom
+scattering factors and reciprocal-space point lists.  It contains none of the
+sum's own arithmetic, imports neither the GPU library nor the CPU oracle, and is
+the one module both sides draw their inputs from.
+
+Conventions (Favre-Nicolin et al., 2010):
+
+* positions r in lattice units and S in reciprocal-lattice units (r.l.u.), so S.r
+  is in cycles -- Section 4.2 converts orthonormal coordinates to fractional ones
+  before calling the sum;
+* inputs are built in float64 and rounded once to float32; the float32 arrays are
+  the problem both sides evaluate;
+* atoms are listed with the x cell index slowest, z fastest and the fcc basis
+  innermost; point grids with h fastest, then k, then l (any order is valid for
+  the sum, Section 3 notes that shape and order are irrelevant);
+* ``f`` is None when every atom has f_j = 1 (the unit-occupancy sum of Section 3
+  and of the speed tests of Section 2.2), else a complex64 array.
+
+The five named workloads are the synthetic stand-ins for the paper's strained
+nanostructures (its coordinate files and scripts are not available):
+
+* ``c1`` 16^3 simple-cubic block, Gaussian disorder 0.02, f=1, 64x64 map at l=4;
+* ``c2`` Ge-like truncated-pyramid dot on an fcc lattice with radial strain and a
+  20->80 % composition profile (cf. the Ge dot of Section 4.3), 128^3 grid at (404);
+* ``c3`` 100^3 simple-cubic crystal (the Section 4.1 cube size), disorder 0.01,
+  256x256 map near (8,8,8): phases up to ~2.4e3 cycles;
+* ``c4`` 29^3-cell fcc cube with a sinusoidal displacement field, 64^3 grid at (220),
+  plus the perturbed target structure whose intensity is fitted;
+* ``c5`` fcc nanowire segment with radial and axial strain, core/shell species,
+  256^3 grid at (004), plus a target structure with strain x1.1.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+# fcc basis in lattice units (a = 1)
+FCC_BASIS = np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.0], [0.5, 0.0, 0.5], [0.0, 0.5, 0.5]])
+
+# two species' complex scattering factors (Ge-like and a lighter partner), constant
+# over the small S windows used here
+F_SPECIES_0 = complex(31.0, 1.0)
+F_SPECIES_1 = complex(22.0, 3.5)
+
+
+@dataclass
+class Workload:
+    """One synthetic problem: atoms, factors, points (all float32 / complex64)."""
+    name: str
+    xyz: np.ndarray                      # (N, 3) float32
+    f: Optional[np.ndarray]              # (N,) complex64 or None for f_j = 1
+    S: np.ndarray                        # (K, 3) float32
+    target_xyz: Optional[np.ndarray] = None   # (N, 3) float32: structure whose |A|^2 is fitted
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_atoms(self) -> int:
+        return int(self.xyz.shape[0])
+
+    @property
+    def n_points(self) -> int:
+        return int(self.S.shape[0])
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).astype(np.float32))
+
+
+def cubic_sites(nx: int, ny: int, nz: int, origin=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Simple-cubic sites n = (ix, iy, iz) + origin, x slowest, z fastest, float64."""
+    ix, iy, iz = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    p = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1).astype(np.float64)
+    return p + np.asarray(origin, dtype=np.float64)
+
+
+def fcc_sites(xr, yr, zr) -> np.ndarray:
+    """fcc sites for cells ix in range(*xr) etc., basis innermost, float64."""
+    ix, iy, iz = np.meshgrid(np.arange(*xr), np.arange(*yr), np.arange(*zr), indexing="ij")
+    cells = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1).astype(np.float64)
+    return (cells[:, None, :] + FCC_BASIS[None, :, :]).reshape(-1, 3)
+
+
+def grid_points(h, k, l) -> np.ndarray:
+    """All (h, k, l) combinations with h fastest, then k, then l, float64 (K, 3)."""
+    h = np.atleast_1d(np.asarray(h, dtype=np.float64))
+    k = np.atleast_1d(np.asarray(k, dtype=np.float64))
+    l = np.atleast_1d(np.asarray(l, dtype=np.float64))
+    L, K, H = np.meshgrid(l, k, h, indexing="ij")
+    return np.stack([H.ravel(), K.ravel(), L.ravel()], axis=1)
+
+
+# ----------------------------------------------------------------------------- named workloads
+
+def c1(seed: int = 1001, sigma: float = 0.02) -> Workload:
+    """16^3 simple-cubic block (4096 atoms) + N(0, sigma^2) per component, f = 1;
+    64x64 map (h, k, 4), h, k in linspace(-0.5, 0.5, 64)."""
+    rng = np.random.default_rng(seed)
+    p = cubic_sites(16, 16, 16)
+    if sigma:
+        p = p + rng.normal(0.0, sigma, size=p.shape)
+    d = np.linspace(-0.5, 0.5, 64)
+    S = grid_points(d, d, 4.0)
+    return Workload("c1", _f32(p), None, _f32(S), meta=dict(sigma=sigma, seed=seed))
+
+
+def _pyramid_mask(p):
+    z = p[:, 2]
+    half = 32.0 - 16.0 * z / 21.0
+    return (z >= 0) & (z < 21) & (np.abs(p[:, 0]) < half) & (np.abs(p[:, 1]) < half)
+
+
+def _radial_displacement(p, amp, R=16.0):
+    """u = amp * R * (1 - exp(-rho/R)) * rho_hat about the origin (strain amp*exp(-rho/R))."""
+    rho = np.linalg.norm(p, axis=1)
+    scale = np.zeros_like(rho)
+    nz = rho > 0
+    scale[nz] = amp * R * (1.0 - np.exp(-rho[nz] / R)) / rho[nz]
+    return p * scale[:, None]
+
+
+def c2(seed: int = 1002, n_grid: int = 128, strain: float = 0.04) -> Workload:
+    """Ge-like truncated square pyramid on fcc (a=1): 0 <= z < 21, |x|,|y| < 32 - 16 z/21
+    (203,557 atoms); radial strain eps(rho) = strain*exp(-rho/16) about the base centre;
+    species Bernoulli(p = 0.2 + 0.6 z/21) -> F_SPECIES_0 else F_SPECIES_1;
+    grid (4+d, d, 4+d), d in linspace(-0.05, 0.05, n_grid)^3.  The target structure
+    (for a fit step) has the strain scaled by 1.1."""
+    rng = np.random.default_rng(seed)
+    p0 = fcc_sites((-32, 32), (-32, 32), (0, 21))
+    p0 = p0[_pyramid_mask(p0)]
+    ge = rng.random(p0.shape[0]) < (0.2 + 0.6 * p0[:, 2] / 21.0)
+    f = np.where(ge, F_SPECIES_0, F_SPECIES_1).astype(np.complex64)
+    p = p0 + _radial_displacement(p0, strain)
+    pt = p0 + _radial_displacement(p0, strain * 1.1)
+    d = np.linspace(-0.05, 0.05, n_grid)
+    S = grid_points(4.0 + d, d, 4.0 + d)
+    return Workload("c2", _f32(p), f, _f32(S), target_xyz=_f32(pt),
+                    meta=dict(seed=seed, strain=strain))
+
+
+def c3(seed: int = 1003, sigma: float = 0.01, n_side: int = 100, n_grid: int = 256) -> Workload:
+    """100^3 simple-cubic crystal (1e6 atoms) + N(0, sigma^2), f = 1;
+    map (8+d, 8+d, 8), d in linspace(-0.05, 0.05, 256)^2 (65,536 points)."""
+    rng = np.random.default_rng(seed)
+    p = cubic_sites(n_side, n_side, n_side)
+    if sigma:
+        p = p + rng.normal(0.0, sigma, size=p.shape)
+    d = np.linspace(-0.05, 0.05, n_grid)
+    S = grid_points(8.0 + d, 8.0 + d, 8.0)
+    return Workload("c3", _f32(p), None, _f32(S), meta=dict(seed=seed, sigma=sigma))
+
+
+def _sine_field(p0, amp, phase):
+    """u = amp * (sin(2 pi z/20 + phase), sin(2 pi x/20 + phase), sin(2 pi y/20 + phase))."""
+    w = 2.0 * np.pi / 20.0
+    return amp * np.stack([np.sin(w * p0[:, 2] + phase),
+                           np.sin(w * p0[:, 0] + phase),
+                           np.sin(w * p0[:, 1] + phase)], axis=1)
+
+
+def c4(seed: int = 1004, n_cells: int = 29, n_grid: int = 64) -> Workload:
+    """fcc cube of 29^3 cells (97,556 atoms), u = 0.03 sin(2 pi (z, x, y)/20), f = 1;
+    grid (2+d, 2+d, d), d in linspace(-0.08, 0.08, 64)^3 (262,144 points).
+    Target structure: amplitude 0.033 and phase +0.3 rad in each sine."""
+    p0 = fcc_sites((0, n_cells), (0, n_cells), (0, n_cells))
+    p = p0 + _sine_field(p0, 0.03, 0.0)
+    pt = p0 + _sine_field(p0, 0.033, 0.3)
+    d = np.linspace(-0.08, 0.08, n_grid)
+    S = grid_points(2.0 + d, 2.0 + d, d)
+    return Workload("c4", _f32(p), None, _f32(S), target_xyz=_f32(pt), meta=dict(seed=seed))
+
+
+def _wire_displacement(p0, scale):
+    rho2 = p0[:, 0] ** 2 + p0[:, 1] ** 2
+    rho = np.sqrt(rho2)
+    u = np.zeros_like(p0)
+    ur = scale * 0.005 * rho2 / 40.0             # radial, eps_rr = 0.01 rho/40
+    nz = rho > 0
+    u[nz, 0] = ur[nz] * p0[nz, 0] / rho[nz]
+    u[nz, 1] = ur[nz] * p0[nz, 1] / rho[nz]
+    u[:, 2] = scale * 0.002 * (p0[:, 2] - 100.0) * rho2 / 1600.0   # axial
+    return u
+
+
+def c5(seed: int = 1005, n_grid: int = 256) -> Workload:
+    """fcc cylinder along z, rho < 40, 0 <= z < 200 (4,013,800 atoms); radial
+    u_rho = 0.005 rho^2/40, axial u_z = 0.002 (z-100)(rho/40)^2; core (rho < 28)
+    F_SPECIES_0, shell F_SPECIES_1; grid (d, d, 4+d), d in linspace(-0.05, 0.05, 256)^3
+    (16,777,216 points).  Target structure: the same wire with strain x1.1."""
+    p0 = fcc_sites((-40, 40), (-40, 40), (0, 200))
+    rho = np.sqrt(p0[:, 0] ** 2 + p0[:, 1] ** 2)
+    keep = rho < 40.0
+    p0, rho = p0[keep], rho[keep]
+    f = np.where(rho < 28.0, F_SPECIES_0, F_SPECIES_1).astype(np.complex64)
+    p = p0 + _wire_displacement(p0, 1.0)
+    pt = p0 + _wire_displacement(p0, 1.1)
+    d = np.linspace(-0.05, 0.05, n_grid)
+    S = grid_points(d, d, 4.0 + d)
+    return Workload("c5", _f32(p), f, _f32(S), target_xyz=_f32(pt), meta=dict(seed=seed))
+
+
+NAMED = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
+
+
+def named(name: str) -> Workload:
+    return NAMED[name]()
+
+
+# ----------------------------------------------------------------------------- generic inputs
+
+def random_problem(n_atoms: int, n_points: int, seed: int, extent: float = 50.0,
+                   s_range: float = 4.0, complex_f: bool = True):
+    """Random atoms in [0, extent)^3, random S in [-s_range, s_range)^3 (the paper's
+    speed test uses random atoms and random points, Section 2.2).  Returns
+    (xyz float32 (N,3), f complex64 (N,) or None, S float32 (K,3))."""
+    rng = np.random.default_rng(seed)
+    xyz = _f32(rng.random((n_atoms, 3)) * extent)
+    S = _f32((rng.random((n_points, 3)) * 2.0 - 1.0) * s_range)
+    f = None
+    if complex_f:
+        f = (rng.uniform(0.5, 2.0, n_atoms) * np.exp(1j * rng.uniform(-np.pi, np.pi, n_atoms)))
+        f = f.astype(np.complex64)
+    return xyz, f, S
+
+
+def random_seed_field(n_points: int, seed: int, scale: float = 1.0) -> np.ndarray:
+    """A seeded complex64 adjoint seed G (standard complex normal * scale)."""
+    rng = np.random.default_rng(seed)
+    g = (rng.normal(size=n_points) + 1j * rng.normal(size=n_points)) * scale
+    return g.astype(np.complex64)
+
+
+def random_amplitudes(n_points: int, seed: int, scale: float = 100.0):
+    """Seeded complex64 amplitudes A and float32 intensities I of the same scale,
+    for exercising the misfit step on its own."""
+    rng = np.random.default_rng(seed)
+    A = ((rng.normal(size=n_points) + 1j * rng.normal(size=n_points)) * scale).astype(np.complex64)
+    I = (rng.gamma(1.0, 2.0 * scale * scale, size=n_points)).astype(np.float32)
+    return A, I
+
+
+def chain(n_atoms: int, sigma: float = 0.0, seed: int = 7, h_step: float = 0.001,
+          h_max: float = 1.0):
+    """The accuracy test of Section 2.3: atoms at 0, 1, ..., N-1 along x (optionally with
+    Gaussian disorder sigma in each component) and H from 0 to h_max every h_step r.l.u.
+    along x.  Returns (xyz float32, S float32)."""
+    rng = np.random.default_rng(seed)
+    p = np.zeros((n_atoms, 3))
+    p[:, 0] = np.arange(n_atoms)
+    if sigma:
+        p = p + rng.normal(0.0, sigma, size=p.shape)
+    h = np.arange(0.0, h_max + 0.5 * h_step, h_step)
+    S = np.zeros((h.size, 3))
+    S[:, 0] = h
+    return _f32(p), _f32(S)

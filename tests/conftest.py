@@ -1,0 +1,13 @@
+"""Shared pytest configuration: registers the ``gpu`` marker and puts the repository
+root on sys.path so that ``oracle`` and the package import from the checkout."""
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: long-running check")

@@ -1,0 +1,48 @@
+"""The oracle's pins must reject plausible mistakes.  Each case below plants one
+mistake in a copy of the oracle's C source (a flipped sign, a dropped term, a
+transposed index, a missing conjugate or factor), compiles it on the CPU and runs
+every pin against it: at least one pin has to fail.  The real oracle is never
+modified."""
+import os
+
+import pytest
+
+import oracle
+from tests import test_oracle_pins as pins
+
+MUTATIONS = {
+    "sin_sign": ("*s = sin(a);", "*s = -sin(a);"),
+    "missing_2pi": ("double a = 2.0 * M_PI * t;", "double a = M_PI * t;"),
+    "dropped_z_term": ("sx * xyz[3 * j] + sy * xyz[3 * j + 1] + sz * xyz[3 * j + 2];",
+                       "sx * xyz[3 * j] + sy * xyz[3 * j + 1];"),
+    "transposed_yz": ("sx * xyz[3 * j] + sy * xyz[3 * j + 1] + sz * xyz[3 * j + 2];",
+                      "sx * xyz[3 * j] + sy * xyz[3 * j + 2] + sz * xyz[3 * j + 1];"),
+    "conj_f_re": ("re += fr * c - fi * s;", "re += fr * c + fi * s;"),
+    "conj_f_im": ("im += fr * s + fi * c;", "im += fr * s - fi * c;"),
+    "last_atom_dropped": ("for (int64_t j = 0; j < n_atoms; ++j) {\n            double phase",
+                          "for (int64_t j = 0; j + 1 < n_atoms; ++j) {\n            double phase"),
+    "loss_factor": ("G[2 * k] = 4.0 * e * re;", "G[2 * k] = 2.0 * e * re;"),
+    "loss_not_squared": ("L += e * e;", "L += e;"),
+    "loss_sign_I": ("double e = re * re + im * im - I[k];", "double e = re * re + im * im + I[k];"),
+    "adjoint_no_conj_G": ("double gr = G[2 * k], gi = -G[2 * k + 1];", "double gr = G[2 * k], gi = G[2 * k + 1];"),
+    "adjoint_sign_2pi": ("double qr = -2.0 * M_PI * pi_;", "double qr = 2.0 * M_PI * pi_;"),
+    "adjoint_wrong_index": ("gy += zr * sy;", "gy += zr * sx;"),
+    "adjoint_phase_sign": ("double zr = qr * c - qi * s;", "double zr = qr * c + qi * s;"),
+    "adjoint_ignores_f": ("double pr = gr * fr - gi * fi;\n            double pi_ = gr * fi + gi * fr;",
+                          "double pr = gr;\n            double pi_ = gi;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_reject_mutation(name, tmp_path):
+    old, new = MUTATIONS[name]
+    src = oracle.source()
+    assert src.count(old) >= 1, "mutation target not found in the oracle source"
+    mutant = oracle.compile_variant(src.replace(old, new, 1), os.path.join(tmp_path, f"mut_{name}.so"))
+    failed = []
+    for pin in pins.PINS:
+        try:
+            pin(mutant)
+        except AssertionError:
+            failed.append(pin.__name__)
+    assert failed, f"no pin rejects the planted mistake '{name}'"
