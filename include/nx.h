@@ -1,0 +1,146 @@
+/*
+ * nx.h -- C ABI of libnx, the gfx950 (MI355X) direct scattering-sum library.
+ *
+ * The library evaluates the kinematic scattering amplitude of an atomistic model
+ * (Favre-Nicolin, Coraux, Richard & Renevier, "Fast computing of scattering maps of
+ * nanostructures using graphical processing units", J. Appl. Cryst. 2010, Section
+ * 2.1, Eq. 2):
+ *
+ *     A(S_k) = sum_j f_j exp(2 i pi S_k . r_j)
+ *
+ * over every atom j and every reciprocal-space point k, and the adjoint of that sum
+ * with respect to the atom positions, for fitting displacement fields to measured
+ * intensities.
+ *
+ * Units and layout (all arrays flat and row-major; the order of atoms and of points
+ * is irrelevant, as Section 3 of the paper notes for its own inputs):
+ *   - r_j in lattice (fractional) units, S_k in reciprocal-lattice units, so S.r is in
+ *     cycles (Section 4.2 converts orthonormal coordinates to fractional ones);
+ *   - xyz:      n_atoms  x 3 values (x, y, z);
+ *   - f:        n_atoms complex values stored as (re, im) pairs, or NULL for f_j = 1
+ *               (the unit-occupancy sum of Section 3); occupancy and species
+ *               factors are folded into f_j by the caller (Section 4.2 factors the
+ *               S-dependent atomic factor out of the sum);
+ *   - S:        n_points x 3 values (h, k, l);
+ *   - A, G:     n_points complex values stored as (re, im) pairs;
+ *   - grad_xyz: n_atoms  x 3 values.
+ *
+ * Ownership and execution: every pointer except those of nx_workspace_bytes and
+ * nx_last_error is a DEVICE pointer owned by the caller.  The library never
+ * allocates, frees, copies to or from the host, or synchronises: all work is queued
+ * on `stream` (a hipStream_t; NULL = the null stream) and the call returns once it
+ * is queued.  Outputs must not alias inputs.  The workspace `ws` is caller-owned
+ * device memory of at least nx_workspace_bytes(...) bytes, used for the packed atom
+ * or point records and the split/chunk partial sums; its contents on entry are
+ * ignored and it must not be used by other work until the queued calls finish.
+ * Calls that share a workspace must be ordered on one stream.
+ *
+ * Errors: every entry point validates its arguments on the host before any HIP call
+ * and returns a negative nx_status on failure (nothing is queued then); the text of
+ * the last error of the calling thread is available from nx_last_error().  Faults
+ * during kernel execution surface at the caller's next synchronisation.  Non-finite
+ * inputs propagate to the outputs.
+ *
+ * Results are bitwise reproducible for a fixed mode, input and size: partial sums
+ * are combined in a fixed order and no atomics are used.
+ */
+#ifndef NX_H
+#define NX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NX_OK = 0,
+  NX_ERR_ARG = -1,        /* negative count, count too large, or NULL pointer with count > 0 */
+  NX_ERR_MODE = -2,       /* unknown mode or op */
+  NX_ERR_WORKSPACE = -3,  /* workspace missing or smaller than nx_workspace_bytes() */
+  NX_ERR_DEVICE = -4      /* a HIP call failed (message in nx_last_error) */
+} nx_status;
+
+/* Precision modes of the single-precision entry points.
+ *   NX_F32      the paper's own arithmetic (Section 2.2-2.3): phase S.r formed and
+ *               reduced modulo one cycle in FP32, FP32 sin/cos, plain FP32 sums.
+ *               Its error grows with |S.r| and with the number of atoms
+ *               (the single-precision discussion of Section 2.3).
+ *   NX_F32_PH64 the phase S.r is formed and reduced modulo one cycle in FP64 (exact for
+ *               FP32 inputs up to the final rounding), sin/cos and the complex
+ *               multiply-add run in FP32, and the sums are compensated (FP32
+ *               group partial sums folded into a two-word FP32 accumulator with an
+ *               error-free two-sum).  FP64 is used in the phase reduction only.   */
+typedef enum { NX_F32 = 0, NX_F32_PH64 = 1 } nx_mode;
+
+/* Operation selector for nx_workspace_bytes. */
+typedef enum {
+  NX_OP_FWD = 0,       /* nx_scatter_fwd      */
+  NX_OP_BWD = 1,       /* nx_scatter_bwd      */
+  NX_OP_FWD_F64 = 2,   /* nx_scatter_fwd_f64  */
+  NX_OP_BWD_F64 = 3,   /* nx_scatter_bwd_f64  */
+  NX_OP_LOSS = 4       /* nx_loss_grad        */
+} nx_op;
+
+/* Largest n_atoms / n_points accepted by any entry point. */
+#define NX_MAX_COUNT ((int64_t)1 << 30)
+
+/* Library ABI version (major * 100 + minor). */
+int nx_version(void);
+
+/* Bytes of device workspace the call (op, mode, n_atoms, n_points) needs; 0 when it
+ * needs none.  `f_is_null` must match the f argument of the later call (1 when f
+ * will be NULL).  `mode` is ignored for the FP64 and loss ops.  Returns 0 and sets
+ * the last error on invalid arguments. */
+size_t nx_workspace_bytes(int64_t n_atoms, int64_t n_points, int mode, int op, int f_is_null);
+
+/* Forward sum, Section 2.1 Eq. 2:  A_k = sum_j f_j exp(2 i pi S_k . r_j).
+ *   xyz  float[n_atoms*3], f float[n_atoms*2] or NULL, S float[n_points*3],
+ *   A    float[n_points*2] (complex64), overwritten.
+ * n_atoms == 0 writes A = 0; n_points == 0 queues nothing. */
+int nx_scatter_fwd(const float* xyz, const float* f, int64_t n_atoms,
+                   const float* S, int64_t n_points, float* A,
+                   int mode, void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of the forward sum with respect to the positions (chain rule through Eq. 2).
+ * For a real loss L(A) with seed G_k = dL/dRe A_k + i dL/dIm A_k (the complex gradient
+ * convention of PyTorch):
+ *     grad_xyz_j = dL/dr_j = Re sum_k conj(G_k) f_j (2 i pi S_k) exp(2 i pi S_k . r_j)
+ *   G float[n_points*2], grad_xyz float[n_atoms*3], overwritten.
+ * n_points == 0 writes grad_xyz = 0; n_atoms == 0 queues nothing. */
+int nx_scatter_bwd(const float* xyz, const float* f, int64_t n_atoms,
+                   const float* S, int64_t n_points, const float* G, float* grad_xyz,
+                   int mode, void* ws, size_t ws_bytes, void* stream);
+
+/* All-FP64 forward (Eq. 2 with FP64 phase, FP64 sin/cos and FP64 sums): the
+ * double-precision comparator mentioned at the end of Section 2.3.  Same layout as
+ * nx_scatter_fwd with double arrays; A is complex128. */
+int nx_scatter_fwd_f64(const double* xyz, const double* f, int64_t n_atoms,
+                       const double* S, int64_t n_points, double* A,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* All-FP64 adjoint; same layout as nx_scatter_bwd with double arrays. */
+int nx_scatter_bwd_f64(const double* xyz, const double* f, int64_t n_atoms,
+                       const double* S, int64_t n_points, const double* G, double* grad_xyz,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* Intensity misfit and its seed for fitting a model to measured intensities I:
+ *     e_k = |A_k|^2 - I_k,   L = sum_k e_k^2,   G_k = 4 e_k A_k
+ * (G is dL/dRe A + i dL/dIm A, the input nx_scatter_bwd expects).  e and L are
+ * evaluated in FP64 from the FP32 inputs; G is rounded once to FP32.  L is reduced in
+ * a fixed order (deterministic).
+ *   A float[n_points*2], I float[n_points], L double[1] (device), G float[n_points*2]
+ *   (may be NULL when only L is wanted).  n_points == 0 writes L = 0. */
+int nx_loss_grad(const float* A, const float* I, int64_t n_points, double* L, float* G,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* Message of the calling thread's last error ("" if none).  The pointer stays valid
+ * until the thread's next call into the library. */
+const char* nx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NX_H */

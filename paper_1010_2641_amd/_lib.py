@@ -1,0 +1,70 @@
+"""ctypes binding of libnx (include/nx.h): the same entry points with the same names
+and arguments.  Argument marshalling only -- every step of the sum runs in the HIP
+library.  Importing this module loads libnx.so and fails loudly if it is missing;
+there is no CPU fallback."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnx.so")
+
+NX_OK, NX_ERR_ARG, NX_ERR_MODE, NX_ERR_WORKSPACE, NX_ERR_DEVICE = 0, -1, -2, -3, -4
+NX_F32, NX_F32_PH64 = 0, 1
+NX_OP_FWD, NX_OP_BWD, NX_OP_FWD_F64, NX_OP_BWD_F64, NX_OP_LOSS = 0, 1, 2, 3, 4
+NX_MAX_COUNT = 1 << 30
+
+# every symbol include/nx.h declares, with its ctypes signature
+_VP, _I64, _SZ, _I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t, ctypes.c_int
+SIGNATURES = {
+    "nx_version": ([], _I),
+    "nx_last_error": ([], ctypes.c_char_p),
+    "nx_workspace_bytes": ([_I64, _I64, _I, _I, _I], _SZ),
+    "nx_scatter_fwd": ([_VP, _VP, _I64, _VP, _I64, _VP, _I, _VP, _SZ, _VP], _I),
+    "nx_scatter_bwd": ([_VP, _VP, _I64, _VP, _I64, _VP, _VP, _I, _VP, _SZ, _VP], _I),
+    "nx_scatter_fwd_f64": ([_VP, _VP, _I64, _VP, _I64, _VP, _VP, _SZ, _VP], _I),
+    "nx_scatter_bwd_f64": ([_VP, _VP, _I64, _VP, _I64, _VP, _VP, _VP, _SZ, _VP], _I),
+    "nx_loss_grad": ([_VP, _VP, _I64, _VP, _VP, _VP, _SZ, _VP], _I),
+}
+
+
+class NxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libnx error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1010_2641_amd.build` "
+                           "(the HIP library is required; there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (args, res) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    return lib.nx_last_error().decode()
+
+
+def check(code: int) -> None:
+    if code != NX_OK:
+        raise NxError(code, last_error())
+
+
+# The entry points under their C names.
+nx_version = lib.nx_version
+nx_last_error = lib.nx_last_error
+nx_workspace_bytes = lib.nx_workspace_bytes
+nx_scatter_fwd = lib.nx_scatter_fwd
+nx_scatter_bwd = lib.nx_scatter_bwd
+nx_scatter_fwd_f64 = lib.nx_scatter_fwd_f64
+nx_scatter_bwd_f64 = lib.nx_scatter_bwd_f64
+nx_loss_grad = lib.nx_loss_grad

@@ -1,0 +1,437 @@
+// nx_fwd.hip -- forward direct scattering sum (Eq. 2 of Favre-Nicolin et al. 2010):
+//     A_k = sum_j f_j exp(2 i pi S_k . r_j)
+//
+// Layout on gfx950: every lane owns P points (coalesced rows of S, strided by the
+// work-group size), keeps their S and complex accumulators in registers, and walks
+// the atoms of its slice in order.  The atom index is uniform over the wavefront,
+// so each packed atom record is fetched with scalar loads into SGPRs and used as an
+// SGPR operand of the VALU instructions: the record is broadcast without LDS traffic
+// or barriers (the paper shares atom coordinates between threads through on-chip
+// memory for the same reason, Section 2.2).
+//
+// Per (atom, point) pair:
+//   F32  : phase S.r with FP32 fma, v_fract_f32, v_sin_f32/v_cos_f32 (both take the
+//          angle in turns), plain FP32 complex multiply-add -- the paper's arithmetic.
+//   PH64 : phase with FP64 fma (the products of FP32 inputs are exact in FP64),
+//          reduction modulo one cycle in FP64 (exact), one rounding to FP32, FP32
+//          v_sin/v_cos, FP32 complex multiply-add; terms are summed in quads of
+//          consecutive atoms, quads into a group partial, and every `GRP` atoms the
+//          group partial is folded into a two-word (sum, comp) accumulator with an
+//          error-free two-sum (so FP32 roundings happen only at the magnitude of a
+//          group partial, never at that of the whole sum).
+//   F64  : phase, reduction, sincospi and sums all in FP64.
+#include "nx_internal.h"
+
+namespace nx {
+namespace {
+
+// Knuth's two-sum: s + g = t + err exactly; err is added into the compensation word.
+__device__ __forceinline__ void two_sum_acc(float& s, float& c, float g) {
+  const float t = s + g;
+  const float bp = t - s;
+  const float ap = t - bp;
+  c += (s - ap) + (g - bp);
+  s = t;
+}
+
+template <int MODE> struct AtomOf;
+template <> struct AtomOf<kF32> { using type = AtomF32; };
+template <> struct AtomOf<kPH64> { using type = AtomPH; };
+
+// exp(2 i pi phase) for the FP64-phase mode, phase = S.r (+ 1/2 when RED == 1), as
+// (c, s) in FP32.
+//   RED 0: t = phase - rint(phase) in [-1/2, 1/2] (exact), rounded once to FP32;
+//   RED 1: u = fract(phase + 1/2) in [0, 1) (exact), rounded once to FP32; then
+//          exp(2 i pi u) = -exp(2 i pi S.r) and the caller negates the factor.
+template <int RED>
+__device__ __forceinline__ void cis_ph64(double sx, double sy, double sz, const AtomPH& a,
+                                         float& c, float& s) {
+  double ph;
+  float tf;
+  if constexpr (RED == 0) {
+    ph = __builtin_fma(sz, a.z, __builtin_fma(sy, a.y, sx * a.x));
+    tf = static_cast<float>(ph - __builtin_rint(ph));
+  } else {
+    ph = __builtin_fma(sz, a.z, __builtin_fma(sy, a.y, __builtin_fma(sx, a.x, 0.5)));
+    tf = static_cast<float>(__builtin_amdgcn_fract(ph));
+  }
+  c = __builtin_amdgcn_cosf(tf);
+  s = __builtin_amdgcn_sinf(tf);
+}
+
+// (gr, gi) += sign * f * (c + i s); f = 1 when FK == 0.
+template <int FK, bool NEG>
+__device__ __forceinline__ void cmac(float& gr, float& gi, float fr, float fi, float c, float s) {
+  if constexpr (FK == 0) {
+    if constexpr (NEG) { gr -= c; gi -= s; } else { gr += c; gi += s; }
+  } else {
+    if constexpr (NEG) {
+      gr = __builtin_fmaf(-fr, c, gr);
+      gr = __builtin_fmaf(fi, s, gr);
+      gi = __builtin_fmaf(-fr, s, gi);
+      gi = __builtin_fmaf(-fi, c, gi);
+    } else {
+      gr = __builtin_fmaf(fr, c, gr);
+      gr = __builtin_fmaf(-fi, s, gr);
+      gi = __builtin_fmaf(fr, s, gi);
+      gi = __builtin_fmaf(fi, c, gi);
+    }
+  }
+}
+
+// (gr, gi) = f * (c + i s): the first term of a running sum.
+template <int FK>
+__device__ __forceinline__ void cterm(float& gr, float& gi, float fr, float fi, float c, float s) {
+  if constexpr (FK == 0) {
+    gr = c; gi = s;
+  } else {
+    gr = __builtin_fmaf(-fi, s, fr * c);
+    gi = __builtin_fmaf(fi, c, fr * s);
+  }
+}
+
+// Forward sum over atoms [a_begin + sp*per_split, ...) for P points per lane.
+// Grid: blocks_k * nsplit work-groups; blockIdx = sp * blocks_k + kb.
+template <int MODE, int P, int FK, int GRP, int RED>
+__global__ __launch_bounds__(kThreads) void fwd_kernel(
+    const typename AtomOf<MODE>::type* __restrict__ rec, int a_begin, int a_end, int per_split,
+    const float* __restrict__ S, int64_t K, int blocks_k, float4* __restrict__ part,
+    float2* __restrict__ A, int carry_in, int direct) {
+  using SReg = typename std::conditional<MODE == kPH64, double, float>::type;
+  const int kb = blockIdx.x % blocks_k;
+  const int sp = blockIdx.x / blocks_k;
+  const int64_t k0 = int64_t(kb) * (kThreads * P) + threadIdx.x;
+
+  SReg sx[P], sy[P], sz[P];
+  float sr[P], si[P], cr[P], ci[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int64_t k = k0 + int64_t(p) * kThreads;
+    const int64_t kk = k < K ? k : K - 1;     // lanes past the end compute a valid point, store nothing
+    sx[p] = static_cast<SReg>(S[3 * kk]);
+    sy[p] = static_cast<SReg>(S[3 * kk + 1]);
+    sz[p] = static_cast<SReg>(S[3 * kk + 2]);
+    if (carry_in && k < K) {
+      const float4 st = part[int64_t(sp) * K + k];
+      sr[p] = st.x; si[p] = st.y; cr[p] = st.z; ci[p] = st.w;
+    } else {
+      sr[p] = 0.f; si[p] = 0.f; cr[p] = 0.f; ci[p] = 0.f;
+    }
+  }
+
+  const int j0 = a_begin + sp * per_split;
+  const int j1 = min(j0 + per_split, a_end);
+
+  if constexpr (MODE == kF32) {
+    // The paper's arithmetic: FP32 phase, FP32 reduction, plain FP32 running sums.
+    for (int j = j0; j < j1; ++j) {
+      const AtomF32 a = rec[j];
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const float ph = __builtin_fmaf(sz[p], a.z, __builtin_fmaf(sy[p], a.y, sx[p] * a.x));
+        const float u = __builtin_amdgcn_fractf(ph);
+        const float c = __builtin_amdgcn_cosf(u);
+        const float s = __builtin_amdgcn_sinf(u);
+        cmac<FK, false>(sr[p], si[p], a.fr, a.fi, c, s);
+      }
+    }
+  } else {
+    // The sign of the terms in the RED == 1 variant (exp(2 i pi u) = -exp(2 i pi S.r))
+    // is applied once per group, as a source modifier of the two-sum.
+    constexpr float SGN = (RED == 1) ? -1.f : 1.f;
+    int j = j0;
+    for (; j + GRP <= j1; j += GRP) {
+      // Group partial: GRP/4 quads, each the running sum of 4 consecutive terms, are
+      // added into the group sum; the group sum is then folded into (sum, comp).
+      float gr[P], gi[P];
+#pragma unroll
+      for (int q = 0; q < GRP / 4; ++q) {
+        float qr[P], qi[P];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const AtomPH a = rec[j + 4 * q + u];
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            float c, s;
+            cis_ph64<RED>(sx[p], sy[p], sz[p], a, c, s);
+            if (u == 0) cterm<FK>(qr[p], qi[p], a.fr, a.fi, c, s);
+            else cmac<FK, false>(qr[p], qi[p], a.fr, a.fi, c, s);
+          }
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          if (q == 0) { gr[p] = qr[p]; gi[p] = qi[p]; }
+          else { gr[p] += qr[p]; gi[p] += qi[p]; }
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        two_sum_acc(sr[p], cr[p], SGN * gr[p]);
+        two_sum_acc(si[p], ci[p], SGN * gi[p]);
+      }
+    }
+    if (j < j1) {   // last, partial group: terms added one by one
+      float gr[P], gi[P];
+#pragma unroll
+      for (int p = 0; p < P; ++p) { gr[p] = 0.f; gi[p] = 0.f; }
+      for (; j < j1; ++j) {
+        const AtomPH a = rec[j];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          float c, s;
+          cis_ph64<RED>(sx[p], sy[p], sz[p], a, c, s);
+          cmac<FK, false>(gr[p], gi[p], a.fr, a.fi, c, s);
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        two_sum_acc(sr[p], cr[p], SGN * gr[p]);
+        two_sum_acc(si[p], ci[p], SGN * gi[p]);
+      }
+    }
+  }
+
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int64_t k = k0 + int64_t(p) * kThreads;
+    if (k < K) {
+      if (direct) A[k] = make_float2(sr[p] + cr[p], si[p] + ci[p]);
+      else part[int64_t(sp) * K + k] = make_float4(sr[p], si[p], cr[p], ci[p]);
+    }
+  }
+}
+
+// All-FP64 forward: FP64 phase, FP64 reduction, sincospi in FP64, FP64 sums.
+template <int P, int FK>
+__global__ __launch_bounds__(kThreads) void fwd_f64_kernel(
+    const AtomF64* __restrict__ rec, int a_begin, int a_end, int per_split,
+    const double* __restrict__ S, int64_t K, int blocks_k, double2* __restrict__ part,
+    double2* __restrict__ A, int carry_in, int direct) {
+  const int kb = blockIdx.x % blocks_k;
+  const int sp = blockIdx.x / blocks_k;
+  const int64_t k0 = int64_t(kb) * (kThreads * P) + threadIdx.x;
+  double sx[P], sy[P], sz[P], ar[P], ai[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int64_t k = k0 + int64_t(p) * kThreads;
+    const int64_t kk = k < K ? k : K - 1;
+    sx[p] = S[3 * kk]; sy[p] = S[3 * kk + 1]; sz[p] = S[3 * kk + 2];
+    if (carry_in && k < K) {
+      const double2 st = part[int64_t(sp) * K + k];
+      ar[p] = st.x; ai[p] = st.y;
+    } else {
+      ar[p] = 0.0; ai[p] = 0.0;
+    }
+  }
+  const int j0 = a_begin + sp * per_split;
+  const int j1 = min(j0 + per_split, a_end);
+  for (int j = j0; j < j1; ++j) {
+    const AtomF64 a = rec[j];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const double ph = __builtin_fma(sz[p], a.z, __builtin_fma(sy[p], a.y, sx[p] * a.x));
+      const double t = ph - __builtin_rint(ph);
+      double s, c;
+      sincospi(2.0 * t, &s, &c);
+      if constexpr (FK == 0) {
+        ar[p] += c; ai[p] += s;
+      } else {
+        ar[p] = __builtin_fma(a.fr, c, __builtin_fma(-a.fi, s, ar[p]));
+        ai[p] = __builtin_fma(a.fr, s, __builtin_fma(a.fi, c, ai[p]));
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int64_t k = k0 + int64_t(p) * kThreads;
+    if (k < K) {
+      if (direct) A[k] = make_double2(ar[p], ai[p]);
+      else part[int64_t(sp) * K + k] = make_double2(ar[p], ai[p]);
+    }
+  }
+}
+
+// Combine the split partials of every point in split order (deterministic).
+__global__ __launch_bounds__(kThreads) void fwd_reduce_kernel(const float4* __restrict__ part,
+                                                              int nsplit, int64_t K,
+                                                              float2* __restrict__ A) {
+  const int64_t k = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (k >= K) return;
+  float sr = 0.f, si = 0.f, cr = 0.f, ci = 0.f;
+  for (int sp = 0; sp < nsplit; ++sp) {
+    const float4 st = part[int64_t(sp) * K + k];
+    two_sum_acc(sr, cr, st.x);
+    two_sum_acc(si, ci, st.y);
+    cr += st.z;
+    ci += st.w;
+  }
+  A[k] = make_float2(sr + cr, si + ci);
+}
+
+__global__ __launch_bounds__(kThreads) void fwd_reduce_f64_kernel(const double2* __restrict__ part,
+                                                                  int nsplit, int64_t K,
+                                                                  double2* __restrict__ A) {
+  const int64_t k = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (k >= K) return;
+  double sr = 0.0, si = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) {
+    const double2 st = part[int64_t(sp) * K + k];
+    sr += st.x;
+    si += st.y;
+  }
+  A[k] = make_double2(sr, si);
+}
+
+// Atom records for the three precisions (grid-stride over atoms).
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void pack_atoms_kernel(const void* __restrict__ xyz_v,
+                                                              const void* __restrict__ f_v,
+                                                              int64_t n, void* __restrict__ rec_v) {
+  for (int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x; j < n;
+       j += int64_t(gridDim.x) * kThreads) {
+    if constexpr (MODE == kF64) {
+      const double* xyz = static_cast<const double*>(xyz_v);
+      const double* f = static_cast<const double*>(f_v);
+      AtomF64 r;
+      r.x = xyz[3 * j]; r.y = xyz[3 * j + 1]; r.z = xyz[3 * j + 2];
+      r.fr = f ? f[2 * j] : 1.0;
+      r.fi = f ? f[2 * j + 1] : 0.0;
+      r.pad = 0.0;
+      static_cast<AtomF64*>(rec_v)[j] = r;
+    } else {
+      const float* xyz = static_cast<const float*>(xyz_v);
+      const float* f = static_cast<const float*>(f_v);
+      const float fr = f ? f[2 * j] : 1.f;
+      const float fi = f ? f[2 * j + 1] : 0.f;
+      if constexpr (MODE == kPH64) {
+        AtomPH r;
+        r.x = xyz[3 * j]; r.y = xyz[3 * j + 1]; r.z = xyz[3 * j + 2];   // exact widening
+        r.fr = fr; r.fi = fi;
+        static_cast<AtomPH*>(rec_v)[j] = r;
+      } else {
+        AtomF32 r;
+        r.x = xyz[3 * j]; r.y = xyz[3 * j + 1]; r.z = xyz[3 * j + 2];
+        r.fr = fr; r.fi = fi; r.pad0 = r.pad1 = r.pad2 = 0.f;
+        static_cast<AtomF32*>(rec_v)[j] = r;
+      }
+    }
+  }
+}
+
+unsigned grid_for(int64_t n) {
+  int64_t b = (n + kThreads - 1) / kThreads;
+  if (b < 1) b = 1;
+  if (b > 65536) b = 65536;
+  return static_cast<unsigned>(b);
+}
+
+template <int MODE, int P, int FK>
+hipError_t fwd_dispatch_red(const Plan& p, const void* rec, int64_t a_begin, int64_t a_end,
+                            int64_t per_split, const void* S, void* partial, void* A,
+                            int carry_in, int direct, hipStream_t st, int red) {
+  using AT = typename AtomOf<MODE>::type;
+  const dim3 grid(static_cast<unsigned>(p.blocks * p.nsplit));
+  const auto* r = static_cast<const AT*>(rec);
+  const auto* s = static_cast<const float*>(S);
+  auto* pa = static_cast<float4*>(partial);
+  auto* a = static_cast<float2*>(A);
+  if constexpr (MODE == kF32) {   // plain FP32 sums: no groups, no reduction variants
+    fwd_kernel<MODE, P, FK, 16, 0><<<grid, kThreads, 0, st>>>(
+        r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct);
+    return hipGetLastError();
+  }
+  if (p.grp == 16 && red == 0)
+    fwd_kernel<MODE, P, FK, 16, 0><<<grid, kThreads, 0, st>>>(
+        r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct);
+  else if (p.grp == 16 && red == 1)
+    fwd_kernel<MODE, P, FK, 16, 1><<<grid, kThreads, 0, st>>>(
+        r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct);
+  else if (p.grp == 32 && red == 0)
+    fwd_kernel<MODE, P, FK, 32, 0><<<grid, kThreads, 0, st>>>(
+        r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct);
+  else if (p.grp == 32 && red == 1)
+    fwd_kernel<MODE, P, FK, 32, 1><<<grid, kThreads, 0, st>>>(
+        r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct);
+  else if (p.grp == 8 && red == 0)
+    fwd_kernel<MODE, P, FK, 8, 0><<<grid, kThreads, 0, st>>>(
+        r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct);
+  else
+    fwd_kernel<MODE, P, FK, 8, 1><<<grid, kThreads, 0, st>>>(
+        r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct);
+  return hipGetLastError();
+}
+
+template <int MODE, int P>
+hipError_t fwd_dispatch_fk(const Plan& p, const void* rec, int64_t a_begin, int64_t a_end,
+                           int64_t per_split, const void* S, void* partial, void* A,
+                           int carry_in, int direct, hipStream_t st) {
+  if (p.fk)
+    return fwd_dispatch_red<MODE, P, 1>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in,
+                                        direct, st, p.red);
+  return fwd_dispatch_red<MODE, P, 0>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in,
+                                      direct, st, p.red);
+}
+
+template <int MODE>
+hipError_t fwd_dispatch_p(const Plan& p, const void* rec, int64_t a_begin, int64_t a_end,
+                          int64_t per_split, const void* S, void* partial, void* A, int carry_in,
+                          int direct, hipStream_t st) {
+  switch (p.per_lane) {
+    case 4: return fwd_dispatch_fk<MODE, 4>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st);
+    case 2: return fwd_dispatch_fk<MODE, 2>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st);
+    default: return fwd_dispatch_fk<MODE, 1>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st);
+  }
+}
+
+template <int P, int FK>
+hipError_t fwd_f64_launch(const Plan& p, const void* rec, int64_t a_begin, int64_t a_end,
+                          int64_t per_split, const void* S, void* partial, void* A, int carry_in,
+                          int direct, hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>(p.blocks * p.nsplit));
+  fwd_f64_kernel<P, FK><<<grid, kThreads, 0, st>>>(
+      static_cast<const AtomF64*>(rec), int(a_begin), int(a_end), int(per_split),
+      static_cast<const double*>(S), p.lanes, int(p.blocks), static_cast<double2*>(partial),
+      static_cast<double2*>(A), carry_in, direct);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_pack_atoms(int mode, const void* xyz, const void* f, int64_t n, void* rec,
+                             hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const unsigned g = grid_for(n);
+  if (mode == kF64) pack_atoms_kernel<kF64><<<g, kThreads, 0, st>>>(xyz, f, n, rec);
+  else if (mode == kPH64) pack_atoms_kernel<kPH64><<<g, kThreads, 0, st>>>(xyz, f, n, rec);
+  else pack_atoms_kernel<kF32><<<g, kThreads, 0, st>>>(xyz, f, n, rec);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd_chunk(const Plan& p, const void* rec, int64_t a_begin, int64_t a_end,
+                            int64_t per_split, const void* S, void* partial, void* A,
+                            int carry_in, int direct, hipStream_t st) {
+  if (p.mode == kF64) {
+    if (p.per_lane == 2)
+      return p.fk ? fwd_f64_launch<2, 1>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st)
+                  : fwd_f64_launch<2, 0>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st);
+    return p.fk ? fwd_f64_launch<1, 1>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st)
+                : fwd_f64_launch<1, 0>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st);
+  }
+  if (p.mode == kPH64)
+    return fwd_dispatch_p<kPH64>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st);
+  return fwd_dispatch_p<kF32>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st);
+}
+
+hipError_t launch_fwd_reduce(const Plan& p, const void* partial, void* A, hipStream_t st) {
+  const int64_t K = p.lanes;
+  const unsigned g = static_cast<unsigned>((K + kThreads - 1) / kThreads);
+  if (p.mode == kF64)
+    fwd_reduce_f64_kernel<<<g, kThreads, 0, st>>>(static_cast<const double2*>(partial), p.nsplit, K,
+                                                 static_cast<double2*>(A));
+  else
+    fwd_reduce_kernel<<<g, kThreads, 0, st>>>(static_cast<const float4*>(partial), p.nsplit, K,
+                                             static_cast<float2*>(A));
+  return hipGetLastError();
+}
+
+}  // namespace nx

@@ -1,0 +1,105 @@
+// nx_internal.h -- records, launch plans and kernel launchers shared by the libnx
+// translation units.  Not part of the public ABI (that is include/nx.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace nx {
+
+constexpr int kThreads = 256;          // work-group size of every sum kernel (4 wave64)
+
+// ---------------------------------------------------------------------------------
+// Packed records streamed through the scalar (wave-uniform) load path.  Each record
+// is read by a whole wavefront at once and its fields are used directly as SGPR
+// operands of the VALU instructions, so no LDS staging and no barrier is needed.
+
+// Atom for the FP32 mode: coordinates and factor in FP32.
+struct alignas(16) AtomF32 { float x, y, z, fr, fi, pad0, pad1, pad2; };            // 32 B
+// Atom for the FP64-phase mode: coordinates widened (exactly) to FP64.
+struct alignas(16) AtomPH { double x, y, z; float fr, fi; };                         // 32 B
+// Atom for the all-FP64 path.
+struct alignas(16) AtomF64 { double x, y, z, fr, fi, pad; };                         // 48 B
+// Point for the FP32-mode adjoint: S and the seed G.
+struct alignas(16) PointF32 { float sx, sy, sz, gr, gi, pad0, pad1, pad2; };         // 32 B
+// Point for the FP64-phase adjoint: S in FP64 for the phase, S in FP32 for the
+// multiply-add into the per-atom sums, and the seed G.
+struct alignas(16) PointPH { double sx, sy, sz; float gr, gi, fx, fy, fz, pad; };    // 48 B
+// Point for the all-FP64 adjoint.
+struct alignas(16) PointF64 { double sx, sy, sz, gr, gi, pad; };                     // 48 B
+
+// Running state of one output lane item (a point for the forward, one component of
+// an atom's sum for the adjoint) kept between launches and across splits.
+//   FP32 modes: (sum_re, sum_im, comp_re, comp_im) -- float4 per point;
+//   FP64 path:  (sum_re, sum_im)                   -- double2 per point.
+
+// Kernel variants selected by the host.
+enum Mode : int { kF32 = 0, kPH64 = 1, kF64 = 2 };
+
+// ---------------------------------------------------------------------------------
+// Launch plan.  "Lane items" are the outputs one lane owns (points for the forward,
+// atoms for the adjoint), "stream items" are what every lane loops over (atoms for
+// the forward, points for the adjoint).  The stream is cut into `nsplit` contiguous
+// slices processed by different work-groups when there are too few lane items to
+// fill the chip, and into chunks of at most kLaunchPairs pairs per launch so that
+// no single dispatch runs for long; partial sums are carried between chunks in the
+// workspace and combined across splits in a fixed order.
+struct Plan {
+  int mode = 0;          // Mode
+  int per_lane = 1;      // lane items per lane (P points or Q atoms)
+  int grp = 16;          // stream items per compensated group
+  int fk = 0;            // 0: f_j = 1, 1: complex f_j
+  int red = 0;           // phase reduction variant of the FP64-phase kernels (0 centred, 1 fract)
+  int64_t lanes = 0;     // number of lane items
+  int64_t stream = 0;    // number of stream items
+  int64_t blocks = 0;    // work-groups over lane items
+  int nsplit = 1;        // stream slices
+  int64_t chunk = 0;     // stream items per launch
+  int64_t nchunks = 0;   // launches
+  size_t rec_bytes = 0;      // packed stream records
+  size_t partial_bytes = 0;  // carried / split partial state
+  size_t misc_bytes = 0;     // small scratch (loss partials)
+  size_t total() const { return rec_bytes + partial_bytes + misc_bytes; }
+};
+
+constexpr int64_t kTargetBlocks = 4096;       // work-groups wanted per launch
+constexpr int64_t kMinStreamPerSplit = 64;    // smallest stream slice
+constexpr int64_t kMaxSplit = 1024;
+constexpr int64_t kLaunchPairs = int64_t(1) << 39;   // pairs per launch (well under 1 s)
+constexpr int kLossBlocks = 1024;             // fixed grid of the loss reduction
+
+enum Op : int { kOpFwd = 0, kOpBwd = 1, kOpFwdF64 = 2, kOpBwdF64 = 3, kOpLoss = 4 };
+
+// Builds the plan of (op, mode) for the sizes; pure host code, no HIP call.
+Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_null);
+
+// Per-launch stream range of chunk c: [begin, end) and the slice length per split.
+void chunk_range(const Plan& p, int64_t c, int64_t* begin, int64_t* end, int64_t* per_split);
+
+// ---------------------------------------------------------------------------------
+// Launchers (defined in the kernel translation units).  All return the launch error.
+hipError_t launch_pack_atoms(int mode, const void* xyz, const void* f, int64_t n, void* rec,
+                             hipStream_t st);
+hipError_t launch_pack_points(int mode, const void* S, const void* G, int64_t k, void* rec,
+                              hipStream_t st);
+
+// One forward chunk over points (lane items) for atoms [a_begin, a_end).
+hipError_t launch_fwd_chunk(const Plan& p, const void* rec, int64_t a_begin, int64_t a_end,
+                            int64_t per_split, const void* S, void* partial, void* A,
+                            int carry_in, int direct, hipStream_t st);
+// Combine split partials into A.
+hipError_t launch_fwd_reduce(const Plan& p, const void* partial, void* A, hipStream_t st);
+
+// One adjoint chunk over atoms (lane items) for points [k_begin, k_end).
+hipError_t launch_bwd_chunk(const Plan& p, const void* rec, int64_t k_begin, int64_t k_end,
+                            int64_t per_split, const void* xyz, const void* f, void* partial,
+                            void* grad, int carry_in, int direct, hipStream_t st);
+hipError_t launch_bwd_reduce(const Plan& p, const void* partial, const void* f, void* grad,
+                             hipStream_t st);
+
+hipError_t launch_loss(const float* A, const float* I, int64_t k, double* L, float* G,
+                       double* partial, hipStream_t st);
+
+}  // namespace nx

@@ -1,0 +1,126 @@
+"""The C ABI on the CPU: the library loads without a GPU, exports every entry point
+include/nx.h declares, and rejects invalid arguments on the host, before any HIP
+call, with the documented status codes and a message.  No compute call is made here
+(the pointers below are never dereferenced: validation fails first)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1010_2641_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nx.h")
+
+FAKE = 0x10000          # a non-NULL, well-aligned address that validation never reaches
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nx_\w+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    names = declared_functions()
+    assert "nx_scatter_fwd" in names and "nx_scatter_bwd" in names
+    for name in names:
+        assert hasattr(_lib.lib, name), f"libnx.so does not export {name}"
+        assert name in _lib.SIGNATURES, f"binding has no signature for {name}"
+    assert sorted(_lib.SIGNATURES) == names
+
+
+def test_version():
+    assert _lib.nx_version() == 100
+
+
+def fwd(n_atoms=8, n_points=8, xyz=FAKE, f=None, S=FAKE, A=FAKE, mode=1, ws=FAKE, wsb=1 << 40):
+    return _lib.nx_scatter_fwd(xyz, f, n_atoms, S, n_points, A, mode, ws, wsb, None)
+
+
+def bwd(n_atoms=8, n_points=8, xyz=FAKE, f=None, S=FAKE, G=FAKE, g=FAKE, mode=1, ws=FAKE, wsb=1 << 40):
+    return _lib.nx_scatter_bwd(xyz, f, n_atoms, S, n_points, G, g, mode, ws, wsb, None)
+
+
+def test_negative_and_oversized_counts():
+    assert fwd(n_atoms=-1) == _lib.NX_ERR_ARG
+    assert "negative" in _lib.last_error()
+    assert fwd(n_points=-5) == _lib.NX_ERR_ARG
+    assert fwd(n_points=_lib.NX_MAX_COUNT + 1) == _lib.NX_ERR_ARG
+    assert "NX_MAX_COUNT" in _lib.last_error()
+    assert bwd(n_atoms=-1) == _lib.NX_ERR_ARG
+    assert _lib.nx_scatter_fwd_f64(FAKE, None, -1, FAKE, 4, FAKE, FAKE, 1 << 40, None) == _lib.NX_ERR_ARG
+    assert _lib.nx_scatter_bwd_f64(FAKE, None, 4, FAKE, -1, FAKE, FAKE, FAKE, 1 << 40, None) == _lib.NX_ERR_ARG
+    assert _lib.nx_loss_grad(FAKE, FAKE, -3, FAKE, FAKE, FAKE, 1 << 40, None) == _lib.NX_ERR_ARG
+
+
+def test_null_pointers():
+    assert fwd(S=None) == _lib.NX_ERR_ARG
+    assert "NULL" in _lib.last_error()
+    assert fwd(A=None) == _lib.NX_ERR_ARG
+    assert fwd(xyz=None) == _lib.NX_ERR_ARG
+    assert bwd(G=None) == _lib.NX_ERR_ARG
+    assert bwd(g=None) == _lib.NX_ERR_ARG
+    assert _lib.nx_loss_grad(FAKE, None, 4, FAKE, FAKE, FAKE, 1 << 40, None) == _lib.NX_ERR_ARG
+    assert _lib.nx_loss_grad(FAKE, FAKE, 4, None, FAKE, FAKE, 1 << 40, None) == _lib.NX_ERR_ARG
+
+
+def test_unknown_mode():
+    assert fwd(mode=7) == _lib.NX_ERR_MODE
+    assert "mode" in _lib.last_error()
+    assert bwd(mode=-1) == _lib.NX_ERR_MODE
+    assert _lib.nx_workspace_bytes(4, 4, 3, _lib.NX_OP_FWD, 0) == 0
+    assert "mode" in _lib.last_error()
+    assert _lib.nx_workspace_bytes(4, 4, 1, 9, 0) == 0
+    assert "op" in _lib.last_error()
+
+
+def test_misaligned():
+    assert fwd(A=FAKE + 4) == _lib.NX_ERR_ARG
+    assert fwd(f=FAKE + 2) == _lib.NX_ERR_ARG
+    assert _lib.nx_scatter_fwd_f64(FAKE, None, 4, FAKE, 4, FAKE + 8, FAKE, 1 << 40, None) == _lib.NX_ERR_ARG
+
+
+def test_workspace_checks():
+    need = _lib.nx_workspace_bytes(4096, 4096, 1, _lib.NX_OP_FWD, 1)
+    assert need >= 4096 * 32          # packed FP64-phase atom records
+    assert fwd(n_atoms=4096, n_points=4096, wsb=need - 1) == _lib.NX_ERR_WORKSPACE
+    assert "workspace" in _lib.last_error()
+    assert fwd(n_atoms=4096, n_points=4096, ws=None, wsb=need) == _lib.NX_ERR_WORKSPACE
+    assert fwd(n_atoms=4096, n_points=4096, ws=FAKE + 8, wsb=need) == _lib.NX_ERR_WORKSPACE
+    # loss workspace is a fixed small scratch
+    lw = _lib.nx_workspace_bytes(0, 10, 0, _lib.NX_OP_LOSS, 1)
+    assert 0 < lw <= 1 << 16
+    assert _lib.nx_loss_grad(FAKE, FAKE, 10, FAKE, FAKE, FAKE, lw - 8, None) == _lib.NX_ERR_WORKSPACE
+
+
+def test_workspace_sizes_scale():
+    # split partials appear when there are few points; packed records always
+    small_k = _lib.nx_workspace_bytes(1_000_000, 65_536, 1, _lib.NX_OP_FWD, 1)
+    assert small_k > 1_000_000 * 32
+    big_k = _lib.nx_workspace_bytes(203_557, 2_097_152, 1, _lib.NX_OP_FWD, 0)
+    assert big_k >= 203_557 * 32
+    f64 = _lib.nx_workspace_bytes(1000, 1000, 0, _lib.NX_OP_FWD_F64, 0)
+    assert f64 >= 1000 * 48
+    b = _lib.nx_workspace_bytes(97_556, 262_144, 1, _lib.NX_OP_BWD, 1)
+    assert b >= 262_144 * 48
+
+
+def test_empty_calls_queue_nothing():
+    # n_points == 0 forward and n_atoms == 0 adjoint return OK before any HIP call
+    assert fwd(n_points=0, xyz=None, S=None, A=None, ws=None, wsb=0) == _lib.NX_OK
+    assert _lib.last_error() == ""
+    assert bwd(n_atoms=0, xyz=None, S=None, G=None, g=None, ws=None, wsb=0) == _lib.NX_OK
+    assert _lib.nx_scatter_fwd_f64(None, None, 5, None, 0, None, None, 0, None) == _lib.NX_OK
+    assert _lib.nx_scatter_bwd_f64(None, None, 0, None, 5, None, None, None, 0, None) == _lib.NX_OK
+
+
+def test_python_wrappers_refuse_cpu_tensors():
+    torch = pytest.importorskip("torch")
+    from paper_1010_2641_amd import api
+    x = torch.zeros((4, 3), dtype=torch.float32)
+    with pytest.raises(ValueError, match="GPU"):
+        api.scatter_fwd(x, None, x)
+    with pytest.raises(ValueError, match="unknown mode"):
+        api._mode("fp16")

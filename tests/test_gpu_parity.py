@@ -1,0 +1,305 @@
+"""Parity of the HIP library with the FP64 CPU oracle, element by element, at sizes
+the oracle finishes in seconds that still span several work-groups, several splits
+and a ragged tail; plus edge cases, the chunked launch path, determinism and the
+invariants of Eq. 2 on the GPU.  Every call goes through the C ABI (via the thin
+torch wrappers)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1010_2641_amd import api, workloads as wl
+from tests import metrics as M
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def dev(a):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def run_fwd(xyz, f, S, mode):
+    """GPU forward in the given mode on the FP32 problem; returns complex128 numpy."""
+    if mode == "f64":
+        ff = None if f is None else dev(f.astype(np.complex128))
+        A = api.scatter_fwd_f64(dev(xyz.astype(np.float64)), ff, dev(S.astype(np.float64)))
+    else:
+        A = api.scatter_fwd(dev(xyz), dev(f), dev(S), mode)
+    torch.cuda.synchronize()
+    return A.cpu().numpy().astype(np.complex128)
+
+
+def run_bwd(xyz, f, S, G, mode):
+    if mode == "f64":
+        ff = None if f is None else dev(f.astype(np.complex128))
+        g = api.scatter_bwd_f64(dev(xyz.astype(np.float64)), ff, dev(S.astype(np.float64)),
+                                dev(G.astype(np.complex128)))
+    else:
+        g = api.scatter_bwd(dev(xyz), dev(f), dev(S), dev(G.astype(np.complex64)), mode)
+    torch.cuda.synchronize()
+    return g.cpu().numpy().astype(np.float64)
+
+
+def check_fwd(A, A_ref, mode, label="", f=None, n=None):
+    """Random-position problems (f, n given): T2 and the pointwise error against the
+    random-walk scale.  Crystal-like problems: T1 and T2."""
+    e2 = M.t2(A, A_ref)
+    if n is not None:
+        e1 = M.incoherent(A, A_ref, f, n)
+        print(f"{label} mode={mode} pointwise/sqrt(sum|f|^2)={e1:.3e} T2={e2:.3e}", flush=True)
+        lim1 = {"ph64": M.INC_TOL, "f64": M.F64_INC_TOL}.get(mode)
+    else:
+        e1 = M.t1(A, A_ref)
+        print(f"{label} mode={mode} T1={e1:.3e} T2={e2:.3e}", flush=True)
+        lim1 = {"ph64": M.T1_TOL, "f64": M.F64_T1_TOL}.get(mode)
+    lim2 = {"ph64": M.T2_TOL, "f64": M.F64_T2_TOL}.get(mode)
+    if lim1 is not None:
+        assert e1 <= lim1 and e2 <= lim2
+    return e1, e2
+
+
+# ----------------------------------------------------------------------------- forward
+
+@pytest.mark.parametrize("n,k,cplx", [(3001, 5003, True), (777, 1234, False), (2048, 300, True)])
+@pytest.mark.parametrize("mode", ["ph64", "f64", "f32"])
+def test_fwd_random_ragged(n, k, cplx, mode):
+    xyz, f, S = wl.random_problem(n, k, seed=n + k, extent=50.0, s_range=4.0, complex_f=cplx)
+    print(f"case fwd N={n} K={k} complex={cplx} mode={mode}", flush=True)
+    A_ref = oracle.forward(xyz, f, S)
+    A = run_fwd(xyz, f, S, mode)
+    e1, e2 = check_fwd(A, A_ref, mode, f=f, n=n)
+    if mode == "f32":
+        # the paper's FP32 arithmetic: phases up to ~600 cycles lose ~1e-4 rad per term
+        assert e2 < 5e-3
+
+
+@pytest.mark.parametrize("mode", ["ph64", "f64", "f32"])
+@pytest.mark.parametrize("n,k", [(0, 100), (1, 1), (15, 300), (16, 257), (17, 64), (5, 1)])
+def test_fwd_edge_sizes(n, k, mode):
+    xyz, f, S = wl.random_problem(n, k, seed=100 + n + k)
+    print(f"case fwd-edge N={n} K={k} mode={mode}", flush=True)
+    A_ref = oracle.forward(xyz, f, S)
+    A = run_fwd(xyz, f, S, mode)
+    if n == 0:
+        assert np.all(A == 0)
+    else:
+        tol = {"f64": 1e-12, "ph64": 2e-6, "f32": 2e-3}[mode]
+        assert np.max(np.abs(A - A_ref)) <= tol * np.sum(np.abs(f))
+
+
+def test_fwd_empty_points():
+    xyz, f, S = wl.random_problem(10, 0, seed=1)
+    A = api.scatter_fwd(dev(xyz), dev(f), dev(S), "ph64")
+    assert A.shape == (0,)
+
+
+@pytest.mark.parametrize("mode", ["ph64", "f64"])
+def test_fwd_chunked_launches(mode, monkeypatch):
+    """Force many chunks per call (state carried in the workspace between launches)
+    and many splits; the result must still match the oracle."""
+    xyz, f, S = wl.random_problem(2500, 3000, seed=11, extent=30.0, s_range=3.0)
+    A_ref = oracle.forward(xyz, f, S)
+    monkeypatch.setenv("NX_TUNE_LAUNCH_PAIRS", str(3000 * 256))
+    A = run_fwd(xyz, f, S, mode)
+    check_fwd(A, A_ref, mode, "chunked", f=f, n=len(xyz))
+
+
+@pytest.mark.parametrize("red", ["0", "1"])
+@pytest.mark.parametrize("grp", ["8", "16", "32"])
+def test_fwd_variants(red, grp, monkeypatch):
+    """Both phase-reduction variants and every group size meet the tolerances."""
+    monkeypatch.setenv("NX_TUNE_RED", red)
+    monkeypatch.setenv("NX_TUNE_GRP", grp)
+    xyz, f, S = wl.random_problem(3001, 2100, seed=12, extent=80.0, s_range=6.0)
+    A_ref = oracle.forward(xyz, f, S)
+    check_fwd(run_fwd(xyz, f, S, "ph64"), A_ref, "ph64", f"red={red} grp={grp}", f=f, n=len(xyz))
+
+
+@pytest.mark.parametrize("mode", ["ph64", "f32", "f64"])
+def test_fwd_bitwise_deterministic(mode):
+    xyz, f, S = wl.random_problem(3000, 4000, seed=13)
+    A1 = run_fwd(xyz, f, S, mode)
+    A2 = run_fwd(xyz, f, S, mode)
+    assert np.array_equal(A1.view(np.uint64), A2.view(np.uint64))
+
+
+# ----------------------------------------------------------------------------- invariants on the GPU
+
+def test_gpu_laue_block_and_bragg_node():
+    """sigma = 0 block: the GPU matches the 3D Laue closed form; at a Bragg node every
+    reduced phase is exactly 0, so A = N exactly."""
+    from tests.test_oracle_pins import laue_3d
+    nx_, ny_, nz_ = 16, 12, 20
+    xyz = wl._f32(wl.cubic_sites(nx_, ny_, nz_))
+    rng = np.random.default_rng(14)
+    S = np.concatenate([rng.uniform(-4, 4, size=(2000, 3)),
+                        np.array([[0, 0, 4], [1, 2, 3], [-3, 0, 8]], dtype=float)]).astype(np.float32)
+    ref = laue_3d(nx_, ny_, nz_, S.astype(np.float64))
+    n = nx_ * ny_ * nz_
+    for mode, tol in (("ph64", 2e-6), ("f64", 1e-11)):
+        A = run_fwd(xyz, None, S, mode)
+        assert np.max(np.abs(A - ref)) <= tol * n, mode
+        assert np.all(A[-3:] == n), mode
+
+
+def test_gpu_friedel_and_superposition():
+    xyz, f, S = wl.random_problem(2000, 1500, seed=15, extent=60.0)
+    fr = np.abs(f).astype(np.complex64)
+    Ap = run_fwd(xyz, fr, S, "ph64")
+    Am = run_fwd(xyz, fr, -S, "ph64")
+    scale = np.linalg.norm(Ap)
+    assert np.linalg.norm(Am - np.conj(Ap)) <= 1e-6 * scale
+    A1 = run_fwd(xyz[:777], f[:777], S, "ph64")
+    A2 = run_fwd(xyz[777:], f[777:], S, "ph64")
+    A = run_fwd(xyz, f, S, "ph64")
+    assert np.linalg.norm(A - (A1 + A2)) <= 1e-6 * np.linalg.norm(A)
+
+
+def test_gpu_translation_ph64_vs_f32():
+    """|A(r + t)| = |A(r)|.  With t = (1000, 2000, 500) the FP64-phase mode keeps the
+    intensity within T1; the paper's FP32 arithmetic visibly does not."""
+    xyz, f, S = wl.random_problem(1500, 1200, seed=16, extent=10.0, s_range=4.0)
+    t = np.array([1000.0, 2000.0, 500.0])
+    xt = (xyz.astype(np.float64) + t).astype(np.float32)
+    I_ref = np.abs(oracle.forward(xt, f, S)) ** 2       # the translated FP32 problem itself
+    I_ph = np.abs(run_fwd(xt, f, S, "ph64")) ** 2
+    I_32 = np.abs(run_fwd(xt, f, S, "f32")) ** 2
+    m = I_ref >= 1e-6 * I_ref.max()
+    e_ph = np.max(np.abs(I_ph[m] - I_ref[m]) / I_ref[m])
+    e_32 = np.max(np.abs(I_32[m] - I_ref[m]) / I_ref[m])
+    print(f"translated T1: ph64 {e_ph:.2e}  f32 {e_32:.2e}", flush=True)
+    assert e_ph <= M.T1_TOL
+    assert e_32 > 100 * e_ph
+
+
+# ----------------------------------------------------------------------------- adjoint
+
+@pytest.mark.parametrize("n,k,cplx", [(2999, 4001, True), (1000, 2500, False), (300, 9000, True)])
+@pytest.mark.parametrize("mode", ["ph64", "f64", "f32"])
+def test_bwd_random_ragged(n, k, cplx, mode):
+    xyz, f, S = wl.random_problem(n, k, seed=2 * n + k, extent=40.0, s_range=3.0, complex_f=cplx)
+    G = wl.random_seed_field(k, seed=n, scale=10.0)
+    print(f"case bwd N={n} K={k} complex={cplx} mode={mode}", flush=True)
+    g_ref = oracle.adjoint(xyz, f, S, G)
+    g = run_bwd(xyz, f, S, G, mode)
+    en, em = M.t3(g, g_ref)
+    print(f"  T3 norm={en:.3e} max={em:.3e}", flush=True)
+    if mode == "ph64":
+        assert en <= M.T3_NORM_TOL and em <= M.T3_MAX_TOL
+    elif mode == "f64":
+        assert en <= M.F64_T3_TOL
+    else:
+        assert en < 5e-3
+
+
+@pytest.mark.parametrize("mode", ["ph64", "f64", "f32"])
+@pytest.mark.parametrize("n,k", [(1, 1), (100, 0), (1, 333), (257, 15), (33, 17)])
+def test_bwd_edge_sizes(n, k, mode):
+    xyz, f, S = wl.random_problem(n, k, seed=7 + n + k)
+    G = wl.random_seed_field(k, seed=k + 1)
+    g_ref = oracle.adjoint(xyz, f, S, G)
+    g = run_bwd(xyz, f, S, G, mode)
+    if k == 0:
+        assert np.all(g == 0)
+    else:
+        scale = np.sum(np.abs(G)) * np.max(np.abs(S)) * np.max(np.abs(f)) * 2 * np.pi
+        tol = {"f64": 1e-12, "ph64": 1e-5, "f32": 2e-3}[mode]
+        assert np.max(np.abs(g - g_ref)) <= tol * scale
+
+
+@pytest.mark.parametrize("mode", ["ph64", "f64"])
+def test_bwd_chunked_launches(mode, monkeypatch):
+    xyz, f, S = wl.random_problem(1800, 5000, seed=17, extent=30.0, s_range=3.0)
+    G = wl.random_seed_field(5000, seed=18)
+    g_ref = oracle.adjoint(xyz, f, S, G)
+    monkeypatch.setenv("NX_TUNE_LAUNCH_PAIRS", str(2048 * 256))
+    g = run_bwd(xyz, f, S, G, mode)
+    en, em = M.t3(g, g_ref)
+    assert en <= (M.T3_NORM_TOL if mode == "ph64" else M.F64_T3_TOL)
+
+
+@pytest.mark.parametrize("red", ["0", "1"])
+@pytest.mark.parametrize("grp", ["16", "32"])
+def test_bwd_variants(red, grp, monkeypatch):
+    monkeypatch.setenv("NX_TUNE_RED", red)
+    monkeypatch.setenv("NX_TUNE_GRP", grp)
+    xyz, f, S = wl.random_problem(1500, 3000, seed=19, extent=60.0, s_range=4.0)
+    G = wl.random_seed_field(3000, seed=20)
+    g_ref = oracle.adjoint(xyz, f, S, G)
+    en, em = M.t3(run_bwd(xyz, f, S, G, "ph64"), g_ref)
+    assert en <= M.T3_NORM_TOL and em <= M.T3_MAX_TOL
+
+
+def test_bwd_bitwise_deterministic():
+    xyz, f, S = wl.random_problem(2000, 3000, seed=21)
+    G = wl.random_seed_field(3000, seed=22)
+    g1 = run_bwd(xyz, f, S, G, "ph64")
+    g2 = run_bwd(xyz, f, S, G, "ph64")
+    assert np.array_equal(g1, g2)
+
+
+# ----------------------------------------------------------------------------- misfit and seed
+
+@pytest.mark.parametrize("k", [0, 1, 255, 100_003])
+def test_loss_grad(k):
+    A, I = wl.random_amplitudes(k, seed=23 + k)
+    L_ref, G_ref = oracle.loss(A, I)
+    L, G = api.loss_grad(dev(A), dev(I))
+    torch.cuda.synchronize()
+    L = float(L.cpu())
+    G = G.cpu().numpy()
+    if k == 0:
+        assert L == 0.0
+        return
+    assert abs(L - L_ref) <= 1e-13 * abs(L_ref)
+    # e and G are formed in FP64 exactly as the oracle forms them, then rounded once
+    assert np.array_equal(G, G_ref.astype(np.complex64))
+
+
+# ----------------------------------------------------------------------------- the whole step
+
+@pytest.mark.parametrize("cplx", [True, False])
+def test_fit_step_small(cplx):
+    """Forward, misfit and adjoint on the GPU against the same chain run entirely by
+    the oracle (each side computes its own A, L and G)."""
+    xyz, f, S = wl.random_problem(1200, 2600, seed=24, extent=20.0, s_range=2.5, complex_f=cplx)
+    rng = np.random.default_rng(25)
+    I = (np.abs(oracle.forward(xyz + rng.normal(0, 0.05, xyz.shape), f, S)) ** 2).astype(np.float32)
+    A_ref = oracle.forward(xyz, f, S)
+    L_ref, G_ref = oracle.loss(A_ref, I)
+    g_ref = oracle.adjoint(xyz, f, S, G_ref)
+    L, A, g = api.fit_step(dev(xyz), dev(f), dev(S), dev(I), "ph64")
+    torch.cuda.synchronize()
+    check_fwd(A.cpu().numpy(), A_ref, "ph64", "fit-step", f=f, n=len(xyz))
+    assert abs(float(L.cpu()) - L_ref) <= 1e-5 * L_ref
+    en, em = M.t3(g.cpu().numpy(), g_ref)
+    print(f"fit-step T3 norm={en:.2e} max={em:.2e}", flush=True)
+    assert en <= M.T3_NORM_TOL and em <= M.T3_MAX_TOL
+
+
+def test_autograd_matches_oracle():
+    """torch autograd through ScatterFn: L computed with torch ops from A, gradient by
+    the hand-written adjoint kernel."""
+    xyz, f, S = wl.random_problem(900, 1700, seed=26, extent=15.0, s_range=2.0)
+    I = np.abs(wl.random_seed_field(1700, seed=27, scale=30.0)).astype(np.float32) ** 2
+    A_ref = oracle.forward(xyz, f, S)
+    _, G_ref = oracle.loss(A_ref, I)
+    g_ref = oracle.adjoint(xyz, f, S, G_ref)
+    x = dev(xyz).requires_grad_(True)
+    A = api.scatter(x, dev(f), dev(S), "ph64")
+    L = ((A.abs() ** 2 - dev(I)) ** 2).sum()
+    L.backward()
+    en, em = M.t3(x.grad.cpu().numpy(), g_ref)
+    assert en <= M.T3_NORM_TOL and em <= M.T3_MAX_TOL
+
+
+def test_gradcheck_f64_path():
+    """torch.autograd.gradcheck through the all-FP64 forward and adjoint kernels."""
+    xyz, f, S = wl.random_problem(12, 20, seed=28, extent=4.0, s_range=1.0)
+    x = dev(xyz.astype(np.float64)).requires_grad_(True)
+    ff = dev(f.astype(np.complex128))
+    SS = dev(S.astype(np.float64))
+    assert torch.autograd.gradcheck(lambda t: api.scatter(t, ff, SS), (x,), eps=1e-6, atol=1e-7,
+                                    rtol=1e-5)
