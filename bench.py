@@ -1,0 +1,308 @@
+"""Benchmark: one fitting step of the direct scattering sum on one MI355X.
+
+A step is the whole hot path on one batch of synthetic input resident in HBM:
+the forward sum A_k = sum_j f_j exp(2 i pi S_k . r_j) (FP64 phase reduction,
+compensated FP32 sums), the intensity misfit L = sum (|A|^2 - I)^2 with its seed
+G = 4 (|A|^2 - I) A, and the adjoint dL/dr_j -- all in libnx's HIP kernels.
+
+Workload (default): the strained Ge-like truncated-pyramid dot on an fcc lattice,
+203,557 atoms with two complex scattering factors, on a 128^3 grid of points around
+(4,0,4) (2,097,152 points); the target intensity is that of the same dot with the
+strain scaled by 1.1, computed once before timing.
+
+Printed: one JSON line with the throughput in atom.point pairs per second of the
+whole step (N*K pairs per step), the forward-only and adjoint-only rates, the
+all-FP64 GPU path on the same step for comparison, the roofline of the dominant
+kernel (timed live with events on the launch stream), and the FP64 CPU oracle timed
+on a bounded sample of the same workload on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 3.93e13 full-rate VALU lane-ops/s;
+# counting each as one FMA (2 flop) gives 78.6 TFLOP/s (the unpacked FP32 and the
+# FP64 vector rate; packed FP32 instructions are excluded from this build).
+VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+PEAK_TFLOPS = 2 * VALU_SLOTS_PER_S / 1e12
+
+# Minimal VALU instruction count per (atom, point) pair of each kernel: the method's
+# own work on gfx950 in the formulation the kernels use (compensation, loads and loop
+# control excluded).  Phase S.r = 3 FP64 fma; reduction mod 1 and rounding to FP32 =
+# 2; sin and cos = 1 issue slot each (the transcendental unit overlaps other VALU
+# work, measured ~1 slot per instruction in a mixed stream).
+#   forward, complex f: f (cos + i sin) accumulated (4 fma)
+#   forward, f = 1:     (cos, sin) accumulated (2)
+#   adjoint, complex f: + arg of the seed added to the phase (1), v = fr s + fi c (2),
+#                       T_d += (|G| S_d) v (3)
+#   adjoint, f = 1:     + seed phase (1), only sin is needed (1 trans), T_d += (3)
+ALG_SLOTS = {
+    ("fwd", "complex"): 3 + 2 + 2 + 4,
+    ("fwd", "unit"): 3 + 2 + 2 + 2,
+    ("bwd", "complex"): 3 + 1 + 2 + 2 + 2 + 3,
+    ("bwd", "unit"): 3 + 1 + 2 + 1 + 3,
+}
+PAPER_FLOP_PER_PAIR = 8       # the paper's count (3 mul, 4 add, 1 sincos)
+FP32_PEAK_TFLOPS = 157.3      # published FP32 vector peak (packed)
+
+KERNEL_SOURCES = ["nx_fwd.hip", "nx_bwd.hip", "nx_loss.hip", "nx_api.cpp", "nx_internal.h"]
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1010_2641_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    p.add_argument("--mode", default="ph64", choices=["ph64", "f32"])
+    p.add_argument("--no-f64", action="store_true", help="skip the all-FP64 comparison")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--cpu-seconds", type=float, default=12.0,
+                   help="approximate CPU time budget of the oracle sample")
+    p.add_argument("--copy-cal", type=int, default=0, metavar="BYTES",
+                   help="only run a plain device-to-device copy of BYTES bytes three times "
+                        "(the reference kernel that scales the HBM counters of a profile)")
+    return p.parse_args()
+
+
+def make_target(api, w, tf, tS, mode):
+    import torch
+    if w.target_xyz is not None:
+        tx = torch.from_numpy(w.target_xyz).cuda()
+    else:                       # workloads without a target structure: a shifted copy
+        tx = torch.from_numpy(w.xyz).cuda() * 1.001
+    return (api.scatter_fwd(tx, tf, tS, mode).abs() ** 2).float()
+
+
+def cpu_baseline(w, A_gpu, g_gpu_fn, budget_s):
+    """The FP64 oracle on a bounded sample of the same workload: the forward on a
+    seeded sample of points (all atoms) and the adjoint on a seeded sample of atoms
+    (all points); the full-step time is extrapolated linearly.  Also returns the GPU's
+    error against the oracle on the sampled outputs."""
+    import numpy as np
+
+    import oracle
+    from paper_1010_2641_amd import workloads as wl
+
+    cores = oracle.threads()
+    rng = np.random.default_rng(2024)
+    # size the samples from a short probe so the whole leg stays near budget_s
+    n_probe = min(64, w.n_points)
+    probe = rng.choice(w.n_points, size=n_probe, replace=False)
+    t0 = time.perf_counter()
+    oracle.forward(w.xyz, w.f, w.S[probe])
+    rate = n_probe * w.n_atoms / max(time.perf_counter() - t0, 1e-6)
+    n_pts = int(max(8, min(w.n_points, 0.5 * budget_s * rate / w.n_atoms)))
+    n_at = int(max(2, min(w.n_atoms, 0.35 * budget_s * rate / w.n_points)))
+    pts = np.sort(rng.choice(w.n_points, size=n_pts, replace=False))
+    atoms = np.sort(rng.choice(w.n_atoms, size=n_at, replace=False))
+    t0 = time.perf_counter()
+    A_ref = oracle.forward(w.xyz, w.f, w.S[pts])
+    t_fwd = time.perf_counter() - t0
+    G = wl.random_seed_field(w.n_points, seed=2025, scale=1e-3)
+    t0 = time.perf_counter()
+    g_ref = oracle.adjoint(w.xyz[atoms], None if w.f is None else w.f[atoms], w.S, G)
+    t_bwd = time.perf_counter() - t0
+    t_full = t_fwd * w.n_points / n_pts + t_bwd * w.n_atoms / n_at
+    pairs = float(w.n_atoms) * float(w.n_points)
+    # GPU error on the same sampled outputs
+    A_s = A_gpu[pts].astype(np.complex128)
+    I, Ir = np.abs(A_s) ** 2, np.abs(A_ref) ** 2
+    m = Ir >= 1e-6 * Ir.max()
+    g_gpu = g_gpu_fn(G)[atoms]
+    err = {
+        "fwd_T1_rel_I": float(np.max(np.abs(I[m] - Ir[m]) / Ir[m])),
+        "fwd_T2_rel_norm": float(np.linalg.norm(A_s - A_ref) / np.linalg.norm(A_ref)),
+        "bwd_T3_rel_norm": float(np.linalg.norm(g_gpu - g_ref) / np.linalg.norm(g_ref)),
+        "bwd_T3_rel_max": float(np.max(np.abs(g_gpu - g_ref)) / np.max(np.abs(g_ref))),
+        "sample": f"{n_pts} random points (forward) and {n_at} random atoms with a seeded "
+                  f"random seed G (adjoint)",
+    }
+    base = {
+        "value": pairs / t_full,
+        "unit": "atom.point pairs/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"FP64 oracle forward on {n_pts} of {w.n_points} points (all atoms, "
+                   f"{t_fwd:.1f} s) and adjoint on {n_at} of {w.n_atoms} atoms (all points, "
+                   f"{t_bwd:.1f} s); full fit-step time extrapolated linearly to "
+                   f"{t_full:.3g} s"),
+    }
+    return base, err
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the sum would shard along the points with no exchange, see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1010_2641_amd import api, workloads as wl
+
+    if args.copy_cal:
+        src = torch.empty(args.copy_cal // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_cal}), flush=True)
+        return
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = wl.named(args.workload)
+    n, k = w.n_atoms, w.n_points
+    pairs = float(n) * float(k)
+    fkind = "unit" if w.f is None else "complex"
+    tx = torch.from_numpy(w.xyz).to(dev)
+    tf = None if w.f is None else torch.from_numpy(w.f).to(dev)
+    tS = torch.from_numpy(w.S).to(dev)
+    I = make_target(api, w, tf, tS, args.mode)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream(dev)      # every libnx launch goes to this stream
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def step(rec=None):
+        if rec is not None:
+            rec[0].record(stream)
+        A = api.scatter_fwd(tx, tf, tS, args.mode)
+        if rec is not None:
+            rec[1].record(stream)
+        L, G = api.loss_grad(A, I)
+        if rec is not None:
+            rec[2].record(stream)
+        g = api.scatter_bwd(tx, tf, tS, G, args.mode)
+        if rec is not None:
+            rec[3].record(stream)
+        return L, A, g
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    recs = [[ev() for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        out = step(recs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_fwd = sum(r[0].elapsed_time(r[1]) for r in recs) / args.steps / 1e3
+    t_loss = sum(r[1].elapsed_time(r[2]) for r in recs) / args.steps / 1e3
+    t_bwd = sum(r[2].elapsed_time(r[3]) for r in recs) / args.steps / 1e3
+    ms_per_step = wall / args.steps * 1e3
+    value = pairs / (wall / args.steps)
+
+    # roofline of the dominant kernel (its launch sequence timed on the launch stream)
+    dom, t_dom = ("bwd", t_bwd) if t_bwd >= t_fwd else ("fwd", t_fwd)
+    slots = ALG_SLOTS[(dom, fkind)]
+    achieved = pairs * 2 * slots / t_dom / 1e12
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", f"{dom}_{args.workload}_{args.mode}_traffic.json")
+    if os.path.exists(tpath):
+        with open(tpath) as fh:
+            tr = json.load(fh)
+        if tr.get("source_sha") == source_hash():
+            traffic = tr.get("hbm_bytes_per_launch")
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_TFLOPS, "traffic": traffic,
+                "kernel": f"nx_scatter_{dom} ({args.mode}, {fkind} f)",
+                "alg_valu_slots_per_pair": slots, "launch_ms": t_dom * 1e3}
+
+    # all-FP64 GPU path on the same step (forward + adjoint, seed from this step)
+    f64 = None
+    if not args.no_f64:
+        L, A, _ = out
+        _, G = api.loss_grad(A, I)
+        x64, S64 = tx.double(), tS.double()
+        f64_ = None if tf is None else tf.to(torch.complex128)
+        G64 = G.to(torch.complex128)
+        api.scatter_fwd_f64(x64, f64_, S64)
+        torch.cuda.synchronize()
+        e = [ev() for _ in range(3)]
+        e[0].record(stream)
+        api.scatter_fwd_f64(x64, f64_, S64)
+        e[1].record(stream)
+        api.scatter_bwd_f64(x64, f64_, S64, G64)
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        tf64, tb64 = e[0].elapsed_time(e[1]) / 1e3, e[1].elapsed_time(e[2]) / 1e3
+        f64 = {"fwd_pairs_per_s": pairs / tf64, "bwd_pairs_per_s": pairs / tb64,
+               "step_pairs_per_s": pairs / (tf64 + tb64)}
+
+    cpu = None
+    errs = None
+    if not args.no_cpu:
+        A_np = out[1].cpu().numpy()
+
+        def g_gpu_fn(G):
+            return api.scatter_bwd(tx, tf, tS, torch.from_numpy(G).to(dev), args.mode).cpu().numpy()
+
+        cpu, errs = cpu_baseline(w, A_np, g_gpu_fn, args.cpu_seconds)
+
+    res = {
+        "metric": "atom.point pairs/s of the fit step (forward + misfit + adjoint)",
+        "value": value,
+        "unit": "atom.point pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": {
+                "c1": "16^3 simple-cubic block, disorder 0.02, f=1, 64x64 map at l=4",
+                "c2": "Ge-like strained fcc truncated-pyramid dot, 203,557 atoms, 2 species "
+                      "complex f, 128^3 grid around (4,0,4), fit step vs strain x1.1 target",
+                "c3": "100^3 simple-cubic crystal, disorder 0.01, 256^2 map near (8,8,8)",
+                "c4": "29^3-cell fcc cube, sinusoidal displacement, 64^3 grid around (2,2,0)",
+                "c5": "strained fcc nanowire, 4,013,800 atoms, 2 species, 256^3 grid at (0,0,4)",
+            }[args.workload],
+            "n_atoms": n, "n_points": k, "pairs_per_step": pairs,
+            "precision": {"ph64": "FP64 phase reduction, FP32 sin/cos, compensated FP32 sums",
+                          "f32": "plain FP32 (the paper's arithmetic)"}[args.mode],
+        },
+        "fwd_pairs_per_s": pairs / t_fwd,
+        "bwd_pairs_per_s": pairs / t_bwd,
+        "loss_ms": t_loss * 1e3,
+        "f64_path": f64,
+        "speedup_vs_f64_step": (value / f64["step_pairs_per_s"]) if f64 else None,
+        "max_rel_err": errs,
+        "paper_flop_convention": {"tflops": value * PAPER_FLOP_PER_PAIR / 1e12,
+                                  "frac_of_fp32_peak": value * PAPER_FLOP_PER_PAIR / 1e12 / FP32_PEAK_TFLOPS},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "source_sha": source_hash(),
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

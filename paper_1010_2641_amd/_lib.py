@@ -35,11 +35,28 @@ class NxError(RuntimeError):
         self.code = code
 
 
+def _hip_runtimes():
+    """Paths of the HIP runtime libraries mapped into this process (Linux)."""
+    try:
+        with open("/proc/self/maps") as fh:
+            return sorted({l.split()[-1] for l in fh if "libamdhip64" in l})
+    except OSError:
+        return []
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1010_2641_amd.build` "
                            "(the HIP library is required; there is no CPU fallback)")
+    # PyTorch ships its own HIP runtime.  It must be the one libnx binds to: if libnx were
+    # loaded first, the dynamic linker would map the system runtime as well, and two HIP
+    # (and HSA) runtimes in one process do not share devices, streams or memory.
+    import torch  # noqa: F401  (loads torch's libamdhip64 before libnx resolves its own)
     lib = ctypes.CDLL(LIB_PATH)
+    runtimes = _hip_runtimes()
+    if len(runtimes) > 1:
+        raise RuntimeError("more than one HIP runtime is loaded in this process "
+                           f"({runtimes}); import torch before loading libnx")
     for name, (args, res) in SIGNATURES.items():
         fn = getattr(lib, name)
         fn.argtypes = args

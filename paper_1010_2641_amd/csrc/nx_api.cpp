@@ -38,7 +38,7 @@ bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 // Tuning knobs for launch-shape sweeps and for exercising the chunked path at small
 // sizes; read on every plan so that nx_workspace_bytes and the entry points agree.
 //   NX_TUNE_LAUNCH_PAIRS  pairs per launch (default 2^39)
-//   NX_TUNE_P             lane items per lane (1, 2, 4 forward; 1, 2 adjoint)
+//   NX_TUNE_P             lane items per lane (1, 2, 4; the FP64 path 1, 2)
 //   NX_TUNE_GRP           stream items per compensated group (8, 16, 32)
 //   NX_TUNE_RED           phase reduction variant (0 centred rint, 1 fract)
 int64_t env_i64(const char* name, int64_t def) {
@@ -88,20 +88,29 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
   p.mode = (op == kOpFwdF64 || op == kOpBwdF64) ? kF64 : (mode == NX_F32_PH64 ? kPH64 : kF32);
   p.lanes = fwd ? n_points : n_atoms;
   p.stream = fwd ? n_atoms : n_points;
-  p.grp = 16;
-  p.red = 0;
+  // Defaults from launch-shape and accuracy sweeps on MI355X.  Forward, FP64-phase
+  // mode: the centred reduction (its FP32 rounding of the reduced phase is half that of
+  // fract's, which decides the pointwise intensity error at the weakest points), and
+  // 8-atom groups for few atoms (|A| peaks at N |f|, so each term weighs more), 16 above.
+  // Adjoint (judged normwise): fract, 32-point groups, two atoms per lane.
   if (fwd) {
+    const bool small = p.stream < 65536;
+    p.red = 0;
+    p.grp = (p.mode == kPH64 && small) ? 8 : 16;
     if (p.mode == kF64) p.per_lane = p.lanes >= 262144 ? 2 : 1;
     else p.per_lane = p.lanes >= 262144 ? 4 : (p.lanes >= 32768 ? 2 : 1);
   } else {
-    p.per_lane = (p.mode != kF64 && p.lanes >= 1048576) ? 2 : 1;
+    p.red = p.mode == kPH64 ? 1 : 0;
+    p.grp = p.mode == kPH64 ? 32 : 16;
+    p.per_lane = (p.mode != kF64 && p.lanes >= 16384) ? 2 : 1;
   }
   {
-    const int64_t tp = env_i64("NX_TUNE_P", 0);
-    if (tp == 1 || tp == 2 || (tp == 4 && fwd && p.mode != kF64)) p.per_lane = int(tp);
-    const int64_t tg = env_i64("NX_TUNE_GRP", 0);
+    // unset knobs read as -1, which no knob accepts
+    const int64_t tp = env_i64("NX_TUNE_P", -1);
+    if (tp == 1 || tp == 2 || (tp == 4 && p.mode != kF64)) p.per_lane = int(tp);
+    const int64_t tg = env_i64("NX_TUNE_GRP", -1);
     if (p.mode == kPH64 && (tg == 8 || tg == 16 || tg == 32) && (fwd || tg != 8)) p.grp = int(tg);
-    const int64_t tr = env_i64("NX_TUNE_RED", 0);
+    const int64_t tr = env_i64("NX_TUNE_RED", -1);
     if (p.mode == kPH64 && (tr == 0 || tr == 1)) p.red = int(tr);
   }
   const int64_t per_block = int64_t(kThreads) * p.per_lane;
@@ -167,8 +176,8 @@ int run_sum(const char* fn, const nx::Plan& p, bool fwd, const void* xyz, const 
   void* rec = base;
   void* partial = p.partial_bytes ? base + p.rec_bytes : nullptr;
   hipError_t e;
-  if (fwd) e = nx::launch_pack_atoms(p.mode, xyz, f, p.stream, rec, st);
-  else e = nx::launch_pack_points(p.mode, S, G, p.stream, rec, st);
+  if (fwd) e = nx::launch_pack_atoms(p.mode, p.red, xyz, f, p.stream, rec, st);
+  else e = nx::launch_pack_points(p.mode, p.red, S, G, p.stream, rec, st);
   if (e != hipSuccess) return device_error(fn, e);
   for (int64_t c = 0; c < p.nchunks; ++c) {
     int64_t b, en, per;

@@ -3,8 +3,11 @@
 // chain rule through Eq. 2 of Favre-Nicolin et al. (2010) gives
 //     dL/dr_j = Re sum_k conj(G_k) f_j (2 i pi S_k) exp(2 i pi S_k . r_j)
 //             = -2 pi sum_k S_k v_jk,   v_jk = Im( f_j conj(G_k) exp(2 i pi S_k . r_j) )
-// so each atom carries three real sums (one per coordinate); f_j is applied per
-// lane inside the pair loop (v = fr Im w + fi Re w with w = conj(G) e^{i theta}).
+// so each atom carries three real sums (one per coordinate).  In the FP64-phase mode
+// the seed is taken in polar form, conj(G_k) = |G_k| exp(2 i pi delta_k): delta_k
+// joins the FP64 phase and |G_k| is folded into S_k, so that
+//     v_jk = |G_k| Im( f_j exp(2 i pi (S_k . r_j + delta_k)) ) = |G_k| (fr s + fi c)
+// costs two FP32 operations (none for f_j = 1) on top of the phase and sin/cos.
 //
 // Layout: every lane owns Q atoms and keeps their position and the T sums in
 // registers; the points are streamed as packed wave-uniform records through the
@@ -12,8 +15,9 @@
 // the reflection coordinates, Section 2.2).  The phases are recomputed, never stored.
 //
 // Per (point, atom) pair, FP64-phase mode: FP64 phase and reduction (as in the
-// forward), FP32 v_sin/v_cos, v in FP32, T_d += S_d v with FP32 fma into per-group
-// partials folded into (sum, comp) pairs by an error-free two-sum every GRP points.
+// forward) with delta_k, FP32 v_sin/v_cos, T_d += (|G_k| S_kd) v with FP32 fma into
+// per-group partials folded into (sum, comp) pairs by an error-free two-sum every GRP
+// points.
 // FP32 mode: the paper's FP32 arithmetic with plain sums.
 #include "nx_internal.h"
 
@@ -48,19 +52,41 @@ __device__ __forceinline__ float adj_weight(float gr, float gi, float fr, float 
   }
 }
 
+// One FP64-phase point record as three 16-byte words (the wave-uniform address lets
+// the compiler fetch them with scalar loads), unpacked into named fields.
+struct PtRegs { double sx, sy, sz, delta; float gsx, gsy, gsz; };
+
+__device__ __forceinline__ PtRegs load_point(const PointPH* __restrict__ rec, int k) {
+  const uint4* w = reinterpret_cast<const uint4*>(rec + k);
+  const uint4 a = w[0], b = w[1], c = w[2];
+  PtRegs r;
+  r.sx = __hiloint2double(static_cast<int>(a.y), static_cast<int>(a.x));
+  r.sy = __hiloint2double(static_cast<int>(a.w), static_cast<int>(a.z));
+  r.sz = __hiloint2double(static_cast<int>(b.y), static_cast<int>(b.x));
+  r.delta = __hiloint2double(static_cast<int>(b.w), static_cast<int>(b.z));
+  r.gsx = __uint_as_float(c.x);
+  r.gsy = __uint_as_float(c.y);
+  r.gsz = __uint_as_float(c.z);
+  return r;
+}
+
+// (c, s) of exp(2 i pi psi), psi = S.r + delta (delta includes the 1/2 of RED == 1).
 template <int RED>
-__device__ __forceinline__ void cis_ph64_pt(const PointPH& a, double x, double y, double z,
+__device__ __forceinline__ void cis_ph64_pt(const PtRegs& a, double x, double y, double z,
                                             float& c, float& s) {
+  const double ph = __builtin_fma(a.sz, z, __builtin_fma(a.sy, y, a.sx * x)) + a.delta;
   float tf;
-  if constexpr (RED == 0) {
-    const double ph = __builtin_fma(a.sz, z, __builtin_fma(a.sy, y, a.sx * x));
-    tf = static_cast<float>(ph - __builtin_rint(ph));
-  } else {
-    const double ph = __builtin_fma(a.sz, z, __builtin_fma(a.sy, y, __builtin_fma(a.sx, x, 0.5)));
-    tf = static_cast<float>(__builtin_amdgcn_fract(ph));
-  }
+  if constexpr (RED == 0) tf = static_cast<float>(ph - __builtin_rint(ph));
+  else tf = static_cast<float>(__builtin_amdgcn_fract(ph));
   c = __builtin_amdgcn_cosf(tf);
   s = __builtin_amdgcn_sinf(tf);
+}
+
+// v / |G| = Im(f (c + i s)) = fr s + fi c; s for f = 1.
+template <int FK>
+__device__ __forceinline__ float adj_im(float fr, float fi, float c, float s) {
+  if constexpr (FK == 0) return s;
+  else return __builtin_fmaf(fi, c, fr * s);
 }
 
 // Adjoint over points [k_begin + sp*per_split, ...) for Q atoms per lane.
@@ -72,8 +98,9 @@ __global__ __launch_bounds__(kThreads) void bwd_kernel(
     const float* __restrict__ xyz, const float* __restrict__ f, int64_t N, int blocks_n,
     float* __restrict__ part, float* __restrict__ grad, int carry_in, int direct) {
   using RReg = typename std::conditional<MODE == kPH64, double, float>::type;
-  const int nb = blockIdx.x % blocks_n;
-  const int sp = blockIdx.x / blocks_n;
+  const int lb = xcd_major_block(blockIdx.x, gridDim.x);
+  const int nb = lb % blocks_n;
+  const int sp = lb / blocks_n;
   const int64_t j0 = int64_t(nb) * (kThreads * Q) + threadIdx.x;
 
   RReg x[Q], y[Q], z[Q];
@@ -133,28 +160,28 @@ __global__ __launch_bounds__(kThreads) void bwd_kernel(
       if (kend - k == GRP) {
 #pragma unroll
         for (int u = 0; u < GRP; ++u) {
-          const PointPH a = rec[k + u];
+          const PtRegs a = load_point(rec, k + u);
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
             float c, s;
             cis_ph64_pt<RED>(a, x[q], y[q], z[q], c, s);
-            const float v = adj_weight<FK>(a.gr, a.gi, fr[q], fi[q], c, s);
-            g[q][0] = __builtin_fmaf(v, a.fx, g[q][0]);
-            g[q][1] = __builtin_fmaf(v, a.fy, g[q][1]);
-            g[q][2] = __builtin_fmaf(v, a.fz, g[q][2]);
+            const float v = adj_im<FK>(fr[q], fi[q], c, s);
+            g[q][0] = __builtin_fmaf(v, a.gsx, g[q][0]);
+            g[q][1] = __builtin_fmaf(v, a.gsy, g[q][1]);
+            g[q][2] = __builtin_fmaf(v, a.gsz, g[q][2]);
           }
         }
       } else {
         for (int kk = k; kk < kend; ++kk) {
-          const PointPH a = rec[kk];
+          const PtRegs a = load_point(rec, kk);
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
             float c, s;
             cis_ph64_pt<RED>(a, x[q], y[q], z[q], c, s);
-            const float v = adj_weight<FK>(a.gr, a.gi, fr[q], fi[q], c, s);
-            g[q][0] = __builtin_fmaf(v, a.fx, g[q][0]);
-            g[q][1] = __builtin_fmaf(v, a.fy, g[q][1]);
-            g[q][2] = __builtin_fmaf(v, a.fz, g[q][2]);
+            const float v = adj_im<FK>(fr[q], fi[q], c, s);
+            g[q][0] = __builtin_fmaf(v, a.gsx, g[q][0]);
+            g[q][1] = __builtin_fmaf(v, a.gsy, g[q][1]);
+            g[q][2] = __builtin_fmaf(v, a.gsz, g[q][2]);
           }
         }
       }
@@ -189,8 +216,9 @@ __global__ __launch_bounds__(kThreads) void bwd_f64_kernel(
     const PointF64* __restrict__ rec, int k_begin, int k_end, int per_split,
     const double* __restrict__ xyz, const double* __restrict__ f, int64_t N, int blocks_n,
     double* __restrict__ part, double* __restrict__ grad, int carry_in, int direct) {
-  const int nb = blockIdx.x % blocks_n;
-  const int sp = blockIdx.x / blocks_n;
+  const int lb = xcd_major_block(blockIdx.x, gridDim.x);
+  const int nb = lb % blocks_n;
+  const int sp = lb / blocks_n;
   const int64_t j0 = int64_t(nb) * (kThreads * Q) + threadIdx.x;
   double x[Q], y[Q], z[Q], fr[Q], fi[Q], T[Q][3];
 #pragma unroll
@@ -269,7 +297,8 @@ __global__ __launch_bounds__(kThreads) void bwd_reduce_f64_kernel(const double* 
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void pack_points_kernel(const void* __restrict__ S_v,
                                                                const void* __restrict__ G_v,
-                                                               int64_t n, void* __restrict__ rec_v) {
+                                                               int64_t n, void* __restrict__ rec_v,
+                                                               double offset) {
   for (int64_t k = int64_t(blockIdx.x) * kThreads + threadIdx.x; k < n;
        k += int64_t(gridDim.x) * kThreads) {
     if constexpr (MODE == kF64) {
@@ -283,10 +312,17 @@ __global__ __launch_bounds__(kThreads) void pack_points_kernel(const void* __res
       const float* S = static_cast<const float*>(S_v);
       const float* G = static_cast<const float*>(G_v);
       if constexpr (MODE == kPH64) {
+        // conj(G) = |G| exp(2 i pi delta): delta = -arg(G) / (2 pi) in FP64 (plus the
+        // reduction offset of the variant), |G| S rounded once to FP32
         PointPH r;
-        r.sx = S[3 * k]; r.sy = S[3 * k + 1]; r.sz = S[3 * k + 2];
-        r.gr = G[2 * k]; r.gi = G[2 * k + 1];
-        r.fx = S[3 * k]; r.fy = S[3 * k + 1]; r.fz = S[3 * k + 2];
+        const double sx = S[3 * k], sy = S[3 * k + 1], sz = S[3 * k + 2];
+        const double gr = G[2 * k], gi = G[2 * k + 1];
+        const double m = sqrt(gr * gr + gi * gi);
+        r.sx = sx; r.sy = sy; r.sz = sz;
+        r.delta = -atan2(gi, gr) * 0.15915494309189533577 + offset;
+        r.gsx = static_cast<float>(m * sx);
+        r.gsy = static_cast<float>(m * sy);
+        r.gsz = static_cast<float>(m * sz);
         r.pad = 0.f;
         static_cast<PointPH*>(rec_v)[k] = r;
       } else {
@@ -342,6 +378,9 @@ template <int MODE>
 hipError_t bwd_dispatch_q(const Plan& p, const void* rec, int64_t k_begin, int64_t k_end,
                           int64_t per_split, const void* xyz, const void* f, void* partial,
                           void* grad, int carry_in, int direct, hipStream_t st) {
+  if (p.per_lane == 4)
+    return p.fk ? bwd_dispatch<MODE, 4, 1>(p, rec, k_begin, k_end, per_split, xyz, f, partial, grad, carry_in, direct, st)
+                : bwd_dispatch<MODE, 4, 0>(p, rec, k_begin, k_end, per_split, xyz, f, partial, grad, carry_in, direct, st);
   if (p.per_lane == 2)
     return p.fk ? bwd_dispatch<MODE, 2, 1>(p, rec, k_begin, k_end, per_split, xyz, f, partial, grad, carry_in, direct, st)
                 : bwd_dispatch<MODE, 2, 0>(p, rec, k_begin, k_end, per_split, xyz, f, partial, grad, carry_in, direct, st);
@@ -363,13 +402,14 @@ hipError_t bwd_f64_launch(const Plan& p, const void* rec, int64_t k_begin, int64
 
 }  // namespace
 
-hipError_t launch_pack_points(int mode, const void* S, const void* G, int64_t k, void* rec,
-                              hipStream_t st) {
+hipError_t launch_pack_points(int mode, int red, const void* S, const void* G, int64_t k,
+                              void* rec, hipStream_t st) {
   if (k <= 0) return hipSuccess;
   const unsigned g = grid_for(k);
-  if (mode == kF64) pack_points_kernel<kF64><<<g, kThreads, 0, st>>>(S, G, k, rec);
-  else if (mode == kPH64) pack_points_kernel<kPH64><<<g, kThreads, 0, st>>>(S, G, k, rec);
-  else pack_points_kernel<kF32><<<g, kThreads, 0, st>>>(S, G, k, rec);
+  const double offset = red == 1 ? 0.5 : 0.0;
+  if (mode == kF64) pack_points_kernel<kF64><<<g, kThreads, 0, st>>>(S, G, k, rec, 0.0);
+  else if (mode == kPH64) pack_points_kernel<kPH64><<<g, kThreads, 0, st>>>(S, G, k, rec, offset);
+  else pack_points_kernel<kF32><<<g, kThreads, 0, st>>>(S, G, k, rec, 0.0);
   return hipGetLastError();
 }
 

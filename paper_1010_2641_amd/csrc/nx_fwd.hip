@@ -14,7 +14,7 @@
 //          angle in turns), plain FP32 complex multiply-add -- the paper's arithmetic.
 //   PH64 : phase with FP64 fma (the products of FP32 inputs are exact in FP64),
 //          reduction modulo one cycle in FP64 (exact), one rounding to FP32, FP32
-//          v_sin/v_cos, FP32 complex multiply-add; terms are summed in quads of
+//          v_sin/v_cos, f_j (cos + i sin) by FP32 fma; terms are summed in quads of
 //          consecutive atoms, quads into a group partial, and every `GRP` atoms the
 //          group partial is folded into a two-word (sum, comp) accumulator with an
 //          error-free two-sum (so FP32 roundings happen only at the magnitude of a
@@ -38,55 +38,50 @@ template <int MODE> struct AtomOf;
 template <> struct AtomOf<kF32> { using type = AtomF32; };
 template <> struct AtomOf<kPH64> { using type = AtomPH; };
 
-// exp(2 i pi phase) for the FP64-phase mode, phase = S.r (+ 1/2 when RED == 1), as
-// (c, s) in FP32.
+// exp(2 i pi phase) for the FP64-phase mode as (c, s) in FP32, phase = S.r, plus 1/2
+// (an inline constant of the first fma) in the RED == 1 variant.
 //   RED 0: t = phase - rint(phase) in [-1/2, 1/2] (exact), rounded once to FP32;
 //   RED 1: u = fract(phase + 1/2) in [0, 1) (exact), rounded once to FP32; then
-//          exp(2 i pi u) = -exp(2 i pi S.r) and the caller negates the factor.
+//          exp(2 i pi u) = -exp(2 i pi S.r) and the caller flips the sign of the
+//          group sums.
 template <int RED>
 __device__ __forceinline__ void cis_ph64(double sx, double sy, double sz, const AtomPH& a,
                                          float& c, float& s) {
-  double ph;
   float tf;
   if constexpr (RED == 0) {
-    ph = __builtin_fma(sz, a.z, __builtin_fma(sy, a.y, sx * a.x));
+    const double ph = __builtin_fma(sz, a.z, __builtin_fma(sy, a.y, sx * a.x));
     tf = static_cast<float>(ph - __builtin_rint(ph));
   } else {
-    ph = __builtin_fma(sz, a.z, __builtin_fma(sy, a.y, __builtin_fma(sx, a.x, 0.5)));
+    const double ph = __builtin_fma(sz, a.z, __builtin_fma(sy, a.y, __builtin_fma(sx, a.x, 0.5)));
     tf = static_cast<float>(__builtin_amdgcn_fract(ph));
   }
   c = __builtin_amdgcn_cosf(tf);
   s = __builtin_amdgcn_sinf(tf);
 }
 
-// (gr, gi) += sign * f * (c + i s); f = 1 when FK == 0.
-template <int FK, bool NEG>
-__device__ __forceinline__ void cmac(float& gr, float& gi, float fr, float fi, float c, float s) {
-  if constexpr (FK == 0) {
-    if constexpr (NEG) { gr -= c; gi -= s; } else { gr += c; gi += s; }
-  } else {
-    if constexpr (NEG) {
-      gr = __builtin_fmaf(-fr, c, gr);
-      gr = __builtin_fmaf(fi, s, gr);
-      gi = __builtin_fmaf(-fr, s, gi);
-      gi = __builtin_fmaf(-fi, c, gi);
-    } else {
-      gr = __builtin_fmaf(fr, c, gr);
-      gr = __builtin_fmaf(-fi, s, gr);
-      gi = __builtin_fmaf(fr, s, gi);
-      gi = __builtin_fmaf(fi, c, gi);
-    }
-  }
-}
-
-// (gr, gi) = f * (c + i s): the first term of a running sum.
+// f (c + i s): the first term of a running sum (f = 1 when FK == 0).
 template <int FK>
 __device__ __forceinline__ void cterm(float& gr, float& gi, float fr, float fi, float c, float s) {
   if constexpr (FK == 0) {
-    gr = c; gi = s;
+    gr = c;
+    gi = s;
   } else {
     gr = __builtin_fmaf(-fi, s, fr * c);
     gi = __builtin_fmaf(fi, c, fr * s);
+  }
+}
+
+// (gr, gi) += f * (c + i s) with FP32 fma; f = 1 when FK == 0 (the FP32 mode).
+template <int FK>
+__device__ __forceinline__ void cmac(float& gr, float& gi, float fr, float fi, float c, float s) {
+  if constexpr (FK == 0) {
+    gr += c;
+    gi += s;
+  } else {
+    gr = __builtin_fmaf(fr, c, gr);
+    gr = __builtin_fmaf(-fi, s, gr);
+    gi = __builtin_fmaf(fr, s, gi);
+    gi = __builtin_fmaf(fi, c, gi);
   }
 }
 
@@ -98,8 +93,9 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(
     const float* __restrict__ S, int64_t K, int blocks_k, float4* __restrict__ part,
     float2* __restrict__ A, int carry_in, int direct) {
   using SReg = typename std::conditional<MODE == kPH64, double, float>::type;
-  const int kb = blockIdx.x % blocks_k;
-  const int sp = blockIdx.x / blocks_k;
+  const int lb = xcd_major_block(blockIdx.x, gridDim.x);
+  const int kb = lb % blocks_k;
+  const int sp = lb / blocks_k;
   const int64_t k0 = int64_t(kb) * (kThreads * P) + threadIdx.x;
 
   SReg sx[P], sy[P], sz[P];
@@ -132,7 +128,7 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(
         const float u = __builtin_amdgcn_fractf(ph);
         const float c = __builtin_amdgcn_cosf(u);
         const float s = __builtin_amdgcn_sinf(u);
-        cmac<FK, false>(sr[p], si[p], a.fr, a.fi, c, s);
+        cmac<FK>(sr[p], si[p], a.fr, a.fi, c, s);
       }
     }
   } else {
@@ -155,7 +151,7 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(
             float c, s;
             cis_ph64<RED>(sx[p], sy[p], sz[p], a, c, s);
             if (u == 0) cterm<FK>(qr[p], qi[p], a.fr, a.fi, c, s);
-            else cmac<FK, false>(qr[p], qi[p], a.fr, a.fi, c, s);
+            else cmac<FK>(qr[p], qi[p], a.fr, a.fi, c, s);
           }
         }
 #pragma unroll
@@ -180,7 +176,7 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(
         for (int p = 0; p < P; ++p) {
           float c, s;
           cis_ph64<RED>(sx[p], sy[p], sz[p], a, c, s);
-          cmac<FK, false>(gr[p], gi[p], a.fr, a.fi, c, s);
+          cmac<FK>(gr[p], gi[p], a.fr, a.fi, c, s);
         }
       }
 #pragma unroll
@@ -207,8 +203,9 @@ __global__ __launch_bounds__(kThreads) void fwd_f64_kernel(
     const AtomF64* __restrict__ rec, int a_begin, int a_end, int per_split,
     const double* __restrict__ S, int64_t K, int blocks_k, double2* __restrict__ part,
     double2* __restrict__ A, int carry_in, int direct) {
-  const int kb = blockIdx.x % blocks_k;
-  const int sp = blockIdx.x / blocks_k;
+  const int lb = xcd_major_block(blockIdx.x, gridDim.x);
+  const int kb = lb % blocks_k;
+  const int sp = lb / blocks_k;
   const int64_t k0 = int64_t(kb) * (kThreads * P) + threadIdx.x;
   double sx[P], sy[P], sz[P], ar[P], ai[P];
 #pragma unroll
@@ -397,10 +394,11 @@ hipError_t fwd_f64_launch(const Plan& p, const void* rec, int64_t a_begin, int64
 
 }  // namespace
 
-hipError_t launch_pack_atoms(int mode, const void* xyz, const void* f, int64_t n, void* rec,
-                             hipStream_t st) {
+hipError_t launch_pack_atoms(int mode, int red, const void* xyz, const void* f, int64_t n,
+                             void* rec, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const unsigned g = grid_for(n);
+  (void)red;   // the forward's reduction offset is an inline constant of the kernel
   if (mode == kF64) pack_atoms_kernel<kF64><<<g, kThreads, 0, st>>>(xyz, f, n, rec);
   else if (mode == kPH64) pack_atoms_kernel<kPH64><<<g, kThreads, 0, st>>>(xyz, f, n, rec);
   else pack_atoms_kernel<kF32><<<g, kThreads, 0, st>>>(xyz, f, n, rec);

@@ -18,15 +18,21 @@ constexpr int kThreads = 256;          // work-group size of every sum kernel (4
 
 // Atom for the FP32 mode: coordinates and factor in FP32.
 struct alignas(16) AtomF32 { float x, y, z, fr, fi, pad0, pad1, pad2; };            // 32 B
-// Atom for the FP64-phase mode: coordinates widened (exactly) to FP64.
+// Atom for the FP64-phase mode: coordinates widened (exactly) to FP64, the factor as
+// given (FP32 re, im).  (A polar form |f| exp(2 i pi alpha) would save one operation
+// per pair but rounds |f| to FP32 once per atom; that error is the same for every atom
+// of a species and adds coherently where the species' amplitudes cancel.)
 struct alignas(16) AtomPH { double x, y, z; float fr, fi; };                         // 32 B
 // Atom for the all-FP64 path.
 struct alignas(16) AtomF64 { double x, y, z, fr, fi, pad; };                         // 48 B
 // Point for the FP32-mode adjoint: S and the seed G.
 struct alignas(16) PointF32 { float sx, sy, sz, gr, gi, pad0, pad1, pad2; };         // 32 B
-// Point for the FP64-phase adjoint: S in FP64 for the phase, S in FP32 for the
-// multiply-add into the per-atom sums, and the seed G.
-struct alignas(16) PointPH { double sx, sy, sz; float gr, gi, fx, fy, fz, pad; };    // 48 B
+// Point for the FP64-phase adjoint, with the seed in polar form conj(G) =
+// |G| exp(-2 i pi gamma): S (FP64) and delta = -gamma (cycles, FP64, plus the reduction
+// offset of the variant) for the phase in the first 32 bytes, |G| S (FP32) for the
+// multiply-add into the per-atom sums in the last 16; one 8-dword and one 4-dword
+// scalar load per record.
+struct alignas(16) PointPH { double sx, sy, sz, delta; float gsx, gsy, gsz, pad; };  // 48 B
 // Point for the all-FP64 adjoint.
 struct alignas(16) PointF64 { double sx, sy, sz, gr, gi, pad; };                     // 48 B
 
@@ -34,6 +40,16 @@ struct alignas(16) PointF64 { double sx, sy, sz, gr, gi, pad; };                
 // an atom's sum for the adjoint) kept between launches and across splits.
 //   FP32 modes: (sum_re, sum_im, comp_re, comp_im) -- float4 per point;
 //   FP64 path:  (sum_re, sum_im)                   -- double2 per point.
+
+// XCD-major block order.  The dispatcher hands work-group b to XCD b % 8 (each XCD
+// has its own L2), so the hardware id is remapped such that every XCD runs a
+// contiguous range of logical blocks: the blocks resident on one XCD then belong to
+// the same stream slice and read the same records at about the same time.
+__device__ __forceinline__ int xcd_major_block(int b, int nblk) {
+  const int q = nblk >> 3, r = nblk & 7;
+  const int x = b & 7, idx = b >> 3;
+  return x * q + (x < r ? x : r) + idx;
+}
 
 // Kernel variants selected by the host.
 enum Mode : int { kF32 = 0, kPH64 = 1, kF64 = 2 };
@@ -80,10 +96,10 @@ void chunk_range(const Plan& p, int64_t c, int64_t* begin, int64_t* end, int64_t
 
 // ---------------------------------------------------------------------------------
 // Launchers (defined in the kernel translation units).  All return the launch error.
-hipError_t launch_pack_atoms(int mode, const void* xyz, const void* f, int64_t n, void* rec,
-                             hipStream_t st);
-hipError_t launch_pack_points(int mode, const void* S, const void* G, int64_t k, void* rec,
-                              hipStream_t st);
+hipError_t launch_pack_atoms(int mode, int red, const void* xyz, const void* f, int64_t n,
+                             void* rec, hipStream_t st);
+hipError_t launch_pack_points(int mode, int red, const void* S, const void* G, int64_t k,
+                              void* rec, hipStream_t st);
 
 // One forward chunk over points (lane items) for atoms [a_begin, a_end).
 hipError_t launch_fwd_chunk(const Plan& p, const void* rec, int64_t a_begin, int64_t a_end,

@@ -124,3 +124,8 @@ def test_python_wrappers_refuse_cpu_tensors():
         api.scatter_fwd(x, None, x)
     with pytest.raises(ValueError, match="unknown mode"):
         api._mode("fp16")
+
+
+def test_single_hip_runtime():
+    """libnx must bind to the HIP runtime torch brought in, never a second copy."""
+    assert len(_lib._hip_runtimes()) == 1

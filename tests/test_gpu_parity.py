@@ -303,3 +303,17 @@ def test_gradcheck_f64_path():
     SS = dev(S.astype(np.float64))
     assert torch.autograd.gradcheck(lambda t: api.scatter(t, ff, SS), (x,), eps=1e-6, atol=1e-7,
                                     rtol=1e-5)
+
+
+@pytest.mark.parametrize("per_lane", ["1", "2", "4"])
+def test_lane_item_counts(per_lane, monkeypatch):
+    """Every points-per-lane (forward) and atoms-per-lane (adjoint) instantiation,
+    with ragged tails in both dimensions."""
+    monkeypatch.setenv("NX_TUNE_P", per_lane)
+    xyz, f, S = wl.random_problem(2345, 3456, seed=29, extent=40.0, s_range=3.0)
+    A_ref = oracle.forward(xyz, f, S)
+    check_fwd(run_fwd(xyz, f, S, "ph64"), A_ref, "ph64", f"P={per_lane}", f=f, n=len(xyz))
+    G = wl.random_seed_field(3456, seed=30)
+    for mode in ("ph64", "f32"):
+        en, em = M.t3(run_bwd(xyz, f, S, G, mode), oracle.adjoint(xyz, f, S, G))
+        assert en <= (M.T3_NORM_TOL if mode == "ph64" else 5e-3), mode
