@@ -37,19 +37,20 @@ PEAK_TFLOPS = 2 * VALU_SLOTS_PER_S / 1e12
 
 # Minimal VALU instruction count per (atom, point) pair of each kernel: the method's
 # own work on gfx950 in the formulation the kernels use (compensation, loads and loop
-# control excluded).  Phase S.r = 3 FP64 fma; reduction mod 1 and rounding to FP32 =
-# 2; sin and cos = 1 issue slot each (the transcendental unit overlaps other VALU
-# work, measured ~1 slot per instruction in a mixed stream).
-#   forward, complex f: f (cos + i sin) accumulated (4 fma)
-#   forward, f = 1:     (cos, sin) accumulated (2)
-#   adjoint, complex f: + arg of the seed added to the phase (1), v = fr s + fi c (2),
-#                       T_d += (|G| S_d) v (3)
-#   adjoint, f = 1:     + seed phase (1), only sin is needed (1 trans), T_d += (3)
+# control excluded).  Phase S.r = 3 FP64 fma.  Forward: centred reduction mod 1 (rint,
+# subtract) and rounding to FP32 = 3; adjoint: fract and rounding = 2.  sin and cos = 1
+# issue slot each (the transcendental unit overlaps other VALU work, measured ~1 slot
+# per instruction in a mixed stream).
+#   forward, complex f: f (cos + i sin) accumulated with 4 fma
+#   forward, f = 1:     (cos, sin) accumulated with 2 add
+#   adjoint, complex f: v = fr sin + fi cos (2), T_d += (|G| S_d) v (3); the seed phase
+#                       rides in the first fma of the phase
+#   adjoint, f = 1:     only sin is needed, T_d += (3)
 ALG_SLOTS = {
-    ("fwd", "complex"): 3 + 2 + 2 + 4,
-    ("fwd", "unit"): 3 + 2 + 2 + 2,
-    ("bwd", "complex"): 3 + 1 + 2 + 2 + 2 + 3,
-    ("bwd", "unit"): 3 + 1 + 2 + 1 + 3,
+    ("fwd", "complex"): 3 + 3 + 2 + 4,
+    ("fwd", "unit"): 3 + 3 + 2 + 2,
+    ("bwd", "complex"): 3 + 2 + 2 + 2 + 3,
+    ("bwd", "unit"): 3 + 2 + 1 + 3,
 }
 PAPER_FLOP_PER_PAIR = 8       # the paper's count (3 mul, 4 add, 1 sincos)
 FP32_PEAK_TFLOPS = 157.3      # published FP32 vector peak (packed)
@@ -74,7 +75,7 @@ def parse():
     p.add_argument("--mode", default="ph64", choices=["ph64", "f32"])
     p.add_argument("--no-f64", action="store_true", help="skip the all-FP64 comparison")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    p.add_argument("--cpu-seconds", type=float, default=12.0,
+    p.add_argument("--cpu-seconds", type=float, default=20.0,
                    help="approximate CPU time budget of the oracle sample")
     p.add_argument("--copy-cal", type=int, default=0, metavar="BYTES",
                    help="only run a plain device-to-device copy of BYTES bytes three times "
@@ -103,23 +104,31 @@ def cpu_baseline(w, A_gpu, g_gpu_fn, budget_s):
 
     cores = oracle.threads()
     rng = np.random.default_rng(2024)
-    # size the samples from a short probe so the whole leg stays near budget_s
-    n_probe = min(64, w.n_points)
-    probe = rng.choice(w.n_points, size=n_probe, replace=False)
-    t0 = time.perf_counter()
-    oracle.forward(w.xyz, w.f, w.S[probe])
-    rate = n_probe * w.n_atoms / max(time.perf_counter() - t0, 1e-6)
-    n_pts = int(max(8, min(w.n_points, 0.5 * budget_s * rate / w.n_atoms)))
-    n_at = int(max(2, min(w.n_atoms, 0.35 * budget_s * rate / w.n_points)))
-    pts = np.sort(rng.choice(w.n_points, size=n_pts, replace=False))
-    atoms = np.sort(rng.choice(w.n_atoms, size=n_at, replace=False))
-    t0 = time.perf_counter()
-    A_ref = oracle.forward(w.xyz, w.f, w.S[pts])
-    t_fwd = time.perf_counter() - t0
+    # forward on seeded batches of points (all atoms) until half the budget is spent,
+    # then the adjoint on seeded batches of atoms (all points) for the other half
+    order_p = rng.permutation(w.n_points)
+    order_a = rng.permutation(w.n_atoms)
     G = wl.random_seed_field(w.n_points, seed=2025, scale=1e-3)
-    t0 = time.perf_counter()
-    g_ref = oracle.adjoint(w.xyz[atoms], None if w.f is None else w.f[atoms], w.S, G)
-    t_bwd = time.perf_counter() - t0
+    bp = max(1, min(w.n_points, int(2e8 // max(w.n_atoms, 1))))
+    ba = max(1, min(w.n_atoms, int(2e8 // max(w.n_points, 1))))
+    A_parts, n_pts, t_fwd = [], 0, 0.0
+    while n_pts < w.n_points and t_fwd < 0.5 * budget_s:
+        idx = order_p[n_pts:n_pts + bp]
+        t0 = time.perf_counter()
+        A_parts.append(oracle.forward(w.xyz, w.f, w.S[idx]))
+        t_fwd += time.perf_counter() - t0
+        n_pts += len(idx)
+    g_parts, n_at, t_bwd = [], 0, 0.0
+    while n_at < w.n_atoms and t_bwd < 0.5 * budget_s:
+        idx = order_a[n_at:n_at + ba]
+        t0 = time.perf_counter()
+        g_parts.append(oracle.adjoint(w.xyz[idx], None if w.f is None else w.f[idx], w.S, G))
+        t_bwd += time.perf_counter() - t0
+        n_at += len(idx)
+    pts = order_p[:n_pts]
+    atoms = order_a[:n_at]
+    A_ref = np.concatenate(A_parts)
+    g_ref = np.concatenate(g_parts)
     t_full = t_fwd * w.n_points / n_pts + t_bwd * w.n_atoms / n_at
     pairs = float(w.n_atoms) * float(w.n_points)
     # GPU error on the same sampled outputs
@@ -227,10 +236,19 @@ def main():
             tr = json.load(fh)
         if tr.get("source_sha") == source_hash():
             traffic = tr.get("hbm_bytes_per_launch")
+    valu = None
+    vpath = os.path.join(ROOT, "profiles", f"{dom}_{args.workload}_{args.mode}_valu.json")
+    if os.path.exists(vpath):
+        with open(vpath) as fh:
+            vr = json.load(fh)
+        if vr.get("source_sha") == source_hash():
+            valu = {k: vr[k] for k in ("valu_issue_util", "valu_busy", "valu_insts_per_pair",
+                                       "trans_insts_per_pair") if k in vr}
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_TFLOPS, "traffic": traffic,
                 "kernel": f"nx_scatter_{dom} ({args.mode}, {fkind} f)",
-                "alg_valu_slots_per_pair": slots, "launch_ms": t_dom * 1e3}
+                "alg_valu_slots_per_pair": slots, "launch_ms": t_dom * 1e3,
+                "counters": valu}
 
     # all-FP64 GPU path on the same step (forward + adjoint, seed from this step)
     f64 = None

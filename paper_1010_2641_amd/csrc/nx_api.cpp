@@ -98,7 +98,7 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
     p.red = 0;
     p.grp = (p.mode == kPH64 && small) ? 8 : 16;
     if (p.mode == kF64) p.per_lane = p.lanes >= 262144 ? 2 : 1;
-    else p.per_lane = p.lanes >= 262144 ? 4 : (p.lanes >= 32768 ? 2 : 1);
+    else p.per_lane = (p.lanes >= 32768 && p.lanes < 1048576) ? 2 : 1;
   } else {
     p.red = p.mode == kPH64 ? 1 : 0;
     p.grp = p.mode == kPH64 ? 32 : 16;

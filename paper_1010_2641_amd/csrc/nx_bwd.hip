@@ -71,10 +71,12 @@ __device__ __forceinline__ PtRegs load_point(const PointPH* __restrict__ rec, in
 }
 
 // (c, s) of exp(2 i pi psi), psi = S.r + delta (delta includes the 1/2 of RED == 1).
+// The seed phase enters as the addend of the first fma: with delta copied once per point
+// into a VGPR pair (shared by the lane's Q atoms), each pair saves an FP64 add.
 template <int RED>
-__device__ __forceinline__ void cis_ph64_pt(const PtRegs& a, double x, double y, double z,
-                                            float& c, float& s) {
-  const double ph = __builtin_fma(a.sz, z, __builtin_fma(a.sy, y, a.sx * x)) + a.delta;
+__device__ __forceinline__ void cis_ph64_pt(const PtRegs& a, double dv, double x, double y,
+                                            double z, float& c, float& s) {
+  const double ph = __builtin_fma(a.sz, z, __builtin_fma(a.sy, y, __builtin_fma(a.sx, x, dv)));
   float tf;
   if constexpr (RED == 0) tf = static_cast<float>(ph - __builtin_rint(ph));
   else tf = static_cast<float>(__builtin_amdgcn_fract(ph));
@@ -161,10 +163,11 @@ __global__ __launch_bounds__(kThreads) void bwd_kernel(
 #pragma unroll
         for (int u = 0; u < GRP; ++u) {
           const PtRegs a = load_point(rec, k + u);
+          const double dv = a.delta;
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
             float c, s;
-            cis_ph64_pt<RED>(a, x[q], y[q], z[q], c, s);
+            cis_ph64_pt<RED>(a, dv, x[q], y[q], z[q], c, s);
             const float v = adj_im<FK>(fr[q], fi[q], c, s);
             g[q][0] = __builtin_fmaf(v, a.gsx, g[q][0]);
             g[q][1] = __builtin_fmaf(v, a.gsy, g[q][1]);
@@ -174,10 +177,11 @@ __global__ __launch_bounds__(kThreads) void bwd_kernel(
       } else {
         for (int kk = k; kk < kend; ++kk) {
           const PtRegs a = load_point(rec, kk);
+          const double dv = a.delta;
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
             float c, s;
-            cis_ph64_pt<RED>(a, x[q], y[q], z[q], c, s);
+            cis_ph64_pt<RED>(a, dv, x[q], y[q], z[q], c, s);
             const float v = adj_im<FK>(fr[q], fi[q], c, s);
             g[q][0] = __builtin_fmaf(v, a.gsx, g[q][0]);
             g[q][1] = __builtin_fmaf(v, a.gsy, g[q][1]);
