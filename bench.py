@@ -55,7 +55,8 @@ ALG_SLOTS = {
 PAPER_FLOP_PER_PAIR = 8       # the paper's count (3 mul, 4 add, 1 sincos)
 FP32_PEAK_TFLOPS = 157.3      # published FP32 vector peak (packed)
 
-KERNEL_SOURCES = ["nx_fwd.hip", "nx_bwd.hip", "nx_loss.hip", "nx_api.cpp", "nx_internal.h"]
+KERNEL_SOURCES = ["nx_fwd.hip", "nx_bwd.hip", "nx_loss.hip", "nx_species.hip", "nx_api.cpp",
+                  "nx_internal.h"]
 
 
 def source_hash() -> str:
@@ -75,6 +76,8 @@ def parse():
     p.add_argument("--mode", default="ph64", choices=["ph64", "f32"])
     p.add_argument("--no-f64", action="store_true", help="skip the all-FP64 comparison")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--no-species", action="store_true",
+                   help="skip the species-factorised step (workloads with several species)")
     p.add_argument("--cpu-seconds", type=float, default=20.0,
                    help="approximate CPU time budget of the oracle sample")
     p.add_argument("--copy-cal", type=int, default=0, metavar="BYTES",
@@ -271,6 +274,40 @@ def main():
         f64 = {"fwd_pairs_per_s": pairs / tf64, "bwd_pairs_per_s": pairs / tb64,
                "step_pairs_per_s": pairs / (tf64 + tb64)}
 
+    # the same step with the species factored out of the sum (Section 4.2): one
+    # unit-factor sum per species, atoms regrouped by species once, outside the timing
+    species = None
+    if not args.no_species and w.f is not None:
+        xs, start, vals, _ = wl.group_by_species(w.xyz, w.f)
+        if len(vals) <= 16:
+            txs = torch.from_numpy(xs).to(dev)
+            fs = torch.from_numpy(np.repeat(vals[:, None], k, axis=1)).to(dev)
+
+            def sstep(rec):
+                rec[0].record(stream)
+                A = api.scatter_fwd_species(txs, start, fs, tS, args.mode)
+                rec[1].record(stream)
+                _, G = api.loss_grad(A, I)
+                rec[2].record(stream)
+                api.scatter_bwd_species(txs, start, fs, tS, G, None, args.mode)
+                rec[3].record(stream)
+                return A
+
+            sstep([ev() for _ in range(4)])
+            srecs = [[ev() for _ in range(4)] for _ in range(max(1, min(args.steps, 3)))]
+            torch.cuda.synchronize()
+            for r in srecs:
+                A_sp = sstep(r)
+            torch.cuda.synchronize()
+            ts = [sum(r[a].elapsed_time(r[b]) for r in srecs) / len(srecs) / 1e3
+                  for a, b in ((0, 1), (2, 3), (0, 3))]
+            Ad = out[1].cpu().numpy().astype(np.complex128)
+            As_ = A_sp.cpu().numpy().astype(np.complex128)
+            species = {"n_species": len(vals), "fwd_pairs_per_s": pairs / ts[0],
+                       "bwd_pairs_per_s": pairs / ts[1], "step_pairs_per_s": pairs / ts[2],
+                       "t2_vs_per_atom_step": float(np.linalg.norm(As_ - Ad) / np.linalg.norm(Ad))}
+            del txs, fs
+
     cpu = None
     errs = None
     if not args.no_cpu:
@@ -311,6 +348,7 @@ def main():
         "bwd_pairs_per_s": pairs / t_bwd,
         "loss_ms": t_loss * 1e3,
         "f64_path": f64,
+        "species_path": species,
         "speedup_vs_f64_step": (value / f64["step_pairs_per_s"]) if f64 else None,
         "max_rel_err": errs,
         "paper_flop_convention": {"tflops": value * PAPER_FLOP_PER_PAIR / 1e12,

@@ -76,12 +76,17 @@ typedef enum { NX_F32 = 0, NX_F32_PH64 = 1 } nx_mode;
 
 /* Operation selector for nx_workspace_bytes. */
 typedef enum {
-  NX_OP_FWD = 0,       /* nx_scatter_fwd      */
-  NX_OP_BWD = 1,       /* nx_scatter_bwd      */
-  NX_OP_FWD_F64 = 2,   /* nx_scatter_fwd_f64  */
-  NX_OP_BWD_F64 = 3,   /* nx_scatter_bwd_f64  */
-  NX_OP_LOSS = 4       /* nx_loss_grad        */
+  NX_OP_FWD = 0,          /* nx_scatter_fwd                                  */
+  NX_OP_BWD = 1,          /* nx_scatter_bwd, nx_scatter_bwd_ex without grad_f */
+  NX_OP_FWD_F64 = 2,      /* nx_scatter_fwd_f64                              */
+  NX_OP_BWD_F64 = 3,      /* nx_scatter_bwd_f64                              */
+  NX_OP_LOSS = 4,         /* nx_loss_grad                                    */
+  NX_OP_BWD_GF = 5,       /* nx_scatter_bwd_ex with grad_f                   */
+  NX_OP_BWD_GF_F64 = 6    /* nx_scatter_bwd_ex_f64 with grad_f               */
 } nx_op;
+
+/* Most species accepted by the species-factorised entry points. */
+#define NX_MAX_SPECIES 16
 
 /* Largest n_atoms / n_points accepted by any entry point. */
 #define NX_MAX_COUNT ((int64_t)1 << 30)
@@ -134,6 +139,54 @@ int nx_scatter_bwd_f64(const double* xyz, const double* f, int64_t n_atoms,
  *   (may be NULL when only L is wanted).  n_points == 0 writes L = 0. */
 int nx_loss_grad(const float* A, const float* I, int64_t n_points, double* L, float* G,
                  void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint with the gradient with respect to the factors as well (for fitting
+ * occupancies or compositions):
+ *     grad_f_j = dL/dRe f_j + i dL/dIm f_j = conj( sum_k conj(G_k) exp(2 i pi S_k . r_j) )
+ * grad_f float[n_atoms*2] (complex64) or NULL (then this is nx_scatter_bwd);
+ * grad_xyz may be NULL when only grad_f is wanted.  Workspace: op NX_OP_BWD_GF. */
+int nx_scatter_bwd_ex(const float* xyz, const float* f, int64_t n_atoms,
+                      const float* S, int64_t n_points, const float* G, float* grad_xyz,
+                      float* grad_f, int mode, void* ws, size_t ws_bytes, void* stream);
+
+/* All-FP64 counterpart of nx_scatter_bwd_ex (workspace op NX_OP_BWD_GF_F64). */
+int nx_scatter_bwd_ex_f64(const double* xyz, const double* f, int64_t n_atoms,
+                          const double* S, int64_t n_points, const double* G, double* grad_xyz,
+                          double* grad_f, void* ws, size_t ws_bytes, void* stream);
+
+/* Species-factorised sum (Section 4.2 of the paper: the atoms of one type are summed
+ * with unit factor, and each type's sum is multiplied by that type's scattering factor at
+ * S, which may depend on |S| and on the energy):
+ *     A_k = sum_s fs[s][k] * sum_{j in species s} exp(2 i pi S_k . r_j)
+ * The atoms are listed species by species: species s holds atoms
+ * [species_start[s], species_start[s+1]); species_start is a HOST array of n_species + 1
+ * non-decreasing entries from 0 to n_atoms, 1 <= n_species <= NX_MAX_SPECIES.
+ *   fs        float[n_species * n_points * 2] (complex64, species-major), or NULL for 1;
+ *   A         float[n_points * 2], overwritten;
+ *   A_species float[n_species * n_points * 2] or NULL: the per-species sums (needed by
+ *             nx_scatter_bwd_species for the gradient with respect to fs).
+ * The per-species (sum, comp) states are combined in FP64 and rounded once.
+ * Workspace: nx_workspace_bytes_species(..., op = 0). */
+int nx_scatter_fwd_species(const float* xyz, int64_t n_atoms, const int64_t* species_start,
+                           int n_species, const float* fs, const float* S, int64_t n_points,
+                           float* A, float* A_species, int mode, void* ws, size_t ws_bytes,
+                           void* stream);
+
+/* Adjoint of nx_scatter_fwd_species for the seed G:
+ *   grad_xyz (may be NULL): dL/dr_j for every atom (the per-species seeds G conj(fs[s])
+ *            drive the unit-factor adjoint over that species' atoms);
+ *   grad_fs  (may be NULL): dL/dRe fs[s][k] + i dL/dIm fs[s][k] = G_k conj(A_species[s][k]),
+ *            complex64 [n_species][n_points]; needs A_species.
+ * Workspace: nx_workspace_bytes_species(..., op = 1) (only when grad_xyz is wanted). */
+int nx_scatter_bwd_species(const float* xyz, int64_t n_atoms, const int64_t* species_start,
+                           int n_species, const float* fs, const float* S, int64_t n_points,
+                           const float* G, const float* A_species, float* grad_xyz,
+                           float* grad_fs, int mode, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes of the species-factorised calls: op 0 forward, op 1 adjoint.  Returns 0
+ * and sets the last error on invalid arguments. */
+size_t nx_workspace_bytes_species(const int64_t* species_start, int n_species, int64_t n_points,
+                                  int mode, int op);
 
 /* Message of the calling thread's last error ("" if none).  The pointer stays valid
  * until the thread's next call into the library. */

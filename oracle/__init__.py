@@ -13,6 +13,10 @@ What it computes (Favre-Nicolin et al., 2010):
   the paper prints no loss).
 * ``adjoint``  -- the chain rule through Eq. 2,
   dL/dr_j = Re sum_k conj(G_k) f_j (2 i pi S_k) exp(2 i pi S_k . r_j).
+* ``adjoint_f`` -- the same for the factors, dL/df_j = conj(sum_k conj(G_k) exp(2 i pi S_k . r_j)).
+* ``forward_species`` / ``adjoint_species`` -- the species-factorised sum of Section 4.2,
+  A_k = sum_s fs[s][k] sum_{j in s} exp(2 i pi S_k . r_j), composed from the functions
+  above (per-species unit-factor sums; the seed of species s is G conj(fs[s])).
 
 Inputs are the caller's arrays widened exactly to float64 (FP32 inputs become the
 same numbers in FP64), so the oracle evaluates exactly the problem the GPU sees.
@@ -55,6 +59,8 @@ def _bind(path):
     lib.nxo_loss.restype = ctypes.c_double
     lib.nxo_adjoint.argtypes = [_I64, _DP, _DP, _I64, _DP, _DP, _DP]
     lib.nxo_adjoint.restype = None
+    lib.nxo_adjoint_f.argtypes = [_I64, _DP, _I64, _DP, _DP, _DP]
+    lib.nxo_adjoint_f.restype = None
     lib.nxo_threads.argtypes = []
     lib.nxo_threads.restype = ctypes.c_int
     return lib
@@ -138,6 +144,47 @@ def adjoint(xyz, f, S, G, lib=None) -> np.ndarray:
     return grad
 
 
+def adjoint_f(xyz, S, G, lib=None) -> np.ndarray:
+    """dL/dRe f_j + i dL/dIm f_j = conj(sum_k conj(G_k) exp(2 i pi S_k . r_j)).  Complex (N,)."""
+    lib = lib or _load()
+    xyz = _f64(xyz, 3)
+    S = _f64(S, 3)
+    n, k = xyz.shape[0], S.shape[0]
+    G = np.asarray(G)
+    Gp = np.empty((k, 2), dtype=np.float64)
+    Gp[:, 0] = G.real.reshape(-1)
+    Gp[:, 1] = G.imag.reshape(-1)
+    out = np.zeros((n, 2), dtype=np.float64)
+    lib.nxo_adjoint_f(n, _ptr(xyz), k, _ptr(S), _ptr(Gp), _ptr(out))
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def forward_species(xyz, species_start, fs, S, lib=None):
+    """A_k = sum_s fs[s][k] sum_{j in s} exp(2 i pi S_k . r_j); returns (A, A_species)."""
+    xyz = _f64(xyz, 3)
+    k = np.asarray(S).reshape(-1, 3).shape[0]
+    start = [int(v) for v in species_start]
+    As = np.stack([forward(xyz[start[s]:start[s + 1]], None, S, lib=lib)
+                   for s in range(len(start) - 1)]) if len(start) > 1 else np.zeros((0, k))
+    f = np.ones_like(As) if fs is None else np.asarray(fs, dtype=np.complex128).reshape(As.shape)
+    return (f * As).sum(axis=0), As
+
+
+def adjoint_species(xyz, species_start, fs, S, G, A_species=None, lib=None):
+    """dL/dr for every atom (species s driven by the seed G conj(fs[s])) and, when the
+    per-species sums are given, dL/dfs = G conj(A_species)."""
+    xyz = _f64(xyz, 3)
+    start = [int(v) for v in species_start]
+    G = np.asarray(G, dtype=np.complex128).reshape(-1)
+    grads = []
+    for s in range(len(start) - 1):
+        seed = G if fs is None else G * np.conj(np.asarray(fs, dtype=np.complex128)[s])
+        grads.append(adjoint(xyz[start[s]:start[s + 1]], None, S, seed, lib=lib))
+    grad = np.concatenate(grads) if grads else np.zeros((0, 3))
+    gfs = None if A_species is None else G[None, :] * np.conj(np.asarray(A_species))
+    return grad, gfs
+
+
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(_load().nxo_threads())
@@ -159,6 +206,9 @@ class Variant:
 
     def adjoint(self, xyz, f, S, G):
         return adjoint(xyz, f, S, G, lib=self.lib)
+
+    def adjoint_f(self, xyz, S, G):
+        return adjoint_f(xyz, S, G, lib=self.lib)
 
 
 def compile_variant(source_text: str, out_path: str) -> "Variant":

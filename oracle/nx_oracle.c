@@ -17,6 +17,8 @@
  *               loss is pinned by a worked value and by finite differences.
  *   adjoint  -- chain rule through Eq. 2:
  *               dL/dr_j = Re sum_k conj(G_k) f_j (2 i pi S_k) exp(2 i pi S_k.r_j)
+ *   adjoint_f -- the same chain rule for the factors (A is linear in f_j):
+ *               dL/dRe f_j + i dL/dIm f_j = conj( sum_k conj(G_k) exp(2 i pi S_k.r_j) )
  *
  * Conventions (readings of the paper):
  *   - sign +2 i pi as printed in Eq. 2; S in reciprocal-lattice units and r in
@@ -131,6 +133,29 @@ void nxo_adjoint(int64_t n_atoms, const double *xyz, const double *f,
         grad[3 * j] = gx;
         grad[3 * j + 1] = gy;
         grad[3 * j + 2] = gz;
+    }
+}
+
+/* Gradient with respect to the per-atom factors: with dA_k = exp(2 i pi S_k.r_j) df_j,
+ * dL = Re sum_k conj(G_k) dA_k = Re(W_j df_j), W_j = sum_k conj(G_k) exp(2 i pi S_k.r_j),
+ * so dL/dRe f_j = Re W_j and dL/dIm f_j = -Im W_j.  gradf: n_atoms complex, overwritten. */
+void nxo_adjoint_f(int64_t n_atoms, const double *xyz, int64_t n_points, const double *S,
+                   const double *G, double *gradf)
+{
+    int64_t j;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (j = 0; j < n_atoms; ++j) {
+        const double x = xyz[3 * j], y = xyz[3 * j + 1], z = xyz[3 * j + 2];
+        double wr = 0.0, wi = 0.0;
+        for (int64_t k = 0; k < n_points; ++k) {
+            double c, s;
+            cis_cycles(S[3 * k] * x + S[3 * k + 1] * y + S[3 * k + 2] * z, &c, &s);
+            double gr = G[2 * k], gi = -G[2 * k + 1];      /* conj(G_k) */
+            wr += gr * c - gi * s;
+            wi += gr * s + gi * c;
+        }
+        gradf[2 * j] = wr;
+        gradf[2 * j + 1] = -wi;
     }
 }
 

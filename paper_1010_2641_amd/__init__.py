@@ -7,7 +7,9 @@ loaded on first use, so that ``workloads`` (input generation) imports without th
 GPU library.
 """
 __all__ = ["scatter", "scatter_fwd", "scatter_bwd", "scatter_fwd_f64", "scatter_bwd_f64",
-           "loss_grad", "fit_step", "ScatterFn", "workspace_bytes"]
+           "scatter_bwd_ex", "scatter_bwd_ex_f64", "scatter_fwd_species", "scatter_bwd_species",
+           "scatter_species", "loss_grad", "fit_step", "fit_step_species", "ScatterFn",
+           "ScatterSpeciesFn", "workspace_bytes"]
 
 
 def __getattr__(name):

@@ -13,7 +13,9 @@ LIB_PATH = os.path.join(_HERE, "libnx.so")
 NX_OK, NX_ERR_ARG, NX_ERR_MODE, NX_ERR_WORKSPACE, NX_ERR_DEVICE = 0, -1, -2, -3, -4
 NX_F32, NX_F32_PH64 = 0, 1
 NX_OP_FWD, NX_OP_BWD, NX_OP_FWD_F64, NX_OP_BWD_F64, NX_OP_LOSS = 0, 1, 2, 3, 4
+NX_OP_BWD_GF, NX_OP_BWD_GF_F64 = 5, 6
 NX_MAX_COUNT = 1 << 30
+NX_MAX_SPECIES = 16
 
 # every symbol include/nx.h declares, with its ctypes signature
 _VP, _I64, _SZ, _I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t, ctypes.c_int
@@ -26,6 +28,12 @@ SIGNATURES = {
     "nx_scatter_fwd_f64": ([_VP, _VP, _I64, _VP, _I64, _VP, _VP, _SZ, _VP], _I),
     "nx_scatter_bwd_f64": ([_VP, _VP, _I64, _VP, _I64, _VP, _VP, _VP, _SZ, _VP], _I),
     "nx_loss_grad": ([_VP, _VP, _I64, _VP, _VP, _VP, _SZ, _VP], _I),
+    "nx_scatter_bwd_ex": ([_VP, _VP, _I64, _VP, _I64, _VP, _VP, _VP, _I, _VP, _SZ, _VP], _I),
+    "nx_scatter_bwd_ex_f64": ([_VP, _VP, _I64, _VP, _I64, _VP, _VP, _VP, _VP, _SZ, _VP], _I),
+    "nx_scatter_fwd_species": ([_VP, _I64, _VP, _I, _VP, _VP, _I64, _VP, _VP, _I, _VP, _SZ, _VP], _I),
+    "nx_scatter_bwd_species": ([_VP, _I64, _VP, _I, _VP, _VP, _I64, _VP, _VP, _VP, _VP, _I, _VP, _SZ,
+                                _VP], _I),
+    "nx_workspace_bytes_species": ([_VP, _I, _I64, _I, _I], _SZ),
 }
 
 
@@ -85,3 +93,8 @@ nx_scatter_bwd = lib.nx_scatter_bwd
 nx_scatter_fwd_f64 = lib.nx_scatter_fwd_f64
 nx_scatter_bwd_f64 = lib.nx_scatter_bwd_f64
 nx_loss_grad = lib.nx_loss_grad
+nx_scatter_bwd_ex = lib.nx_scatter_bwd_ex
+nx_scatter_bwd_ex_f64 = lib.nx_scatter_bwd_ex_f64
+nx_scatter_fwd_species = lib.nx_scatter_fwd_species
+nx_scatter_bwd_species = lib.nx_scatter_bwd_species
+nx_workspace_bytes_species = lib.nx_workspace_bytes_species

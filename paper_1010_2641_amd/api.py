@@ -8,12 +8,16 @@ library (include/nx.h), which does all the arithmetic.
   paper's plain FP32 arithmetic (``mode="f32"``);
 * ``scatter_fwd_f64`` / ``scatter_bwd_f64`` -- the all-FP64 path;
 * ``loss_grad``                             -- misfit L = sum (|A|^2 - I)^2 and seed G;
-* ``scatter``                               -- differentiable forward (autograd.Function);
-* ``fit_step``                              -- forward, misfit and adjoint in one call.
+* ``scatter_bwd_ex`` / ``scatter_bwd_ex_f64`` -- the adjoint with dL/df as well;
+* ``scatter_fwd_species`` / ``scatter_bwd_species`` -- the species-factorised sum of
+  Section 4.2 (unit-factor sums per species times S-dependent species factors);
+* ``scatter``, ``scatter_species``          -- differentiable forwards (autograd.Function);
+* ``fit_step``, ``fit_step_species``        -- forward, misfit and adjoint in one call.
 """
 from __future__ import annotations
 
-from typing import Optional, Tuple
+import ctypes
+from typing import Optional, Sequence, Tuple
 
 import torch
 
@@ -147,6 +151,124 @@ def scatter_bwd_f64(xyz: torch.Tensor, f: Optional[torch.Tensor], S: torch.Tenso
     return grad
 
 
+def scatter_bwd_ex(xyz: torch.Tensor, f: Optional[torch.Tensor], S: torch.Tensor, G: torch.Tensor,
+                   mode="ph64", want_xyz: bool = True, want_f: bool = True):
+    """The adjoint with the factor gradient: returns (dL/dxyz (N,3) float32 or None,
+    dL/df (N,) complex64 or None)."""
+    _need_gpu(xyz, "xyz", torch.float32, 3)
+    _need_gpu(S, "S", torch.float32, 3)
+    _need_gpu(G, "G", torch.complex64)
+    n, k = xyz.shape[0], S.shape[0]
+    if G.dim() != 1 or G.shape[0] != k:
+        raise ValueError(f"G must have shape ({k},)")
+    fr = _f_arg(f, n, torch.complex64)
+    m = _mode(mode)
+    grad = torch.empty((n, 3), dtype=torch.float32, device=xyz.device) if want_xyz else None
+    gradf = torch.empty(n, dtype=torch.complex64, device=xyz.device) if want_f else None
+    op = _lib.NX_OP_BWD_GF if want_f else _lib.NX_OP_BWD
+    ws, wsb = _workspace(workspace_bytes(n, k, m, op, f is None), xyz.device)
+    _lib.check(_lib.nx_scatter_bwd_ex(_ptr(xyz), _ptr(fr), n, _ptr(S), k,
+                                      _ptr(torch.view_as_real(G)), _ptr(grad),
+                                      None if gradf is None else _ptr(torch.view_as_real(gradf)),
+                                      m, _ptr(ws), wsb, _stream(xyz.device)))
+    return grad, gradf
+
+
+def scatter_bwd_ex_f64(xyz: torch.Tensor, f: Optional[torch.Tensor], S: torch.Tensor,
+                       G: torch.Tensor, want_xyz: bool = True, want_f: bool = True):
+    """All-FP64 adjoint with the factor gradient: (dL/dxyz float64 or None, dL/df complex128
+    or None)."""
+    _need_gpu(xyz, "xyz", torch.float64, 3)
+    _need_gpu(S, "S", torch.float64, 3)
+    _need_gpu(G, "G", torch.complex128)
+    n, k = xyz.shape[0], S.shape[0]
+    if G.dim() != 1 or G.shape[0] != k:
+        raise ValueError(f"G must have shape ({k},)")
+    fr = _f_arg(f, n, torch.complex128)
+    grad = torch.empty((n, 3), dtype=torch.float64, device=xyz.device) if want_xyz else None
+    gradf = torch.empty(n, dtype=torch.complex128, device=xyz.device) if want_f else None
+    op = _lib.NX_OP_BWD_GF_F64 if want_f else _lib.NX_OP_BWD_F64
+    ws, wsb = _workspace(workspace_bytes(n, k, 0, op, f is None), xyz.device)
+    _lib.check(_lib.nx_scatter_bwd_ex_f64(_ptr(xyz), _ptr(fr), n, _ptr(S), k,
+                                          _ptr(torch.view_as_real(G)), _ptr(grad),
+                                          None if gradf is None else _ptr(torch.view_as_real(gradf)),
+                                          _ptr(ws), wsb, _stream(xyz.device)))
+    return grad, gradf
+
+
+def _species_array(species_start: Sequence[int], n_atoms: int):
+    start = [int(v) for v in species_start]
+    if len(start) < 2 or start[0] != 0 or start[-1] != n_atoms or any(
+            b < a for a, b in zip(start, start[1:])):
+        raise ValueError("species_start must run from 0 to n_atoms without decreasing")
+    if len(start) - 1 > _lib.NX_MAX_SPECIES:
+        raise ValueError(f"at most {_lib.NX_MAX_SPECIES} species")
+    return (ctypes.c_int64 * len(start))(*start), len(start) - 1
+
+
+def _fs_arg(fs: Optional[torch.Tensor], ns: int, k: int):
+    if fs is None:
+        return None
+    _need_gpu(fs, "fs", torch.complex64)
+    if tuple(fs.shape) != (ns, k):
+        raise ValueError(f"fs must have shape ({ns}, {k}) (got {tuple(fs.shape)})")
+    return torch.view_as_real(fs)
+
+
+def scatter_fwd_species(xyz: torch.Tensor, species_start: Sequence[int], fs: Optional[torch.Tensor],
+                        S: torch.Tensor, mode="ph64", return_species: bool = False):
+    """A_k = sum_s fs[s, k] sum_{j in species s} exp(2 i pi S_k . r_j) (Section 4.2): atoms
+    listed species by species, species s = atoms [species_start[s], species_start[s+1]);
+    fs (n_species, K) complex64 or None.  Returns A (K,) complex64, and the per-species
+    sums (n_species, K) when return_species."""
+    _need_gpu(xyz, "xyz", torch.float32, 3)
+    _need_gpu(S, "S", torch.float32, 3)
+    n, k = xyz.shape[0], S.shape[0]
+    start, ns = _species_array(species_start, n)
+    fsr = _fs_arg(fs, ns, k)
+    m = _mode(mode)
+    A = torch.empty(k, dtype=torch.complex64, device=S.device)
+    As = torch.empty((ns, k), dtype=torch.complex64, device=S.device) if return_species else None
+    nb = _lib.nx_workspace_bytes_species(start, ns, k, m, 0)
+    if _lib.last_error():
+        raise _lib.NxError(_lib.NX_ERR_ARG, _lib.last_error())
+    ws, wsb = _workspace(int(nb), S.device)
+    _lib.check(_lib.nx_scatter_fwd_species(_ptr(xyz), n, start, ns, _ptr(fsr), _ptr(S), k,
+                                           _ptr(torch.view_as_real(A)),
+                                           None if As is None else _ptr(torch.view_as_real(As)),
+                                           m, _ptr(ws), wsb, _stream(S.device)))
+    return (A, As) if return_species else A
+
+
+def scatter_bwd_species(xyz: torch.Tensor, species_start: Sequence[int], fs: Optional[torch.Tensor],
+                        S: torch.Tensor, G: torch.Tensor, A_species: Optional[torch.Tensor] = None,
+                        mode="ph64", want_xyz: bool = True):
+    """Adjoint of ``scatter_fwd_species``: (dL/dxyz (N,3) float32 or None, dL/dfs
+    (n_species, K) complex64 or None -- the latter when A_species is given)."""
+    _need_gpu(xyz, "xyz", torch.float32, 3)
+    _need_gpu(S, "S", torch.float32, 3)
+    _need_gpu(G, "G", torch.complex64)
+    n, k = xyz.shape[0], S.shape[0]
+    start, ns = _species_array(species_start, n)
+    fsr = _fs_arg(fs, ns, k)
+    m = _mode(mode)
+    Asr = None
+    if A_species is not None:
+        _need_gpu(A_species, "A_species", torch.complex64)
+        Asr = torch.view_as_real(A_species)
+    grad = torch.empty((n, 3), dtype=torch.float32, device=xyz.device) if want_xyz else None
+    gfs = torch.empty((ns, k), dtype=torch.complex64, device=xyz.device) if A_species is not None else None
+    nb = _lib.nx_workspace_bytes_species(start, ns, k, m, 1)
+    if _lib.last_error():
+        raise _lib.NxError(_lib.NX_ERR_ARG, _lib.last_error())
+    ws, wsb = _workspace(int(nb), xyz.device)
+    _lib.check(_lib.nx_scatter_bwd_species(_ptr(xyz), n, start, ns, _ptr(fsr), _ptr(S), k,
+                                           _ptr(torch.view_as_real(G)), _ptr(Asr), _ptr(grad),
+                                           None if gfs is None else _ptr(torch.view_as_real(gfs)),
+                                           m, _ptr(ws), wsb, _stream(xyz.device)))
+    return grad, gfs
+
+
 def loss_grad(A: torch.Tensor, I: torch.Tensor, want_grad: bool = True):
     """L = sum_k (|A_k|^2 - I_k)^2 (float64 scalar tensor on the device) and the seed
     G = 4 (|A|^2 - I) A (complex64) or None."""
@@ -165,9 +287,9 @@ def loss_grad(A: torch.Tensor, I: torch.Tensor, want_grad: bool = True):
 
 
 class ScatterFn(torch.autograd.Function):
-    """Differentiable Eq. 2 with respect to the positions (f and S are constants).
-    Backward receives torch's complex gradient dL/dRe A + i dL/dIm A and calls the
-    hand-written adjoint kernel; the phases are recomputed, never stored."""
+    """Differentiable Eq. 2 with respect to the positions and the factors (S is a
+    constant).  Backward receives torch's complex gradient dL/dRe A + i dL/dIm A and calls
+    the hand-written adjoint kernel; the phases are recomputed, never stored."""
 
     @staticmethod
     def forward(ctx, xyz, f, S, mode):
@@ -184,18 +306,62 @@ class ScatterFn(torch.autograd.Function):
             xyz, f, S = ctx.saved_tensors
         else:
             (xyz, S), f = ctx.saved_tensors, None
-        if not ctx.needs_input_grad[0]:
+        want_x = ctx.needs_input_grad[0]
+        want_f = ctx.has_f and ctx.needs_input_grad[1]
+        if not (want_x or want_f):
             return None, None, None, None
         if xyz.dtype == torch.float64:
-            g = scatter_bwd_f64(xyz, f, S, gA.to(torch.complex128).contiguous())
+            gx, gf = scatter_bwd_ex_f64(xyz, f, S, gA.to(torch.complex128).contiguous(), want_x, want_f)
         else:
-            g = scatter_bwd(xyz, f, S, gA.to(torch.complex64).contiguous(), ctx.mode)
-        return g, None, None, None
+            gx, gf = scatter_bwd_ex(xyz, f, S, gA.to(torch.complex64).contiguous(), ctx.mode,
+                                    want_x, want_f)
+        return gx, gf, None, None
+
+
+class ScatterSpeciesFn(torch.autograd.Function):
+    """Differentiable species-factorised sum with respect to the positions and the
+    per-species factors fs (n_species, K)."""
+
+    @staticmethod
+    def forward(ctx, xyz, fs, S, species_start, mode):
+        A, As = scatter_fwd_species(xyz, species_start, fs, S, mode, return_species=True)
+        ctx.save_for_backward(xyz, S, As, fs) if fs is not None else ctx.save_for_backward(xyz, S, As)
+        ctx.has_fs = fs is not None
+        ctx.species_start = list(species_start)
+        ctx.mode = mode
+        return A
+
+    @staticmethod
+    def backward(ctx, gA):
+        if ctx.has_fs:
+            xyz, S, As, fs = ctx.saved_tensors
+        else:
+            (xyz, S, As), fs = ctx.saved_tensors, None
+        want_x = ctx.needs_input_grad[0]
+        want_fs = ctx.has_fs and ctx.needs_input_grad[1]
+        gx, gfs = scatter_bwd_species(xyz, ctx.species_start, fs, S, gA.to(torch.complex64).contiguous(),
+                                      As if want_fs else None, ctx.mode, want_x)
+        return gx, gfs, None, None, None
+
+
+def scatter_species(xyz: torch.Tensor, species_start: Sequence[int], fs: Optional[torch.Tensor],
+                    S: torch.Tensor, mode="ph64"):
+    """Differentiable species-factorised forward."""
+    return ScatterSpeciesFn.apply(xyz, fs, S, list(species_start), mode)
 
 
 def scatter(xyz: torch.Tensor, f: Optional[torch.Tensor], S: torch.Tensor, mode="ph64"):
     """Differentiable forward sum; float64 xyz/S select the all-FP64 path."""
     return ScatterFn.apply(xyz, f, S, mode)
+
+
+def fit_step_species(xyz: torch.Tensor, species_start: Sequence[int], fs: Optional[torch.Tensor],
+                     S: torch.Tensor, I: torch.Tensor, mode="ph64"):
+    """The fit step with the species-factorised sum: (L, A, dL/dxyz)."""
+    A = scatter_fwd_species(xyz, species_start, fs, S, mode)
+    L, G = loss_grad(A, I)
+    grad, _ = scatter_bwd_species(xyz, species_start, fs, S, G, None, mode)
+    return L, A, grad
 
 
 def fit_step(xyz: torch.Tensor, f: Optional[torch.Tensor], S: torch.Tensor, I: torch.Tensor,

@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libnx.so")
 BUILD = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 
-SOURCES = ["nx_fwd.hip", "nx_bwd.hip", "nx_loss.hip", "nx_api.cpp"]
+SOURCES = ["nx_fwd.hip", "nx_bwd.hip", "nx_loss.hip", "nx_species.hip", "nx_api.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

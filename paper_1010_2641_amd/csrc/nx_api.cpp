@@ -85,7 +85,9 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
     p.misc_bytes = size_t(kLossBlocks) * sizeof(double);
     return p;
   }
-  p.mode = (op == kOpFwdF64 || op == kOpBwdF64) ? kF64 : (mode == NX_F32_PH64 ? kPH64 : kF32);
+  p.gf = (op == kOpBwdGf || op == kOpBwdGfF64) ? 1 : 0;
+  p.mode = (op == kOpFwdF64 || op == kOpBwdF64 || op == kOpBwdGfF64) ? kF64
+                                                                     : (mode == NX_F32_PH64 ? kPH64 : kF32);
   p.lanes = fwd ? n_points : n_atoms;
   p.stream = fwd ? n_atoms : n_points;
   // Defaults from launch-shape and accuracy sweeps on MI355X.  Forward, FP64-phase
@@ -148,7 +150,10 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
   if (need_partial) {
     size_t per_item;
     if (fwd) per_item = 16;                                  // float4 or double2 per point
-    else per_item = p.mode == kF64 ? 3 * 8 : 3 * 2 * 4;      // 3 sums (+ comps) per atom
+    else {
+      const size_t ns = p.gf ? 5 : 3;                        // 3 (+ 2 for dL/df) sums per atom
+      per_item = p.mode == kF64 ? ns * 8 : ns * 2 * 4;       // (+ comps in FP32)
+    }
     p.partial_bytes = align_up(size_t(p.nsplit) * size_t(p.lanes) * per_item, 256);
   }
   return p;
@@ -169,9 +174,10 @@ void chunk_range(const Plan& p, int64_t c, int64_t* begin, int64_t* end, int64_t
 
 namespace {
 
-// Chunked launch sequence shared by the four sum entry points.
+// Chunked launch sequence shared by the sum entry points.  `out` is A (forward) or
+// grad_xyz (adjoint, may be NULL when only dL/df is asked for); `outf` is dL/df.
 int run_sum(const char* fn, const nx::Plan& p, bool fwd, const void* xyz, const void* f,
-            const void* S, const void* G, void* out, void* ws, hipStream_t st) {
+            const void* S, const void* G, void* out, void* outf, void* ws, hipStream_t st) {
   char* base = static_cast<char*>(ws);
   void* rec = base;
   void* partial = p.partial_bytes ? base + p.rec_bytes : nullptr;
@@ -185,32 +191,73 @@ int run_sum(const char* fn, const nx::Plan& p, bool fwd, const void* xyz, const 
     const int carry = c > 0 ? 1 : 0;
     const int direct = (p.nsplit == 1 && c == p.nchunks - 1) ? 1 : 0;
     if (fwd) e = nx::launch_fwd_chunk(p, rec, b, en, per, S, partial, out, carry, direct, st);
-    else e = nx::launch_bwd_chunk(p, rec, b, en, per, xyz, f, partial, out, carry, direct, st);
+    else e = nx::launch_bwd_chunk(p, rec, b, en, per, xyz, f, partial, out, outf, carry, direct, st);
     if (e != hipSuccess) return device_error(fn, e);
   }
   if (p.nsplit > 1) {
     if (fwd) e = nx::launch_fwd_reduce(p, partial, out, st);
-    else e = nx::launch_bwd_reduce(p, partial, f, out, st);
+    else e = nx::launch_bwd_reduce(p, partial, out, outf, st);
     if (e != hipSuccess) return device_error(fn, e);
   }
   return ok();
+}
+
+// Validates a species partition: start[0] = 0, non-decreasing, start[n] = n_atoms.
+int check_species(const char* fn, int64_t n_atoms, const int64_t* start, int n_species) {
+  if (n_species < 1 || n_species > nx::kMaxSpecies)
+    return fail(NX_ERR_ARG, "%s: n_species %d outside [1, %d]", fn, n_species, nx::kMaxSpecies);
+  if (!start) return fail(NX_ERR_ARG, "%s: NULL species_start", fn);
+  if (start[0] != 0 || start[n_species] != n_atoms)
+    return fail(NX_ERR_ARG, "%s: species_start must run from 0 to n_atoms (%lld .. %lld given)", fn,
+                (long long)start[0], (long long)start[n_species]);
+  for (int s = 0; s < n_species; ++s)
+    if (start[s + 1] < start[s])
+      return fail(NX_ERR_ARG, "%s: species_start decreases at %d", fn, s);
+  return NX_OK;
+}
+
+// Workspace of the species-factorised calls.
+//   forward: atom records for all atoms, then one (sum, comp) state per species;
+//   adjoint: the per-species seed, the point records, the largest per-species partial.
+size_t species_ws(int op, int mode, int64_t n_points, const int64_t* start, int n_species,
+                  size_t* state_off) {
+  size_t total = 0;
+  if (op == 0) {
+    const nx::Plan p0 = nx::make_plan(nx::kOpFwd, mode, start[n_species], n_points, 1);
+    total = p0.rec_bytes;
+    for (int s = 0; s < n_species; ++s) {
+      const nx::Plan ps = nx::make_plan(nx::kOpFwd, mode, start[s + 1] - start[s], n_points, 1);
+      if (state_off) state_off[s] = total;
+      total += align_up(size_t(ps.nsplit) * size_t(n_points) * 16, 256);
+    }
+  } else {
+    size_t part = 0, rec = 0;
+    for (int s = 0; s < n_species; ++s) {
+      const nx::Plan ps = nx::make_plan(nx::kOpBwd, mode, start[s + 1] - start[s], n_points, 1);
+      if (ps.partial_bytes > part) part = ps.partial_bytes;
+      rec = ps.rec_bytes;
+    }
+    total = align_up(size_t(n_points) * 8, 256) + rec + part;
+  }
+  return total;
 }
 
 }  // namespace
 
 extern "C" {
 
-int nx_version(void) { return 100; }
+int nx_version(void) { return 101; }
 
 const char* nx_last_error(void) { return g_last_error.c_str(); }
 
 size_t nx_workspace_bytes(int64_t n_atoms, int64_t n_points, int mode, int op, int f_is_null) {
   if (check_counts("nx_workspace_bytes", n_atoms, n_points) != NX_OK) return 0;
-  if (op < NX_OP_FWD || op > NX_OP_LOSS) {
+  if (op < NX_OP_FWD || op > NX_OP_BWD_GF_F64) {
     fail(NX_ERR_MODE, "nx_workspace_bytes: unknown op %d", op);
     return 0;
   }
-  if ((op == NX_OP_FWD || op == NX_OP_BWD) && mode != NX_F32 && mode != NX_F32_PH64) {
+  if ((op == NX_OP_FWD || op == NX_OP_BWD || op == NX_OP_BWD_GF) && mode != NX_F32 &&
+      mode != NX_F32_PH64) {
     fail(NX_ERR_MODE, "nx_workspace_bytes: unknown mode %d", mode);
     return 0;
   }
@@ -232,7 +279,7 @@ int nx_scatter_fwd(const float* xyz, const float* f, int64_t n_atoms, const floa
     return fail(NX_ERR_ARG, "%s: A and f must be 8-byte aligned (complex64)", fn);
   const nx::Plan p = nx::make_plan(nx::kOpFwd, mode, n_atoms, n_points, f == nullptr);
   if (int r = check_ws(fn, p, ws, ws_bytes)) return r;
-  return run_sum(fn, p, true, xyz, f, S, nullptr, A, ws, static_cast<hipStream_t>(stream));
+  return run_sum(fn, p, true, xyz, f, S, nullptr, A, nullptr, ws, static_cast<hipStream_t>(stream));
 }
 
 int nx_scatter_bwd(const float* xyz, const float* f, int64_t n_atoms, const float* S,
@@ -249,7 +296,7 @@ int nx_scatter_bwd(const float* xyz, const float* f, int64_t n_atoms, const floa
     return fail(NX_ERR_ARG, "%s: G and f must be 8-byte aligned (complex64)", fn);
   const nx::Plan p = nx::make_plan(nx::kOpBwd, mode, n_atoms, n_points, f == nullptr);
   if (int r = check_ws(fn, p, ws, ws_bytes)) return r;
-  return run_sum(fn, p, false, xyz, f, S, G, grad_xyz, ws, static_cast<hipStream_t>(stream));
+  return run_sum(fn, p, false, xyz, f, S, G, grad_xyz, nullptr, ws, static_cast<hipStream_t>(stream));
 }
 
 int nx_scatter_fwd_f64(const double* xyz, const double* f, int64_t n_atoms, const double* S,
@@ -264,7 +311,7 @@ int nx_scatter_fwd_f64(const double* xyz, const double* f, int64_t n_atoms, cons
     return fail(NX_ERR_ARG, "%s: misaligned double array (A needs 16 bytes)", fn);
   const nx::Plan p = nx::make_plan(nx::kOpFwdF64, 0, n_atoms, n_points, f == nullptr);
   if (int r = check_ws(fn, p, ws, ws_bytes)) return r;
-  return run_sum(fn, p, true, xyz, f, S, nullptr, A, ws, static_cast<hipStream_t>(stream));
+  return run_sum(fn, p, true, xyz, f, S, nullptr, A, nullptr, ws, static_cast<hipStream_t>(stream));
 }
 
 int nx_scatter_bwd_f64(const double* xyz, const double* f, int64_t n_atoms, const double* S,
@@ -281,7 +328,7 @@ int nx_scatter_bwd_f64(const double* xyz, const double* f, int64_t n_atoms, cons
     return fail(NX_ERR_ARG, "%s: misaligned double array", fn);
   const nx::Plan p = nx::make_plan(nx::kOpBwdF64, 0, n_atoms, n_points, f == nullptr);
   if (int r = check_ws(fn, p, ws, ws_bytes)) return r;
-  return run_sum(fn, p, false, xyz, f, S, G, grad_xyz, ws, static_cast<hipStream_t>(stream));
+  return run_sum(fn, p, false, xyz, f, S, G, grad_xyz, nullptr, ws, static_cast<hipStream_t>(stream));
 }
 
 int nx_loss_grad(const float* A, const float* I, int64_t n_points, double* L, float* G, void* ws,
@@ -298,6 +345,158 @@ int nx_loss_grad(const float* A, const float* I, int64_t n_points, double* L, fl
   hipError_t e = nx::launch_loss(A, I, n_points, L, G, static_cast<double*>(ws),
                                  static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_error(fn, e);
+  return ok();
+}
+
+int nx_scatter_bwd_ex(const float* xyz, const float* f, int64_t n_atoms, const float* S,
+                      int64_t n_points, const float* G, float* grad_xyz, float* grad_f, int mode,
+                      void* ws, size_t ws_bytes, void* stream) {
+  const char* fn = "nx_scatter_bwd_ex";
+  if (!grad_f)
+    return nx_scatter_bwd(xyz, f, n_atoms, S, n_points, G, grad_xyz, mode, ws, ws_bytes, stream);
+  if (int r = check_counts(fn, n_atoms, n_points)) return r;
+  if (mode != NX_F32 && mode != NX_F32_PH64) return fail(NX_ERR_MODE, "%s: unknown mode %d", fn, mode);
+  if (n_atoms == 0) return ok();
+  if (!xyz || (n_points > 0 && (!S || !G)))
+    return fail(NX_ERR_ARG, "%s: NULL pointer (xyz=%p S=%p G=%p)", fn, (const void*)xyz,
+                (const void*)S, (const void*)G);
+  if ((G && !aligned(G, 8)) || (f && !aligned(f, 8)) || !aligned(grad_f, 8))
+    return fail(NX_ERR_ARG, "%s: G, f and grad_f must be 8-byte aligned (complex64)", fn);
+  const nx::Plan p = nx::make_plan(nx::kOpBwdGf, mode, n_atoms, n_points, f == nullptr);
+  if (int r = check_ws(fn, p, ws, ws_bytes)) return r;
+  return run_sum(fn, p, false, xyz, f, S, G, grad_xyz, grad_f, ws, static_cast<hipStream_t>(stream));
+}
+
+int nx_scatter_bwd_ex_f64(const double* xyz, const double* f, int64_t n_atoms, const double* S,
+                          int64_t n_points, const double* G, double* grad_xyz, double* grad_f,
+                          void* ws, size_t ws_bytes, void* stream) {
+  const char* fn = "nx_scatter_bwd_ex_f64";
+  if (!grad_f)
+    return nx_scatter_bwd_f64(xyz, f, n_atoms, S, n_points, G, grad_xyz, ws, ws_bytes, stream);
+  if (int r = check_counts(fn, n_atoms, n_points)) return r;
+  if (n_atoms == 0) return ok();
+  if (!xyz || (n_points > 0 && (!S || !G)))
+    return fail(NX_ERR_ARG, "%s: NULL pointer (xyz=%p S=%p G=%p)", fn, (const void*)xyz,
+                (const void*)S, (const void*)G);
+  if (!aligned(xyz, 8) || (grad_xyz && !aligned(grad_xyz, 8)) || !aligned(grad_f, 8) ||
+      (S && !aligned(S, 8)) || (G && !aligned(G, 8)) || (f && !aligned(f, 8)))
+    return fail(NX_ERR_ARG, "%s: misaligned double array", fn);
+  const nx::Plan p = nx::make_plan(nx::kOpBwdGfF64, 0, n_atoms, n_points, f == nullptr);
+  if (int r = check_ws(fn, p, ws, ws_bytes)) return r;
+  return run_sum(fn, p, false, xyz, f, S, G, grad_xyz, grad_f, ws, static_cast<hipStream_t>(stream));
+}
+
+size_t nx_workspace_bytes_species(const int64_t* species_start, int n_species, int64_t n_points,
+                                  int mode, int op) {
+  const char* fn = "nx_workspace_bytes_species";
+  if (n_species < 1 || n_species > nx::kMaxSpecies || !species_start) {
+    fail(NX_ERR_ARG, "%s: n_species %d outside [1, %d] or NULL species_start", fn, n_species,
+         nx::kMaxSpecies);
+    return 0;
+  }
+  const int64_t n_atoms = species_start[n_species];
+  if (check_counts(fn, n_atoms, n_points) != NX_OK) return 0;
+  if (check_species(fn, n_atoms, species_start, n_species) != NX_OK) return 0;
+  if (mode != NX_F32 && mode != NX_F32_PH64) {
+    fail(NX_ERR_MODE, "%s: unknown mode %d", fn, mode);
+    return 0;
+  }
+  if (op != 0 && op != 1) {
+    fail(NX_ERR_MODE, "%s: op must be 0 (forward) or 1 (adjoint), got %d", fn, op);
+    return 0;
+  }
+  ok();
+  return species_ws(op, mode, n_points, species_start, n_species, nullptr);
+}
+
+int nx_scatter_fwd_species(const float* xyz, int64_t n_atoms, const int64_t* species_start,
+                           int n_species, const float* fs, const float* S, int64_t n_points,
+                           float* A, float* A_species, int mode, void* ws, size_t ws_bytes,
+                           void* stream) {
+  const char* fn = "nx_scatter_fwd_species";
+  if (int r = check_counts(fn, n_atoms, n_points)) return r;
+  if (int r = check_species(fn, n_atoms, species_start, n_species)) return r;
+  if (mode != NX_F32 && mode != NX_F32_PH64) return fail(NX_ERR_MODE, "%s: unknown mode %d", fn, mode);
+  if (n_points == 0) return ok();
+  if (!S || !A || (n_atoms > 0 && !xyz))
+    return fail(NX_ERR_ARG, "%s: NULL pointer (xyz=%p S=%p A=%p)", fn, (const void*)xyz,
+                (const void*)S, (void*)A);
+  if (!aligned(A, 8) || (fs && !aligned(fs, 8)) || (A_species && !aligned(A_species, 8)))
+    return fail(NX_ERR_ARG, "%s: A, fs and A_species must be 8-byte aligned (complex64)", fn);
+  size_t off[nx::kMaxSpecies];
+  const size_t need = species_ws(0, mode, n_points, species_start, n_species, off);
+  if (need > 0 && (ws == nullptr || ws_bytes < need || !aligned(ws, 16)))
+    return fail(NX_ERR_WORKSPACE, "%s: workspace of %zu bytes (16-byte aligned) needed, %zu given", fn,
+                need, ws_bytes);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  const nx::Plan p0 = nx::make_plan(nx::kOpFwd, mode, n_atoms, n_points, 1);
+  hipError_t e = nx::launch_pack_atoms(p0.mode, p0.red, xyz, nullptr, n_atoms, base, st);
+  if (e != hipSuccess) return device_error(fn, e);
+  nx::SpeciesStates ss{};
+  ss.n = n_species;
+  for (int s = 0; s < n_species; ++s) {
+    const int64_t a0 = species_start[s];
+    const nx::Plan ps = nx::make_plan(nx::kOpFwd, mode, species_start[s + 1] - a0, n_points, 1);
+    void* state = base + off[s];
+    ss.state[s] = state;
+    ss.nsplit[s] = ps.nsplit;
+    for (int64_t c = 0; c < ps.nchunks; ++c) {
+      int64_t b, en, per;
+      nx::chunk_range(ps, c, &b, &en, &per);
+      e = nx::launch_fwd_chunk(ps, base, a0 + b, a0 + en, per, S, state, nullptr, c > 0 ? 1 : 0, 0, st);
+      if (e != hipSuccess) return device_error(fn, e);
+    }
+  }
+  e = nx::launch_species_combine(ss, fs, n_points, A, A_species, st);
+  if (e != hipSuccess) return device_error(fn, e);
+  return ok();
+}
+
+int nx_scatter_bwd_species(const float* xyz, int64_t n_atoms, const int64_t* species_start,
+                           int n_species, const float* fs, const float* S, int64_t n_points,
+                           const float* G, const float* A_species, float* grad_xyz,
+                           float* grad_fs, int mode, void* ws, size_t ws_bytes, void* stream) {
+  const char* fn = "nx_scatter_bwd_species";
+  if (int r = check_counts(fn, n_atoms, n_points)) return r;
+  if (int r = check_species(fn, n_atoms, species_start, n_species)) return r;
+  if (mode != NX_F32 && mode != NX_F32_PH64) return fail(NX_ERR_MODE, "%s: unknown mode %d", fn, mode);
+  if (!grad_xyz && !grad_fs) return ok();
+  if (n_points > 0 && (!S || !G))
+    return fail(NX_ERR_ARG, "%s: NULL pointer (S=%p G=%p)", fn, (const void*)S, (const void*)G);
+  if (grad_xyz && n_atoms > 0 && !xyz) return fail(NX_ERR_ARG, "%s: NULL xyz", fn);
+  if (grad_fs && n_points > 0 && !A_species)
+    return fail(NX_ERR_ARG, "%s: grad_fs needs the per-species sums A_species", fn);
+  if ((G && !aligned(G, 8)) || (fs && !aligned(fs, 8)) || (grad_fs && !aligned(grad_fs, 8)) ||
+      (A_species && !aligned(A_species, 8)))
+    return fail(NX_ERR_ARG, "%s: G, fs, A_species and grad_fs must be 8-byte aligned", fn);
+  const size_t need = species_ws(1, mode, n_points, species_start, n_species, nullptr);
+  if (grad_xyz && n_atoms > 0 && need > 0 && (ws == nullptr || ws_bytes < need || !aligned(ws, 16)))
+    return fail(NX_ERR_WORKSPACE, "%s: workspace of %zu bytes (16-byte aligned) needed, %zu given", fn,
+                need, ws_bytes);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (grad_fs) {
+    for (int s = 0; s < n_species; ++s) {
+      e = nx::launch_species_gradf(G, A_species + 2 * int64_t(s) * n_points, n_points,
+                                   grad_fs + 2 * int64_t(s) * n_points, st);
+      if (e != hipSuccess) return device_error(fn, e);
+    }
+  }
+  if (!grad_xyz || n_atoms == 0) return ok();
+  char* base = static_cast<char*>(ws);
+  float* seed = reinterpret_cast<float*>(base);
+  char* rest = base + align_up(size_t(n_points) * 8, 256);
+  for (int s = 0; s < n_species; ++s) {
+    const int64_t a0 = species_start[s], ns = species_start[s + 1] - a0;
+    if (ns == 0) continue;
+    e = nx::launch_species_seed(G, fs ? fs + 2 * int64_t(s) * n_points : nullptr, n_points, seed, st);
+    if (e != hipSuccess) return device_error(fn, e);
+    const nx::Plan ps = nx::make_plan(nx::kOpBwd, mode, ns, n_points, 1);
+    const int r = run_sum(fn, ps, false, xyz + 3 * a0, nullptr, S, seed, grad_xyz + 3 * a0, nullptr,
+                          rest, st);
+    if (r != NX_OK) return r;
+  }
   return ok();
 }
 

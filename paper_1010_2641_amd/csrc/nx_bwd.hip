@@ -1,24 +1,24 @@
-// nx_bwd.hip -- adjoint of the direct scattering sum with respect to the atom
-// positions.  For a real loss L(A) with seed G_k = dL/dRe A_k + i dL/dIm A_k, the
-// chain rule through Eq. 2 of Favre-Nicolin et al. (2010) gives
+// nx_bwd.hip -- adjoint of the direct scattering sum.  For a real loss L(A) with seed
+// G_k = dL/dRe A_k + i dL/dIm A_k, the chain rule through Eq. 2 of Favre-Nicolin et al.
+// (2010) gives, for the positions,
 //     dL/dr_j = Re sum_k conj(G_k) f_j (2 i pi S_k) exp(2 i pi S_k . r_j)
 //             = -2 pi sum_k S_k v_jk,   v_jk = Im( f_j conj(G_k) exp(2 i pi S_k . r_j) )
-// so each atom carries three real sums (one per coordinate).  In the FP64-phase mode
-// the seed is taken in polar form, conj(G_k) = |G_k| exp(2 i pi delta_k): delta_k
-// joins the FP64 phase and |G_k| is folded into S_k, so that
-//     v_jk = |G_k| Im( f_j exp(2 i pi (S_k . r_j + delta_k)) ) = |G_k| (fr s + fi c)
-// costs two FP32 operations (none for f_j = 1) on top of the phase and sin/cos.
+// (three real sums per atom), and for the factors (torch's convention for a complex
+// parameter, dL/dRe f + i dL/dIm f)
+//     dL/df_j = conj(W_j),   W_j = sum_k conj(G_k) exp(2 i pi S_k . r_j)
+// (one complex sum per atom, computed only when asked for).
 //
-// Layout: every lane owns Q atoms and keeps their position and the T sums in
-// registers; the points are streamed as packed wave-uniform records through the
-// scalar load path (the paper's alternative of parallelising over atoms and sharing
-// the reflection coordinates, Section 2.2).  The phases are recomputed, never stored.
+// In the FP64-phase mode the seed is taken in polar form, conj(G_k) =
+// |G_k| exp(2 i pi delta_k): delta_k rides in the FP64 phase and |G_k| is folded into S_k,
+// so that v_jk = |G_k| Im(f_j exp(2 i pi psi)) = |G_k| (fr s + fi c), psi = S_k.r_j +
+// delta_k, costs two FP32 operations (none for f_j = 1), and W_j += |G_k| (c + i s).
 //
-// Per (point, atom) pair, FP64-phase mode: FP64 phase and reduction (as in the
-// forward) with delta_k, FP32 v_sin/v_cos, T_d += (|G_k| S_kd) v with FP32 fma into
-// per-group partials folded into (sum, comp) pairs by an error-free two-sum every GRP
-// points.
-// FP32 mode: the paper's FP32 arithmetic with plain sums.
+// Layout: every lane owns Q atoms and keeps their position and the sums in registers;
+// the points are streamed as packed wave-uniform records through the scalar load path
+// (the paper's alternative of parallelising over atoms and sharing the reflection
+// coordinates, Section 2.2).  The phases are recomputed, never stored.  Sums are
+// accumulated in FP32 per group of GRP points and folded into (sum, comp) pairs with an
+// error-free two-sum.  FP32 mode: the paper's FP32 arithmetic with plain sums.
 #include "nx_internal.h"
 
 namespace nx {
@@ -37,9 +37,13 @@ template <> struct PointOf<kF32> { using type = PointF32; };
 template <> struct PointOf<kPH64> { using type = PointPH; };
 
 constexpr float kTwoPi = 6.283185307179586f;
+constexpr double kTwoPiD = 6.283185307179586476925286766559;
 
-// v = Im(f conj(G) (c + i s)) for the lane's atom; f = 1 when FK == 0.
-//   conj(G) (c + i s) = (gr c + gi s) + i (gr s - gi c)
+// Sums carried per atom: 3 position components, plus Re W and Im W with GF.
+template <bool GF> struct NSum { static constexpr int value = GF ? 5 : 3; };
+
+// FP32 mode: w = conj(G) (c + i s) = (gr c + gi s) + i (gr s - gi c);
+// v = Im(f w) = fr Im w + fi Re w (f = 1 when FK == 0).
 template <int FK>
 __device__ __forceinline__ float adj_weight(float gr, float gi, float fr, float fi, float c,
                                             float s) {
@@ -54,7 +58,7 @@ __device__ __forceinline__ float adj_weight(float gr, float gi, float fr, float 
 
 // One FP64-phase point record as three 16-byte words (the wave-uniform address lets
 // the compiler fetch them with scalar loads), unpacked into named fields.
-struct PtRegs { double sx, sy, sz, delta; float gsx, gsy, gsz; };
+struct PtRegs { double sx, sy, sz, delta; float gsx, gsy, gsz, gmag; };
 
 __device__ __forceinline__ PtRegs load_point(const PointPH* __restrict__ rec, int k) {
   const uint4* w = reinterpret_cast<const uint4*>(rec + k);
@@ -67,16 +71,16 @@ __device__ __forceinline__ PtRegs load_point(const PointPH* __restrict__ rec, in
   r.gsx = __uint_as_float(c.x);
   r.gsy = __uint_as_float(c.y);
   r.gsz = __uint_as_float(c.z);
+  r.gmag = __uint_as_float(c.w);
   return r;
 }
 
 // (c, s) of exp(2 i pi psi), psi = S.r + delta (delta includes the 1/2 of RED == 1).
-// The seed phase enters as the addend of the first fma: with delta copied once per point
-// into a VGPR pair (shared by the lane's Q atoms), each pair saves an FP64 add.
+// The seed phase enters as the addend of the first fma.
 template <int RED>
-__device__ __forceinline__ void cis_ph64_pt(const PtRegs& a, double dv, double x, double y,
-                                            double z, float& c, float& s) {
-  const double ph = __builtin_fma(a.sz, z, __builtin_fma(a.sy, y, __builtin_fma(a.sx, x, dv)));
+__device__ __forceinline__ void cis_ph64_pt(const PtRegs& a, double x, double y, double z,
+                                            float& c, float& s) {
+  const double ph = __builtin_fma(a.sz, z, __builtin_fma(a.sy, y, __builtin_fma(a.sx, x, a.delta)));
   float tf;
   if constexpr (RED == 0) tf = static_cast<float>(ph - __builtin_rint(ph));
   else tf = static_cast<float>(__builtin_amdgcn_fract(ph));
@@ -84,21 +88,46 @@ __device__ __forceinline__ void cis_ph64_pt(const PtRegs& a, double dv, double x
   s = __builtin_amdgcn_sinf(tf);
 }
 
-// v / |G| = Im(f (c + i s)) = fr s + fi c; s for f = 1.
-template <int FK>
-__device__ __forceinline__ float adj_im(float fr, float fi, float c, float s) {
-  if constexpr (FK == 0) return s;
-  else return __builtin_fmaf(fi, c, fr * s);
+// One point's contribution to the FP64-phase group partials g[0..NS).
+template <int FK, bool GF>
+__device__ __forceinline__ void ph64_pair(float* g, const PtRegs& a, float fr, float fi, float c,
+                                          float s) {
+  float v;
+  if constexpr (FK == 0) v = s;
+  else v = __builtin_fmaf(fi, c, fr * s);
+  g[0] = __builtin_fmaf(v, a.gsx, g[0]);
+  g[1] = __builtin_fmaf(v, a.gsy, g[1]);
+  g[2] = __builtin_fmaf(v, a.gsz, g[2]);
+  if constexpr (GF) {
+    g[3] = __builtin_fmaf(a.gmag, c, g[3]);
+    g[4] = __builtin_fmaf(a.gmag, s, g[4]);
+  }
+}
+
+// Writes the outputs of one atom from its total sums T[0..NS).
+template <bool GF>
+__device__ __forceinline__ void write_out(float* grad, float* gradf, int64_t j, const float* T) {
+  if (grad) {
+    grad[3 * j] = -kTwoPi * T[0];
+    grad[3 * j + 1] = -kTwoPi * T[1];
+    grad[3 * j + 2] = -kTwoPi * T[2];
+  }
+  if constexpr (GF) {
+    gradf[2 * j] = T[3];          // dL/df = conj(W)
+    gradf[2 * j + 1] = -T[4];
+  }
 }
 
 // Adjoint over points [k_begin + sp*per_split, ...) for Q atoms per lane.
-// Grid: blocks_n * nsplit; blockIdx = sp * blocks_n + nb.
-// part layout: [sp][coordinate][sum | comp][N] floats.
-template <int MODE, int Q, int FK, int GRP, int RED>
+// Grid: blocks_n * nsplit; logical block = sp * blocks_n + nb (XCD-major order).
+// part layout: [sp][sum index][sum | comp][N] floats.
+template <int MODE, int Q, int FK, int GRP, int RED, bool GF>
 __global__ __launch_bounds__(kThreads) void bwd_kernel(
     const typename PointOf<MODE>::type* __restrict__ rec, int k_begin, int k_end, int per_split,
     const float* __restrict__ xyz, const float* __restrict__ f, int64_t N, int blocks_n,
-    float* __restrict__ part, float* __restrict__ grad, int carry_in, int direct) {
+    float* __restrict__ part, float* __restrict__ grad, float* __restrict__ gradf, int carry_in,
+    int direct) {
+  constexpr int NS = NSum<GF>::value;
   using RReg = typename std::conditional<MODE == kPH64, double, float>::type;
   const int lb = xcd_major_block(blockIdx.x, gridDim.x);
   const int nb = lb % blocks_n;
@@ -107,7 +136,7 @@ __global__ __launch_bounds__(kThreads) void bwd_kernel(
 
   RReg x[Q], y[Q], z[Q];
   float fr[Q], fi[Q];
-  float sum[Q][3], cmp[Q][3];
+  float sum[Q][NS], cmp[Q][NS];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int64_t j = j0 + int64_t(q) * kThreads;
@@ -118,10 +147,10 @@ __global__ __launch_bounds__(kThreads) void bwd_kernel(
     fr[q] = (FK && f) ? f[2 * jj] : 1.f;
     fi[q] = (FK && f) ? f[2 * jj + 1] : 0.f;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
+    for (int d = 0; d < NS; ++d) {
       if (carry_in && j < N) {
-        sum[q][d] = part[((int64_t(sp) * 3 + d) * 2 + 0) * N + j];
-        cmp[q][d] = part[((int64_t(sp) * 3 + d) * 2 + 1) * N + j];
+        sum[q][d] = part[((int64_t(sp) * NS + d) * 2 + 0) * N + j];
+        cmp[q][d] = part[((int64_t(sp) * NS + d) * 2 + 1) * N + j];
       } else {
         sum[q][d] = 0.f;
         cmp[q][d] = 0.f;
@@ -146,6 +175,10 @@ __global__ __launch_bounds__(kThreads) void bwd_kernel(
         sum[q][0] = __builtin_fmaf(v, a.sx, sum[q][0]);
         sum[q][1] = __builtin_fmaf(v, a.sy, sum[q][1]);
         sum[q][2] = __builtin_fmaf(v, a.sz, sum[q][2]);
+        if constexpr (GF) {
+          sum[q][3] += __builtin_fmaf(a.gi, s, a.gr * c);
+          sum[q][4] += __builtin_fmaf(-a.gi, c, a.gr * s);
+        }
       }
     }
   } else {
@@ -154,45 +187,37 @@ __global__ __launch_bounds__(kThreads) void bwd_kernel(
     int k = k0;
     while (k < k1) {
       const int kend = (k + GRP <= k1) ? k + GRP : k1;
-      float g[Q][3];
+      float g[Q][NS];
 #pragma unroll
       for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) g[q][d] = 0.f;
+        for (int d = 0; d < NS; ++d) g[q][d] = 0.f;
       if (kend - k == GRP) {
 #pragma unroll
         for (int u = 0; u < GRP; ++u) {
           const PtRegs a = load_point(rec, k + u);
-          const double dv = a.delta;
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
             float c, s;
-            cis_ph64_pt<RED>(a, dv, x[q], y[q], z[q], c, s);
-            const float v = adj_im<FK>(fr[q], fi[q], c, s);
-            g[q][0] = __builtin_fmaf(v, a.gsx, g[q][0]);
-            g[q][1] = __builtin_fmaf(v, a.gsy, g[q][1]);
-            g[q][2] = __builtin_fmaf(v, a.gsz, g[q][2]);
+            cis_ph64_pt<RED>(a, x[q], y[q], z[q], c, s);
+            ph64_pair<FK, GF>(g[q], a, fr[q], fi[q], c, s);
           }
         }
       } else {
         for (int kk = k; kk < kend; ++kk) {
           const PtRegs a = load_point(rec, kk);
-          const double dv = a.delta;
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
             float c, s;
-            cis_ph64_pt<RED>(a, dv, x[q], y[q], z[q], c, s);
-            const float v = adj_im<FK>(fr[q], fi[q], c, s);
-            g[q][0] = __builtin_fmaf(v, a.gsx, g[q][0]);
-            g[q][1] = __builtin_fmaf(v, a.gsy, g[q][1]);
-            g[q][2] = __builtin_fmaf(v, a.gsz, g[q][2]);
+            cis_ph64_pt<RED>(a, x[q], y[q], z[q], c, s);
+            ph64_pair<FK, GF>(g[q], a, fr[q], fi[q], c, s);
           }
         }
       }
 #pragma unroll
       for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) two_sum_acc(sum[q][d], cmp[q][d], SGN * g[q][d]);
+        for (int d = 0; d < NS; ++d) two_sum_acc(sum[q][d], cmp[q][d], SGN * g[q][d]);
       k = kend;
     }
   }
@@ -201,30 +226,35 @@ __global__ __launch_bounds__(kThreads) void bwd_kernel(
   for (int q = 0; q < Q; ++q) {
     const int64_t j = j0 + int64_t(q) * kThreads;
     if (j < N) {
+      if (direct) {
+        float T[NS];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        if (direct) {
-          grad[3 * j + d] = -kTwoPi * (sum[q][d] + cmp[q][d]);
-        } else {
-          part[((int64_t(sp) * 3 + d) * 2 + 0) * N + j] = sum[q][d];
-          part[((int64_t(sp) * 3 + d) * 2 + 1) * N + j] = cmp[q][d];
+        for (int d = 0; d < NS; ++d) T[d] = sum[q][d] + cmp[q][d];
+        write_out<GF>(grad, gradf, j, T);
+      } else {
+#pragma unroll
+        for (int d = 0; d < NS; ++d) {
+          part[((int64_t(sp) * NS + d) * 2 + 0) * N + j] = sum[q][d];
+          part[((int64_t(sp) * NS + d) * 2 + 1) * N + j] = cmp[q][d];
         }
       }
     }
   }
 }
 
-// All-FP64 adjoint.  part layout: [sp][coordinate][N] doubles.
-template <int Q, int FK>
+// All-FP64 adjoint.  part layout: [sp][sum index][N] doubles.
+template <int Q, int FK, bool GF>
 __global__ __launch_bounds__(kThreads) void bwd_f64_kernel(
     const PointF64* __restrict__ rec, int k_begin, int k_end, int per_split,
     const double* __restrict__ xyz, const double* __restrict__ f, int64_t N, int blocks_n,
-    double* __restrict__ part, double* __restrict__ grad, int carry_in, int direct) {
+    double* __restrict__ part, double* __restrict__ grad, double* __restrict__ gradf, int carry_in,
+    int direct) {
+  constexpr int NS = NSum<GF>::value;
   const int lb = xcd_major_block(blockIdx.x, gridDim.x);
   const int nb = lb % blocks_n;
   const int sp = lb / blocks_n;
   const int64_t j0 = int64_t(nb) * (kThreads * Q) + threadIdx.x;
-  double x[Q], y[Q], z[Q], fr[Q], fi[Q], T[Q][3];
+  double x[Q], y[Q], z[Q], fr[Q], fi[Q], T[Q][NS];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int64_t j = j0 + int64_t(q) * kThreads;
@@ -233,8 +263,8 @@ __global__ __launch_bounds__(kThreads) void bwd_f64_kernel(
     fr[q] = (FK && f) ? f[2 * jj] : 1.0;
     fi[q] = (FK && f) ? f[2 * jj + 1] : 0.0;
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
-      T[q][d] = (carry_in && j < N) ? part[(int64_t(sp) * 3 + d) * N + j] : 0.0;
+    for (int d = 0; d < NS; ++d)
+      T[q][d] = (carry_in && j < N) ? part[(int64_t(sp) * NS + d) * N + j] : 0.0;
   }
   const int k0 = k_begin + sp * per_split;
   const int k1 = min(k0 + per_split, k_end);
@@ -246,55 +276,84 @@ __global__ __launch_bounds__(kThreads) void bwd_f64_kernel(
       const double t = ph - __builtin_rint(ph);
       double s, c;
       sincospi(2.0 * t, &s, &c);
-      double v = __builtin_fma(-a.gi, c, a.gr * s);                  // Im conj(G) e^{i theta}
-      if constexpr (FK) v = __builtin_fma(fi[q], __builtin_fma(a.gi, s, a.gr * c), fr[q] * v);
+      const double wre = __builtin_fma(a.gi, s, a.gr * c);      // conj(G) e^{i theta}
+      const double wim = __builtin_fma(-a.gi, c, a.gr * s);
+      double v = wim;
+      if constexpr (FK) v = __builtin_fma(fi[q], wre, fr[q] * wim);
       T[q][0] = __builtin_fma(v, a.sx, T[q][0]);
       T[q][1] = __builtin_fma(v, a.sy, T[q][1]);
       T[q][2] = __builtin_fma(v, a.sz, T[q][2]);
+      if constexpr (GF) {
+        T[q][3] += wre;
+        T[q][4] += wim;
+      }
     }
   }
-  constexpr double kTwoPiD = 6.283185307179586476925286766559;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int64_t j = j0 + int64_t(q) * kThreads;
     if (j < N) {
+      if (direct) {
+        if (grad) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        if (direct) grad[3 * j + d] = -kTwoPiD * T[q][d];
-        else part[(int64_t(sp) * 3 + d) * N + j] = T[q][d];
+          for (int d = 0; d < 3; ++d) grad[3 * j + d] = -kTwoPiD * T[q][d];
+        }
+        if constexpr (GF) {
+          gradf[2 * j] = T[q][3];
+          gradf[2 * j + 1] = -T[q][4];
+        }
+      } else {
+#pragma unroll
+        for (int d = 0; d < NS; ++d) part[(int64_t(sp) * NS + d) * N + j] = T[q][d];
       }
     }
   }
 }
 
-// Combine the split partials of every atom in split order, then grad = -2 pi T.
+// Combine the split partials of every atom in split order (deterministic).
+template <bool GF>
 __global__ __launch_bounds__(kThreads) void bwd_reduce_kernel(const float* __restrict__ part,
                                                               int nsplit, int64_t N,
-                                                              float* __restrict__ grad) {
+                                                              float* __restrict__ grad,
+                                                              float* __restrict__ gradf) {
+  constexpr int NS = NSum<GF>::value;
   const int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x;
   if (j >= N) return;
+  float T[NS];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
+  for (int d = 0; d < NS; ++d) {
     float s = 0.f, cm = 0.f;
     for (int sp = 0; sp < nsplit; ++sp) {
-      two_sum_acc(s, cm, part[((int64_t(sp) * 3 + d) * 2 + 0) * N + j]);
-      cm += part[((int64_t(sp) * 3 + d) * 2 + 1) * N + j];
+      two_sum_acc(s, cm, part[((int64_t(sp) * NS + d) * 2 + 0) * N + j]);
+      cm += part[((int64_t(sp) * NS + d) * 2 + 1) * N + j];
     }
-    grad[3 * j + d] = -kTwoPi * (s + cm);
+    T[d] = s + cm;
   }
+  write_out<GF>(grad, gradf, j, T);
 }
 
+template <bool GF>
 __global__ __launch_bounds__(kThreads) void bwd_reduce_f64_kernel(const double* __restrict__ part,
                                                                   int nsplit, int64_t N,
-                                                                  double* __restrict__ grad) {
+                                                                  double* __restrict__ grad,
+                                                                  double* __restrict__ gradf) {
+  constexpr int NS = NSum<GF>::value;
   const int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x;
   if (j >= N) return;
-  constexpr double kTwoPiD = 6.283185307179586476925286766559;
+  double T[NS];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
+  for (int d = 0; d < NS; ++d) {
     double s = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) s += part[(int64_t(sp) * 3 + d) * N + j];
-    grad[3 * j + d] = -kTwoPiD * s;
+    for (int sp = 0; sp < nsplit; ++sp) s += part[(int64_t(sp) * NS + d) * N + j];
+    T[d] = s;
+  }
+  if (grad) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) grad[3 * j + d] = -kTwoPiD * T[d];
+  }
+  if constexpr (GF) {
+    gradf[2 * j] = T[3];
+    gradf[2 * j + 1] = -T[4];
   }
 }
 
@@ -317,7 +376,7 @@ __global__ __launch_bounds__(kThreads) void pack_points_kernel(const void* __res
       const float* G = static_cast<const float*>(G_v);
       if constexpr (MODE == kPH64) {
         // conj(G) = |G| exp(2 i pi delta): delta = -arg(G) / (2 pi) in FP64 (plus the
-        // reduction offset of the variant), |G| S rounded once to FP32
+        // reduction offset of the variant); |G| S and |G| rounded once to FP32
         PointPH r;
         const double sx = S[3 * k], sy = S[3 * k + 1], sz = S[3 * k + 2];
         const double gr = G[2 * k], gi = G[2 * k + 1];
@@ -327,7 +386,7 @@ __global__ __launch_bounds__(kThreads) void pack_points_kernel(const void* __res
         r.gsx = static_cast<float>(m * sx);
         r.gsy = static_cast<float>(m * sy);
         r.gsz = static_cast<float>(m * sz);
-        r.pad = 0.f;
+        r.gmag = static_cast<float>(m);
         static_cast<PointPH*>(rec_v)[k] = r;
       } else {
         PointF32 r;
@@ -347,61 +406,71 @@ unsigned grid_for(int64_t n) {
   return static_cast<unsigned>(b);
 }
 
-template <int MODE, int Q, int FK>
-hipError_t bwd_dispatch(const Plan& p, const void* rec, int64_t k_begin, int64_t k_end,
-                        int64_t per_split, const void* xyz, const void* f, void* partial,
-                        void* grad, int carry_in, int direct, hipStream_t st) {
+struct BwdArgs {
+  const void* rec; int64_t k_begin, k_end, per_split;
+  const void* xyz; const void* f; void* partial; void* grad; void* gradf;
+  int carry_in, direct;
+};
+
+template <int MODE, int Q, int FK, bool GF>
+hipError_t bwd_dispatch(const Plan& p, const BwdArgs& b, hipStream_t st) {
   using PT = typename PointOf<MODE>::type;
   const dim3 grid(static_cast<unsigned>(p.blocks * p.nsplit));
-  const auto* r = static_cast<const PT*>(rec);
-  const auto* x = static_cast<const float*>(xyz);
-  const auto* ff = static_cast<const float*>(f);
-  auto* pa = static_cast<float*>(partial);
-  auto* g = static_cast<float*>(grad);
+  const auto* r = static_cast<const PT*>(b.rec);
+  const auto* x = static_cast<const float*>(b.xyz);
+  const auto* ff = static_cast<const float*>(b.f);
+  auto* pa = static_cast<float*>(b.partial);
+  auto* g = static_cast<float*>(b.grad);
+  auto* gf = static_cast<float*>(b.gradf);
+  const int k0 = int(b.k_begin), k1 = int(b.k_end), per = int(b.per_split), nblk = int(p.blocks);
   if constexpr (MODE == kF32) {
-    bwd_kernel<MODE, Q, FK, 16, 0><<<grid, kThreads, 0, st>>>(
-        r, int(k_begin), int(k_end), int(per_split), x, ff, p.lanes, int(p.blocks), pa, g, carry_in, direct);
+    bwd_kernel<MODE, Q, FK, 16, 0, GF><<<grid, kThreads, 0, st>>>(
+        r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);
   } else {
     if (p.grp == 16 && p.red == 0)
-      bwd_kernel<MODE, Q, FK, 16, 0><<<grid, kThreads, 0, st>>>(
-          r, int(k_begin), int(k_end), int(per_split), x, ff, p.lanes, int(p.blocks), pa, g, carry_in, direct);
+      bwd_kernel<MODE, Q, FK, 16, 0, GF><<<grid, kThreads, 0, st>>>(
+          r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);
     else if (p.grp == 16)
-      bwd_kernel<MODE, Q, FK, 16, 1><<<grid, kThreads, 0, st>>>(
-          r, int(k_begin), int(k_end), int(per_split), x, ff, p.lanes, int(p.blocks), pa, g, carry_in, direct);
+      bwd_kernel<MODE, Q, FK, 16, 1, GF><<<grid, kThreads, 0, st>>>(
+          r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);
     else if (p.red == 0)
-      bwd_kernel<MODE, Q, FK, 32, 0><<<grid, kThreads, 0, st>>>(
-          r, int(k_begin), int(k_end), int(per_split), x, ff, p.lanes, int(p.blocks), pa, g, carry_in, direct);
+      bwd_kernel<MODE, Q, FK, 32, 0, GF><<<grid, kThreads, 0, st>>>(
+          r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);
     else
-      bwd_kernel<MODE, Q, FK, 32, 1><<<grid, kThreads, 0, st>>>(
-          r, int(k_begin), int(k_end), int(per_split), x, ff, p.lanes, int(p.blocks), pa, g, carry_in, direct);
+      bwd_kernel<MODE, Q, FK, 32, 1, GF><<<grid, kThreads, 0, st>>>(
+          r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);
   }
   return hipGetLastError();
 }
 
-template <int MODE>
-hipError_t bwd_dispatch_q(const Plan& p, const void* rec, int64_t k_begin, int64_t k_end,
-                          int64_t per_split, const void* xyz, const void* f, void* partial,
-                          void* grad, int carry_in, int direct, hipStream_t st) {
-  if (p.per_lane == 4)
-    return p.fk ? bwd_dispatch<MODE, 4, 1>(p, rec, k_begin, k_end, per_split, xyz, f, partial, grad, carry_in, direct, st)
-                : bwd_dispatch<MODE, 4, 0>(p, rec, k_begin, k_end, per_split, xyz, f, partial, grad, carry_in, direct, st);
-  if (p.per_lane == 2)
-    return p.fk ? bwd_dispatch<MODE, 2, 1>(p, rec, k_begin, k_end, per_split, xyz, f, partial, grad, carry_in, direct, st)
-                : bwd_dispatch<MODE, 2, 0>(p, rec, k_begin, k_end, per_split, xyz, f, partial, grad, carry_in, direct, st);
-  return p.fk ? bwd_dispatch<MODE, 1, 1>(p, rec, k_begin, k_end, per_split, xyz, f, partial, grad, carry_in, direct, st)
-              : bwd_dispatch<MODE, 1, 0>(p, rec, k_begin, k_end, per_split, xyz, f, partial, grad, carry_in, direct, st);
+template <int MODE, int Q, bool GF>
+hipError_t bwd_dispatch_fk(const Plan& p, const BwdArgs& b, hipStream_t st) {
+  return p.fk ? bwd_dispatch<MODE, Q, 1, GF>(p, b, st) : bwd_dispatch<MODE, Q, 0, GF>(p, b, st);
 }
 
-template <int Q, int FK>
-hipError_t bwd_f64_launch(const Plan& p, const void* rec, int64_t k_begin, int64_t k_end,
-                          int64_t per_split, const void* xyz, const void* f, void* partial,
-                          void* grad, int carry_in, int direct, hipStream_t st) {
+template <int MODE, bool GF>
+hipError_t bwd_dispatch_q(const Plan& p, const BwdArgs& b, hipStream_t st) {
+  if (p.per_lane == 4) return bwd_dispatch_fk<MODE, 4, GF>(p, b, st);
+  if (p.per_lane == 2) return bwd_dispatch_fk<MODE, 2, GF>(p, b, st);
+  return bwd_dispatch_fk<MODE, 1, GF>(p, b, st);
+}
+
+template <int Q, int FK, bool GF>
+hipError_t bwd_f64_launch(const Plan& p, const BwdArgs& b, hipStream_t st) {
   const dim3 grid(static_cast<unsigned>(p.blocks * p.nsplit));
-  bwd_f64_kernel<Q, FK><<<grid, kThreads, 0, st>>>(
-      static_cast<const PointF64*>(rec), int(k_begin), int(k_end), int(per_split),
-      static_cast<const double*>(xyz), static_cast<const double*>(f), p.lanes, int(p.blocks),
-      static_cast<double*>(partial), static_cast<double*>(grad), carry_in, direct);
+  bwd_f64_kernel<Q, FK, GF><<<grid, kThreads, 0, st>>>(
+      static_cast<const PointF64*>(b.rec), int(b.k_begin), int(b.k_end), int(b.per_split),
+      static_cast<const double*>(b.xyz), static_cast<const double*>(b.f), p.lanes, int(p.blocks),
+      static_cast<double*>(b.partial), static_cast<double*>(b.grad), static_cast<double*>(b.gradf),
+      b.carry_in, b.direct);
   return hipGetLastError();
+}
+
+template <bool GF>
+hipError_t bwd_f64_dispatch(const Plan& p, const BwdArgs& b, hipStream_t st) {
+  if (p.per_lane == 2)
+    return p.fk ? bwd_f64_launch<2, 1, GF>(p, b, st) : bwd_f64_launch<2, 0, GF>(p, b, st);
+  return p.fk ? bwd_f64_launch<1, 1, GF>(p, b, st) : bwd_f64_launch<1, 0, GF>(p, b, st);
 }
 
 }  // namespace
@@ -419,29 +488,32 @@ hipError_t launch_pack_points(int mode, int red, const void* S, const void* G, i
 
 hipError_t launch_bwd_chunk(const Plan& p, const void* rec, int64_t k_begin, int64_t k_end,
                             int64_t per_split, const void* xyz, const void* f, void* partial,
-                            void* grad, int carry_in, int direct, hipStream_t st) {
-  if (p.mode == kF64) {
-    if (p.per_lane == 2)
-      return p.fk ? bwd_f64_launch<2, 1>(p, rec, k_begin, k_end, per_split, xyz, f, partial, grad, carry_in, direct, st)
-                  : bwd_f64_launch<2, 0>(p, rec, k_begin, k_end, per_split, xyz, f, partial, grad, carry_in, direct, st);
-    return p.fk ? bwd_f64_launch<1, 1>(p, rec, k_begin, k_end, per_split, xyz, f, partial, grad, carry_in, direct, st)
-                : bwd_f64_launch<1, 0>(p, rec, k_begin, k_end, per_split, xyz, f, partial, grad, carry_in, direct, st);
-  }
-  if (p.mode == kPH64)
-    return bwd_dispatch_q<kPH64>(p, rec, k_begin, k_end, per_split, xyz, f, partial, grad, carry_in, direct, st);
-  return bwd_dispatch_q<kF32>(p, rec, k_begin, k_end, per_split, xyz, f, partial, grad, carry_in, direct, st);
+                            void* grad, void* gradf, int carry_in, int direct, hipStream_t st) {
+  const BwdArgs b{rec, k_begin, k_end, per_split, xyz, f, partial, grad, gradf, carry_in, direct};
+  if (p.mode == kF64) return p.gf ? bwd_f64_dispatch<true>(p, b, st) : bwd_f64_dispatch<false>(p, b, st);
+  if (p.mode == kPH64) return p.gf ? bwd_dispatch_q<kPH64, true>(p, b, st) : bwd_dispatch_q<kPH64, false>(p, b, st);
+  return p.gf ? bwd_dispatch_q<kF32, true>(p, b, st) : bwd_dispatch_q<kF32, false>(p, b, st);
 }
 
-hipError_t launch_bwd_reduce(const Plan& p, const void* partial, const void* /*f*/, void* grad,
+hipError_t launch_bwd_reduce(const Plan& p, const void* partial, void* grad, void* gradf,
                              hipStream_t st) {
   const int64_t N = p.lanes;
   const unsigned g = static_cast<unsigned>((N + kThreads - 1) / kThreads);
-  if (p.mode == kF64)
-    bwd_reduce_f64_kernel<<<g, kThreads, 0, st>>>(static_cast<const double*>(partial), p.nsplit, N,
-                                                 static_cast<double*>(grad));
-  else
-    bwd_reduce_kernel<<<g, kThreads, 0, st>>>(static_cast<const float*>(partial), p.nsplit, N,
-                                             static_cast<float*>(grad));
+  if (p.mode == kF64) {
+    if (p.gf)
+      bwd_reduce_f64_kernel<true><<<g, kThreads, 0, st>>>(static_cast<const double*>(partial), p.nsplit, N,
+                                                         static_cast<double*>(grad), static_cast<double*>(gradf));
+    else
+      bwd_reduce_f64_kernel<false><<<g, kThreads, 0, st>>>(static_cast<const double*>(partial), p.nsplit, N,
+                                                          static_cast<double*>(grad), static_cast<double*>(gradf));
+  } else {
+    if (p.gf)
+      bwd_reduce_kernel<true><<<g, kThreads, 0, st>>>(static_cast<const float*>(partial), p.nsplit, N,
+                                                     static_cast<float*>(grad), static_cast<float*>(gradf));
+    else
+      bwd_reduce_kernel<false><<<g, kThreads, 0, st>>>(static_cast<const float*>(partial), p.nsplit, N,
+                                                      static_cast<float*>(grad), static_cast<float*>(gradf));
+  }
   return hipGetLastError();
 }
 

@@ -28,11 +28,11 @@ struct alignas(16) AtomF64 { double x, y, z, fr, fi, pad; };                    
 // Point for the FP32-mode adjoint: S and the seed G.
 struct alignas(16) PointF32 { float sx, sy, sz, gr, gi, pad0, pad1, pad2; };         // 32 B
 // Point for the FP64-phase adjoint, with the seed in polar form conj(G) =
-// |G| exp(-2 i pi gamma): S (FP64) and delta = -gamma (cycles, FP64, plus the reduction
-// offset of the variant) for the phase in the first 32 bytes, |G| S (FP32) for the
-// multiply-add into the per-atom sums in the last 16; one 8-dword and one 4-dword
+// |G| exp(2 i pi delta): S (FP64) and delta (cycles, FP64, plus the reduction offset of
+// the variant) for the phase in the first 32 bytes, |G| S and |G| (FP32) for the
+// multiply-adds into the per-atom sums in the last 16; one 8-dword and one 4-dword
 // scalar load per record.
-struct alignas(16) PointPH { double sx, sy, sz, delta; float gsx, gsy, gsz, pad; };  // 48 B
+struct alignas(16) PointPH { double sx, sy, sz, delta; float gsx, gsy, gsz, gmag; }; // 48 B
 // Point for the all-FP64 adjoint.
 struct alignas(16) PointF64 { double sx, sy, sz, gr, gi, pad; };                     // 48 B
 
@@ -68,6 +68,7 @@ struct Plan {
   int grp = 16;          // stream items per compensated group
   int fk = 0;            // 0: f_j = 1, 1: complex f_j
   int red = 0;           // phase reduction variant of the FP64-phase kernels (0 centred, 1 fract)
+  int gf = 0;            // adjoint also returns dL/df
   int64_t lanes = 0;     // number of lane items
   int64_t stream = 0;    // number of stream items
   int64_t blocks = 0;    // work-groups over lane items
@@ -86,7 +87,10 @@ constexpr int64_t kMaxSplit = 1024;
 constexpr int64_t kLaunchPairs = int64_t(1) << 39;   // pairs per launch (well under 1 s)
 constexpr int kLossBlocks = 1024;             // fixed grid of the loss reduction
 
-enum Op : int { kOpFwd = 0, kOpBwd = 1, kOpFwdF64 = 2, kOpBwdF64 = 3, kOpLoss = 4 };
+enum Op : int { kOpFwd = 0, kOpBwd = 1, kOpFwdF64 = 2, kOpBwdF64 = 3, kOpLoss = 4,
+                kOpBwdGf = 5, kOpBwdGfF64 = 6 };
+
+constexpr int kMaxSpecies = 16;   // species of the factorised entry points
 
 // Builds the plan of (op, mode) for the sizes; pure host code, no HIP call.
 Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_null);
@@ -108,12 +112,29 @@ hipError_t launch_fwd_chunk(const Plan& p, const void* rec, int64_t a_begin, int
 // Combine split partials into A.
 hipError_t launch_fwd_reduce(const Plan& p, const void* partial, void* A, hipStream_t st);
 
-// One adjoint chunk over atoms (lane items) for points [k_begin, k_end).
+// One adjoint chunk over atoms (lane items) for points [k_begin, k_end); grad and
+// gradf (only with p.gf) receive the outputs of the last chunk when `direct`.
 hipError_t launch_bwd_chunk(const Plan& p, const void* rec, int64_t k_begin, int64_t k_end,
                             int64_t per_split, const void* xyz, const void* f, void* partial,
-                            void* grad, int carry_in, int direct, hipStream_t st);
-hipError_t launch_bwd_reduce(const Plan& p, const void* partial, const void* f, void* grad,
+                            void* grad, void* gradf, int carry_in, int direct, hipStream_t st);
+hipError_t launch_bwd_reduce(const Plan& p, const void* partial, void* grad, void* gradf,
                              hipStream_t st);
+
+// Species-factorised forward: A_k = sum_s fs[s][k] * sum_sp state_s[sp][k] (FP64
+// combination of the per-species (sum, comp) states), optionally the per-species sums.
+struct SpeciesStates {
+  const void* state[kMaxSpecies];   // float4 [nsplit][K] per species
+  int nsplit[kMaxSpecies];
+  int n;
+};
+hipError_t launch_species_combine(const SpeciesStates& ss, const float* fs, int64_t k, float* A,
+                                  float* A_species, hipStream_t st);
+// seed_s = G * conj(fs_s) (or G when fs_s is NULL), formed in FP64, rounded once.
+hipError_t launch_species_seed(const float* G, const float* fs_s, int64_t k, float* seed,
+                               hipStream_t st);
+// grad_fs_s = G * conj(A_s) (the gradient of L with respect to the factor fs_s).
+hipError_t launch_species_gradf(const float* G, const float* A_s, int64_t k, float* grad_fs_s,
+                                hipStream_t st);
 
 hipError_t launch_loss(const float* A, const float* I, int64_t k, double* L, float* G,
                        double* partial, hipStream_t st);

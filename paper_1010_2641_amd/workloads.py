@@ -256,3 +256,34 @@ def chain(n_atoms: int, sigma: float = 0.0, seed: int = 7, h_step: float = 0.001
     S = np.zeros((h.size, 3))
     S[:, 0] = h
     return _f32(p), _f32(S)
+
+
+# ----------------------------------------------------------------------------- species inputs
+
+def group_by_species(xyz: np.ndarray, f: np.ndarray):
+    """Reorder the atoms species by species (stable within a species) for the
+    species-factorised sum of Section 4.2.  Returns (xyz reordered, species_start
+    list of n_species + 1 offsets, the distinct factors in species order, the
+    permutation applied)."""
+    vals, inv = np.unique(np.asarray(f), return_inverse=True)
+    order = np.argsort(inv, kind="stable")
+    counts = np.bincount(inv, minlength=len(vals))
+    start = [0] + np.cumsum(counts).astype(int).tolist()
+    return np.ascontiguousarray(xyz[order]), start, vals.astype(np.complex64), order
+
+
+def species_factor_table(S: np.ndarray, f_species, b_iso=(1.2, 0.6), anomalous=None) -> np.ndarray:
+    """S-dependent species factors fs[s, k] = Re(f_s) exp(-b_s |S|^2 / 4) + i Im(f_s)
+    (+ an optional per-species anomalous complex term): a Debye-Waller-like decay of the
+    normal part with |S| standing in for the tabulated f0(|S|) the paper folds out of
+    the sum, and an S-independent resonant part.  complex64 (n_species, K)."""
+    S = np.asarray(S, dtype=np.float64)
+    s2 = np.sum(S * S, axis=1)
+    rows = []
+    for s, fv in enumerate(f_species):
+        b = b_iso[s % len(b_iso)]
+        row = np.real(fv) * np.exp(-b * s2 / 4.0) + 1j * np.imag(fv)
+        if anomalous is not None:
+            row = row + anomalous[s]
+        rows.append(row)
+    return np.asarray(rows).astype(np.complex64)

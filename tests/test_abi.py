@@ -32,7 +32,7 @@ def test_header_symbols_exported():
 
 
 def test_version():
-    assert _lib.nx_version() == 100
+    assert _lib.nx_version() == 101
 
 
 def fwd(n_atoms=8, n_points=8, xyz=FAKE, f=None, S=FAKE, A=FAKE, mode=1, ws=FAKE, wsb=1 << 40):
@@ -129,3 +129,63 @@ def test_python_wrappers_refuse_cpu_tensors():
 def test_single_hip_runtime():
     """libnx must bind to the HIP runtime torch brought in, never a second copy."""
     assert len(_lib._hip_runtimes()) == 1
+
+
+def starts(*v):
+    return (ctypes.c_int64 * len(v))(*v)
+
+
+def fwd_sp(start, ns, n_atoms=8, n_points=8, xyz=FAKE, fs=None, S=FAKE, A=FAKE, As=None, mode=1,
+           ws=FAKE, wsb=1 << 40):
+    return _lib.nx_scatter_fwd_species(xyz, n_atoms, start, ns, fs, S, n_points, A, As, mode, ws, wsb,
+                                       None)
+
+
+def test_species_partition_checks():
+    assert fwd_sp(starts(0, 3, 8), 2, wsb=0) == _lib.NX_ERR_WORKSPACE   # valid partition
+    assert fwd_sp(None, 2) == _lib.NX_ERR_ARG
+    assert "species_start" in _lib.last_error()
+    assert fwd_sp(starts(1, 3, 8), 2) == _lib.NX_ERR_ARG           # must start at 0
+    assert fwd_sp(starts(0, 3, 7), 2) == _lib.NX_ERR_ARG           # must end at n_atoms
+    assert fwd_sp(starts(0, 5, 3, 8), 3) == _lib.NX_ERR_ARG        # decreasing
+    assert "decreases" in _lib.last_error()
+    assert fwd_sp(starts(0, 8), 0) == _lib.NX_ERR_ARG
+    assert fwd_sp(starts(*range(0, 18)), 17, n_atoms=17) == _lib.NX_ERR_ARG
+    assert "n_species" in _lib.last_error()
+    assert fwd_sp(starts(0, 8), 1, mode=5) == _lib.NX_ERR_MODE
+    g = _lib.nx_scatter_bwd_species
+    assert g(FAKE, 8, starts(0, 9), 1, None, FAKE, 8, FAKE, None, FAKE, None, 1, FAKE, 1 << 40,
+             None) == _lib.NX_ERR_ARG
+    # the factor gradient needs the per-species sums
+    assert g(FAKE, 8, starts(0, 8), 1, None, FAKE, 8, FAKE, None, None, FAKE, 1, FAKE, 1 << 40,
+             None) == _lib.NX_ERR_ARG
+    assert "A_species" in _lib.last_error()
+    # neither gradient asked for: nothing to do
+    assert g(FAKE, 8, starts(0, 8), 1, None, FAKE, 8, FAKE, None, None, None, 1, None, 0,
+             None) == _lib.NX_OK
+
+
+def test_species_workspace():
+    ws1 = _lib.nx_workspace_bytes_species(starts(0, 100_000, 203_557), 2, 2_097_152, 1, 0)
+    # all atom records, then one (sum, comp) state of 16 bytes per point and species
+    assert ws1 >= 203_557 * 32 + 2 * 2_097_152 * 16
+    ws0 = _lib.nx_workspace_bytes_species(starts(0, 100_000, 203_557), 2, 2_097_152, 1, 1)
+    assert ws0 >= 2_097_152 * (8 + 48)       # per-species seed and the point records
+    assert _lib.nx_workspace_bytes_species(starts(0, 4), 1, 8, 1, 2) == 0
+    assert "op" in _lib.last_error()
+    assert _lib.nx_workspace_bytes_species(starts(0, 4), 1, 8, 9, 0) == 0
+    assert "mode" in _lib.last_error()
+    assert fwd_sp(starts(0, 4096), 1, n_atoms=4096, n_points=4096, wsb=100) == _lib.NX_ERR_WORKSPACE
+
+
+def test_species_and_factor_gradient_empty_calls():
+    assert fwd_sp(starts(0, 8), 1, n_points=0, xyz=None, S=None, A=None, ws=None, wsb=0) == _lib.NX_OK
+    assert _lib.nx_scatter_bwd_ex(None, None, 0, None, 5, None, None, FAKE, 1, None, 0, None) == _lib.NX_OK
+    assert _lib.nx_scatter_bwd_ex(FAKE, None, 4, FAKE, 5, FAKE, None, FAKE + 4, 1, FAKE, 1 << 40,
+                                  None) == _lib.NX_ERR_ARG
+    assert _lib.nx_scatter_bwd_ex(FAKE, None, 4, FAKE, 5, FAKE, None, FAKE, 6, FAKE, 1 << 40,
+                                  None) == _lib.NX_ERR_MODE
+    need = _lib.nx_workspace_bytes(1000, 1000, 1, _lib.NX_OP_BWD_GF, 0)
+    assert need > _lib.nx_workspace_bytes(1000, 1000, 1, _lib.NX_OP_BWD, 0)   # two more sums
+    assert _lib.nx_scatter_bwd_ex(FAKE, FAKE, 1000, FAKE, 1000, FAKE, FAKE, FAKE, 1, FAKE, need - 1,
+                                  None) == _lib.NX_ERR_WORKSPACE

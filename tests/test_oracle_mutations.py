@@ -28,6 +28,9 @@ MUTATIONS = {
     "adjoint_sign_2pi": ("double qr = -2.0 * M_PI * pi_;", "double qr = 2.0 * M_PI * pi_;"),
     "adjoint_wrong_index": ("gy += zr * sy;", "gy += zr * sx;"),
     "adjoint_phase_sign": ("double zr = qr * c - qi * s;", "double zr = qr * c + qi * s;"),
+    "adjoint_f_no_conj_G": ("double gr = G[2 * k], gi = -G[2 * k + 1];      /* conj(G_k) */",
+                            "double gr = G[2 * k], gi = G[2 * k + 1];      /* conj(G_k) */"),
+    "adjoint_f_sign": ("gradf[2 * j + 1] = -wi;", "gradf[2 * j + 1] = wi;"),
     "adjoint_ignores_f": ("double pr = gr * fr - gi * fi;\n            double pi_ = gr * fi + gi * fr;",
                           "double pr = gr;\n            double pi_ = gi;"),
 }

@@ -291,11 +291,96 @@ def test_paper_flop_model():
     assert n == pytest.approx(g["n_flop"], rel=g["rel_tol"])
 
 
+# ----------------------------------------------------------------------------- the factor gradient
+
+def pin_adjoint_f_matches_finite_differences(orc):
+    """dL/dRe f_j + i dL/dIm f_j from the adjoint equals central differences of the FP64
+    loss in the real and imaginary part of f_j (pins the conjugation convention)."""
+    rng = np.random.default_rng(31)
+    xyz, f, S = wl.random_problem(20, 40, seed=31, extent=8.0, s_range=1.5)
+    f = f.astype(np.complex128)
+    I = rng.uniform(0, 30, size=40)
+    _, G = orc.loss(orc.forward(xyz, f, S), I)
+    gf = orc.adjoint_f(xyz, S, G)
+    h = 1e-6
+    for j in (0, 9, 19):
+        for unit in (1.0, 1j):
+            fp, fm = f.copy(), f.copy()
+            fp[j] += h * unit
+            fm[j] -= h * unit
+            d = (orc.loss(orc.forward(xyz, fp, S), I)[0] - orc.loss(orc.forward(xyz, fm, S), I)[0]) / (2 * h)
+            g = gf[j].real if unit == 1.0 else gf[j].imag
+            assert d == pytest.approx(g, rel=1e-6, abs=1e-6 * np.max(np.abs(gf)))
+
+
+def pin_adjoint_f_one_atom_closed_form(orc):
+    """One atom at r with factor f: A_k = f e_k, so with L = sum (|A|^2 - I)^2 and
+    G = 4 e A, dL/df = sum_k G_k conj(e_k) = 4 f sum_k (|f|^2 - I_k)."""
+    rng = np.random.default_rng(32)
+    r = rng.uniform(-3, 3, size=(1, 3))
+    f = np.array([1.2 - 0.7j])
+    S = rng.uniform(-2, 2, size=(30, 3))
+    I = rng.uniform(0, 4, size=30)
+    _, G = orc.loss(orc.forward(r, f, S), I)
+    gf = orc.adjoint_f(r, S, G)
+    ref = 4 * f[0] * np.sum(abs(f[0]) ** 2 - I)
+    assert abs(gf[0] - ref) <= 1e-12 * abs(ref)
+
+
 # ----------------------------------------------------------------------------- the pins as tests
 
-PINS = [pin_laue_block_closed_form, pin_fft_special_case, pin_bragg_nodes_and_fcc_extinction, pin_friedel_symmetry, pin_translation_phase_factor, pin_superposition_and_linearity, pin_empty_inputs, pin_precision_bound_mpmath, pin_paper_chain_formula, pin_paper_cube_bragg_node, pin_loss_worked_values, pin_loss_seed_is_gradient, pin_adjoint_matches_finite_differences, pin_adjoint_two_atom_closed_form, pin_adjoint_translation_invariance_and_dot_test, pin_adjoint_empty]
+PINS = [pin_laue_block_closed_form, pin_fft_special_case, pin_bragg_nodes_and_fcc_extinction, pin_friedel_symmetry, pin_translation_phase_factor, pin_superposition_and_linearity, pin_empty_inputs, pin_precision_bound_mpmath, pin_paper_chain_formula, pin_paper_cube_bragg_node, pin_loss_worked_values, pin_loss_seed_is_gradient, pin_adjoint_matches_finite_differences, pin_adjoint_two_atom_closed_form, pin_adjoint_translation_invariance_and_dot_test, pin_adjoint_empty,
+        pin_adjoint_f_matches_finite_differences, pin_adjoint_f_one_atom_closed_form]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=[p.__name__[4:] for p in PINS])
 def test_oracle_pin(pin):
     pin(oracle)
+
+
+def test_species_composition_equals_per_atom_factors():
+    """The species-factorised sum with S-independent factors equals Eq. 2 with the
+    factor of each atom's species (linearity of the sum)."""
+    xyz, _, S = wl.random_problem(60, 35, seed=33, complex_f=False)
+    start = [0, 25, 25, 60]                       # an empty species in the middle
+    fsp = np.array([1.5 - 0.2j, 9.0 + 1.0j, -0.3 + 2.0j])
+    fs = np.repeat(fsp[:, None], 35, axis=1)
+    A, As = oracle.forward_species(xyz, start, fs, S)
+    f_atom = np.concatenate([np.full(start[s + 1] - start[s], fsp[s]) for s in range(3)])
+    ref = oracle.forward(xyz, f_atom, S)
+    assert np.max(np.abs(A - ref)) <= 1e-12 * np.sum(np.abs(f_atom))
+    assert np.all(As[1] == 0)
+
+
+def test_species_adjoint_matches_finite_differences():
+    """The species adjoint (positions, and the factor of species s at point k) against
+    central differences of the FP64 loss through the species-factorised forward, with
+    S-dependent factors."""
+    rng = np.random.default_rng(34)
+    xyz, _, S = wl.random_problem(30, 24, seed=34, extent=6.0, s_range=1.2, complex_f=False)
+    start = [0, 12, 30]
+    fs = wl.species_factor_table(S, [complex(3.0, 0.5), complex(1.5, -0.2)]).astype(np.complex128)
+    I = rng.uniform(0, 200, size=24)
+    xyz = xyz.astype(np.float64)
+
+    def L(x, f):
+        return oracle.loss(oracle.forward_species(x, start, f, S)[0], I)[0]
+
+    A, As = oracle.forward_species(xyz, start, fs, S)
+    _, G = oracle.loss(A, I)
+    g, gfs = oracle.adjoint_species(xyz, start, fs, S, G, As)
+    h = 1e-6
+    for j, d in ((0, 0), (11, 2), (12, 1), (29, 2)):
+        xp, xm = xyz.copy(), xyz.copy()
+        xp[j, d] += h
+        xm[j, d] -= h
+        fd = (L(xp, fs) - L(xm, fs)) / (2 * h)
+        assert fd == pytest.approx(g[j, d], rel=1e-5, abs=1e-6 * np.max(np.abs(g)))
+    for s, k in ((0, 0), (1, 7), (0, 23)):
+        for unit in (1.0, 1j):
+            fp, fm = fs.copy(), fs.copy()
+            fp[s, k] += h * unit
+            fm[s, k] -= h * unit
+            fd = (L(xyz, fp) - L(xyz, fm)) / (2 * h)
+            ref = gfs[s, k].real if unit == 1.0 else gfs[s, k].imag
+            assert fd == pytest.approx(ref, rel=1e-5, abs=1e-6 * np.max(np.abs(gfs)))
