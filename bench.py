@@ -72,7 +72,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    p.add_argument("--workload", default="c2",
+                   choices=["c1", "c2", "c3", "c4", "c5", "ewald", "cube41", "cube41s"])
     p.add_argument("--mode", default="ph64", choices=["ph64", "f32"])
     p.add_argument("--no-f64", action="store_true", help="skip the all-FP64 comparison")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -339,6 +340,11 @@ def main():
                 "c3": "100^3 simple-cubic crystal, disorder 0.01, 256^2 map near (8,8,8)",
                 "c4": "29^3-cell fcc cube, sinusoidal displacement, 64^3 grid around (2,2,0)",
                 "c5": "strained fcc nanowire, 4,013,800 atoms, 2 species, 256^3 grid at (0,0,4)",
+                "ewald": "the c2 dot on 2,097,152 area-detector points on Ewald's sphere "
+                         "(128^2 pixels x 128 rocking frames around (4,0,4)), fit step vs strain "
+                         "x1.1 target",
+                "cube41": "Section 4.1 cube, 1e6 atoms, 200x200 map around (004)",
+                "cube41s": "Section 4.1 strained cube, 1e6 atoms, 200x200 map around (004)",
             }[args.workload],
             "n_atoms": n, "n_points": k, "pairs_per_step": pairs,
             "precision": {"ph64": "FP64 phase reduction, FP32 sin/cos, compensated FP32 sums",

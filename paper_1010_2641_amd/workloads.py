@@ -202,7 +202,97 @@ def c5(seed: int = 1005, n_grid: int = 256) -> Workload:
     return Workload("c5", _f32(p), f, _f32(S), target_xyz=_f32(pt), meta=dict(seed=seed))
 
 
-NAMED = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
+# ----------------------------------------------------------------------------- unstructured points
+
+GE_A = 5.658            # Ge lattice constant (angstrom): converts r.l.u. to 1/angstrom
+HC_KEV_A = 12.39842     # h c in keV.angstrom: wavelength = HC_KEV_A / energy
+
+
+def _rotate(v, axis, angle):
+    """Rodrigues rotation of the rows of v about the unit vector axis."""
+    c, s = np.cos(angle), np.sin(angle)
+    return v * c + np.cross(axis, v) * s + np.outer(v @ axis, axis) * (1.0 - c)
+
+
+def ewald_geometry(hkl, a=GE_A, energy_kev=8.0):
+    """Symmetric Bragg geometry for node hkl of a cubic crystal with lattice constant a:
+    returns (wavelength, unit incident direction, unit exit direction, unit normal of
+    the scattering plane), all in the crystal frame, with k_f - k_i = hkl / a (in
+    1/angstrom, crystallographic convention, no 2 pi)."""
+    G = np.asarray(hkl, dtype=np.float64) / a
+    lam = HC_KEV_A / energy_kev
+    sin_t = 0.5 * lam * np.linalg.norm(G)
+    if not 0.0 < sin_t < 1.0:
+        raise ValueError(f"node {hkl} is not reachable at {energy_kev} keV")
+    cos_t = np.sqrt(1.0 - sin_t * sin_t)
+    g = G / np.linalg.norm(G)
+    ref = np.array([0.0, 1.0, 0.0]) if abs(g[1]) < 0.9 else np.array([1.0, 0.0, 0.0])
+    n = ref - (ref @ g) * g
+    n /= np.linalg.norm(n)
+    ki = -sin_t * g + cos_t * n
+    kf = sin_t * g + cos_t * n
+    normal = np.cross(ki, kf)
+    normal /= np.linalg.norm(normal)
+    return lam, ki, kf, normal
+
+
+def ewald_scan(hkl, a=GE_A, energy_kev=8.0, distance=0.5, pitch=55e-6, n_pix=(128, 128),
+               n_frames=128, rock_deg=0.5) -> np.ndarray:
+    """The reciprocal-space points (r.l.u., float64 (K, 3)) recorded by a flat 2D detector
+    during a rocking scan about node hkl: the detector (n_pix pixels of size `pitch`, at
+    `distance` metres, centred on the exit beam of the Bragg condition) measures points on
+    Ewald's sphere, S = (k_hat - k_i_hat) / wavelength; rocking the crystal by omega about
+    the normal of the scattering plane rotates that curved sheet in the crystal frame.
+    n_frames = 1 gives one detector frame (no rotation).  Points are listed frame by
+    frame, detector rows, then columns fastest.  Neither a frame nor the scan is a grid
+    of the reciprocal lattice: this is the unstructured point set that motivates the
+    direct sum (Section 1)."""
+    lam, ki, kf, normal = ewald_geometry(hkl, a, energy_kev)
+    e1 = np.cross(normal, kf)                   # in the scattering plane, across the beam
+    e2 = normal
+    n1, n2 = n_pix
+    u = (np.arange(n1) - 0.5 * (n1 - 1)) * pitch
+    v = (np.arange(n2) - 0.5 * (n2 - 1)) * pitch
+    U, V = np.meshgrid(u, v, indexing="ij")
+    p = distance * kf[None, :] + U.reshape(-1, 1) * e1[None, :] + V.reshape(-1, 1) * e2[None, :]
+    k_hat = p / np.linalg.norm(p, axis=1, keepdims=True)
+    frame = (k_hat - ki[None, :]) / lam * a                 # r.l.u.
+    if n_frames == 1:
+        return frame
+    omegas = np.deg2rad(np.linspace(-rock_deg, rock_deg, n_frames))
+    return np.concatenate([_rotate(frame, normal, w) for w in omegas])
+
+
+def ewald(seed: int = 1002, n_pix: int = 128, n_frames: int = 128) -> Workload:
+    """The C2 dot measured as an area detector records it: 8 keV, detector at 0.5 m with
+    55 um pixels (128 x 128) centred on the (4,0,4) exit beam, 128 frames over a
+    +-0.5 degree rocking scan: 2,097,152 points on curved sheets spanning about the C2
+    window.  Atoms, factors and the fit target are those of C2."""
+    w = c2(seed)
+    S = ewald_scan((4.0, 0.0, 4.0), n_pix=(n_pix, n_pix), n_frames=n_frames)
+    return Workload("ewald", w.xyz, w.f, _f32(S), target_xyz=w.target_xyz,
+                    meta=dict(seed=seed, detector=dict(n_pix=n_pix, n_frames=n_frames)))
+
+
+def cube41(strained: bool = False) -> Workload:
+    """The Section 4.1 example: 100 x 100 x 100 simple-cubic cells, x, y in [-50, 50),
+    z in [0, 100), f = 1, on the 200 x 200 map h in [-0.1, 0.1), k = 0, l in [3.9, 4.1)
+    with 0.001 steps (40,000 points around (004)); strained: z += 1e-6 z (x^2 + y^2)."""
+    x = np.arange(-50, 50, dtype=np.float32).astype(np.float64)
+    z = np.arange(0, 100, dtype=np.float32).astype(np.float64)
+    X, Y, Z = np.meshgrid(x, x, z, indexing="ij")
+    if strained:
+        Z = Z + 1e-6 * Z * (X * X + Y * Y)
+    p = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    h = np.arange(-0.1, 0.1, 0.001)[:200]
+    l = np.arange(3.9, 4.1, 0.001)[:200]
+    S = grid_points(h, 0.0, l)
+    return Workload("cube41s" if strained else "cube41", _f32(p), None, _f32(S),
+                    meta=dict(strained=strained))
+
+
+NAMED = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "ewald": ewald, "cube41": cube41,
+         "cube41s": lambda: cube41(True)}
 
 
 def named(name: str) -> Workload:
