@@ -251,6 +251,7 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_TFLOPS, "traffic": traffic,
                 "kernel": f"nx_scatter_{dom} ({args.mode}, {fkind} f)",
+                "launch": "one entry-point call (all of its dispatches and launch chunks)",
                 "alg_valu_slots_per_pair": slots, "launch_ms": t_dom * 1e3,
                 "counters": valu}
 

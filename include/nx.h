@@ -70,8 +70,8 @@ typedef enum {
  *   NX_F32_PH64 the phase S.r is formed and reduced modulo one cycle in FP64 (exact for
  *               FP32 inputs up to the final rounding), sin/cos and the complex
  *               multiply-add run in FP32, and the sums are compensated (FP32
- *               group partial sums folded into a two-word FP32 accumulator with an
- *               error-free two-sum).  FP64 is used in the phase reduction only.   */
+ *               group partial sums folded into a two-word FP32 accumulator by Kahan's
+ *               compensated addition).  FP64 is used in the phase reduction only.  */
 typedef enum { NX_F32 = 0, NX_F32_PH64 = 1 } nx_mode;
 
 /* Operation selector for nx_workspace_bytes. */

@@ -3,6 +3,7 @@
 // launch sequence of each entry point.
 #include "nx.h"
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -41,6 +42,7 @@ bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 //   NX_TUNE_P             lane items per lane (1, 2, 4; the FP64 path 1, 2)
 //   NX_TUNE_GRP           stream items per compensated group (8, 16, 32)
 //   NX_TUNE_RED           phase reduction variant (0 centred rint, 1 fract)
+//   NX_TUNE_L2_CHUNK      0 turns off the L2-sized atom chunks of the forward
 int64_t env_i64(const char* name, int64_t def) {
   const char* v = std::getenv(name);
   if (!v || !*v) return def;
@@ -131,7 +133,13 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
   const int64_t gran = int64_t(p.nsplit) * p.grp;
   int64_t launch_pairs = env_i64("NX_TUNE_LAUNCH_PAIRS", kLaunchPairs);
   if (launch_pairs < 1) launch_pairs = kLaunchPairs;
+  size_t rec_size;
+  if (fwd) rec_size = p.mode == kF64 ? sizeof(AtomF64) : (p.mode == kPH64 ? sizeof(AtomPH) : sizeof(AtomF32));
+  else rec_size = p.mode == kF64 ? sizeof(PointF64) : (p.mode == kPH64 ? sizeof(PointPH) : sizeof(PointF32));
   int64_t chunk = lane_pad > 0 ? launch_pairs / lane_pad : p.stream;
+  if (fwd && ceil_div(p.stream, p.nsplit) * int64_t(rec_size) > kL2Bytes &&
+      env_i64("NX_TUNE_L2_CHUNK", 1) != 0)
+    chunk = std::min<int64_t>(chunk, int64_t(p.nsplit) * (kL2SliceBytes / int64_t(rec_size)));
   chunk = chunk / gran * gran;
   if (chunk < gran) chunk = gran;
   if (chunk >= p.stream) {
@@ -142,9 +150,6 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
     p.nchunks = ceil_div(p.stream, chunk);
   }
   // workspace: packed stream records, then the partial state
-  size_t rec_size;
-  if (fwd) rec_size = p.mode == kF64 ? sizeof(AtomF64) : (p.mode == kPH64 ? sizeof(AtomPH) : sizeof(AtomF32));
-  else rec_size = p.mode == kF64 ? sizeof(PointF64) : (p.mode == kPH64 ? sizeof(PointPH) : sizeof(PointF32));
   p.rec_bytes = align_up(size_t(p.stream) * rec_size, 256);
   const bool need_partial = p.lanes > 0 && (p.nsplit > 1 || p.nchunks > 1);
   if (need_partial) {

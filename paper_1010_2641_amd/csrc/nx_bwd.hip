@@ -17,18 +17,30 @@
 // the points are streamed as packed wave-uniform records through the scalar load path
 // (the paper's alternative of parallelising over atoms and sharing the reflection
 // coordinates, Section 2.2).  The phases are recomputed, never stored.  Sums are
-// accumulated in FP32 per group of GRP points and folded into (sum, comp) pairs with an
-// error-free two-sum.  FP32 mode: the paper's FP32 arithmetic with plain sums.
+// accumulated in FP32 per group of GRP points and folded into (sum, comp) pairs by
+// Kahan's compensated addition.  FP32 mode: the paper's FP32 arithmetic with plain sums.
 #include "nx_internal.h"
 
 namespace nx {
 namespace {
 
+// Knuth's two-sum: s + g = t + err exactly; err is added into the compensation word
+// (the split reduction, once per split and output).
 __device__ __forceinline__ void two_sum_acc(float& s, float& c, float g) {
   const float t = s + g;
   const float bp = t - s;
   const float ap = t - bp;
   c += (s - ap) + (g - bp);
+  s = t;
+}
+
+// Kahan's compensated addition with the correction kept as the error to add (sum + comp
+// is the running total): the error of s + y is recovered exactly while |s| >= |y|, which
+// holds once the running sum exceeds one group partial.  Four FP32 operations.
+__device__ __forceinline__ void kahan_acc(float& s, float& c, float g) {
+  const float y = g + c;
+  const float t = s + y;
+  c = y - (t - s);
   s = t;
 }
 
@@ -217,7 +229,7 @@ __global__ __launch_bounds__(kThreads) void bwd_kernel(
 #pragma unroll
       for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int d = 0; d < NS; ++d) two_sum_acc(sum[q][d], cmp[q][d], SGN * g[q][d]);
+        for (int d = 0; d < NS; ++d) kahan_acc(sum[q][d], cmp[q][d], SGN * g[q][d]);
       k = kend;
     }
   }

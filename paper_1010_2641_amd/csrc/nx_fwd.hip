@@ -16,8 +16,8 @@
 //          reduction modulo one cycle in FP64 (exact), one rounding to FP32, FP32
 //          v_sin/v_cos, f_j (cos + i sin) by FP32 fma; terms are summed in quads of
 //          consecutive atoms, quads into a group partial, and every `GRP` atoms the
-//          group partial is folded into a two-word (sum, comp) accumulator with an
-//          error-free two-sum (so FP32 roundings happen only at the magnitude of a
+//          group partial is folded into a two-word (sum, comp) accumulator by Kahan's
+//          compensated addition (so FP32 roundings happen only at the magnitude of a
 //          group partial, never at that of the whole sum).
 //   F64  : phase, reduction, sincospi and sums all in FP64.
 #include "nx_internal.h"
@@ -25,12 +25,23 @@
 namespace nx {
 namespace {
 
-// Knuth's two-sum: s + g = t + err exactly; err is added into the compensation word.
+// Knuth's two-sum: s + g = t + err exactly; err is added into the compensation word
+// (the split reduction, once per split and output).
 __device__ __forceinline__ void two_sum_acc(float& s, float& c, float g) {
   const float t = s + g;
   const float bp = t - s;
   const float ap = t - bp;
   c += (s - ap) + (g - bp);
+  s = t;
+}
+
+// Kahan's compensated addition with the correction kept as the error to add (sum + comp
+// is the running total): the error of s + y is recovered exactly while |s| >= |y|, which
+// holds once the running sum exceeds one group partial.  Four FP32 operations.
+__device__ __forceinline__ void kahan_acc(float& s, float& c, float g) {
+  const float y = g + c;
+  const float t = s + y;
+  c = y - (t - s);
   s = t;
 }
 
@@ -133,7 +144,7 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(
     }
   } else {
     // The sign of the terms in the RED == 1 variant (exp(2 i pi u) = -exp(2 i pi S.r))
-    // is applied once per group, as a source modifier of the two-sum.
+    // is applied once per group, as a source modifier of the compensated addition.
     constexpr float SGN = (RED == 1) ? -1.f : 1.f;
     int j = j0;
     for (; j + GRP <= j1; j += GRP) {
@@ -162,8 +173,8 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(
       }
 #pragma unroll
       for (int p = 0; p < P; ++p) {
-        two_sum_acc(sr[p], cr[p], SGN * gr[p]);
-        two_sum_acc(si[p], ci[p], SGN * gi[p]);
+        kahan_acc(sr[p], cr[p], SGN * gr[p]);
+        kahan_acc(si[p], ci[p], SGN * gi[p]);
       }
     }
     if (j < j1) {   // last, partial group: terms added one by one
@@ -181,8 +192,8 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(
       }
 #pragma unroll
       for (int p = 0; p < P; ++p) {
-        two_sum_acc(sr[p], cr[p], SGN * gr[p]);
-        two_sum_acc(si[p], ci[p], SGN * gi[p]);
+        kahan_acc(sr[p], cr[p], SGN * gr[p]);
+        kahan_acc(si[p], ci[p], SGN * gi[p]);
       }
     }
   }

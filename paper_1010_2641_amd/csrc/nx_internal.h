@@ -85,6 +85,11 @@ constexpr int64_t kTargetBlocks = 4096;       // work-groups wanted per launch
 constexpr int64_t kMinStreamPerSplit = 64;    // smallest stream slice
 constexpr int64_t kMaxSplit = 1024;
 constexpr int64_t kLaunchPairs = int64_t(1) << 39;   // pairs per launch (well under 1 s)
+// Forward: when one split's slice of packed atom records exceeds an XCD's 4 MiB L2, the
+// resident work-groups of an XCD drift apart along it and re-read it from HBM; launches
+// then take at most this many record bytes per split, so each launch's slice stays in L2.
+constexpr int64_t kL2SliceBytes = int64_t(2) << 20;
+constexpr int64_t kL2Bytes = int64_t(4) << 20;
 constexpr int kLossBlocks = 1024;             // fixed grid of the loss reduction
 
 enum Op : int { kOpFwd = 0, kOpBwd = 1, kOpFwdF64 = 2, kOpBwdF64 = 3, kOpLoss = 4,
