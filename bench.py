@@ -38,9 +38,9 @@ PEAK_TFLOPS = 2 * VALU_SLOTS_PER_S / 1e12
 # Minimal VALU instruction count per (atom, point) pair of each kernel: the method's
 # own work on gfx950 in the formulation the kernels use (compensation, loads and loop
 # control excluded).  Phase S.r = 3 FP64 fma.  Forward: centred reduction mod 1 (rint,
-# subtract) and rounding to FP32 = 3; adjoint: fract and rounding = 2.  sin and cos = 1
-# issue slot each (the transcendental unit overlaps other VALU work, measured ~1 slot
-# per instruction in a mixed stream).
+# subtract) and rounding to FP32 = 3; adjoint: fract and rounding = 2.  sin and cos count
+# one issue slot each, the strict bound: at half rate they keep the VALU busy for two
+# slots, partly overlapped with other work (the VALU counters give ~1.75 slots each).
 #   forward, complex f: f (cos + i sin) accumulated with 4 fma
 #   forward, f = 1:     (cos, sin) accumulated with 2 add
 #   adjoint, complex f: v = fr sin + fi cos (2), T_d += (|G| S_d) v (3); the seed phase
