@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 3.93e13 full-rate VALU lane-ops/s;
 # counting each as one FMA (2 flop) gives 78.6 TFLOP/s (the unpacked FP32 and the
-# FP64 vector rate; packed FP32 instructions are excluded from this build).
+# FP64 vector rate; the library is compiled without packed FP32 instructions).
 VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 PEAK_TFLOPS = 2 * VALU_SLOTS_PER_S / 1e12
 
@@ -169,7 +169,7 @@ def cpu_baseline(w, A_gpu, g_gpu_fn, budget_s):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
               "(the sum would shard along the points with no exchange)",
               file=sys.stderr)
         sys.exit(2)
