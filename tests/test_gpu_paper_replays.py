@@ -64,3 +64,15 @@ def test_fig1_sweep_code_runs_small():
     text = replay.fig1(max_pairs=1e8, sizes=(100, 1000, 10000))
     rows = [ln for ln in text.splitlines() if ln.startswith("| 1e+0")]
     assert len(rows) == 6 and all(ln.count("e+") == 4 for ln in rows)
+
+
+def test_cube_and_chain_reports_run():
+    """The replay reports themselves (timing loops included) on the GPU."""
+    cube = replay.cube()
+    rows = [ln for ln in cube.splitlines() if ln.startswith("| plain") or ln.startswith("| strained")]
+    assert len(rows) == 7
+    chain = replay.chain()
+    ph64 = [ln for ln in chain.splitlines() if "| ph64 |" in ln]
+    assert len(ph64) == 3
+    for ln in ph64:
+        assert float(ln.split("|")[3]) >= 1e10      # reliable range of the FP64-phase mode
