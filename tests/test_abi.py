@@ -189,3 +189,9 @@ def test_species_and_factor_gradient_empty_calls():
     assert need > _lib.nx_workspace_bytes(1000, 1000, 1, _lib.NX_OP_BWD, 0)   # two more sums
     assert _lib.nx_scatter_bwd_ex(FAKE, FAKE, 1000, FAKE, 1000, FAKE, FAKE, FAKE, 1, FAKE, need - 1,
                                   None) == _lib.NX_ERR_WORKSPACE
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    monkeypatch.setattr(_lib, "LIB_PATH", "/nonexistent/libnx.so")
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        _lib._load()

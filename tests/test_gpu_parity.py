@@ -317,3 +317,32 @@ def test_lane_item_counts(per_lane, monkeypatch):
     for mode in ("ph64", "f32"):
         en, em = M.t3(run_bwd(xyz, f, S, G, mode), oracle.adjoint(xyz, f, S, G))
         assert en <= (M.T3_NORM_TOL if mode == "ph64" else 5e-3), mode
+
+
+@pytest.mark.parametrize("mode", ["ph64", "f64", "f32"])
+def test_degenerate_inputs(mode):
+    """Degenerate cases of Eq. 2: points at S = 0 (A = sum f), every atom at one site
+    (A = (sum f) exp(2 i pi S.r0)), zero factors; a zero seed or S = 0 gives an exactly
+    zero position gradient."""
+    rng = np.random.default_rng(101)
+    n, k = 777, 301
+    xyz, f, S = wl.random_problem(n, k, seed=102, extent=20.0, s_range=2.0)
+    S = S.copy()
+    S[::7] = 0.0                                    # points at the origin of reciprocal space
+    f = f.copy()
+    f[::5] = 0.0                                    # zero factors
+    A = run_fwd(xyz, f, S, mode)
+    A_ref = oracle.forward(xyz, f, S)
+    tol = {"ph64": M.INC_TOL, "f64": M.F64_INC_TOL, "f32": 1e-4}[mode]
+    assert M.incoherent(A, A_ref, f, n) <= tol
+    zero_rows = np.all(S == 0, axis=1)
+    assert np.max(np.abs(A[zero_rows] - np.sum(f.astype(np.complex128)))) <= tol * np.sqrt(n) * 2
+    # one site for every atom
+    same = np.repeat(xyz[:1], n, axis=0)
+    A1 = run_fwd(same, f, S, mode)
+    assert M.incoherent(A1, oracle.forward(same, f, S), f, n) <= tol * np.sqrt(n)
+    # zero seed, and a seed on S = 0 points only: exactly zero gradients
+    G0 = np.zeros(k, dtype=np.complex64)
+    assert np.all(run_bwd(xyz, f, S, G0, mode) == 0)
+    Gz = np.where(zero_rows, (rng.normal(size=k) + 1j * rng.normal(size=k)), 0).astype(np.complex64)
+    assert np.all(run_bwd(xyz, f, S, Gz, mode) == 0)
