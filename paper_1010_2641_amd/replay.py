@@ -180,7 +180,7 @@ def chain():
              "- median |dI|/max I: the typical absolute intensity error on the map's scale;",
              "- the disordered chain (Gaussian 1e-3 on each coordinate, the paper's gray curve) "
              "gives the median of I/max I it reaches: the noise level an error must stay under.",
-             "", "| atoms | mode | reliable range | within 1e-2 | median \|dI\|/max I |",
+             "", "| atoms | mode | reliable range | within 1e-2 | median \\|dI\\|/max I |",
              "|---:|---|---:|---:|---:|"]
     for n in (1000, 10_000, 100_000):
         xyz, S = wl.chain(n)
