@@ -153,10 +153,18 @@ def cpu_baseline(w, A_gpu, g_gpu_fn, budget_s):
         "sample": f"{n_pts} random points (forward) and {n_at} random atoms with a seeded "
                   f"random seed G (adjoint)",
     }
+    cpu_model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        pass
     base = {
         "value": pairs / t_full,
         "unit": "atom.point pairs/s",
         "cores": cores,
+        "cpu_model": cpu_model,
+        "affinity_cpus": len(os.sched_getaffinity(0)),
         "kind": "oracle",
         "sample": (f"FP64 oracle forward on {n_pts} of {w.n_points} points (all atoms, "
                    f"{t_fwd:.1f} s) and adjoint on {n_at} of {w.n_atoms} atoms (all points, "
@@ -255,7 +263,7 @@ def main():
             vr = json.load(fh)
         if vr.get("source_sha") == source_hash():
             valu = {k: vr[k] for k in ("valu_issue_util", "valu_busy", "valu_insts_per_pair",
-                                       "trans_insts_per_pair") if k in vr}
+                                       "trans_insts_per_pair", "clock_ghz") if k in vr}
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_TFLOPS, "traffic": traffic,
                 "kernel": f"nx_scatter_{dom} ({args.mode}, {fkind} f)",
