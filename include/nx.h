@@ -8,9 +8,10 @@
  *
  *     A(S_k) = sum_j f_j exp(2 i pi S_k . r_j)
  *
- * over every atom j and every reciprocal-space point k, and the adjoint of that sum
- * with respect to the atom positions, for fitting displacement fields to measured
- * intensities.
+ * over every atom j and every reciprocal-space point k, the adjoint of that sum with
+ * respect to the atom positions and the factors (for fitting displacement fields,
+ * occupancies or compositions to measured intensities), and the species-factorised
+ * form of Section 4.2.
  *
  * Units and layout (all arrays flat and row-major; the order of atoms and of points
  * is irrelevant, as Section 3 of the paper notes for its own inputs):
@@ -56,7 +57,8 @@ extern "C" {
 
 typedef enum {
   NX_OK = 0,
-  NX_ERR_ARG = -1,        /* negative count, count too large, or NULL pointer with count > 0 */
+  NX_ERR_ARG = -1,        /* negative count, count too large, NULL pointer with count > 0,
+                             misaligned complex array, or an invalid species partition */
   NX_ERR_MODE = -2,       /* unknown mode or op */
   NX_ERR_WORKSPACE = -3,  /* workspace missing or smaller than nx_workspace_bytes() */
   NX_ERR_DEVICE = -4      /* a HIP call failed (message in nx_last_error) */
@@ -166,7 +168,8 @@ int nx_scatter_bwd_ex_f64(const double* xyz, const double* f, int64_t n_atoms,
  *   A_species float[n_species * n_points * 2] or NULL: the per-species sums (needed by
  *             nx_scatter_bwd_species for the gradient with respect to fs).
  * The per-species (sum, comp) states are combined in FP64 and rounded once.
- * Workspace: nx_workspace_bytes_species(..., op = 0). */
+ * Workspace: nx_workspace_bytes_species(..., op = 0).  Errors as for nx_scatter_fwd,
+ * plus NX_ERR_ARG for an invalid species partition. */
 int nx_scatter_fwd_species(const float* xyz, int64_t n_atoms, const int64_t* species_start,
                            int n_species, const float* fs, const float* S, int64_t n_points,
                            float* A, float* A_species, int mode, void* ws, size_t ws_bytes,
