@@ -49,3 +49,44 @@ def test_pins_reject_mutation(name, tmp_path):
         except AssertionError:
             failed.append(pin.__name__)
     assert failed, f"no pin rejects the planted mistake '{name}'"
+
+
+# ----------------------------------------------------------------------------- Python compositions
+
+PY_MUTATIONS = {
+    "species_seed_no_conj": ("adjoint_species",
+                             "seed = G if fs is None else G * np.conj(np.asarray(fs, dtype=np.complex128)[s])",
+                             "seed = G if fs is None else G * np.asarray(fs, dtype=np.complex128)[s]"),
+    "species_gradf_no_conj": ("adjoint_species",
+                              "gfs = None if A_species is None else G[None, :] * np.conj(np.asarray(A_species))",
+                              "gfs = None if A_species is None else G[None, :] * np.asarray(A_species)"),
+    "species_factor_conj": ("forward_species", "return (f * As).sum(axis=0), As",
+                            "return (np.conj(f) * As).sum(axis=0), As"),
+    "species_boundary_off_by_one": ("forward_species", "forward(xyz[start[s]:start[s + 1]], None, S, lib=lib)",
+                                    "forward(xyz[start[s]:max(start[s], start[s + 1] - 1)], None, S, lib=lib)"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTATIONS))
+def test_species_pins_reject_mutation(name):
+    """The same check for the species compositions, which are Python: a mutated copy of
+    the function is compiled from its source and handed to the species pins."""
+    import inspect
+    import types
+
+    fn_name, old, new = PY_MUTATIONS[name]
+    src = inspect.getsource(getattr(oracle, fn_name))
+    assert src.count(old) == 1, "mutation target not found in the oracle source"
+    namespace = dict(vars(oracle))
+    exec(compile(src.replace(old, new), f"<mutant {name}>", "exec"), namespace)
+    mutant = types.SimpleNamespace(forward=oracle.forward, loss=oracle.loss,
+                                   forward_species=oracle.forward_species,
+                                   adjoint_species=oracle.adjoint_species)
+    setattr(mutant, fn_name, namespace[fn_name])
+    failed = []
+    for pin in pins.SPECIES_PINS:
+        try:
+            pin(mutant)
+        except AssertionError:
+            failed.append(pin.__name__)
+    assert failed, f"no pin rejects the planted mistake '{name}'"

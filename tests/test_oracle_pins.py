@@ -338,21 +338,21 @@ def test_oracle_pin(pin):
     pin(oracle)
 
 
-def test_species_composition_equals_per_atom_factors():
+def pin_species_composition_equals_per_atom_factors(orc):
     """The species-factorised sum with S-independent factors equals Eq. 2 with the
     factor of each atom's species (linearity of the sum)."""
     xyz, _, S = wl.random_problem(60, 35, seed=33, complex_f=False)
     start = [0, 25, 25, 60]                       # an empty species in the middle
     fsp = np.array([1.5 - 0.2j, 9.0 + 1.0j, -0.3 + 2.0j])
     fs = np.repeat(fsp[:, None], 35, axis=1)
-    A, As = oracle.forward_species(xyz, start, fs, S)
+    A, As = orc.forward_species(xyz, start, fs, S)
     f_atom = np.concatenate([np.full(start[s + 1] - start[s], fsp[s]) for s in range(3)])
-    ref = oracle.forward(xyz, f_atom, S)
+    ref = orc.forward(xyz, f_atom, S)
     assert np.max(np.abs(A - ref)) <= 1e-12 * np.sum(np.abs(f_atom))
     assert np.all(As[1] == 0)
 
 
-def test_species_adjoint_matches_finite_differences():
+def pin_species_adjoint_matches_finite_differences(orc):
     """The species adjoint (positions, and the factor of species s at point k) against
     central differences of the FP64 loss through the species-factorised forward, with
     S-dependent factors."""
@@ -364,11 +364,11 @@ def test_species_adjoint_matches_finite_differences():
     xyz = xyz.astype(np.float64)
 
     def L(x, f):
-        return oracle.loss(oracle.forward_species(x, start, f, S)[0], I)[0]
+        return orc.loss(orc.forward_species(x, start, f, S)[0], I)[0]
 
-    A, As = oracle.forward_species(xyz, start, fs, S)
-    _, G = oracle.loss(A, I)
-    g, gfs = oracle.adjoint_species(xyz, start, fs, S, G, As)
+    A, As = orc.forward_species(xyz, start, fs, S)
+    _, G = orc.loss(A, I)
+    g, gfs = orc.adjoint_species(xyz, start, fs, S, G, As)
     h = 1e-6
     for j, d in ((0, 0), (11, 2), (12, 1), (29, 2)):
         xp, xm = xyz.copy(), xyz.copy()
@@ -384,3 +384,15 @@ def test_species_adjoint_matches_finite_differences():
             fd = (L(xyz, fp) - L(xyz, fm)) / (2 * h)
             ref = gfs[s, k].real if unit == 1.0 else gfs[s, k].imag
             assert fd == pytest.approx(ref, rel=1e-5, abs=1e-6 * np.max(np.abs(gfs)))
+
+
+# The species-factorised forms are compositions in Python (per-species sums, then numpy
+# products); their pins take an object with forward, loss, forward_species and
+# adjoint_species, so that the planted-mistake test can hand them a mutant.
+SPECIES_PINS = [pin_species_composition_equals_per_atom_factors,
+                pin_species_adjoint_matches_finite_differences]
+
+
+@pytest.mark.parametrize("pin", SPECIES_PINS, ids=[p.__name__[4:] for p in SPECIES_PINS])
+def test_oracle_species_pin(pin):
+    pin(oracle)
