@@ -43,6 +43,8 @@ bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 //   NX_TUNE_GRP           stream items per compensated group (8, 16, 32)
 //   NX_TUNE_RED           phase reduction variant (0 centred rint, 1 fract)
 //   NX_TUNE_L2_CHUNK      0 turns off the L2-sized atom chunks of the forward
+//   NX_TUNE_LDS           forward, FP64-phase: 1 stages atom tiles in LDS, 0 streams
+//                         them through scalar loads (default: LDS for complex f)
 int64_t env_i64(const char* name, int64_t def) {
   const char* v = std::getenv(name);
   if (!v || !*v) return def;
@@ -100,6 +102,9 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
   if (fwd) {
     const bool small = p.stream < 65536;
     p.red = 0;
+    // complex factors: atom tiles staged in LDS (+5 % on C2 over scalar loads); f = 1:
+    // scalar loads (LDS 2-3 % slower there)
+    p.lds = (p.mode == kPH64 && p.fk == 1) ? 1 : 0;
     p.grp = (p.mode == kPH64 && small) ? 8 : 16;
     if (p.mode == kF64) p.per_lane = p.lanes >= 262144 ? 2 : 1;
     else p.per_lane = (p.lanes >= 32768 && p.lanes < 1048576) ? 2 : 1;
@@ -116,6 +121,8 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
     if (p.mode == kPH64 && (tg == 8 || tg == 16 || tg == 32) && (fwd || tg != 8)) p.grp = int(tg);
     const int64_t tr = env_i64("NX_TUNE_RED", -1);
     if (p.mode == kPH64 && (tr == 0 || tr == 1)) p.red = int(tr);
+    const int64_t tl = env_i64("NX_TUNE_LDS", -1);
+    if (fwd && p.mode == kPH64 && (tl == 0 || tl == 1)) p.lds = int(tl);
   }
   const int64_t per_block = int64_t(kThreads) * p.per_lane;
   p.blocks = p.lanes > 0 ? ceil_div(p.lanes, per_block) : 0;

@@ -3,11 +3,14 @@
 //
 // Layout on gfx950: every lane owns P points (coalesced rows of S, strided by the
 // work-group size), keeps their S and complex accumulators in registers, and walks
-// the atoms of its slice in order.  The atom index is uniform over the wavefront,
-// so each packed atom record is fetched with scalar loads into SGPRs and used as an
-// SGPR operand of the VALU instructions: the record is broadcast without LDS traffic
-// or barriers (the paper shares atom coordinates between threads through on-chip
-// memory for the same reason, Section 2.2).
+// the atoms of its slice in order.  The atom index is uniform over the wavefront, so
+// every packed atom record is a broadcast.  Two forms (the paper shares atom
+// coordinates between threads through on-chip memory for the same reason, Section 2.2):
+//   fwd_kernel     -- records fetched with scalar loads into SGPRs and used as SGPR
+//                     operands: no LDS traffic, no barriers (used for f_j = 1);
+//   fwd_lds_kernel -- records staged per work-group in LDS tiles and read back as
+//                     broadcasts (used for complex f_j, where it measured faster).
+// Both sum in the same order, so their results are bitwise equal.
 //
 // Per (atom, point) pair:
 //   F32  : phase S.r with FP32 fma, v_fract_f32, v_sin_f32/v_cos_f32 (both take the
@@ -208,6 +211,103 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(
   }
 }
 
+// FP64-phase forward with the atom records staged through LDS: each work-group copies a
+// tile of kThreads records into LDS (one record per thread, coalesced), and every wave
+// then reads the records from LDS as broadcasts.  Groups, quads and compensation are
+// those of fwd_kernel (tiles are whole groups), so the result is bitwise the same.
+template <int P, int FK, int GRP>
+__global__ __launch_bounds__(kThreads) void fwd_lds_kernel(
+    const AtomPH* __restrict__ rec, int a_begin, int a_end, int per_split,
+    const float* __restrict__ S, int64_t K, int blocks_k, float4* __restrict__ part,
+    float2* __restrict__ A, int carry_in, int direct) {
+  static_assert(kThreads % GRP == 0, "tiles must hold whole groups");
+  __shared__ AtomPH tile[kThreads];
+  const int lb = xcd_major_block(blockIdx.x, gridDim.x);
+  const int kb = lb % blocks_k;
+  const int sp = lb / blocks_k;
+  const int64_t k0 = int64_t(kb) * (kThreads * P) + threadIdx.x;
+  double sx[P], sy[P], sz[P];
+  float sr[P], si[P], cr[P], ci[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int64_t k = k0 + int64_t(p) * kThreads;
+    const int64_t kk = k < K ? k : K - 1;
+    sx[p] = S[3 * kk];
+    sy[p] = S[3 * kk + 1];
+    sz[p] = S[3 * kk + 2];
+    if (carry_in && k < K) {
+      const float4 st = part[int64_t(sp) * K + k];
+      sr[p] = st.x; si[p] = st.y; cr[p] = st.z; ci[p] = st.w;
+    } else {
+      sr[p] = 0.f; si[p] = 0.f; cr[p] = 0.f; ci[p] = 0.f;
+    }
+  }
+  const int j0 = a_begin + sp * per_split;
+  const int j1 = min(j0 + per_split, a_end);
+  for (int t0 = j0; t0 < j1; t0 += kThreads) {
+    const int nt = min(kThreads, j1 - t0);
+    __syncthreads();                        // the previous tile is no longer read
+    if (int(threadIdx.x) < nt) tile[threadIdx.x] = rec[t0 + threadIdx.x];
+    __syncthreads();
+    int u0 = 0;
+    for (; u0 + GRP <= nt; u0 += GRP) {
+      float gr[P], gi[P];
+#pragma unroll
+      for (int q = 0; q < GRP / 4; ++q) {
+        float qr[P], qi[P];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const AtomPH a = tile[u0 + 4 * q + u];
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            float c, s;
+            cis_ph64<0>(sx[p], sy[p], sz[p], a, c, s);
+            if (u == 0) cterm<FK>(qr[p], qi[p], a.fr, a.fi, c, s);
+            else cmac<FK>(qr[p], qi[p], a.fr, a.fi, c, s);
+          }
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          if (q == 0) { gr[p] = qr[p]; gi[p] = qi[p]; }
+          else { gr[p] += qr[p]; gi[p] += qi[p]; }
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        kahan_acc(sr[p], cr[p], gr[p]);
+        kahan_acc(si[p], ci[p], gi[p]);
+      }
+    }
+    if (u0 < nt) {    // the split's last, partial group
+      float gr[P], gi[P];
+#pragma unroll
+      for (int p = 0; p < P; ++p) { gr[p] = 0.f; gi[p] = 0.f; }
+      for (int u = u0; u < nt; ++u) {
+        const AtomPH a = tile[u];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          float c, s;
+          cis_ph64<0>(sx[p], sy[p], sz[p], a, c, s);
+          cmac<FK>(gr[p], gi[p], a.fr, a.fi, c, s);
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        kahan_acc(sr[p], cr[p], gr[p]);
+        kahan_acc(si[p], ci[p], gi[p]);
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int64_t k = k0 + int64_t(p) * kThreads;
+    if (k < K) {
+      if (direct) A[k] = make_float2(sr[p] + cr[p], si[p] + ci[p]);
+      else part[int64_t(sp) * K + k] = make_float4(sr[p], si[p], cr[p], ci[p]);
+    }
+  }
+}
+
 // All-FP64 forward: FP64 phase, FP64 reduction, sincospi in FP64, FP64 sums.
 template <int P, int FK>
 __global__ __launch_bounds__(kThreads) void fwd_f64_kernel(
@@ -347,6 +447,17 @@ hipError_t fwd_dispatch_red(const Plan& p, const void* rec, int64_t a_begin, int
     fwd_kernel<MODE, P, FK, 16, 0><<<grid, kThreads, 0, st>>>(
         r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct);
     return hipGetLastError();
+  }
+  if constexpr (MODE == kPH64) {
+    if (p.lds && red == 0 && (p.grp == 16 || p.grp == 8)) {
+      if (p.grp == 16)
+        fwd_lds_kernel<P, FK, 16><<<grid, kThreads, 0, st>>>(
+            r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct);
+      else
+        fwd_lds_kernel<P, FK, 8><<<grid, kThreads, 0, st>>>(
+            r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct);
+      return hipGetLastError();
+    }
   }
   if (p.grp == 16 && red == 0)
     fwd_kernel<MODE, P, FK, 16, 0><<<grid, kThreads, 0, st>>>(

@@ -69,6 +69,7 @@ struct Plan {
   int fk = 0;            // 0: f_j = 1, 1: complex f_j
   int red = 0;           // phase reduction variant of the FP64-phase kernels (0 centred, 1 fract)
   int gf = 0;            // adjoint also returns dL/df
+  int lds = 0;           // forward, FP64-phase: atom tiles staged in LDS instead of scalar loads
   int64_t lanes = 0;     // number of lane items
   int64_t stream = 0;    // number of stream items
   int64_t blocks = 0;    // work-groups over lane items

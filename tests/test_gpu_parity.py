@@ -346,3 +346,19 @@ def test_degenerate_inputs(mode):
     assert np.all(run_bwd(xyz, f, S, G0, mode) == 0)
     Gz = np.where(zero_rows, (rng.normal(size=k) + 1j * rng.normal(size=k)), 0).astype(np.complex64)
     assert np.all(run_bwd(xyz, f, S, Gz, mode) == 0)
+
+
+@pytest.mark.parametrize("n,k", [(3001, 5003), (517, 12345), (40000, 300), (300000, 2000)])
+@pytest.mark.parametrize("cplx", [True, False])
+def test_lds_staged_forward_bitwise(n, k, cplx, monkeypatch):
+    """The LDS-staged forward (atom tiles per work-group) and the scalar-load forward sum
+    in the same order: bitwise equal, with ragged tails, splits and L2-sized chunks."""
+    xyz, f, S = wl.random_problem(n, k, seed=n + k, extent=40.0, s_range=3.0, complex_f=cplx)
+    out = {}
+    for lds in ("0", "1"):
+        monkeypatch.setenv("NX_TUNE_LDS", lds)
+        for grp in ("16", "8"):
+            monkeypatch.setenv("NX_TUNE_GRP", grp)
+            out[(lds, grp)] = run_fwd(xyz, f, S, "ph64")
+    for grp in ("16", "8"):
+        assert np.array_equal(out[("0", grp)], out[("1", grp)]), grp
