@@ -14,9 +14,10 @@
 // delta_k, costs two FP32 operations (none for f_j = 1), and W_j += |G_k| (c + i s).
 //
 // Layout: every lane owns Q atoms and keeps their position and the sums in registers;
-// the points are streamed as packed wave-uniform records through the scalar load path
-// (the paper's alternative of parallelising over atoms and sharing the reflection
-// coordinates, Section 2.2).  The phases are recomputed, never stored.  Sums are
+// the points are wave-uniform records (the paper's alternative of parallelising over
+// atoms and sharing the reflection coordinates, Section 2.2).  bwd_kernel streams them
+// through the scalar load path; bwd_split_kernel (the FP64-phase default) stages their
+// phase part in LDS tiles and reads the rest with scalar loads.  The phases are recomputed, never stored.  Sums are
 // accumulated in FP32 per group of GRP points and folded into (sum, comp) pairs by
 // Kahan's compensated addition.  FP32 mode: the paper's FP32 arithmetic with plain sums.
 #include "nx_internal.h"
@@ -77,9 +78,27 @@ __device__ __forceinline__ PtRegs load_point(const PointPH* __restrict__ rec, in
   const uint4 a = w[0], b = w[1], c = w[2];
   PtRegs r;
   r.sx = __hiloint2double(static_cast<int>(a.y), static_cast<int>(a.x));
-  r.sy = __hiloint2double(static_cast<int>(a.w), static_cast<int>(a.z));
-  r.sz = __hiloint2double(static_cast<int>(b.y), static_cast<int>(b.x));
-  r.delta = __hiloint2double(static_cast<int>(b.w), static_cast<int>(b.z));
+  r.delta = __hiloint2double(static_cast<int>(a.w), static_cast<int>(a.z));
+  r.sy = __hiloint2double(static_cast<int>(b.y), static_cast<int>(b.x));
+  r.sz = __hiloint2double(static_cast<int>(b.w), static_cast<int>(b.z));
+  r.gsx = __uint_as_float(c.x);
+  r.gsy = __uint_as_float(c.y);
+  r.gsz = __uint_as_float(c.z);
+  r.gmag = __uint_as_float(c.w);
+  return r;
+}
+
+// The same record with its phase part (sx, delta, sy, sz: the first two words) taken
+// from an LDS tile and its last word (|G| S, |G|) from the record itself (scalar loads).
+__device__ __forceinline__ PtRegs load_point_split(const uint4* sd, int u,
+                                                   const PointPH* __restrict__ rec, int k) {
+  const uint4* w = reinterpret_cast<const uint4*>(rec + k);
+  const uint4 a = sd[2 * u], b = sd[2 * u + 1], c = w[2];
+  PtRegs r;
+  r.sx = __hiloint2double(static_cast<int>(a.y), static_cast<int>(a.x));
+  r.delta = __hiloint2double(static_cast<int>(a.w), static_cast<int>(a.z));
+  r.sy = __hiloint2double(static_cast<int>(b.y), static_cast<int>(b.x));
+  r.sz = __hiloint2double(static_cast<int>(b.w), static_cast<int>(b.z));
   r.gsx = __uint_as_float(c.x);
   r.gsy = __uint_as_float(c.y);
   r.gsz = __uint_as_float(c.z);
@@ -234,6 +253,113 @@ __global__ __launch_bounds__(kThreads) void bwd_kernel(
     }
   }
 
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t j = j0 + int64_t(q) * kThreads;
+    if (j < N) {
+      if (direct) {
+        float T[NS];
+#pragma unroll
+        for (int d = 0; d < NS; ++d) T[d] = sum[q][d] + cmp[q][d];
+        write_out<GF>(grad, gradf, j, T);
+      } else {
+#pragma unroll
+        for (int d = 0; d < NS; ++d) {
+          part[((int64_t(sp) * NS + d) * 2 + 0) * N + j] = sum[q][d];
+          part[((int64_t(sp) * NS + d) * 2 + 1) * N + j] = cmp[q][d];
+        }
+      }
+    }
+  }
+}
+
+// FP64-phase adjoint with the phase part of each point (sx, delta, sy, sz: 32 bytes)
+// staged in an LDS tile and the rest of the record (|G| S, |G|) read with scalar loads:
+// the phase's fma chain then takes its point values from VGPRs.  Groups and compensation are those of bwd_kernel
+// (tiles are whole groups), so the result is bitwise the same.
+template <int Q, int FK, int GRP, int RED, bool GF>
+__global__ __launch_bounds__(kThreads) void bwd_split_kernel(
+    const PointPH* __restrict__ rec, int k_begin, int k_end, int per_split,
+    const float* __restrict__ xyz, const float* __restrict__ f, int64_t N, int blocks_n,
+    float* __restrict__ part, float* __restrict__ grad, float* __restrict__ gradf, int carry_in,
+    int direct) {
+  static_assert(kThreads % GRP == 0, "tiles must hold whole groups");
+  constexpr int NS = NSum<GF>::value;
+  constexpr float SGN = (RED == 1) ? -1.f : 1.f;
+  __shared__ uint4 sd[2 * kThreads];
+  const int lb = xcd_major_block(blockIdx.x, gridDim.x);
+  const int nb = lb % blocks_n;
+  const int sp = lb / blocks_n;
+  const int64_t j0 = int64_t(nb) * (kThreads * Q) + threadIdx.x;
+  double x[Q], y[Q], z[Q];
+  float fr[Q], fi[Q];
+  float sum[Q][NS], cmp[Q][NS];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t j = j0 + int64_t(q) * kThreads;
+    const int64_t jj = j < N ? j : N - 1;
+    x[q] = xyz[3 * jj];
+    y[q] = xyz[3 * jj + 1];
+    z[q] = xyz[3 * jj + 2];
+    fr[q] = (FK && f) ? f[2 * jj] : 1.f;
+    fi[q] = (FK && f) ? f[2 * jj + 1] : 0.f;
+#pragma unroll
+    for (int d = 0; d < NS; ++d) {
+      if (carry_in && j < N) {
+        sum[q][d] = part[((int64_t(sp) * NS + d) * 2 + 0) * N + j];
+        cmp[q][d] = part[((int64_t(sp) * NS + d) * 2 + 1) * N + j];
+      } else {
+        sum[q][d] = 0.f;
+        cmp[q][d] = 0.f;
+      }
+    }
+  }
+  const int k0 = k_begin + sp * per_split;
+  const int k1 = min(k0 + per_split, k_end);
+  for (int t0 = k0; t0 < k1; t0 += kThreads) {
+    const int nt = min(kThreads, k1 - t0);
+    __syncthreads();                        // the previous tile is no longer read
+    if (int(threadIdx.x) < nt) {
+      const uint4* w = reinterpret_cast<const uint4*>(rec + t0 + threadIdx.x);
+      sd[2 * threadIdx.x] = w[0];
+      sd[2 * threadIdx.x + 1] = w[1];
+    }
+    __syncthreads();
+    for (int u0 = 0; u0 < nt; u0 += GRP) {
+      const int ue = (u0 + GRP <= nt) ? u0 + GRP : nt;
+      float g[Q][NS];
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int d = 0; d < NS; ++d) g[q][d] = 0.f;
+      if (ue - u0 == GRP) {
+#pragma unroll
+        for (int u = 0; u < GRP; ++u) {
+          const PtRegs a = load_point_split(sd, u0 + u, rec, t0 + u0 + u);
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            float c, s;
+            cis_ph64_pt<RED>(a, x[q], y[q], z[q], c, s);
+            ph64_pair<FK, GF>(g[q], a, fr[q], fi[q], c, s);
+          }
+        }
+      } else {
+        for (int u = u0; u < ue; ++u) {
+          const PtRegs a = load_point_split(sd, u, rec, t0 + u);
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            float c, s;
+            cis_ph64_pt<RED>(a, x[q], y[q], z[q], c, s);
+            ph64_pair<FK, GF>(g[q], a, fr[q], fi[q], c, s);
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int d = 0; d < NS; ++d) kahan_acc(sum[q][d], cmp[q][d], SGN * g[q][d]);
+    }
+  }
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int64_t j = j0 + int64_t(q) * kThreads;
@@ -439,6 +565,15 @@ hipError_t bwd_dispatch(const Plan& p, const BwdArgs& b, hipStream_t st) {
     bwd_kernel<MODE, Q, FK, 16, 0, GF><<<grid, kThreads, 0, st>>>(
         r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);
   } else {
+    if (p.lds && p.red == 1 && (p.grp == 32 || p.grp == 16)) {
+      if (p.grp == 32)
+        bwd_split_kernel<Q, FK, 32, 1, GF><<<grid, kThreads, 0, st>>>(
+            r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);
+      else
+        bwd_split_kernel<Q, FK, 16, 1, GF><<<grid, kThreads, 0, st>>>(
+            r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);
+      return hipGetLastError();
+    }
     if (p.grp == 16 && p.red == 0)
       bwd_kernel<MODE, Q, FK, 16, 0, GF><<<grid, kThreads, 0, st>>>(
           r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);

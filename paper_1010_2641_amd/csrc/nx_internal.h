@@ -30,9 +30,10 @@ struct alignas(16) PointF32 { float sx, sy, sz, gr, gi, pad0, pad1, pad2; };    
 // Point for the FP64-phase adjoint, with the seed in polar form conj(G) =
 // |G| exp(2 i pi delta): S (FP64) and delta (cycles, FP64, plus the reduction offset of
 // the variant) for the phase in the first 32 bytes, |G| S and |G| (FP32) for the
-// multiply-adds into the per-atom sums in the last 16; one 8-dword and one 4-dword
-// scalar load per record.
-struct alignas(16) PointPH { double sx, sy, sz, delta; float gsx, gsy, gsz, gmag; }; // 48 B
+// multiply-adds into the per-atom sums in the last 16.  sx and delta come first: they
+// are the two point values of the phase's first fma, which the adjoint reads from an
+// LDS tile (an fma takes at most one scalar operand), the rest with scalar loads.
+struct alignas(16) PointPH { double sx, delta, sy, sz; float gsx, gsy, gsz, gmag; }; // 48 B
 // Point for the all-FP64 adjoint.
 struct alignas(16) PointF64 { double sx, sy, sz, gr, gi, pad; };                     // 48 B
 
@@ -69,7 +70,7 @@ struct Plan {
   int fk = 0;            // 0: f_j = 1, 1: complex f_j
   int red = 0;           // phase reduction variant of the FP64-phase kernels (0 centred, 1 fract)
   int gf = 0;            // adjoint also returns dL/df
-  int lds = 0;           // forward, FP64-phase: atom tiles staged in LDS instead of scalar loads
+  int lds = 0;           // FP64-phase sums: record tiles staged in LDS instead of scalar loads
   int64_t lanes = 0;     // number of lane items
   int64_t stream = 0;    // number of stream items
   int64_t blocks = 0;    // work-groups over lane items

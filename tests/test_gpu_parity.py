@@ -362,3 +362,24 @@ def test_lds_staged_forward_bitwise(n, k, cplx, monkeypatch):
             out[(lds, grp)] = run_fwd(xyz, f, S, "ph64")
     for grp in ("16", "8"):
         assert np.array_equal(out[("0", grp)], out[("1", grp)]), grp
+
+
+@pytest.mark.parametrize("n,k", [(3001, 5003), (517, 12345), (40000, 300), (2000, 200000)])
+@pytest.mark.parametrize("cplx", [True, False])
+def test_split_adjoint_bitwise(n, k, cplx, monkeypatch):
+    """The adjoint with the phase part of the point records in LDS tiles and the one with
+    scalar loads only sum in the same order: bitwise equal, with and without dL/df, both
+    group sizes, ragged tails and splits."""
+    xyz, f, S = wl.random_problem(n, k, seed=n + k, extent=40.0, s_range=3.0, complex_f=cplx)
+    G = wl.random_seed_field(k, seed=k)
+    out = {}
+    for lds in ("0", "1"):
+        monkeypatch.setenv("NX_TUNE_LDS", lds)
+        for grp in ("32", "16"):
+            monkeypatch.setenv("NX_TUNE_GRP", grp)
+            gx, gf = api.scatter_bwd_ex(dev(xyz), dev(f), dev(S), dev(G), "ph64")
+            torch.cuda.synchronize()
+            out[(lds, grp, "gf")] = (gx.cpu().numpy(), gf.cpu().numpy())
+            out[(lds, grp, "x")] = (run_bwd(xyz, f, S, G, "ph64"),)
+    for key in [k_ for k_ in out if k_[0] == "0"]:
+        assert all(np.array_equal(a, b) for a, b in zip(out[key], out[("1",) + key[1:]])), key
