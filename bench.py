@@ -59,11 +59,22 @@ KERNEL_SOURCES = ["nx_fwd.hip", "nx_bwd.hip", "nx_loss.hip", "nx_species.hip", "
                   "nx_internal.h"]
 
 
+def _code_only(text: str) -> str:
+    """C/C++ source without comments and blank lines (string literals in these sources
+    hold no comment markers), so that editing a comment keeps the hash."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip())
+
+
 def source_hash() -> str:
+    """Hash of the library's kernel and launch sources (code only): the traffic and
+    counter summaries under profiles/ are used only while it matches theirs."""
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1010_2641_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1010_2641_amd", "csrc", name)) as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
