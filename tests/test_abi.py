@@ -195,3 +195,30 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(_lib, "LIB_PATH", "/nonexistent/libnx.so")
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         _lib._load()
+
+
+def test_plan_l2_sized_forward_chunks(monkeypatch):
+    """The forward cuts its launches when a split's slice of atom records exceeds an
+    XCD's L2: the carried running sums then appear in the workspace (host-side plan)."""
+    n, k = 203_557, 2_097_152                      # 6.5 MB of records, one split
+    rec = -(-n * 32 // 256) * 256
+    with_chunks = _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_FWD, 0)
+    assert with_chunks == rec + k * 16             # one (sum, comp) state per point
+    monkeypatch.setenv("NX_TUNE_L2_CHUNK", "0")
+    assert _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_FWD, 0) == rec
+    monkeypatch.delenv("NX_TUNE_L2_CHUNK")
+    # slices that fit the L2 are not cut
+    assert _lib.nx_workspace_bytes(100_000, k, 1, _lib.NX_OP_FWD, 0) == -(-100_000 * 32 // 256) * 256
+
+
+def test_plan_launch_chunks_and_splits(monkeypatch):
+    # few points: the atoms are split across work-groups, with one state per split
+    few = _lib.nx_workspace_bytes(1_000_000, 65_536, 1, _lib.NX_OP_FWD, 1)
+    assert few > 1_000_000 * 32 + 65_536 * 16
+    # enough points to fill the chip: no split, no carried state ...
+    n, k = 5000, 1 << 20
+    rec = -(-n * 32 // 256) * 256
+    assert _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_FWD, 1) == rec
+    # ... until a small launch size forces chunks, which carry one state per point
+    monkeypatch.setenv("NX_TUNE_LAUNCH_PAIRS", str(1 << 24))
+    assert _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_FWD, 1) == rec + k * 16
