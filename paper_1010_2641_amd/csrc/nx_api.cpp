@@ -213,7 +213,7 @@ int run_sum(const char* fn, const nx::Plan& p, bool fwd, const void* xyz, const 
   }
   if (p.nsplit > 1) {
     if (fwd) e = nx::launch_fwd_reduce(p, partial, out, st);
-    else e = nx::launch_bwd_reduce(p, partial, out, outf, st);
+    else e = nx::launch_bwd_reduce(p, partial, f, out, outf, st);
     if (e != hipSuccess) return device_error(fn, e);
   }
   return ok();

@@ -8,10 +8,13 @@
 //     dL/df_j = conj(W_j),   W_j = sum_k conj(G_k) exp(2 i pi S_k . r_j)
 // (one complex sum per atom, computed only when asked for).
 //
-// In the FP64-phase mode the seed is taken in polar form, conj(G_k) =
-// |G_k| exp(2 i pi delta_k): delta_k rides in the FP64 phase and |G_k| is folded into S_k,
-// so that v_jk = |G_k| Im(f_j exp(2 i pi psi)) = |G_k| (fr s + fi c), psi = S_k.r_j +
-// delta_k, costs two FP32 operations (none for f_j = 1), and W_j += |G_k| (c + i s).
+// In the FP64-phase mode both factors are taken in polar form, conj(G_k) =
+// |G_k| exp(2 i pi delta_k) and f_j = |f_j| exp(2 i pi alpha_j): delta_k and alpha_j ride in
+// the FP64 phase psi = S_k.r_j + delta_k + alpha_j, |G_k| is folded into S_k, and |f_j|
+// leaves the sums altogether, so that
+//     dL/dr_j = -2 pi |f_j| sum_k |G_k| S_k sin(2 pi psi)          (sin only), and
+//     W_j = exp(-2 i pi alpha_j) sum_k |G_k| exp(2 i pi psi);
+// |f_j| and the rotation by arg f_j are applied once per atom to the finished sums.
 //
 // Layout: every lane owns Q atoms and keeps their position and the sums in registers;
 // the points are wave-uniform records (the paper's alternative of parallelising over
@@ -51,6 +54,13 @@ template <> struct PointOf<kPH64> { using type = PointPH; };
 
 constexpr float kTwoPi = 6.283185307179586f;
 constexpr double kTwoPiD = 6.283185307179586476925286766559;
+constexpr double kInvTwoPiD = 0.15915494309189533577;
+
+// arg(f) in cycles, FP64 (0 for f = 0, whose signed zeros carry no angle).
+__device__ __forceinline__ double arg_cycles(float fr, float fi) {
+  if (fr == 0.f && fi == 0.f) return 0.0;
+  return atan2(static_cast<double>(fi), static_cast<double>(fr)) * kInvTwoPiD;
+}
 
 // Sums carried per atom: 3 position components, plus Re W and Im W with GF.
 template <bool GF> struct NSum { static constexpr int value = GF ? 5 : 3; };
@@ -106,12 +116,14 @@ __device__ __forceinline__ PtRegs load_point_split(const uint4* sd, int u,
   return r;
 }
 
-// (c, s) of exp(2 i pi psi), psi = S.r + delta (delta includes the 1/2 of RED == 1).
-// The seed phase enters as the addend of the first fma.
-template <int RED>
+// (c, s) of exp(2 i pi psi), psi = S.r + delta + alpha (delta includes the 1/2 of
+// RED == 1; alpha = arg f in cycles, absent for f = 1).  The seed angle enters as the
+// addend of the first fma, the atom's angle as one FP64 add.
+template <int RED, int FK>
 __device__ __forceinline__ void cis_ph64_pt(const PtRegs& a, double x, double y, double z,
-                                            float& c, float& s) {
-  const double ph = __builtin_fma(a.sz, z, __builtin_fma(a.sy, y, __builtin_fma(a.sx, x, a.delta)));
+                                            double al, float& c, float& s) {
+  double ph = __builtin_fma(a.sz, z, __builtin_fma(a.sy, y, __builtin_fma(a.sx, x, a.delta)));
+  if constexpr (FK != 0) ph += al;
   float tf;
   if constexpr (RED == 0) tf = static_cast<float>(ph - __builtin_rint(ph));
   else tf = static_cast<float>(__builtin_amdgcn_fract(ph));
@@ -120,32 +132,51 @@ __device__ __forceinline__ void cis_ph64_pt(const PtRegs& a, double x, double y,
 }
 
 // One point's contribution to the FP64-phase group partials g[0..NS).
-template <int FK, bool GF>
-__device__ __forceinline__ void ph64_pair(float* g, const PtRegs& a, float fr, float fi, float c,
-                                          float s) {
-  float v;
-  if constexpr (FK == 0) v = s;
-  else v = __builtin_fmaf(fi, c, fr * s);
-  g[0] = __builtin_fmaf(v, a.gsx, g[0]);
-  g[1] = __builtin_fmaf(v, a.gsy, g[1]);
-  g[2] = __builtin_fmaf(v, a.gsz, g[2]);
+template <bool GF>
+__device__ __forceinline__ void ph64_pair(float* g, const PtRegs& a, float c, float s) {
+  g[0] = __builtin_fmaf(s, a.gsx, g[0]);
+  g[1] = __builtin_fmaf(s, a.gsy, g[1]);
+  g[2] = __builtin_fmaf(s, a.gsz, g[2]);
   if constexpr (GF) {
     g[3] = __builtin_fmaf(a.gmag, c, g[3]);
     g[4] = __builtin_fmaf(a.gmag, s, g[4]);
   }
 }
 
-// Writes the outputs of one atom from its total sums T[0..NS).
-template <bool GF>
-__device__ __forceinline__ void write_out(float* grad, float* gradf, int64_t j, const float* T) {
-  if (grad) {
-    grad[3 * j] = -kTwoPi * T[0];
-    grad[3 * j + 1] = -kTwoPi * T[1];
-    grad[3 * j + 2] = -kTwoPi * T[2];
-  }
-  if constexpr (GF) {
-    gradf[2 * j] = T[3];          // dL/df = conj(W)
-    gradf[2 * j + 1] = -T[4];
+// Writes the outputs of one atom from its total sums T[0..NS).  POLAR (FP64-phase mode
+// with complex f): the sums hold sin and exp of the phase shifted by arg f_j and no
+// |f_j|, so dL/dr = -2 pi |f| T and dL/df = conj(W) = (f / |f|) conj(T3 + i T4), formed in
+// FP64 and rounded once.
+template <bool GF, bool POLAR>
+__device__ __forceinline__ void write_out(float* grad, float* gradf, int64_t j, const float* T,
+                                          const float* __restrict__ f) {
+  if constexpr (POLAR) {
+    const double fr = f[2 * j], fi = f[2 * j + 1];
+    const double m = sqrt(fr * fr + fi * fi);
+    if (grad) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) grad[3 * j + d] = static_cast<float>(-kTwoPiD * m * T[d]);
+    }
+    if constexpr (GF) {
+      const double t3 = T[3], t4 = T[4];
+      if (m > 0.0) {
+        gradf[2 * j] = static_cast<float>((fr * t3 + fi * t4) / m);
+        gradf[2 * j + 1] = static_cast<float>((fi * t3 - fr * t4) / m);
+      } else {
+        gradf[2 * j] = T[3];
+        gradf[2 * j + 1] = -T[4];
+      }
+    }
+  } else {
+    if (grad) {
+      grad[3 * j] = -kTwoPi * T[0];
+      grad[3 * j + 1] = -kTwoPi * T[1];
+      grad[3 * j + 2] = -kTwoPi * T[2];
+    }
+    if constexpr (GF) {
+      gradf[2 * j] = T[3];          // dL/df = conj(W)
+      gradf[2 * j + 1] = -T[4];
+    }
   }
 }
 
@@ -167,6 +198,7 @@ __global__ __launch_bounds__(kThreads) void bwd_kernel(
 
   RReg x[Q], y[Q], z[Q];
   float fr[Q], fi[Q];
+  double al[Q];
   float sum[Q][NS], cmp[Q][NS];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -177,6 +209,7 @@ __global__ __launch_bounds__(kThreads) void bwd_kernel(
     z[q] = static_cast<RReg>(xyz[3 * jj + 2]);
     fr[q] = (FK && f) ? f[2 * jj] : 1.f;
     fi[q] = (FK && f) ? f[2 * jj + 1] : 0.f;
+    al[q] = (MODE == kPH64 && FK) ? arg_cycles(fr[q], fi[q]) : 0.0;
 #pragma unroll
     for (int d = 0; d < NS; ++d) {
       if (carry_in && j < N) {
@@ -230,8 +263,8 @@ __global__ __launch_bounds__(kThreads) void bwd_kernel(
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
             float c, s;
-            cis_ph64_pt<RED>(a, x[q], y[q], z[q], c, s);
-            ph64_pair<FK, GF>(g[q], a, fr[q], fi[q], c, s);
+            cis_ph64_pt<RED, FK>(a, x[q], y[q], z[q], al[q], c, s);
+            ph64_pair<GF>(g[q], a, c, s);
           }
         }
       } else {
@@ -240,8 +273,8 @@ __global__ __launch_bounds__(kThreads) void bwd_kernel(
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
             float c, s;
-            cis_ph64_pt<RED>(a, x[q], y[q], z[q], c, s);
-            ph64_pair<FK, GF>(g[q], a, fr[q], fi[q], c, s);
+            cis_ph64_pt<RED, FK>(a, x[q], y[q], z[q], al[q], c, s);
+            ph64_pair<GF>(g[q], a, c, s);
           }
         }
       }
@@ -261,7 +294,7 @@ __global__ __launch_bounds__(kThreads) void bwd_kernel(
         float T[NS];
 #pragma unroll
         for (int d = 0; d < NS; ++d) T[d] = sum[q][d] + cmp[q][d];
-        write_out<GF>(grad, gradf, j, T);
+        write_out<GF, MODE == kPH64 && FK != 0>(grad, gradf, j, T, f);
       } else {
 #pragma unroll
         for (int d = 0; d < NS; ++d) {
@@ -291,8 +324,7 @@ __global__ __launch_bounds__(kThreads) void bwd_split_kernel(
   const int nb = lb % blocks_n;
   const int sp = lb / blocks_n;
   const int64_t j0 = int64_t(nb) * (kThreads * Q) + threadIdx.x;
-  double x[Q], y[Q], z[Q];
-  float fr[Q], fi[Q];
+  double x[Q], y[Q], z[Q], al[Q];
   float sum[Q][NS], cmp[Q][NS];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -301,8 +333,7 @@ __global__ __launch_bounds__(kThreads) void bwd_split_kernel(
     x[q] = xyz[3 * jj];
     y[q] = xyz[3 * jj + 1];
     z[q] = xyz[3 * jj + 2];
-    fr[q] = (FK && f) ? f[2 * jj] : 1.f;
-    fi[q] = (FK && f) ? f[2 * jj + 1] : 0.f;
+    al[q] = (FK && f) ? arg_cycles(f[2 * jj], f[2 * jj + 1]) : 0.0;
 #pragma unroll
     for (int d = 0; d < NS; ++d) {
       if (carry_in && j < N) {
@@ -339,8 +370,8 @@ __global__ __launch_bounds__(kThreads) void bwd_split_kernel(
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
             float c, s;
-            cis_ph64_pt<RED>(a, x[q], y[q], z[q], c, s);
-            ph64_pair<FK, GF>(g[q], a, fr[q], fi[q], c, s);
+            cis_ph64_pt<RED, FK>(a, x[q], y[q], z[q], al[q], c, s);
+            ph64_pair<GF>(g[q], a, c, s);
           }
         }
       } else {
@@ -349,8 +380,8 @@ __global__ __launch_bounds__(kThreads) void bwd_split_kernel(
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
             float c, s;
-            cis_ph64_pt<RED>(a, x[q], y[q], z[q], c, s);
-            ph64_pair<FK, GF>(g[q], a, fr[q], fi[q], c, s);
+            cis_ph64_pt<RED, FK>(a, x[q], y[q], z[q], al[q], c, s);
+            ph64_pair<GF>(g[q], a, c, s);
           }
         }
       }
@@ -368,7 +399,7 @@ __global__ __launch_bounds__(kThreads) void bwd_split_kernel(
         float T[NS];
 #pragma unroll
         for (int d = 0; d < NS; ++d) T[d] = sum[q][d] + cmp[q][d];
-        write_out<GF>(grad, gradf, j, T);
+        write_out<GF, FK != 0>(grad, gradf, j, T, f);
       } else {
 #pragma unroll
         for (int d = 0; d < NS; ++d) {
@@ -449,9 +480,10 @@ __global__ __launch_bounds__(kThreads) void bwd_f64_kernel(
 }
 
 // Combine the split partials of every atom in split order (deterministic).
-template <bool GF>
+template <bool GF, bool POLAR>
 __global__ __launch_bounds__(kThreads) void bwd_reduce_kernel(const float* __restrict__ part,
                                                               int nsplit, int64_t N,
+                                                              const float* __restrict__ f,
                                                               float* __restrict__ grad,
                                                               float* __restrict__ gradf) {
   constexpr int NS = NSum<GF>::value;
@@ -467,7 +499,7 @@ __global__ __launch_bounds__(kThreads) void bwd_reduce_kernel(const float* __res
     }
     T[d] = s + cm;
   }
-  write_out<GF>(grad, gradf, j, T);
+  write_out<GF, POLAR>(grad, gradf, j, T, f);
 }
 
 template <bool GF>
@@ -642,8 +674,8 @@ hipError_t launch_bwd_chunk(const Plan& p, const void* rec, int64_t k_begin, int
   return p.gf ? bwd_dispatch_q<kF32, true>(p, b, st) : bwd_dispatch_q<kF32, false>(p, b, st);
 }
 
-hipError_t launch_bwd_reduce(const Plan& p, const void* partial, void* grad, void* gradf,
-                             hipStream_t st) {
+hipError_t launch_bwd_reduce(const Plan& p, const void* partial, const void* f, void* grad,
+                             void* gradf, hipStream_t st) {
   const int64_t N = p.lanes;
   const unsigned g = static_cast<unsigned>((N + kThreads - 1) / kThreads);
   if (p.mode == kF64) {
@@ -654,12 +686,15 @@ hipError_t launch_bwd_reduce(const Plan& p, const void* partial, void* grad, voi
       bwd_reduce_f64_kernel<false><<<g, kThreads, 0, st>>>(static_cast<const double*>(partial), p.nsplit, N,
                                                           static_cast<double*>(grad), static_cast<double*>(gradf));
   } else {
-    if (p.gf)
-      bwd_reduce_kernel<true><<<g, kThreads, 0, st>>>(static_cast<const float*>(partial), p.nsplit, N,
-                                                     static_cast<float*>(grad), static_cast<float*>(gradf));
-    else
-      bwd_reduce_kernel<false><<<g, kThreads, 0, st>>>(static_cast<const float*>(partial), p.nsplit, N,
-                                                      static_cast<float*>(grad), static_cast<float*>(gradf));
+    const auto* pa = static_cast<const float*>(partial);
+    const auto* ff = static_cast<const float*>(f);
+    auto* g0 = static_cast<float*>(grad);
+    auto* g1 = static_cast<float*>(gradf);
+    const bool polar = p.mode == kPH64 && p.fk;
+    if (p.gf && polar) bwd_reduce_kernel<true, true><<<g, kThreads, 0, st>>>(pa, p.nsplit, N, ff, g0, g1);
+    else if (p.gf) bwd_reduce_kernel<true, false><<<g, kThreads, 0, st>>>(pa, p.nsplit, N, ff, g0, g1);
+    else if (polar) bwd_reduce_kernel<false, true><<<g, kThreads, 0, st>>>(pa, p.nsplit, N, ff, g0, g1);
+    else bwd_reduce_kernel<false, false><<<g, kThreads, 0, st>>>(pa, p.nsplit, N, ff, g0, g1);
   }
   return hipGetLastError();
 }

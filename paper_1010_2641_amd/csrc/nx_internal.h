@@ -19,9 +19,7 @@ constexpr int kThreads = 256;          // work-group size of every sum kernel (4
 // Atom for the FP32 mode: coordinates and factor in FP32.
 struct alignas(16) AtomF32 { float x, y, z, fr, fi, pad0, pad1, pad2; };            // 32 B
 // Atom for the FP64-phase mode: coordinates widened (exactly) to FP64, the factor as
-// given (FP32 re, im).  (A polar form |f| exp(2 i pi alpha) would save one operation
-// per pair but rounds |f| to FP32 once per atom; that error is the same for every atom
-// of a species and adds coherently where the species' amplitudes cancel.)
+// given (FP32 re, im).
 struct alignas(16) AtomPH { double x, y, z; float fr, fi; };                         // 32 B
 // Atom for the all-FP64 path.
 struct alignas(16) AtomF64 { double x, y, z, fr, fi, pad; };                         // 48 B
@@ -124,8 +122,9 @@ hipError_t launch_fwd_reduce(const Plan& p, const void* partial, void* A, hipStr
 hipError_t launch_bwd_chunk(const Plan& p, const void* rec, int64_t k_begin, int64_t k_end,
                             int64_t per_split, const void* xyz, const void* f, void* partial,
                             void* grad, void* gradf, int carry_in, int direct, hipStream_t st);
-hipError_t launch_bwd_reduce(const Plan& p, const void* partial, void* grad, void* gradf,
-                             hipStream_t st);
+// f: the atom factors (complex f in the FP64-phase mode scales and rotates the sums).
+hipError_t launch_bwd_reduce(const Plan& p, const void* partial, const void* f, void* grad,
+                             void* gradf, hipStream_t st);
 
 // Species-factorised forward: A_k = sum_s fs[s][k] * sum_sp state_s[sp][k] (FP64
 // combination of the per-species (sum, comp) states), optionally the per-species sums.
