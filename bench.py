@@ -41,14 +41,15 @@ PEAK_TFLOPS = 2 * VALU_SLOTS_PER_S / 1e12
 # subtract) and rounding to FP32 = 3; adjoint: fract and rounding = 2.  sin and cos count
 # one issue slot each, the strict bound: at half rate they keep the VALU busy for two
 # slots, partly overlapped with other work (the VALU counters give ~1.75 slots each).
-#   forward, complex f: f (cos + i sin) accumulated with 4 fma
+#   forward, complex f: f in polar form m exp(2 i pi a), a the addend of the phase's first
+#                       fma; m (cos + i sin) accumulated with 2 fma
 #   forward, f = 1:     (cos, sin) accumulated with 2 add
 #   adjoint, complex f: f in polar form, its angle added to the phase (1 FP64 add), then
 #                       only sin is needed and T_d += (|G| S_d) sin (3); |f| scales the
 #                       finished sums; the seed phase rides in the first fma of the phase
 #   adjoint, f = 1:     only sin is needed, T_d += (3)
 ALG_SLOTS = {
-    ("fwd", "complex"): 3 + 3 + 2 + 4,
+    ("fwd", "complex"): 3 + 3 + 2 + 2,
     ("fwd", "unit"): 3 + 3 + 2 + 2,
     ("bwd", "complex"): 3 + 1 + 2 + 1 + 3,
     ("bwd", "unit"): 3 + 2 + 1 + 3,

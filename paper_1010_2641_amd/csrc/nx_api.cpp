@@ -146,7 +146,9 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
   int64_t launch_pairs = env_i64("NX_TUNE_LAUNCH_PAIRS", kLaunchPairs);
   if (launch_pairs < 1) launch_pairs = kLaunchPairs;
   size_t rec_size;
-  if (fwd) rec_size = p.mode == kF64 ? sizeof(AtomF64) : (p.mode == kPH64 ? sizeof(AtomPH) : sizeof(AtomF32));
+  if (fwd)
+    rec_size = p.mode == kF64 ? sizeof(AtomF64)
+                              : (p.mode == kPH64 ? (p.fk ? sizeof(AtomPHP) : sizeof(AtomPH)) : sizeof(AtomF32));
   else rec_size = p.mode == kF64 ? sizeof(PointF64) : (p.mode == kPH64 ? sizeof(PointPH) : sizeof(PointF32));
   int64_t chunk = lane_pad > 0 ? launch_pairs / lane_pad : p.stream;
   if (fwd && ceil_div(p.stream, p.nsplit) * int64_t(rec_size) > kL2Bytes &&

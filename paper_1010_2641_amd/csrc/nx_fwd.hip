@@ -17,7 +17,14 @@
 //          angle in turns), plain FP32 complex multiply-add -- the paper's arithmetic.
 //   PH64 : phase with FP64 fma (the products of FP32 inputs are exact in FP64),
 //          reduction modulo one cycle in FP64 (exact), one rounding to FP32, FP32
-//          v_sin/v_cos, f_j (cos + i sin) by FP32 fma; terms are summed in quads of
+//          v_sin/v_cos.  A complex f_j is taken in polar form m_j exp(2 i pi a_j):
+//          a_j (FP64, cycles) is the addend of the phase's first fma and the term is
+//          m_j (cos + i sin), two FP32 fma instead of four.  Every atom's record also
+//          carries a pseudo-random half turn (m_j -> -m_j, a_j -> a_j + 1/2, the same
+//          factor): the error of the hardware sin/cos is a fixed periodic function of
+//          the reduced phase whose harmonics p add up over the atoms like amplitudes at
+//          p S_k; the random signs make the even ones (among them the constant term,
+//          about -1.2e-9 per unit term) add up incoherently.  Terms are summed in quads of
 //          consecutive atoms, quads into a group partial, and every `GRP` atoms the
 //          group partial is folded into a two-word (sum, comp) accumulator by Kahan's
 //          compensated addition (so FP32 roundings happen only at the magnitude of a
@@ -48,9 +55,12 @@ __device__ __forceinline__ void kahan_acc(float& s, float& c, float g) {
   s = t;
 }
 
-template <int MODE> struct AtomOf;
-template <> struct AtomOf<kF32> { using type = AtomF32; };
-template <> struct AtomOf<kPH64> { using type = AtomPH; };
+// Atom record of a (mode, factor kind): the FP64-phase mode keeps f = 1 and complex f in
+// different records (the polar record is 16 bytes longer).
+template <int MODE, int FK> struct AtomOf;
+template <int FK> struct AtomOf<kF32, FK> { using type = AtomF32; };
+template <> struct AtomOf<kPH64, 0> { using type = AtomPH; };
+template <> struct AtomOf<kPH64, 1> { using type = AtomPHP; };
 
 // exp(2 i pi phase) for the FP64-phase mode as (c, s) in FP32, phase = S.r, plus 1/2
 // (an inline constant of the first fma) in the RED == 1 variant.
@@ -58,31 +68,46 @@ template <> struct AtomOf<kPH64> { using type = AtomPH; };
 //   RED 1: u = fract(phase + 1/2) in [0, 1) (exact), rounded once to FP32; then
 //          exp(2 i pi u) = -exp(2 i pi S.r) and the caller flips the sign of the
 //          group sums.
+// For the polar record the phase also carries a = arg f (plus the 1/2 of RED == 1,
+// added when the record is packed), as the addend of the first fma.
 template <int RED>
-__device__ __forceinline__ void cis_ph64(double sx, double sy, double sz, const AtomPH& a,
-                                         float& c, float& s) {
+__device__ __forceinline__ double phase_of(double sx, double sy, double sz, const AtomPH& a) {
+  if constexpr (RED == 0) return __builtin_fma(sz, a.z, __builtin_fma(sy, a.y, sx * a.x));
+  else return __builtin_fma(sz, a.z, __builtin_fma(sy, a.y, __builtin_fma(sx, a.x, 0.5)));
+}
+template <int RED>
+__device__ __forceinline__ double phase_of(double sx, double sy, double sz, const AtomPHP& a) {
+  return __builtin_fma(sz, a.z, __builtin_fma(sy, a.y, __builtin_fma(sx, a.x, a.a)));
+}
+
+template <int RED, typename AT>
+__device__ __forceinline__ void cis_ph64(double sx, double sy, double sz, const AT& a, float& c,
+                                         float& s) {
+  const double ph = phase_of<RED>(sx, sy, sz, a);
   float tf;
-  if constexpr (RED == 0) {
-    const double ph = __builtin_fma(sz, a.z, __builtin_fma(sy, a.y, sx * a.x));
-    tf = static_cast<float>(ph - __builtin_rint(ph));
-  } else {
-    const double ph = __builtin_fma(sz, a.z, __builtin_fma(sy, a.y, __builtin_fma(sx, a.x, 0.5)));
-    tf = static_cast<float>(__builtin_amdgcn_fract(ph));
-  }
+  if constexpr (RED == 0) tf = static_cast<float>(ph - __builtin_rint(ph));
+  else tf = static_cast<float>(__builtin_amdgcn_fract(ph));
   c = __builtin_amdgcn_cosf(tf);
   s = __builtin_amdgcn_sinf(tf);
 }
 
-// f (c + i s): the first term of a running sum (f = 1 when FK == 0).
-template <int FK>
-__device__ __forceinline__ void cterm(float& gr, float& gi, float fr, float fi, float c, float s) {
-  if constexpr (FK == 0) {
-    gr = c;
-    gi = s;
-  } else {
-    gr = __builtin_fmaf(-fi, s, fr * c);
-    gi = __builtin_fmaf(fi, c, fr * s);
-  }
+// FP64-phase terms: the first term of a running sum, and the sum plus one more term.
+// f = 1 (AtomPH): c + i s; polar f (AtomPHP): |f| (c + i s), the angle being in the phase.
+__device__ __forceinline__ void first_term(const AtomPH&, float c, float s, float& gr, float& gi) {
+  gr = c;
+  gi = s;
+}
+__device__ __forceinline__ void first_term(const AtomPHP& a, float c, float s, float& gr, float& gi) {
+  gr = a.m * c;
+  gi = a.m * s;
+}
+__device__ __forceinline__ void add_term(const AtomPH&, float c, float s, float& gr, float& gi) {
+  gr += c;
+  gi += s;
+}
+__device__ __forceinline__ void add_term(const AtomPHP& a, float c, float s, float& gr, float& gi) {
+  gr = __builtin_fmaf(a.m, c, gr);
+  gi = __builtin_fmaf(a.m, s, gi);
 }
 
 // (gr, gi) += f * (c + i s) with FP32 fma; f = 1 when FK == 0 (the FP32 mode).
@@ -103,7 +128,7 @@ __device__ __forceinline__ void cmac(float& gr, float& gi, float fr, float fi, f
 // Grid: blocks_k * nsplit work-groups; blockIdx = sp * blocks_k + kb.
 template <int MODE, int P, int FK, int GRP, int RED>
 __global__ __launch_bounds__(kThreads) void fwd_kernel(
-    const typename AtomOf<MODE>::type* __restrict__ rec, int a_begin, int a_end, int per_split,
+    const typename AtomOf<MODE, FK>::type* __restrict__ rec, int a_begin, int a_end, int per_split,
     const float* __restrict__ S, int64_t K, int blocks_k, float4* __restrict__ part,
     float2* __restrict__ A, int carry_in, int direct) {
   using SReg = typename std::conditional<MODE == kPH64, double, float>::type;
@@ -159,13 +184,13 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(
         float qr[P], qi[P];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const AtomPH a = rec[j + 4 * q + u];
+          const auto a = rec[j + 4 * q + u];
 #pragma unroll
           for (int p = 0; p < P; ++p) {
             float c, s;
             cis_ph64<RED>(sx[p], sy[p], sz[p], a, c, s);
-            if (u == 0) cterm<FK>(qr[p], qi[p], a.fr, a.fi, c, s);
-            else cmac<FK>(qr[p], qi[p], a.fr, a.fi, c, s);
+            if (u == 0) first_term(a, c, s, qr[p], qi[p]);
+            else add_term(a, c, s, qr[p], qi[p]);
           }
         }
 #pragma unroll
@@ -185,12 +210,12 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(
 #pragma unroll
       for (int p = 0; p < P; ++p) { gr[p] = 0.f; gi[p] = 0.f; }
       for (; j < j1; ++j) {
-        const AtomPH a = rec[j];
+        const auto a = rec[j];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
           float c, s;
           cis_ph64<RED>(sx[p], sy[p], sz[p], a, c, s);
-          cmac<FK>(gr[p], gi[p], a.fr, a.fi, c, s);
+          add_term(a, c, s, gr[p], gi[p]);
         }
       }
 #pragma unroll
@@ -217,11 +242,12 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(
 // those of fwd_kernel (tiles are whole groups), so the result is bitwise the same.
 template <int P, int FK, int GRP>
 __global__ __launch_bounds__(kThreads) void fwd_lds_kernel(
-    const AtomPH* __restrict__ rec, int a_begin, int a_end, int per_split,
+    const typename AtomOf<kPH64, FK>::type* __restrict__ rec, int a_begin, int a_end, int per_split,
     const float* __restrict__ S, int64_t K, int blocks_k, float4* __restrict__ part,
     float2* __restrict__ A, int carry_in, int direct) {
   static_assert(kThreads % GRP == 0, "tiles must hold whole groups");
-  __shared__ AtomPH tile[kThreads];
+  using AT = typename AtomOf<kPH64, FK>::type;
+  __shared__ AT tile[kThreads];
   const int lb = xcd_major_block(blockIdx.x, gridDim.x);
   const int kb = lb % blocks_k;
   const int sp = lb / blocks_k;
@@ -257,13 +283,13 @@ __global__ __launch_bounds__(kThreads) void fwd_lds_kernel(
         float qr[P], qi[P];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const AtomPH a = tile[u0 + 4 * q + u];
+          const AT a = tile[u0 + 4 * q + u];
 #pragma unroll
           for (int p = 0; p < P; ++p) {
             float c, s;
             cis_ph64<0>(sx[p], sy[p], sz[p], a, c, s);
-            if (u == 0) cterm<FK>(qr[p], qi[p], a.fr, a.fi, c, s);
-            else cmac<FK>(qr[p], qi[p], a.fr, a.fi, c, s);
+            if (u == 0) first_term(a, c, s, qr[p], qi[p]);
+            else add_term(a, c, s, qr[p], qi[p]);
           }
         }
 #pragma unroll
@@ -283,12 +309,12 @@ __global__ __launch_bounds__(kThreads) void fwd_lds_kernel(
 #pragma unroll
       for (int p = 0; p < P; ++p) { gr[p] = 0.f; gi[p] = 0.f; }
       for (int u = u0; u < nt; ++u) {
-        const AtomPH a = tile[u];
+        const AT a = tile[u];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
           float c, s;
           cis_ph64<0>(sx[p], sy[p], sz[p], a, c, s);
-          cmac<FK>(gr[p], gi[p], a.fr, a.fi, c, s);
+          add_term(a, c, s, gr[p], gi[p]);
         }
       }
 #pragma unroll
@@ -411,7 +437,7 @@ __global__ __launch_bounds__(kThreads) void pack_atoms_kernel(const void* __rest
       const float* f = static_cast<const float*>(f_v);
       const float fr = f ? f[2 * j] : 1.f;
       const float fi = f ? f[2 * j + 1] : 0.f;
-      if constexpr (MODE == kPH64) {
+      if constexpr (MODE == kPH64) {                  // f = 1 (complex f: the polar pack)
         AtomPH r;
         r.x = xyz[3 * j]; r.y = xyz[3 * j + 1]; r.z = xyz[3 * j + 2];   // exact widening
         r.fr = fr; r.fi = fi;
@@ -426,6 +452,55 @@ __global__ __launch_bounds__(kThreads) void pack_atoms_kernel(const void* __rest
   }
 }
 
+// SplitMix64's output function (Steele, Lea and Flood, OOPSLA 2014) of the atom index:
+// 64 pseudo-random bits, the same for an atom on every call; atom_uniform takes the top
+// 53 as a double in [0, 1).
+__device__ __forceinline__ uint64_t atom_bits(int64_t j) {
+  uint64_t z = static_cast<uint64_t>(j) + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ double atom_uniform(int64_t j) {
+  return static_cast<double>(atom_bits(j) >> 11) * 0x1.0p-53;
+}
+
+// m >= 0 to FP32 by unbiased (stochastic) rounding: the FP32 value above m with
+// probability equal to the fraction of the gap by which m exceeds the value below it,
+// drawn from atom_uniform(j).  The expected result is m, so the rounding errors of atoms
+// with equal factors are independent and add up incoherently instead of as one
+// relative error of their species' amplitude.
+__device__ __forceinline__ float round_unbiased(double m, int64_t j) {
+  float lo = static_cast<float>(m);
+  if (static_cast<double>(lo) > m) lo = __uint_as_float(__float_as_uint(lo) - 1u);
+  const float hi = __uint_as_float(__float_as_uint(lo) + 1u);
+  const double t = (m - static_cast<double>(lo)) / (static_cast<double>(hi) - static_cast<double>(lo));
+  return atom_uniform(j) < t ? hi : lo;
+}
+
+// Polar atom records of the FP64-phase forward with complex f: a = arg f in cycles (0
+// for f = 0) plus the reduction offset, m = |f| from FP64 and rounded without bias, and
+// the atom's half turn (lowest hash bit): m -> -m and a -> a + 1/2, which leaves
+// m exp(2 i pi a) = f unchanged.
+__global__ __launch_bounds__(kThreads) void pack_atoms_polar_kernel(const float* __restrict__ xyz,
+                                                                    const float* __restrict__ f,
+                                                                    int64_t n, AtomPHP* __restrict__ rec,
+                                                                    double offset) {
+  for (int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x; j < n;
+       j += int64_t(gridDim.x) * kThreads) {
+    const double fr = f[2 * j], fi = f[2 * j + 1];
+    AtomPHP r;
+    r.x = xyz[3 * j]; r.y = xyz[3 * j + 1]; r.z = xyz[3 * j + 2];       // exact widening
+    const bool zero = fr == 0.0 && fi == 0.0;
+    const bool flip = (atom_bits(j) & 1u) != 0;
+    r.a = (zero ? 0.0 : atan2(fi, fr) * 0.15915494309189533577) + offset + (flip ? 0.5 : 0.0);
+    const float m = round_unbiased(sqrt(fr * fr + fi * fi), j);
+    r.m = flip ? -m : m;
+    r.pad0 = r.pad1 = r.pad2 = 0.f;
+    rec[j] = r;
+  }
+}
+
 unsigned grid_for(int64_t n) {
   int64_t b = (n + kThreads - 1) / kThreads;
   if (b < 1) b = 1;
@@ -437,7 +512,7 @@ template <int MODE, int P, int FK>
 hipError_t fwd_dispatch_red(const Plan& p, const void* rec, int64_t a_begin, int64_t a_end,
                             int64_t per_split, const void* S, void* partial, void* A,
                             int carry_in, int direct, hipStream_t st, int red) {
-  using AT = typename AtomOf<MODE>::type;
+  using AT = typename AtomOf<MODE, FK>::type;
   const dim3 grid(static_cast<unsigned>(p.blocks * p.nsplit));
   const auto* r = static_cast<const AT*>(rec);
   const auto* s = static_cast<const float*>(S);
@@ -520,8 +595,11 @@ hipError_t launch_pack_atoms(int mode, int red, const void* xyz, const void* f, 
                              void* rec, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const unsigned g = grid_for(n);
-  (void)red;   // the forward's reduction offset is an inline constant of the kernel
+  // f = 1: the reduction offset is an inline constant of the kernel; polar records carry it
   if (mode == kF64) pack_atoms_kernel<kF64><<<g, kThreads, 0, st>>>(xyz, f, n, rec);
+  else if (mode == kPH64 && f)
+    pack_atoms_polar_kernel<<<g, kThreads, 0, st>>>(static_cast<const float*>(xyz), static_cast<const float*>(f),
+                                                    n, static_cast<AtomPHP*>(rec), red == 1 ? 0.5 : 0.0);
   else if (mode == kPH64) pack_atoms_kernel<kPH64><<<g, kThreads, 0, st>>>(xyz, f, n, rec);
   else pack_atoms_kernel<kF32><<<g, kThreads, 0, st>>>(xyz, f, n, rec);
   return hipGetLastError();

@@ -18,9 +18,14 @@ constexpr int kThreads = 256;          // work-group size of every sum kernel (4
 
 // Atom for the FP32 mode: coordinates and factor in FP32.
 struct alignas(16) AtomF32 { float x, y, z, fr, fi, pad0, pad1, pad2; };            // 32 B
-// Atom for the FP64-phase mode: coordinates widened (exactly) to FP64, the factor as
-// given (FP32 re, im).
+// Atom for the FP64-phase mode with f = 1: coordinates widened (exactly) to FP64
+// (fr, fi are written as 1, 0 and not read).
 struct alignas(16) AtomPH { double x, y, z; float fr, fi; };                         // 32 B
+// Atom for the FP64-phase mode with complex f, in polar form f = m exp(2 i pi a):
+// coordinates widened to FP64; a (FP64, cycles) = arg f plus the reduction offset of the
+// variant plus the atom's half turn, if it has one; m (FP32) = |f| rounded without bias
+// (stochastic rounding keyed by the atom index), negated for a half turn.
+struct alignas(16) AtomPHP { double x, y, z, a; float m, pad0, pad1, pad2; };        // 48 B
 // Atom for the all-FP64 path.
 struct alignas(16) AtomF64 { double x, y, z, fr, fi, pad; };                         // 48 B
 // Point for the FP32-mode adjoint: S and the seed G.

@@ -200,15 +200,17 @@ def test_missing_library_fails_loudly(monkeypatch):
 def test_plan_l2_sized_forward_chunks(monkeypatch):
     """The forward cuts its launches when a split's slice of atom records exceeds an
     XCD's L2: the carried running sums then appear in the workspace (host-side plan)."""
-    n, k = 203_557, 2_097_152                      # 6.5 MB of records, one split
-    rec = -(-n * 32 // 256) * 256
+    n, k = 203_557, 2_097_152                      # one split; 48-byte polar records (complex f)
+    rec = -(-n * 48 // 256) * 256
     with_chunks = _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_FWD, 0)
     assert with_chunks == rec + k * 16             # one (sum, comp) state per point
     monkeypatch.setenv("NX_TUNE_L2_CHUNK", "0")
     assert _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_FWD, 0) == rec
     monkeypatch.delenv("NX_TUNE_L2_CHUNK")
-    # slices that fit the L2 are not cut
-    assert _lib.nx_workspace_bytes(100_000, k, 1, _lib.NX_OP_FWD, 0) == -(-100_000 * 32 // 256) * 256
+    # slices that fit the L2 are not cut: 80,000 polar records, or 120,000 of 32 bytes (f = 1)
+    assert _lib.nx_workspace_bytes(80_000, k, 1, _lib.NX_OP_FWD, 0) == -(-80_000 * 48 // 256) * 256
+    assert _lib.nx_workspace_bytes(120_000, k, 1, _lib.NX_OP_FWD, 1) == -(-120_000 * 32 // 256) * 256
+    assert _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_FWD, 1) == -(-n * 32 // 256) * 256 + k * 16
 
 
 def test_plan_launch_chunks_and_splits(monkeypatch):
