@@ -70,10 +70,15 @@ typedef enum {
  *               Its error grows with |S.r| and with the number of atoms
  *               (the single-precision discussion of Section 2.3).
  *   NX_F32_PH64 the phase S.r is formed and reduced modulo one cycle in FP64 (exact for
- *               FP32 inputs up to the final rounding), sin/cos and the complex
- *               multiply-add run in FP32, and the sums are compensated (FP32
- *               group partial sums folded into a two-word FP32 accumulator by Kahan's
- *               compensated addition).  FP64 is used in the phase reduction only.  */
+ *               FP32 inputs up to the final rounding), sin/cos and the multiply-adds
+ *               run in FP32, and the sums are compensated (FP32 group partial sums
+ *               folded into a two-word FP32 accumulator by Kahan's compensated
+ *               addition).  FP64 is used in the phase reduction only.  A complex f_j
+ *               enters in polar form, its angle added to the FP64 phase.  In the
+ *               forward every compensated group also carries a pseudo-random eighth
+ *               turn, added to its phases and undone when the group is folded in, so
+ *               that the periodic error of the hardware sin/cos does not add up
+ *               coherently over lattice sites.  */
 typedef enum { NX_F32 = 0, NX_F32_PH64 = 1 } nx_mode;
 
 /* Operation selector for nx_workspace_bytes. */

@@ -98,15 +98,16 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
   p.stream = fwd ? n_atoms : n_points;
   // Defaults from launch-shape and accuracy sweeps on MI355X.  Forward, FP64-phase
   // mode: the centred reduction (its FP32 rounding of the reduced phase is half that of
-  // fract's, which decides the pointwise intensity error at the weakest points), and
-  // 8-atom groups for few atoms (|A| peaks at N |f|, so each term weighs more), 16 above.
+  // fract's, which decides the pointwise intensity error at the weakest points: fract is
+  // 8 % faster but took a strained 100^3 cube from 2.0e-6 to 7.7e-6), and 8-atom groups
+  // for few atoms (|A| peaks at N |f|, so each term weighs more), 16 above.
   // Adjoint (judged normwise): fract, 32-point groups, two atoms per lane.
   if (fwd) {
     const bool small = p.stream < 65536;
     p.red = 0;
-    // complex factors: atom tiles staged in LDS (5 % faster than scalar loads on a
-    // 200k-atom, 2M-point map); f = 1: scalar loads (there LDS is 1-3 % slower)
-    p.lds = (p.mode == kPH64 && p.fk == 1) ? 1 : 0;
+    // atom tiles staged in LDS: the records' phase addend would be a second scalar
+    // operand of the first fma, which the scalar-load form has to copy to VGPRs
+    p.lds = p.mode == kPH64 ? 1 : 0;
     p.grp = (p.mode == kPH64 && small) ? 8 : 16;
     if (p.mode == kF64) p.per_lane = p.lanes >= 262144 ? 2 : 1;
     else p.per_lane = (p.lanes >= 32768 && p.lanes < 1048576) ? 2 : 1;
@@ -146,9 +147,7 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
   int64_t launch_pairs = env_i64("NX_TUNE_LAUNCH_PAIRS", kLaunchPairs);
   if (launch_pairs < 1) launch_pairs = kLaunchPairs;
   size_t rec_size;
-  if (fwd)
-    rec_size = p.mode == kF64 ? sizeof(AtomF64)
-                              : (p.mode == kPH64 ? (p.fk ? sizeof(AtomPHP) : sizeof(AtomPH)) : sizeof(AtomF32));
+  if (fwd) rec_size = p.mode == kF64 ? sizeof(AtomF64) : (p.mode == kPH64 ? sizeof(AtomPH) : sizeof(AtomF32));
   else rec_size = p.mode == kF64 ? sizeof(PointF64) : (p.mode == kPH64 ? sizeof(PointPH) : sizeof(PointF32));
   int64_t chunk = lane_pad > 0 ? launch_pairs / lane_pad : p.stream;
   if (fwd && ceil_div(p.stream, p.nsplit) * int64_t(rec_size) > kL2Bytes &&
@@ -201,7 +200,7 @@ int run_sum(const char* fn, const nx::Plan& p, bool fwd, const void* xyz, const 
   void* rec = base;
   void* partial = p.partial_bytes ? base + p.rec_bytes : nullptr;
   hipError_t e;
-  if (fwd) e = nx::launch_pack_atoms(p.mode, p.red, xyz, f, p.stream, rec, st);
+  if (fwd) e = nx::launch_pack_atoms(p.mode, p.red, p.grp, xyz, f, p.stream, rec, st);
   else e = nx::launch_pack_points(p.mode, p.red, S, G, p.stream, rec, st);
   if (e != hipSuccess) return device_error(fn, e);
   for (int64_t c = 0; c < p.nchunks; ++c) {
@@ -449,14 +448,17 @@ int nx_scatter_fwd_species(const float* xyz, int64_t n_atoms, const int64_t* spe
                 need, ws_bytes);
   const hipStream_t st = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
-  const nx::Plan p0 = nx::make_plan(nx::kOpFwd, mode, n_atoms, n_points, 1);
-  hipError_t e = nx::launch_pack_atoms(p0.mode, p0.red, xyz, nullptr, n_atoms, base, st);
-  if (e != hipSuccess) return device_error(fn, e);
+  hipError_t e;
   nx::SpeciesStates ss{};
   ss.n = n_species;
   for (int s = 0; s < n_species; ++s) {
     const int64_t a0 = species_start[s];
     const nx::Plan ps = nx::make_plan(nx::kOpFwd, mode, species_start[s + 1] - a0, n_points, 1);
+    // each species' records are packed with its own plan (variant, group size), their
+    // groups counted from the species' first atom; they sit at the species' place in ws
+    const size_t rsz = ps.mode == nx::kPH64 ? sizeof(nx::AtomPH) : sizeof(nx::AtomF32);
+    e = nx::launch_pack_atoms(ps.mode, ps.red, ps.grp, xyz + 3 * a0, nullptr, ps.stream, base + a0 * rsz, st);
+    if (e != hipSuccess) return device_error(fn, e);
     void* state = base + off[s];
     ss.state[s] = state;
     ss.nsplit[s] = ps.nsplit;

@@ -7,9 +7,11 @@
 // every packed atom record is a broadcast.  Two forms (the paper shares atom
 // coordinates between threads through on-chip memory for the same reason, Section 2.2):
 //   fwd_kernel     -- records fetched with scalar loads into SGPRs and used as SGPR
-//                     operands: no LDS traffic, no barriers (used for f_j = 1);
+//                     operands: no LDS traffic, no barriers (the FP32 mode; in the
+//                     FP64-phase mode the phase addend is a second scalar operand of an
+//                     fma and costs two copies per atom);
 //   fwd_lds_kernel -- records staged per work-group in LDS tiles and read back as
-//                     broadcasts (used for complex f_j, where it measured faster).
+//                     broadcasts (the FP64-phase default).
 // Both sum in the same order, so their results are bitwise equal.
 //
 // Per (atom, point) pair:
@@ -17,18 +19,23 @@
 //          angle in turns), plain FP32 complex multiply-add -- the paper's arithmetic.
 //   PH64 : phase with FP64 fma (the products of FP32 inputs are exact in FP64),
 //          reduction modulo one cycle in FP64 (exact), one rounding to FP32, FP32
-//          v_sin/v_cos.  A complex f_j is taken in polar form m_j exp(2 i pi a_j):
-//          a_j (FP64, cycles) is the addend of the phase's first fma and the term is
-//          m_j (cos + i sin), two FP32 fma instead of four.  Every atom's record also
-//          carries a pseudo-random half turn (m_j -> -m_j, a_j -> a_j + 1/2, the same
-//          factor): the error of the hardware sin/cos is a fixed periodic function of
-//          the reduced phase whose harmonics p add up over the atoms like amplitudes at
-//          p S_k; the random signs make the even ones (among them the constant term,
-//          about -1.2e-9 per unit term) add up incoherently.  Terms are summed in quads of
-//          consecutive atoms, quads into a group partial, and every `GRP` atoms the
-//          group partial is folded into a two-word (sum, comp) accumulator by Kahan's
-//          compensated addition (so FP32 roundings happen only at the magnitude of a
-//          group partial, never at that of the whole sum).
+//          v_sin/v_cos.  A complex f_j is taken in polar form m_j exp(2 i pi alpha_j):
+//          alpha_j (FP64, cycles) rides in the addend of the phase's first fma and the
+//          term is m_j (cos + i sin), two FP32 fma instead of four.  Terms are summed in
+//          quads of consecutive atoms, quads into a group partial, and every `GRP` atoms
+//          the group partial is folded into a two-word (sum, comp) accumulator by
+//          Kahan's compensated addition (so FP32 roundings happen only at the magnitude
+//          of a group partial, never at that of the whole sum).
+//          Every group also carries a pseudo-random eighth turn k/8 (k = 0..7, a hash
+//          of the group's index): the records of its atoms add k/8 to the phase addend,
+//          and the group partial is turned back by exp(-2 i pi k/8) inside the first
+//          addition of the compensated fold (two fma instead of one add).  The error of
+//          the hardware sin/cos is a fixed periodic function of the reduced phase; its
+//          harmonic p adds up over the atoms like an amplitude at p S_k, coherently
+//          wherever that amplitude is large.  Under the turns harmonic p picks up the
+//          factor exp(2 i pi (p - 1) k/8) per group, so every harmonic but p = 1 (a
+//          relative scale error) and p = 1 mod 8 (measured negligible) adds up
+//          incoherently.
 //   F64  : phase, reduction, sincospi and sums all in FP64.
 #include "nx_internal.h"
 
@@ -45,45 +52,36 @@ __device__ __forceinline__ void two_sum_acc(float& s, float& c, float g) {
   s = t;
 }
 
-// Kahan's compensated addition with the correction kept as the error to add (sum + comp
+// Kahan's compensated addition, with the correction kept as the error to add (sum + comp
 // is the running total): the error of s + y is recovered exactly while |s| >= |y|, which
-// holds once the running sum exceeds one group partial.  Four FP32 operations.
-__device__ __forceinline__ void kahan_acc(float& s, float& c, float g) {
-  const float y = g + c;
-  const float t = s + y;
-  c = y - (t - s);
-  s = t;
+// holds once the running sum exceeds one group partial.  Here the addend is a group
+// partial turned by (ck + i sk), and the turn takes the place of the first addition
+// (two fma per component instead of one add): five FP32 operations per component.
+__device__ __forceinline__ void kahan_rot(float& sr, float& cr, float& si, float& ci, float gr,
+                                          float gi, float ck, float sk) {
+  const float yr = __builtin_fmaf(ck, gr, __builtin_fmaf(-sk, gi, cr));
+  const float yi = __builtin_fmaf(ck, gi, __builtin_fmaf(sk, gr, ci));
+  const float tr = sr + yr;
+  cr = yr - (tr - sr);
+  sr = tr;
+  const float ti = si + yi;
+  ci = yi - (ti - si);
+  si = ti;
 }
 
-// Atom record of a (mode, factor kind): the FP64-phase mode keeps f = 1 and complex f in
-// different records (the polar record is 16 bytes longer).
-template <int MODE, int FK> struct AtomOf;
-template <int FK> struct AtomOf<kF32, FK> { using type = AtomF32; };
-template <> struct AtomOf<kPH64, 0> { using type = AtomPH; };
-template <> struct AtomOf<kPH64, 1> { using type = AtomPHP; };
+template <int MODE> struct AtomOf;
+template <> struct AtomOf<kF32> { using type = AtomF32; };
+template <> struct AtomOf<kPH64> { using type = AtomPH; };
 
-// exp(2 i pi phase) for the FP64-phase mode as (c, s) in FP32, phase = S.r, plus 1/2
-// (an inline constant of the first fma) in the RED == 1 variant.
-//   RED 0: t = phase - rint(phase) in [-1/2, 1/2] (exact), rounded once to FP32;
-//   RED 1: u = fract(phase + 1/2) in [0, 1) (exact), rounded once to FP32; then
-//          exp(2 i pi u) = -exp(2 i pi S.r) and the caller flips the sign of the
-//          group sums.
-// For the polar record the phase also carries a = arg f (plus the 1/2 of RED == 1,
-// added when the record is packed), as the addend of the first fma.
+// exp(2 i pi psi) for the FP64-phase mode as (c, s) in FP32, psi = S.r + a, where the
+// record's addend a holds arg f, the group's eighth turn and the variant's offset:
+//   RED 0: t = psi - rint(psi) in [-1/2, 1/2] (exact), rounded once to FP32;
+//   RED 1: u = fract(psi + 1/2) in [0, 1) (exact), rounded once to FP32, so that
+//          exp(2 i pi u) = -exp(2 i pi psi); the records' turn-back factor carries the -1.
 template <int RED>
-__device__ __forceinline__ double phase_of(double sx, double sy, double sz, const AtomPH& a) {
-  if constexpr (RED == 0) return __builtin_fma(sz, a.z, __builtin_fma(sy, a.y, sx * a.x));
-  else return __builtin_fma(sz, a.z, __builtin_fma(sy, a.y, __builtin_fma(sx, a.x, 0.5)));
-}
-template <int RED>
-__device__ __forceinline__ double phase_of(double sx, double sy, double sz, const AtomPHP& a) {
-  return __builtin_fma(sz, a.z, __builtin_fma(sy, a.y, __builtin_fma(sx, a.x, a.a)));
-}
-
-template <int RED, typename AT>
-__device__ __forceinline__ void cis_ph64(double sx, double sy, double sz, const AT& a, float& c,
+__device__ __forceinline__ void cis_ph64(double sx, double sy, double sz, const AtomPH& a, float& c,
                                          float& s) {
-  const double ph = phase_of<RED>(sx, sy, sz, a);
+  const double ph = __builtin_fma(sz, a.z, __builtin_fma(sy, a.y, __builtin_fma(sx, a.x, a.a)));
   float tf;
   if constexpr (RED == 0) tf = static_cast<float>(ph - __builtin_rint(ph));
   else tf = static_cast<float>(__builtin_amdgcn_fract(ph));
@@ -92,22 +90,26 @@ __device__ __forceinline__ void cis_ph64(double sx, double sy, double sz, const 
 }
 
 // FP64-phase terms: the first term of a running sum, and the sum plus one more term.
-// f = 1 (AtomPH): c + i s; polar f (AtomPHP): |f| (c + i s), the angle being in the phase.
-__device__ __forceinline__ void first_term(const AtomPH&, float c, float s, float& gr, float& gi) {
-  gr = c;
-  gi = s;
+// f = 1 (FK == 0): c + i s; complex f: m (c + i s), its angle being in the phase.
+template <int FK>
+__device__ __forceinline__ void first_term(const AtomPH& a, float c, float s, float& gr, float& gi) {
+  if constexpr (FK == 0) {
+    gr = c;
+    gi = s;
+  } else {
+    gr = a.m * c;
+    gi = a.m * s;
+  }
 }
-__device__ __forceinline__ void first_term(const AtomPHP& a, float c, float s, float& gr, float& gi) {
-  gr = a.m * c;
-  gi = a.m * s;
-}
-__device__ __forceinline__ void add_term(const AtomPH&, float c, float s, float& gr, float& gi) {
-  gr += c;
-  gi += s;
-}
-__device__ __forceinline__ void add_term(const AtomPHP& a, float c, float s, float& gr, float& gi) {
-  gr = __builtin_fmaf(a.m, c, gr);
-  gi = __builtin_fmaf(a.m, s, gi);
+template <int FK>
+__device__ __forceinline__ void add_term(const AtomPH& a, float c, float s, float& gr, float& gi) {
+  if constexpr (FK == 0) {
+    gr += c;
+    gi += s;
+  } else {
+    gr = __builtin_fmaf(a.m, c, gr);
+    gi = __builtin_fmaf(a.m, s, gi);
+  }
 }
 
 // (gr, gi) += f * (c + i s) with FP32 fma; f = 1 when FK == 0 (the FP32 mode).
@@ -128,7 +130,7 @@ __device__ __forceinline__ void cmac(float& gr, float& gi, float fr, float fi, f
 // Grid: blocks_k * nsplit work-groups; blockIdx = sp * blocks_k + kb.
 template <int MODE, int P, int FK, int GRP, int RED>
 __global__ __launch_bounds__(kThreads) void fwd_kernel(
-    const typename AtomOf<MODE, FK>::type* __restrict__ rec, int a_begin, int a_end, int per_split,
+    const typename AtomOf<MODE>::type* __restrict__ rec, int a_begin, int a_end, int per_split,
     const float* __restrict__ S, int64_t K, int blocks_k, float4* __restrict__ part,
     float2* __restrict__ A, int carry_in, int direct) {
   using SReg = typename std::conditional<MODE == kPH64, double, float>::type;
@@ -171,13 +173,15 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(
       }
     }
   } else {
-    // The sign of the terms in the RED == 1 variant (exp(2 i pi u) = -exp(2 i pi S.r))
-    // is applied once per group, as a source modifier of the compensated addition.
-    constexpr float SGN = (RED == 1) ? -1.f : 1.f;
+    // Groups start at multiples of GRP from the first record packed for this plan (the
+    // chunk and split boundaries are multiples of GRP), so every group's atoms share
+    // one eighth turn; its turn-back factor is read from the group's first record.
     int j = j0;
     for (; j + GRP <= j1; j += GRP) {
       // Group partial: GRP/4 quads, each the running sum of 4 consecutive terms, are
-      // added into the group sum; the group sum is then folded into (sum, comp).
+      // added into the group sum; the group sum is then turned back and folded into
+      // (sum, comp).
+      const float ck = rec[j].ck, sk = rec[j].sk;
       float gr[P], gi[P];
 #pragma unroll
       for (int q = 0; q < GRP / 4; ++q) {
@@ -189,8 +193,8 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(
           for (int p = 0; p < P; ++p) {
             float c, s;
             cis_ph64<RED>(sx[p], sy[p], sz[p], a, c, s);
-            if (u == 0) first_term(a, c, s, qr[p], qi[p]);
-            else add_term(a, c, s, qr[p], qi[p]);
+            if (u == 0) first_term<FK>(a, c, s, qr[p], qi[p]);
+            else add_term<FK>(a, c, s, qr[p], qi[p]);
           }
         }
 #pragma unroll
@@ -200,12 +204,10 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(
         }
       }
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        kahan_acc(sr[p], cr[p], SGN * gr[p]);
-        kahan_acc(si[p], ci[p], SGN * gi[p]);
-      }
+      for (int p = 0; p < P; ++p) kahan_rot(sr[p], cr[p], si[p], ci[p], gr[p], gi[p], ck, sk);
     }
     if (j < j1) {   // last, partial group: terms added one by one
+      const float ck = rec[j].ck, sk = rec[j].sk;
       float gr[P], gi[P];
 #pragma unroll
       for (int p = 0; p < P; ++p) { gr[p] = 0.f; gi[p] = 0.f; }
@@ -215,14 +217,11 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(
         for (int p = 0; p < P; ++p) {
           float c, s;
           cis_ph64<RED>(sx[p], sy[p], sz[p], a, c, s);
-          add_term(a, c, s, gr[p], gi[p]);
+          add_term<FK>(a, c, s, gr[p], gi[p]);
         }
       }
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        kahan_acc(sr[p], cr[p], SGN * gr[p]);
-        kahan_acc(si[p], ci[p], SGN * gi[p]);
-      }
+      for (int p = 0; p < P; ++p) kahan_rot(sr[p], cr[p], si[p], ci[p], gr[p], gi[p], ck, sk);
     }
   }
 
@@ -240,13 +239,16 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(
 // tile of kThreads records into LDS (one record per thread, coalesced), and every wave
 // then reads the records from LDS as broadcasts.  Groups, quads and compensation are
 // those of fwd_kernel (tiles are whole groups), so the result is bitwise the same.
-template <int P, int FK, int GRP>
-__global__ __launch_bounds__(kThreads) void fwd_lds_kernel(
-    const typename AtomOf<kPH64, FK>::type* __restrict__ rec, int a_begin, int a_end, int per_split,
+// (At least 5 waves per SIMD: without the bound the compiler keeps whole groups of
+// records in flight, up to 130 VGPRs for two points per lane, and three waves per SIMD
+// then hide the LDS latency worse; with it the same loop takes 52.)
+template <int P, int FK, int GRP, int RED>
+__global__ __launch_bounds__(kThreads, 5) void fwd_lds_kernel(
+    const AtomPH* __restrict__ rec, int a_begin, int a_end, int per_split,
     const float* __restrict__ S, int64_t K, int blocks_k, float4* __restrict__ part,
     float2* __restrict__ A, int carry_in, int direct) {
   static_assert(kThreads % GRP == 0, "tiles must hold whole groups");
-  using AT = typename AtomOf<kPH64, FK>::type;
+  using AT = AtomPH;
   __shared__ AT tile[kThreads];
   const int lb = xcd_major_block(blockIdx.x, gridDim.x);
   const int kb = lb % blocks_k;
@@ -277,6 +279,7 @@ __global__ __launch_bounds__(kThreads) void fwd_lds_kernel(
     __syncthreads();
     int u0 = 0;
     for (; u0 + GRP <= nt; u0 += GRP) {
+      const float ck = tile[u0].ck, sk = tile[u0].sk;
       float gr[P], gi[P];
 #pragma unroll
       for (int q = 0; q < GRP / 4; ++q) {
@@ -287,9 +290,9 @@ __global__ __launch_bounds__(kThreads) void fwd_lds_kernel(
 #pragma unroll
           for (int p = 0; p < P; ++p) {
             float c, s;
-            cis_ph64<0>(sx[p], sy[p], sz[p], a, c, s);
-            if (u == 0) first_term(a, c, s, qr[p], qi[p]);
-            else add_term(a, c, s, qr[p], qi[p]);
+            cis_ph64<RED>(sx[p], sy[p], sz[p], a, c, s);
+            if (u == 0) first_term<FK>(a, c, s, qr[p], qi[p]);
+            else add_term<FK>(a, c, s, qr[p], qi[p]);
           }
         }
 #pragma unroll
@@ -299,12 +302,10 @@ __global__ __launch_bounds__(kThreads) void fwd_lds_kernel(
         }
       }
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        kahan_acc(sr[p], cr[p], gr[p]);
-        kahan_acc(si[p], ci[p], gi[p]);
-      }
+      for (int p = 0; p < P; ++p) kahan_rot(sr[p], cr[p], si[p], ci[p], gr[p], gi[p], ck, sk);
     }
     if (u0 < nt) {    // the split's last, partial group
+      const float ck = tile[u0].ck, sk = tile[u0].sk;
       float gr[P], gi[P];
 #pragma unroll
       for (int p = 0; p < P; ++p) { gr[p] = 0.f; gi[p] = 0.f; }
@@ -313,15 +314,12 @@ __global__ __launch_bounds__(kThreads) void fwd_lds_kernel(
 #pragma unroll
         for (int p = 0; p < P; ++p) {
           float c, s;
-          cis_ph64<0>(sx[p], sy[p], sz[p], a, c, s);
-          add_term(a, c, s, gr[p], gi[p]);
+          cis_ph64<RED>(sx[p], sy[p], sz[p], a, c, s);
+          add_term<FK>(a, c, s, gr[p], gi[p]);
         }
       }
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        kahan_acc(sr[p], cr[p], gr[p]);
-        kahan_acc(si[p], ci[p], gi[p]);
-      }
+      for (int p = 0; p < P; ++p) kahan_rot(sr[p], cr[p], si[p], ci[p], gr[p], gi[p], ck, sk);
     }
   }
 #pragma unroll
@@ -416,7 +414,7 @@ __global__ __launch_bounds__(kThreads) void fwd_reduce_f64_kernel(const double2*
   A[k] = make_double2(sr, si);
 }
 
-// Atom records for the three precisions (grid-stride over atoms).
+// Atom records of the FP32 mode and the all-FP64 path (grid-stride over atoms).
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void pack_atoms_kernel(const void* __restrict__ xyz_v,
                                                               const void* __restrict__ f_v,
@@ -435,68 +433,66 @@ __global__ __launch_bounds__(kThreads) void pack_atoms_kernel(const void* __rest
     } else {
       const float* xyz = static_cast<const float*>(xyz_v);
       const float* f = static_cast<const float*>(f_v);
-      const float fr = f ? f[2 * j] : 1.f;
-      const float fi = f ? f[2 * j + 1] : 0.f;
-      if constexpr (MODE == kPH64) {                  // f = 1 (complex f: the polar pack)
-        AtomPH r;
-        r.x = xyz[3 * j]; r.y = xyz[3 * j + 1]; r.z = xyz[3 * j + 2];   // exact widening
-        r.fr = fr; r.fi = fi;
-        static_cast<AtomPH*>(rec_v)[j] = r;
-      } else {
-        AtomF32 r;
-        r.x = xyz[3 * j]; r.y = xyz[3 * j + 1]; r.z = xyz[3 * j + 2];
-        r.fr = fr; r.fi = fi; r.pad0 = r.pad1 = r.pad2 = 0.f;
-        static_cast<AtomF32*>(rec_v)[j] = r;
-      }
+      AtomF32 r;
+      r.x = xyz[3 * j]; r.y = xyz[3 * j + 1]; r.z = xyz[3 * j + 2];
+      r.fr = f ? f[2 * j] : 1.f;
+      r.fi = f ? f[2 * j + 1] : 0.f;
+      r.pad0 = r.pad1 = r.pad2 = 0.f;
+      static_cast<AtomF32*>(rec_v)[j] = r;
     }
   }
 }
 
-// SplitMix64's output function (Steele, Lea and Flood, OOPSLA 2014) of the atom index:
-// 64 pseudo-random bits, the same for an atom on every call; atom_uniform takes the top
-// 53 as a double in [0, 1).
-__device__ __forceinline__ uint64_t atom_bits(int64_t j) {
-  uint64_t z = static_cast<uint64_t>(j) + 0x9E3779B97F4A7C15ull;
+// SplitMix64's output function (Steele, Lea and Flood, OOPSLA 2014): 64 pseudo-random
+// bits of a 64-bit key.  The atoms' roundings use keys 2j, the groups' turns keys 2g + 1.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
 }
-__device__ __forceinline__ double atom_uniform(int64_t j) {
-  return static_cast<double>(atom_bits(j) >> 11) * 0x1.0p-53;
-}
 
 // m >= 0 to FP32 by unbiased (stochastic) rounding: the FP32 value above m with
 // probability equal to the fraction of the gap by which m exceeds the value below it,
-// drawn from atom_uniform(j).  The expected result is m, so the rounding errors of atoms
-// with equal factors are independent and add up incoherently instead of as one
-// relative error of their species' amplitude.
+// drawn from the top 53 bits of mix64(2 j).  The expected result is m, so the rounding
+// errors of atoms with equal factors are independent and add up incoherently instead
+// of as one relative error of their species' amplitude.
 __device__ __forceinline__ float round_unbiased(double m, int64_t j) {
   float lo = static_cast<float>(m);
   if (static_cast<double>(lo) > m) lo = __uint_as_float(__float_as_uint(lo) - 1u);
   const float hi = __uint_as_float(__float_as_uint(lo) + 1u);
   const double t = (m - static_cast<double>(lo)) / (static_cast<double>(hi) - static_cast<double>(lo));
-  return atom_uniform(j) < t ? hi : lo;
+  const double u = static_cast<double>(mix64(2 * static_cast<uint64_t>(j)) >> 11) * 0x1.0p-53;
+  return u < t ? hi : lo;
 }
 
-// Polar atom records of the FP64-phase forward with complex f: a = arg f in cycles (0
-// for f = 0) plus the reduction offset, m = |f| from FP64 and rounded without bias, and
-// the atom's half turn (lowest hash bit): m -> -m and a -> a + 1/2, which leaves
-// m exp(2 i pi a) = f unchanged.
-__global__ __launch_bounds__(kThreads) void pack_atoms_polar_kernel(const float* __restrict__ xyz,
-                                                                    const float* __restrict__ f,
-                                                                    int64_t n, AtomPHP* __restrict__ rec,
-                                                                    double offset) {
+// FP64-phase atom records (grid-stride over the n atoms of one plan, indices counted from
+// the first of them, which starts the plan's first group):
+//   a  = arg f in cycles (0 for f = 1 or f = 0) + offset (the variant's 1/2) + k/8,
+//   m  = |f| from FP64, rounded without bias (1 for f = 1),
+//   (ck, sk) = sgn exp(-2 i pi k/8) in FP32, sgn = -1 for the fract variant,
+// with k = 0..7 the turn of the atom's group g = j / grp, from mix64(2 g + 1).
+__global__ __launch_bounds__(kThreads) void pack_atoms_ph_kernel(const float* __restrict__ xyz,
+                                                                 const float* __restrict__ f,
+                                                                 int64_t n, AtomPH* __restrict__ rec,
+                                                                 double offset, int grp, float sgn) {
   for (int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x; j < n;
        j += int64_t(gridDim.x) * kThreads) {
-    const double fr = f[2 * j], fi = f[2 * j + 1];
-    AtomPHP r;
+    AtomPH r;
     r.x = xyz[3 * j]; r.y = xyz[3 * j + 1]; r.z = xyz[3 * j + 2];       // exact widening
-    const bool zero = fr == 0.0 && fi == 0.0;
-    const bool flip = (atom_bits(j) & 1u) != 0;
-    r.a = (zero ? 0.0 : atan2(fi, fr) * 0.15915494309189533577) + offset + (flip ? 0.5 : 0.0);
-    const float m = round_unbiased(sqrt(fr * fr + fi * fi), j);
-    r.m = flip ? -m : m;
-    r.pad0 = r.pad1 = r.pad2 = 0.f;
+    double alpha = 0.0;
+    r.m = 1.f;
+    if (f) {
+      const double fr = f[2 * j], fi = f[2 * j + 1];
+      if (fr != 0.0 || fi != 0.0) alpha = atan2(fi, fr) * 0.15915494309189533577;
+      r.m = round_unbiased(sqrt(fr * fr + fi * fi), j);
+    }
+    const uint64_t g = static_cast<uint64_t>(j / grp);
+    const int k = static_cast<int>(mix64(2 * g + 1) & 7u);
+    r.a = alpha + offset + 0.125 * k;
+    r.ck = sgn * static_cast<float>(cospi(0.25 * k));
+    r.sk = -sgn * static_cast<float>(sinpi(0.25 * k));
+    r.pad = 0.f;
     rec[j] = r;
   }
 }
@@ -512,7 +508,7 @@ template <int MODE, int P, int FK>
 hipError_t fwd_dispatch_red(const Plan& p, const void* rec, int64_t a_begin, int64_t a_end,
                             int64_t per_split, const void* S, void* partial, void* A,
                             int carry_in, int direct, hipStream_t st, int red) {
-  using AT = typename AtomOf<MODE, FK>::type;
+  using AT = typename AtomOf<MODE>::type;
   const dim3 grid(static_cast<unsigned>(p.blocks * p.nsplit));
   const auto* r = static_cast<const AT*>(rec);
   const auto* s = static_cast<const float*>(S);
@@ -524,12 +520,18 @@ hipError_t fwd_dispatch_red(const Plan& p, const void* rec, int64_t a_begin, int
     return hipGetLastError();
   }
   if constexpr (MODE == kPH64) {
-    if (p.lds && red == 0 && (p.grp == 16 || p.grp == 8)) {
-      if (p.grp == 16)
-        fwd_lds_kernel<P, FK, 16><<<grid, kThreads, 0, st>>>(
+    if (p.lds && (p.grp == 16 || p.grp == 8)) {
+      if (p.grp == 16 && red == 0)
+        fwd_lds_kernel<P, FK, 16, 0><<<grid, kThreads, 0, st>>>(
+            r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct);
+      else if (p.grp == 16)
+        fwd_lds_kernel<P, FK, 16, 1><<<grid, kThreads, 0, st>>>(
+            r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct);
+      else if (red == 0)
+        fwd_lds_kernel<P, FK, 8, 0><<<grid, kThreads, 0, st>>>(
             r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct);
       else
-        fwd_lds_kernel<P, FK, 8><<<grid, kThreads, 0, st>>>(
+        fwd_lds_kernel<P, FK, 8, 1><<<grid, kThreads, 0, st>>>(
             r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct);
       return hipGetLastError();
     }
@@ -591,16 +593,15 @@ hipError_t fwd_f64_launch(const Plan& p, const void* rec, int64_t a_begin, int64
 
 }  // namespace
 
-hipError_t launch_pack_atoms(int mode, int red, const void* xyz, const void* f, int64_t n,
+hipError_t launch_pack_atoms(int mode, int red, int grp, const void* xyz, const void* f, int64_t n,
                              void* rec, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const unsigned g = grid_for(n);
-  // f = 1: the reduction offset is an inline constant of the kernel; polar records carry it
   if (mode == kF64) pack_atoms_kernel<kF64><<<g, kThreads, 0, st>>>(xyz, f, n, rec);
-  else if (mode == kPH64 && f)
-    pack_atoms_polar_kernel<<<g, kThreads, 0, st>>>(static_cast<const float*>(xyz), static_cast<const float*>(f),
-                                                    n, static_cast<AtomPHP*>(rec), red == 1 ? 0.5 : 0.0);
-  else if (mode == kPH64) pack_atoms_kernel<kPH64><<<g, kThreads, 0, st>>>(xyz, f, n, rec);
+  else if (mode == kPH64)
+    pack_atoms_ph_kernel<<<g, kThreads, 0, st>>>(static_cast<const float*>(xyz), static_cast<const float*>(f), n,
+                                                 static_cast<AtomPH*>(rec), red == 1 ? 0.5 : 0.0, grp,
+                                                 red == 1 ? -1.f : 1.f);
   else pack_atoms_kernel<kF32><<<g, kThreads, 0, st>>>(xyz, f, n, rec);
   return hipGetLastError();
 }

@@ -18,14 +18,12 @@ constexpr int kThreads = 256;          // work-group size of every sum kernel (4
 
 // Atom for the FP32 mode: coordinates and factor in FP32.
 struct alignas(16) AtomF32 { float x, y, z, fr, fi, pad0, pad1, pad2; };            // 32 B
-// Atom for the FP64-phase mode with f = 1: coordinates widened (exactly) to FP64
-// (fr, fi are written as 1, 0 and not read).
-struct alignas(16) AtomPH { double x, y, z; float fr, fi; };                         // 32 B
-// Atom for the FP64-phase mode with complex f, in polar form f = m exp(2 i pi a):
-// coordinates widened to FP64; a (FP64, cycles) = arg f plus the reduction offset of the
-// variant plus the atom's half turn, if it has one; m (FP32) = |f| rounded without bias
-// (stochastic rounding keyed by the atom index), negated for a half turn.
-struct alignas(16) AtomPHP { double x, y, z, a; float m, pad0, pad1, pad2; };        // 48 B
+// Atom for the FP64-phase mode (f = 1 and complex f alike): coordinates widened (exactly)
+// to FP64; a (FP64, cycles) = arg f + the reduction offset of the variant + the eighth
+// turn k/8 of the atom's compensated group; m (FP32) = |f| rounded without bias
+// (stochastic rounding keyed by the atom index; 1 for f = 1); (ck, sk) = the group's
+// turn-back factor exp(-2 i pi k/8), negated for the fract variant.
+struct alignas(16) AtomPH { double x, y, z, a; float m, ck, sk, pad; };              // 48 B
 // Atom for the all-FP64 path.
 struct alignas(16) AtomF64 { double x, y, z, fr, fi, pad; };                         // 48 B
 // Point for the FP32-mode adjoint: S and the seed G.
@@ -110,7 +108,9 @@ void chunk_range(const Plan& p, int64_t c, int64_t* begin, int64_t* end, int64_t
 
 // ---------------------------------------------------------------------------------
 // Launchers (defined in the kernel translation units).  All return the launch error.
-hipError_t launch_pack_atoms(int mode, int red, const void* xyz, const void* f, int64_t n,
+// FP64-phase records depend on the plan's reduction variant and group size, and their
+// groups are counted from the first atom packed: pack the atoms of each plan separately.
+hipError_t launch_pack_atoms(int mode, int red, int grp, const void* xyz, const void* f, int64_t n,
                              void* rec, hipStream_t st);
 hipError_t launch_pack_points(int mode, int red, const void* S, const void* G, int64_t k,
                               void* rec, hipStream_t st);

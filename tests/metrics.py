@@ -20,10 +20,6 @@ T1_TOL, T2_TOL = 1e-5, 1e-6
 T3_NORM_TOL, T3_MAX_TOL = 1e-5, 1e-4
 F64_T1_TOL, F64_T2_TOL = 1e-9, 1e-12
 F64_T3_TOL = 1e-11
-# perfect lattices (no disorder): the hardware sin/cos error is periodic in the phase, and
-# on a perfect lattice each of its harmonics adds up coherently like a Bragg peak, so the
-# weakest admitted points carry ~1e3 times the per-term error in relative terms
-T1_PERFECT_TOL = 5e-5
 # random-position problems: pointwise error against the random-walk scale
 INC_TOL, F64_INC_TOL = 2e-6, 1e-12
 

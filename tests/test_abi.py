@@ -200,17 +200,18 @@ def test_missing_library_fails_loudly(monkeypatch):
 def test_plan_l2_sized_forward_chunks(monkeypatch):
     """The forward cuts its launches when a split's slice of atom records exceeds an
     XCD's L2: the carried running sums then appear in the workspace (host-side plan)."""
-    n, k = 203_557, 2_097_152                      # one split; 48-byte polar records (complex f)
+    n, k = 203_557, 2_097_152                      # one split; 48-byte FP64-phase records
     rec = -(-n * 48 // 256) * 256
-    with_chunks = _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_FWD, 0)
-    assert with_chunks == rec + k * 16             # one (sum, comp) state per point
+    for f_is_null in (0, 1):
+        with_chunks = _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_FWD, f_is_null)
+        assert with_chunks == rec + k * 16         # one (sum, comp) state per point
     monkeypatch.setenv("NX_TUNE_L2_CHUNK", "0")
     assert _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_FWD, 0) == rec
     monkeypatch.delenv("NX_TUNE_L2_CHUNK")
-    # slices that fit the L2 are not cut: 80,000 polar records, or 120,000 of 32 bytes (f = 1)
+    # slices that fit the L2 are not cut: 80,000 records of 48 bytes
     assert _lib.nx_workspace_bytes(80_000, k, 1, _lib.NX_OP_FWD, 0) == -(-80_000 * 48 // 256) * 256
-    assert _lib.nx_workspace_bytes(120_000, k, 1, _lib.NX_OP_FWD, 1) == -(-120_000 * 32 // 256) * 256
-    assert _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_FWD, 1) == -(-n * 32 // 256) * 256 + k * 16
+    # the FP32 mode's records are 32 bytes: 120,000 of them fit
+    assert _lib.nx_workspace_bytes(120_000, k, 0, _lib.NX_OP_FWD, 1) == -(-120_000 * 32 // 256) * 256
 
 
 def test_plan_launch_chunks_and_splits(monkeypatch):
@@ -219,7 +220,7 @@ def test_plan_launch_chunks_and_splits(monkeypatch):
     assert few > 1_000_000 * 32 + 65_536 * 16
     # enough points to fill the chip: no split, no carried state ...
     n, k = 5000, 1 << 20
-    rec = -(-n * 32 // 256) * 256
+    rec = -(-n * 48 // 256) * 256
     assert _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_FWD, 1) == rec
     # ... until a small launch size forces chunks, which carry one state per point
     monkeypatch.setenv("NX_TUNE_LAUNCH_PAIRS", str(1 << 24))

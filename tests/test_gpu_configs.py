@@ -79,16 +79,20 @@ def test_c1_full():
 
 def test_c1_sigma0_bragg_and_laue():
     """The sigma = 0 twin of C1 follows the Laue product at every map point; at the
-    Bragg nodes (0,0,4) and (1,-1,4), added to the map, every reduced phase is exactly
-    zero and A = 4096 exactly."""
+    Bragg nodes (0,0,4) and (1,-1,4), added to the map, every phase S.r is an integer
+    and A = 4096: exactly on the all-FP64 path; within 3e-7 relative in the FP64-phase
+    mode, whose reduced phases there are the eighth turns of the compensated groups
+    (cos and sin of odd multiples of pi/4 and the turn-back factor are rounded)."""
     from tests.test_oracle_pins import laue_3d
     w = wl.c1(sigma=0.0)
     w.S = np.concatenate([w.S, np.array([[0, 0, 4], [1, -1, 4]], dtype=np.float32)])
     ref = laue_3d(16, 16, 16, w.S.astype(np.float64))
-    for mode, tol in (("ph64", 1e-6), ("f64", 1e-12)):
+    for mode, tol, node in (("ph64", 1e-6, 3e-7), ("f64", 1e-12, 0.0)):
         A = gpu_fwd(w, mode)
         assert np.max(np.abs(A - ref)) <= tol * 4096, mode
-        assert np.all(A[-2:] == 4096), mode
+        dev = np.max(np.abs(A[-2:] - 4096)) / 4096
+        print(f"c1 sigma=0 Bragg nodes, mode={mode}: max |A/N - 1| = {dev:.2e}", flush=True)
+        assert dev <= node, mode
 
 
 # ----------------------------------------------------------------------------- C2

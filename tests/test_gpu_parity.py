@@ -129,7 +129,9 @@ def test_fwd_bitwise_deterministic(mode):
 
 def test_gpu_laue_block_and_bragg_node():
     """sigma = 0 block: the GPU matches the 3D Laue closed form; at a Bragg node every
-    reduced phase is exactly 0, so A = N exactly."""
+    phase S.r is an integer and A = N, exactly on the all-FP64 path and within 3e-7
+    relative in the FP64-phase mode (its reduced phases there are the groups' eighth
+    turns, whose cos, sin and turn-back factor are rounded)."""
     from tests.test_oracle_pins import laue_3d
     nx_, ny_, nz_ = 16, 12, 20
     xyz = wl._f32(wl.cubic_sites(nx_, ny_, nz_))
@@ -138,10 +140,12 @@ def test_gpu_laue_block_and_bragg_node():
                         np.array([[0, 0, 4], [1, 2, 3], [-3, 0, 8]], dtype=float)]).astype(np.float32)
     ref = laue_3d(nx_, ny_, nz_, S.astype(np.float64))
     n = nx_ * ny_ * nz_
-    for mode, tol in (("ph64", 2e-6), ("f64", 1e-11)):
+    for mode, tol, node in (("ph64", 2e-6, 3e-7), ("f64", 1e-11, 0.0)):
         A = run_fwd(xyz, None, S, mode)
         assert np.max(np.abs(A - ref)) <= tol * n, mode
-        assert np.all(A[-3:] == n), mode
+        dev = np.max(np.abs(A[-3:] - n)) / n
+        print(f"Bragg nodes, mode={mode}: max |A/N - 1| = {dev:.2e}", flush=True)
+        assert dev <= node, mode
 
 
 def test_gpu_friedel_and_superposition():
