@@ -108,13 +108,17 @@ def test_fwd_chunked_launches(mode, monkeypatch):
 
 @pytest.mark.parametrize("red", ["0", "1"])
 @pytest.mark.parametrize("grp", ["8", "16", "32"])
-def test_fwd_variants(red, grp, monkeypatch):
-    """Both phase-reduction variants and every group size meet the tolerances."""
+@pytest.mark.parametrize("cplx", [True, False])
+def test_fwd_variants(red, grp, cplx, monkeypatch):
+    """Both phase-reduction variants and every group size meet the tolerances, for complex
+    f and f = 1 (the records' eighth turns and offsets follow the plan's variant and
+    group size; 32-atom groups run in the scalar-load form)."""
     monkeypatch.setenv("NX_TUNE_RED", red)
     monkeypatch.setenv("NX_TUNE_GRP", grp)
-    xyz, f, S = wl.random_problem(3001, 2100, seed=12, extent=80.0, s_range=6.0)
+    xyz, f, S = wl.random_problem(3001, 2100, seed=12, extent=80.0, s_range=6.0, complex_f=cplx)
     A_ref = oracle.forward(xyz, f, S)
-    check_fwd(run_fwd(xyz, f, S, "ph64"), A_ref, "ph64", f"red={red} grp={grp}", f=f, n=len(xyz))
+    check_fwd(run_fwd(xyz, f, S, "ph64"), A_ref, "ph64", f"red={red} grp={grp} cplx={cplx}", f=f,
+              n=len(xyz))
 
 
 @pytest.mark.parametrize("mode", ["ph64", "f32", "f64"])

@@ -149,7 +149,11 @@ def species_scale(fs, start):
 
 
 @pytest.mark.parametrize("counts,k", [((1200, 1801), 2500), ((0, 700, 1, 333), 1031),
-                                      ((4097,), 300), ((5, 9, 1000, 0, 17), 64)])
+                                      ((4097,), 300), ((5, 9, 1000, 0, 17), 64),
+                                      # species above and below 65,536 atoms (16- and 8-atom
+                                      # groups) starting at offsets that are not multiples of
+                                      # either: each species' records are packed with its plan
+                                      ((70001, 333, 66001), 300)])
 @pytest.mark.parametrize("mode", ["ph64", "f32"])
 def test_species_forward_random(counts, k, mode):
     xyz, start, fs, S = species_problem(counts, k, seed=sum(counts) + k)
