@@ -48,11 +48,19 @@ PEAK_TFLOPS = 2 * VALU_SLOTS_PER_S / 1e12
 #                       only sin is needed and T_d += (|G| S_d) sin (3); |f| scales the
 #                       finished sums; the seed phase rides in the first fma of the phase
 #   adjoint, f = 1:     only sin is needed, T_d += (3)
+# The FP32 mode (the paper's arithmetic): FP32 phase (3), v_fract_f32 (1), sin and cos (2);
+#   forward: f (cos + i sin) with 4 fma, or 2 add for f = 1;
+#   adjoint: w = conj(G) exp(i theta) (2 for Im w, 4 with Re w), v = Im(f w) (2 for complex
+#            f), T_d += S_d v (3); sin and cos are both needed.
 ALG_SLOTS = {
-    ("fwd", "complex"): 3 + 3 + 2 + 2,
-    ("fwd", "unit"): 3 + 3 + 2 + 2,
-    ("bwd", "complex"): 3 + 1 + 2 + 1 + 3,
-    ("bwd", "unit"): 3 + 2 + 1 + 3,
+    ("ph64", "fwd", "complex"): 3 + 3 + 2 + 2,
+    ("ph64", "fwd", "unit"): 3 + 3 + 2 + 2,
+    ("ph64", "bwd", "complex"): 3 + 1 + 2 + 1 + 3,
+    ("ph64", "bwd", "unit"): 3 + 2 + 1 + 3,
+    ("f32", "fwd", "complex"): 3 + 1 + 2 + 4,
+    ("f32", "fwd", "unit"): 3 + 1 + 2 + 2,
+    ("f32", "bwd", "complex"): 3 + 1 + 2 + 4 + 2 + 3,
+    ("f32", "bwd", "unit"): 3 + 1 + 2 + 2 + 3,
 }
 PAPER_FLOP_PER_PAIR = 8       # the paper's count (3 mul, 4 add, 1 sincos)
 FP32_PEAK_TFLOPS = 157.3      # published FP32 vector peak (packed)
@@ -260,7 +268,7 @@ def main():
 
     # roofline of the dominant kernel (its launch sequence timed on the launch stream)
     dom, t_dom = ("bwd", t_bwd) if t_bwd >= t_fwd else ("fwd", t_fwd)
-    slots = ALG_SLOTS[(dom, fkind)]
+    slots = ALG_SLOTS[(args.mode, dom, fkind)]
     achieved = pairs * 2 * slots / t_dom / 1e12
     traffic = None
     tpath = os.path.join(ROOT, "profiles", f"{dom}_{args.workload}_{args.mode}_traffic.json")
