@@ -73,11 +73,13 @@ template <int MODE> struct AtomOf;
 template <> struct AtomOf<kF32> { using type = AtomF32; };
 template <> struct AtomOf<kPH64> { using type = AtomPH; };
 
-// exp(2 i pi psi) for the FP64-phase mode as (c, s) in FP32, psi = S.r + a, where the
-// record's addend a holds arg f, the group's eighth turn and the variant's offset:
-//   RED 0: t = psi - rint(psi) in [-1/2, 1/2] (exact), rounded once to FP32;
-//   RED 1: u = fract(psi + 1/2) in [0, 1) (exact), rounded once to FP32, so that
-//          exp(2 i pi u) = -exp(2 i pi psi); the records' turn-back factor carries the -1.
+// exp(2 i pi psi) for the FP64-phase mode as (c, s) in FP32, psi = S.r + arg f + k/8 (the
+// group's eighth turn); the record's addend is a = arg f + k/8 + the variant's offset:
+//   RED 0 (offset 0):   t = (S.r + a) - rint(S.r + a) in [-1/2, 1/2] (exact), rounded once
+//                       to FP32;
+//   RED 1 (offset 1/2): u = fract(S.r + a) = fract(psi + 1/2) in [0, 1) (exact), rounded
+//                       once to FP32, so that exp(2 i pi u) = -exp(2 i pi psi); the records'
+//                       turn-back factor carries the -1.
 template <int RED>
 __device__ __forceinline__ void cis_ph64(double sx, double sy, double sz, const AtomPH& a, float& c,
                                          float& s) {
