@@ -149,6 +149,7 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
   size_t rec_size;
   if (fwd) rec_size = p.mode == kF64 ? sizeof(AtomF64) : (p.mode == kPH64 ? sizeof(AtomPH) : sizeof(AtomF32));
   else rec_size = p.mode == kF64 ? sizeof(PointF64) : (p.mode == kPH64 ? sizeof(PointPH) : sizeof(PointF32));
+  p.rec_size = rec_size;
   int64_t chunk = lane_pad > 0 ? launch_pairs / lane_pad : p.stream;
   if (fwd && ceil_div(p.stream, p.nsplit) * int64_t(rec_size) > kL2Bytes &&
       env_i64("NX_TUNE_L2_CHUNK", 1) != 0)
@@ -456,8 +457,8 @@ int nx_scatter_fwd_species(const float* xyz, int64_t n_atoms, const int64_t* spe
     const nx::Plan ps = nx::make_plan(nx::kOpFwd, mode, species_start[s + 1] - a0, n_points, 1);
     // each species' records are packed with its own plan (variant, group size), their
     // groups counted from the species' first atom; they sit at the species' place in ws
-    const size_t rsz = ps.mode == nx::kPH64 ? sizeof(nx::AtomPH) : sizeof(nx::AtomF32);
-    e = nx::launch_pack_atoms(ps.mode, ps.red, ps.grp, xyz + 3 * a0, nullptr, ps.stream, base + a0 * rsz, st);
+    e = nx::launch_pack_atoms(ps.mode, ps.red, ps.grp, xyz + 3 * a0, nullptr, ps.stream,
+                              base + a0 * ps.rec_size, st);
     if (e != hipSuccess) return device_error(fn, e);
     void* state = base + off[s];
     ss.state[s] = state;

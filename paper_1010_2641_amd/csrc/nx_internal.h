@@ -78,6 +78,7 @@ struct Plan {
   int nsplit = 1;        // stream slices
   int64_t chunk = 0;     // stream items per launch
   int64_t nchunks = 0;   // launches
+  size_t rec_size = 0;       // bytes of one packed stream record
   size_t rec_bytes = 0;      // packed stream records
   size_t partial_bytes = 0;  // carried / split partial state
   size_t misc_bytes = 0;     // small scratch (loss partials)
