@@ -1,6 +1,7 @@
 """Seeded random shapes and launch plans against the oracle: atom and point counts drawn
 log-uniformly (with at most 2e8 pairs per case), factor kind, precision mode and the
-plan knobs (items per lane, record staging, launch size) drawn at random, so that the
+plan knobs (items per lane, record staging, launch size, group size, reduction variant)
+drawn at random, so that the
 combinations of splits, chunks, ragged tails and kernel forms are exercised beyond the
 hand-picked cases.  The draws are fixed by the seed; every case prints its parameters."""
 import numpy as np
@@ -21,17 +22,21 @@ def draw(case):
         k = int(np.exp(rng.uniform(0, np.log(60000))))
         if n * k <= 2e8:
             break
-    return dict(n=n, k=k, fkind=str(rng.choice(["none", "real", "complex"])),
-                mode=str(rng.choice(["ph64", "ph64", "f64", "f32"])),
-                P=str(rng.choice(["", "1", "2", "4"])), lds=str(rng.choice(["", "0", "1"])),
-                pairs=str(rng.choice(["", str(1 << 22), str(1 << 26)])), seed=int(rng.integers(1 << 30)))
+    c = dict(n=n, k=k, fkind=str(rng.choice(["none", "real", "complex"])),
+             mode=str(rng.choice(["ph64", "ph64", "f64", "f32"])),
+             P=str(rng.choice(["", "1", "2", "4"])), lds=str(rng.choice(["", "0", "1"])),
+             pairs=str(rng.choice(["", str(1 << 22), str(1 << 26)])), seed=int(rng.integers(1 << 30)))
+    # drawn last, so that the draws above are those of the cases without these knobs
+    c.update(grp=str(rng.choice(["", "8", "16", "32"])), red=str(rng.choice(["", "0", "1"])))
+    return c
 
 
-@pytest.mark.parametrize("case", range(24))
+@pytest.mark.parametrize("case", range(48))
 def test_random_shape(case, monkeypatch):
     c = draw(case)
     print(f"case {case}: {c}", flush=True)
-    for var, val in (("NX_TUNE_P", c["P"]), ("NX_TUNE_LDS", c["lds"]), ("NX_TUNE_LAUNCH_PAIRS", c["pairs"])):
+    for var, val in (("NX_TUNE_P", c["P"]), ("NX_TUNE_LDS", c["lds"]), ("NX_TUNE_LAUNCH_PAIRS", c["pairs"]),
+                     ("NX_TUNE_GRP", c["grp"]), ("NX_TUNE_RED", c["red"])):
         if val and not (var == "NX_TUNE_P" and val == "4" and c["mode"] == "f64"):
             monkeypatch.setenv(var, val)
     n, k = c["n"], c["k"]
