@@ -98,6 +98,9 @@ def parse():
     p.add_argument("--mode", default="ph64", choices=["ph64", "f32"])
     p.add_argument("--no-f64", action="store_true", help="skip the all-FP64 comparison")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--graph", action="store_true",
+                   help="also capture the fit step in one HIP graph and time its replays (reported "
+                        "beside the eager rate, which stays the headline value)")
     p.add_argument("--no-species", action="store_true",
                    help="skip the species-factorised step (workloads with several species)")
     p.add_argument("--cpu-seconds", type=float, default=20.0,
@@ -260,6 +263,34 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     progress(f"{args.steps} timed steps done, {wall / args.steps * 1e3:.1f} ms per step")
+
+    # the same step captured once in a HIP graph (the library issues kernels only: no
+    # allocation, copy, memset or synchronisation), replayed for at least the timed steps
+    # and at least 0.2 s; small problems are bound by launch latency, which replays cut
+    graph = None
+    if args.graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            step()
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        cg = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(cg):
+            _, gA, gg = step()
+        torch.cuda.synchronize()
+        reps = max(args.steps, int(0.2 / max(wall / args.steps, 1e-9)) + 1)
+        cg.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            cg.replay()
+        torch.cuda.synchronize()
+        tg = (time.perf_counter() - t0) / reps
+        graph = {"ms_per_step": tg * 1e3, "pairs_per_s": pairs / tg, "replays": reps,
+                 "bitwise_equal_to_eager": bool(torch.equal(gA, out[1]) and torch.equal(gg, out[2]))}
+        del cg, gA, gg
+        progress(f"graph replays timed: {tg * 1e3:.3f} ms per step")
     t_fwd = sum(r[0].elapsed_time(r[1]) for r in recs) / args.steps / 1e3
     t_loss = sum(r[1].elapsed_time(r[2]) for r in recs) / args.steps / 1e3
     t_bwd = sum(r[2].elapsed_time(r[3]) for r in recs) / args.steps / 1e3
@@ -402,6 +433,7 @@ def main():
         "loss_ms": t_loss * 1e3,
         "f64_path": f64,
         "species_path": species,
+        "graph_replay": graph,
         "speedup_vs_f64_step": (value / f64["step_pairs_per_s"]) if f64 else None,
         "max_rel_err": errs,
         "paper_flop_convention": {"tflops": value * PAPER_FLOP_PER_PAIR / 1e12,
