@@ -447,9 +447,8 @@ __global__ __launch_bounds__(kThreads) void bwd_f64_kernel(
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const double ph = __builtin_fma(a.sz, z[q], __builtin_fma(a.sy, y[q], a.sx * x[q]));
-      const double t = ph - __builtin_rint(ph);
       double s, c;
-      sincospi(2.0 * t, &s, &c);
+      cis_f64(ph, c, s);
       const double wre = __builtin_fma(a.gi, s, a.gr * c);      // conj(G) e^{i theta}
       const double wim = __builtin_fma(-a.gi, c, a.gr * s);
       double v = wim;

@@ -36,7 +36,7 @@
 //          factor exp(2 i pi (p - 1) k/8) per group, so every harmonic but p = 1 (a
 //          relative scale error) and p = 1 mod 8 (measured negligible) adds up
 //          incoherently.
-//   F64  : phase, reduction, sincospi and sums all in FP64.
+//   F64  : phase, reduction, sin/cos (cis_f64) and sums all in FP64.
 #include "nx_internal.h"
 
 namespace nx {
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(kThreads, 5) void fwd_lds_kernel(
   }
 }
 
-// All-FP64 forward: FP64 phase, FP64 reduction, sincospi in FP64, FP64 sums.
+// All-FP64 forward: FP64 phase, reduction and sin/cos (cis_f64), FP64 sums.
 template <int P, int FK>
 __global__ __launch_bounds__(kThreads) void fwd_f64_kernel(
     const AtomF64* __restrict__ rec, int a_begin, int a_end, int per_split,
@@ -364,9 +364,8 @@ __global__ __launch_bounds__(kThreads) void fwd_f64_kernel(
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       const double ph = __builtin_fma(sz[p], a.z, __builtin_fma(sy[p], a.y, sx[p] * a.x));
-      const double t = ph - __builtin_rint(ph);
       double s, c;
-      sincospi(2.0 * t, &s, &c);
+      cis_f64(ph, c, s);
       if constexpr (FK == 0) {
         ar[p] += c; ai[p] += s;
       } else {

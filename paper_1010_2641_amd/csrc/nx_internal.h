@@ -56,6 +56,45 @@ __device__ __forceinline__ int xcd_major_block(int b, int nblk) {
 // Kernel variants selected by the host.
 enum Mode : int { kF32 = 0, kPH64 = 1, kF64 = 2 };
 
+// exp(2 i pi phi) = c + i s in FP64, for the all-FP64 path (phi in cycles, finite).
+// The phase is reduced to t = phi - rint(phi) in [-1/2, 1/2] and split into q quarter
+// turns, q = rint(4 t) in -2..2, and r = t - q/4 with |r| <= 1/8 (both steps exact).
+// sin(2 pi r) and cos(2 pi r) come from their Taylor series in r, through r^17 and r^16:
+// for |2 pi r| <= pi/4 the first omitted terms are below 1e-19 and 3e-18, under FP64's
+// rounding.  Then exp(2 i pi phi) = i^q exp(2 i pi r): a swap and two signs.
+__device__ __forceinline__ void cis_f64(double phi, double& c, double& s) {
+  const double t = phi - __builtin_rint(phi);
+  const double q = __builtin_rint(4.0 * t);
+  const double r = __builtin_fma(-0.25, q, t);
+  const double z = r * r;
+  // (-1)^m (2 pi)^(2m+1) / (2m+1)!, m = 8 .. 0
+  double ps = 0x1.aaec32af93359p-4;
+  ps = __builtin_fma(ps, z, -0x1.6fadb9f155744p-1);
+  ps = __builtin_fma(ps, z, 0x1.e8f434d018d63p+1);
+  ps = __builtin_fma(ps, z, -0x1.e3074fde8871fp+3);
+  ps = __builtin_fma(ps, z, 0x1.50783487ee782p+5);
+  ps = __builtin_fma(ps, z, -0x1.32d2cce62bd86p+6);
+  ps = __builtin_fma(ps, z, 0x1.466bc6775aae2p+6);
+  ps = __builtin_fma(ps, z, -0x1.4abbce625be53p+5);
+  ps = __builtin_fma(ps, z, 0x1.921fb54442d18p+2);
+  const double sr = r * ps;
+  // (-1)^m (2 pi)^(2m) / (2m)!, m = 8 .. 0
+  double pc = 0x1.20c62c2f2d7f5p-2;
+  pc = __builtin_fma(pc, z, -0x1.b6e24f44b128fp+0);
+  pc = __builtin_fma(pc, z, 0x1.f9d38a3763cc3p+2);
+  pc = __builtin_fma(pc, z, -0x1.a6d1f2a204a8cp+4);
+  pc = __builtin_fma(pc, z, 0x1.e1f506891babbp+5);
+  pc = __builtin_fma(pc, z, -0x1.55d3c7e3cbffap+6);
+  pc = __builtin_fma(pc, z, 0x1.03c1f081b5ac4p+6);
+  pc = __builtin_fma(pc, z, -0x1.3bd3cc9be45dep+4);
+  const double cr = __builtin_fma(pc, z, 1.0);
+  const int qi = static_cast<int>(q) & 3;      // i^q: 0 -> (c, s), 1 -> (-s, c), 2 -> (-c, -s), 3 -> (s, -c)
+  const double u = (qi & 1) ? sr : cr;
+  const double v = (qi & 1) ? cr : sr;
+  c = (qi == 1 || qi == 2) ? -u : u;
+  s = (qi >= 2) ? -v : v;
+}
+
 // ---------------------------------------------------------------------------------
 // Launch plan.  "Lane items" are the outputs one lane owns (points for the forward,
 // atoms for the adjoint), "stream items" are what every lane loops over (atoms for
