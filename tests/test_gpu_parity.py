@@ -391,3 +391,40 @@ def test_split_adjoint_bitwise(n, k, cplx, monkeypatch):
             out[(lds, grp, "x")] = (run_bwd(xyz, f, S, G, "ph64"),)
     for key in [k_ for k_ in out if k_[0] == "0"]:
         assert all(np.array_equal(a, b) for a, b in zip(out[key], out[("1",) + key[1:]])), key
+
+
+def _factors(pairs):
+    """complex64 factors from (re, im) pairs, keeping the signs of zeros."""
+    a = np.asarray(pairs, dtype=np.float32).reshape(-1, 2)
+    return np.ascontiguousarray(a).view(np.complex64).reshape(-1)
+
+
+@pytest.mark.parametrize("n_points", [3000, 64])
+def test_polar_factor_edge_cases(n_points):
+    """Factors whose polar form m exp(2 i pi a) has edge cases -- f = 0 with every sign of
+    its zeros (no angle), negative real f (a = 1/2), imaginary f, a negative real part
+    with a -0 imaginary part -- mixed into random complex factors: the forward, the position
+    adjoint and the factor gradient against the oracle.  With 3000 points the adjoint runs
+    46 split slices and its reduce kernel applies |f| and arg f; with 64 points one slice
+    writes the outputs directly.  Atoms with f = 0 must get a zero position gradient."""
+    n = 2048
+    xyz, f, S = wl.random_problem(n, n_points, seed=78, extent=30.0, s_range=3.0)
+    special = _factors([(0.0, 0.0), (-0.0, 0.0), (0.0, -0.0), (-0.0, -0.0), (-1.5, 0.0),
+                        (0.0, 2.0), (0.0, -2.0), (-3.0, -0.0), (1.0, 0.0)])
+    idx = np.random.default_rng(77).choice(n, size=len(special) * 40, replace=False)
+    f[idx] = np.tile(special, 40)
+    G = wl.random_seed_field(n_points, seed=79)
+    A = run_fwd(xyz, f, S, "ph64")
+    check_fwd(A, oracle.forward(xyz, f, S), "ph64", f"polar edges K={n_points}", f=f, n=n)
+    gx, gf = api.scatter_bwd_ex(dev(xyz), dev(f), dev(S), dev(G.astype(np.complex64)), "ph64")
+    torch.cuda.synchronize()
+    gx = gx.cpu().numpy().astype(np.float64)
+    gf = gf.cpu().numpy().astype(np.complex128)
+    en, em = M.t3(gx, oracle.adjoint(xyz, f, S, G))
+    gf_ref = oracle.adjoint_f(xyz, S, G)
+    fn = float(np.linalg.norm(gf - gf_ref) / np.linalg.norm(gf_ref))
+    print(f"polar edges K={n_points}: position T3 norm={en:.2e} max={em:.2e}, dL/df T3 norm={fn:.2e}",
+          flush=True)
+    assert en <= M.T3_NORM_TOL and em <= M.T3_MAX_TOL and fn <= M.T3_NORM_TOL
+    zero = np.abs(f) == 0
+    assert zero.sum() == 4 * 40 and np.all(gx[zero] == 0)
