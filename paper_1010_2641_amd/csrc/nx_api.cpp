@@ -101,7 +101,8 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
   // fract's, which decides the pointwise intensity error at the weakest points: fract is
   // 8 % faster but took a strained 100^3 cube from 2.0e-6 to 7.7e-6), and 8-atom groups
   // for few atoms (|A| peaks at N |f|, so each term weighs more), 16 above.
-  // Adjoint (judged normwise): fract, 32-point groups, two atoms per lane.
+  // Adjoint (judged normwise): fract, 64-point groups (1 % faster than 32 on C2-C4, same
+  // error), two atoms per lane.
   if (fwd) {
     const bool small = p.stream < 65536;
     p.red = 0;
@@ -113,7 +114,7 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
     else p.per_lane = (p.lanes >= 32768 && p.lanes < 1048576) ? 2 : 1;
   } else {
     p.red = p.mode == kPH64 ? 1 : 0;
-    p.grp = p.mode == kPH64 ? 32 : 16;
+    p.grp = p.mode == kPH64 ? 64 : 16;
     // the phase part of the point records from LDS tiles, the rest with scalar loads
     // (1.5-3 % faster than scalar loads alone, from 1e5 to 1e6 atoms)
     p.lds = p.mode == kPH64 ? 1 : 0;
@@ -124,7 +125,9 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
     const int64_t tp = env_i64("NX_TUNE_P", -1);
     if (tp == 1 || tp == 2 || (tp == 4 && p.mode != kF64)) p.per_lane = int(tp);
     const int64_t tg = env_i64("NX_TUNE_GRP", -1);
-    if (p.mode == kPH64 && (tg == 8 || tg == 16 || tg == 32) && (fwd || tg != 8)) p.grp = int(tg);
+    // forward: 8, 16, 32; adjoint: 16, 32, 64
+    if (p.mode == kPH64 && (fwd ? (tg == 8 || tg == 16 || tg == 32) : (tg == 16 || tg == 32 || tg == 64)))
+      p.grp = int(tg);
     const int64_t tr = env_i64("NX_TUNE_RED", -1);
     if (p.mode == kPH64 && (tr == 0 || tr == 1)) p.red = int(tr);
     const int64_t tl = env_i64("NX_TUNE_LDS", -1);

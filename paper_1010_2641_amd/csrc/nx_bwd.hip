@@ -601,8 +601,11 @@ hipError_t bwd_dispatch(const Plan& p, const BwdArgs& b, hipStream_t st) {
     bwd_kernel<MODE, Q, FK, 16, 0, GF><<<grid, kThreads, 0, st>>>(
         r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);
   } else {
-    if (p.lds && p.red == 1 && (p.grp == 32 || p.grp == 16)) {
-      if (p.grp == 32)
+    if (p.lds && p.red == 1 && (p.grp == 64 || p.grp == 32 || p.grp == 16)) {
+      if (p.grp == 64)
+        bwd_split_kernel<Q, FK, 64, 1, GF><<<grid, kThreads, 0, st>>>(
+            r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);
+      else if (p.grp == 32)
         bwd_split_kernel<Q, FK, 32, 1, GF><<<grid, kThreads, 0, st>>>(
             r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);
       else
@@ -610,7 +613,13 @@ hipError_t bwd_dispatch(const Plan& p, const BwdArgs& b, hipStream_t st) {
             r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);
       return hipGetLastError();
     }
-    if (p.grp == 16 && p.red == 0)
+    if (p.grp == 64 && p.red == 0)
+      bwd_kernel<MODE, Q, FK, 64, 0, GF><<<grid, kThreads, 0, st>>>(
+          r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);
+    else if (p.grp == 64)
+      bwd_kernel<MODE, Q, FK, 64, 1, GF><<<grid, kThreads, 0, st>>>(
+          r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);
+    else if (p.grp == 16 && p.red == 0)
       bwd_kernel<MODE, Q, FK, 16, 0, GF><<<grid, kThreads, 0, st>>>(
           r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);
     else if (p.grp == 16)

@@ -229,7 +229,7 @@ def test_bwd_chunked_launches(mode, monkeypatch):
 
 
 @pytest.mark.parametrize("red", ["0", "1"])
-@pytest.mark.parametrize("grp", ["16", "32"])
+@pytest.mark.parametrize("grp", ["16", "32", "64"])
 def test_bwd_variants(red, grp, monkeypatch):
     monkeypatch.setenv("NX_TUNE_RED", red)
     monkeypatch.setenv("NX_TUNE_GRP", grp)
@@ -376,14 +376,14 @@ def test_lds_staged_forward_bitwise(n, k, cplx, monkeypatch):
 @pytest.mark.parametrize("cplx", [True, False])
 def test_split_adjoint_bitwise(n, k, cplx, monkeypatch):
     """The adjoint with the phase part of the point records in LDS tiles and the one with
-    scalar loads only sum in the same order: bitwise equal, with and without dL/df, both
-    group sizes, ragged tails and splits."""
+    scalar loads only sum in the same order: bitwise equal, with and without dL/df, every
+    group size, ragged tails and splits."""
     xyz, f, S = wl.random_problem(n, k, seed=n + k, extent=40.0, s_range=3.0, complex_f=cplx)
     G = wl.random_seed_field(k, seed=k)
     out = {}
     for lds in ("0", "1"):
         monkeypatch.setenv("NX_TUNE_LDS", lds)
-        for grp in ("32", "16"):
+        for grp in ("64", "32", "16"):
             monkeypatch.setenv("NX_TUNE_GRP", grp)
             gx, gf = api.scatter_bwd_ex(dev(xyz), dev(f), dev(S), dev(G), "ph64")
             torch.cuda.synchronize()
