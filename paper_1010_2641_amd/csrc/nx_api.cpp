@@ -42,6 +42,7 @@ bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 //   NX_TUNE_P             lane items per lane (1, 2, 4; the FP64 path 1, 2)
 //   NX_TUNE_GRP           stream items per compensated group (8, 16, 32)
 //   NX_TUNE_RED           phase reduction variant (0 centred rint, 1 fract)
+//   NX_TUNE_TARGET_BLOCKS work-groups wanted per launch (stream splits up to this)
 //   NX_TUNE_L2_CHUNK      0 turns off the L2-sized atom chunks of the forward
 //   NX_TUNE_LDS           FP64-phase sums: 1 stages record tiles in LDS (the forward's
 //                         atom records; the phase part of the adjoint's point records),
@@ -136,8 +137,10 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
   const int64_t per_block = int64_t(kThreads) * p.per_lane;
   p.blocks = p.lanes > 0 ? ceil_div(p.lanes, per_block) : 0;
   p.nsplit = 1;
-  if (p.blocks > 0 && p.blocks < kTargetBlocks) {
-    int64_t want = ceil_div(kTargetBlocks, p.blocks);
+  int64_t target = env_i64("NX_TUNE_TARGET_BLOCKS", kTargetBlocks);
+  if (target < 1) target = kTargetBlocks;
+  if (p.blocks > 0 && p.blocks < target) {
+    int64_t want = ceil_div(target, p.blocks);
     int64_t maxs = p.stream / kMinStreamPerSplit;
     if (maxs < 1) maxs = 1;
     if (want > maxs) want = maxs;

@@ -200,7 +200,8 @@ def test_missing_library_fails_loudly(monkeypatch):
 def test_plan_l2_sized_forward_chunks(monkeypatch):
     """The forward cuts its launches when a split's slice of atom records exceeds an
     XCD's L2: the carried running sums then appear in the workspace (host-side plan)."""
-    n, k = 203_557, 2_097_152                      # one split; 48-byte FP64-phase records
+    monkeypatch.setenv("NX_TUNE_TARGET_BLOCKS", "4096")   # one split at this size
+    n, k = 203_557, 2_097_152                                 # 48-byte FP64-phase records
     rec = -(-n * 48 // 256) * 256
     for f_is_null in (0, 1):
         with_chunks = _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_FWD, f_is_null)
@@ -218,10 +219,23 @@ def test_plan_launch_chunks_and_splits(monkeypatch):
     # few points: the atoms are split across work-groups, with one state per split
     few = _lib.nx_workspace_bytes(1_000_000, 65_536, 1, _lib.NX_OP_FWD, 1)
     assert few > 1_000_000 * 32 + 65_536 * 16
-    # enough points to fill the chip: no split, no carried state ...
+    # enough points for the target number of work-groups: no split, no carried state ...
+    monkeypatch.setenv("NX_TUNE_TARGET_BLOCKS", "4096")
     n, k = 5000, 1 << 20
     rec = -(-n * 48 // 256) * 256
     assert _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_FWD, 1) == rec
     # ... until a small launch size forces chunks, which carry one state per point
     monkeypatch.setenv("NX_TUNE_LAUNCH_PAIRS", str(1 << 24))
     assert _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_FWD, 1) == rec + k * 16
+
+
+def test_plan_stream_splits_for_the_target_block_count(monkeypatch):
+    """The adjoint of a 203,557-atom, 2,097,152-point fit: 398 work-groups of 512 atoms are
+    too few, so the points are cut into ceil(32768 / 398) = 83 slices, each with its own
+    (sum, comp) state of the 3 position sums per atom (24 bytes)."""
+    n, k = 203_557, 2_097_152
+    rec = -(-k * 48 // 256) * 256
+    part = -(-83 * n * 24 // 256) * 256
+    assert _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_BWD, 0) == rec + part
+    monkeypatch.setenv("NX_TUNE_TARGET_BLOCKS", "4096")              # ceil(4096 / 398) = 11
+    assert _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_BWD, 0) == rec + -(-11 * n * 24 // 256) * 256
