@@ -129,7 +129,11 @@ struct Plan {
 // splits the streams further and made the fit step 4-7 % faster on the 200k- to
 // 4M-atom workloads (the adjoint 5-10 %).
 constexpr int64_t kTargetBlocks = 32768;
-constexpr int64_t kMinStreamPerSplit = 64;    // smallest stream slice
+// Smallest stream slice per split.  Each split costs every lane a partial state written
+// and read back, and the reduce reads the splits of one output in sequence, so slices
+// much below a few hundred items lose more than the fuller chip gains (64 took a
+// 1e5-atom, 1e4-point forward from 2.5e12 to 1.7e12 pairs/s at 820 splits).
+constexpr int64_t kMinStreamPerSplit = 256;
 constexpr int64_t kMaxSplit = 1024;
 constexpr int64_t kLaunchPairs = int64_t(1) << 39;   // pairs per launch (well under 1 s)
 // Forward: when one split's slice of packed atom records exceeds an XCD's 4 MiB L2, the
