@@ -46,8 +46,7 @@ bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 //   NX_TUNE_L2_CHUNK      0 turns off the L2-sized atom chunks of the forward
 //   NX_TUNE_LDS           FP64-phase sums: 1 stages record tiles in LDS (the forward's
 //                         atom records; the phase part of the adjoint's point records),
-//                         0 streams them through scalar loads (default: 1 for the
-//                         adjoint and for the forward with complex f)
+//                         0 streams them through scalar loads (default: 1)
 int64_t env_i64(const char* name, int64_t def) {
   const char* v = std::getenv(name);
   if (!v || !*v) return def;
