@@ -239,3 +239,16 @@ def test_plan_stream_splits_for_the_target_block_count(monkeypatch):
     assert _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_BWD, 0) == rec + part
     monkeypatch.setenv("NX_TUNE_TARGET_BLOCKS", "4096")              # ceil(4096 / 398) = 11
     assert _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_BWD, 0) == rec + -(-11 * n * 24 // 256) * 256
+
+
+def test_plan_stream_slices_are_at_least_256_items(monkeypatch):
+    """Splits stop at slices of 256 stream items: a 100,000-atom forward over 10,000 points
+    (40 work-groups) would want ceil(32768 / 40) = 820 slices, and gets 100000 // 256 =
+    390, each with one (sum, comp) float4 per point; 1,000 atoms over 1,000 points get 3."""
+    monkeypatch.delenv("NX_TUNE_TARGET_BLOCKS", raising=False)
+    rec = 100_000 * 48
+    assert _lib.nx_workspace_bytes(100_000, 10_000, 1, _lib.NX_OP_FWD, 1) == rec + 390 * 10_000 * 16
+    a256 = lambda b: -(-b // 256) * 256
+    assert _lib.nx_workspace_bytes(1000, 1000, 1, _lib.NX_OP_FWD, 1) == a256(1000 * 48) + a256(3 * 1000 * 16)
+    # the FP32 mode's 32-byte records, same slices
+    assert _lib.nx_workspace_bytes(1000, 1000, 0, _lib.NX_OP_FWD, 1) == a256(1000 * 32) + a256(3 * 1000 * 16)
