@@ -75,6 +75,17 @@ def test_fwd_random_ragged(n, k, cplx, mode):
         assert e2 < 5e-3
 
 
+@pytest.mark.parametrize("mode", ["ph64", "f64"])
+@pytest.mark.parametrize("n", [255, 256, 257, 1023, 1024, 1025])
+def test_fwd_slice_length_boundaries(n, mode):
+    """Few points want many stream slices; the slices stop at 256 atoms, so these atom
+    counts give 1, 1, 1, 3, 4 and 4 slices (ragged last slices included)."""
+    k = 300
+    xyz, f, S = wl.random_problem(n, k, seed=7 * n, extent=50.0, s_range=4.0, complex_f=True)
+    print(f"case fwd slices N={n} K={k} mode={mode}", flush=True)
+    check_fwd(run_fwd(xyz, f, S, mode), oracle.forward(xyz, f, S), mode, f=f, n=n)
+
+
 @pytest.mark.parametrize("mode", ["ph64", "f64", "f32"])
 @pytest.mark.parametrize("n,k", [(0, 100), (1, 1), (15, 300), (16, 257), (17, 64), (5, 1)])
 def test_fwd_edge_sizes(n, k, mode):
@@ -226,6 +237,23 @@ def test_bwd_chunked_launches(mode, monkeypatch):
     g = run_bwd(xyz, f, S, G, mode)
     en, em = M.t3(g, g_ref)
     assert en <= (M.T3_NORM_TOL if mode == "ph64" else M.F64_T3_TOL)
+
+
+@pytest.mark.parametrize("mode", ["ph64", "f64"])
+@pytest.mark.parametrize("k", [511, 512, 513, 1279, 1280])
+def test_bwd_slice_length_boundaries(k, mode):
+    """The adjoint's stream is the points: 300 atoms (one work-group) over these point
+    counts give 1, 2, 2, 4 and 5 slices of at least 256 points."""
+    n = 300
+    xyz, f, S = wl.random_problem(n, k, seed=5 * k, extent=40.0, s_range=3.0, complex_f=True)
+    G = wl.random_seed_field(k, seed=k, scale=10.0)
+    print(f"case bwd slices N={n} K={k} mode={mode}", flush=True)
+    en, em = M.t3(run_bwd(xyz, f, S, G, mode), oracle.adjoint(xyz, f, S, G))
+    print(f"  T3 norm={en:.3e} max={em:.3e}", flush=True)
+    if mode == "ph64":
+        assert en <= M.T3_NORM_TOL and em <= M.T3_MAX_TOL
+    else:
+        assert en <= M.F64_T3_TOL
 
 
 @pytest.mark.parametrize("red", ["0", "1"])
