@@ -132,12 +132,20 @@ int nx_scatter_fwd_f64(const double* xyz, const double* f, int64_t n_atoms,
                        const double* S, int64_t n_points, double* A,
                        void* ws, size_t ws_bytes, void* stream);
 
-/* All-FP64 adjoint; same layout as nx_scatter_bwd with double arrays. */
+/* All-FP64 adjoint: the chain rule through Eq. 2 (Section 2.1) for the positions,
+ *     grad_xyz_j = Re sum_k conj(G_k) f_j (2 i pi S_k) exp(2 i pi S_k . r_j),
+ * with FP64 phase, sin/cos and sums: the double-precision comparator of the end of
+ * Section 2.3, applied to the adjoint.  Same layout, ownership and errors as
+ * nx_scatter_bwd with double arrays (G and f complex128 as (re, im) pairs). */
 int nx_scatter_bwd_f64(const double* xyz, const double* f, int64_t n_atoms,
                        const double* S, int64_t n_points, const double* G, double* grad_xyz,
                        void* ws, size_t ws_bytes, void* stream);
 
-/* Intensity misfit and its seed for fitting a model to measured intensities I:
+/* Intensity misfit and its seed for fitting a model to measured intensities I (the
+ * paper computes intensity maps |A|^2 of strained nanostructures, Sections 4.1-4.3, and
+ * its conclusion, Section 6, points to fitting such models to measured maps; the
+ * paper prints no loss, so this least-squares misfit in intensity is this library's
+ * choice of objective):
  *     e_k = |A_k|^2 - I_k,   L = sum_k e_k^2,   G_k = 4 e_k A_k
  * (G is dL/dRe A + i dL/dIm A, the input nx_scatter_bwd expects).  e and L are
  * evaluated in FP64 from the FP32 inputs; G is rounded once to FP32.  L is reduced in

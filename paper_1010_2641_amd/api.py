@@ -35,17 +35,44 @@ def _mode(mode) -> int:
         raise ValueError(f"unknown mode {mode!r}; expected one of {sorted(MODES)}") from None
 
 
-def _need_gpu(t: torch.Tensor, name: str, dtype, shape_tail=None):
+def _need(t: torch.Tensor, name: str, dtype, shape=None):
+    """Type, dtype, shape and layout of one tensor argument (no device check, so that
+    these checks also run, and can be tested, on CPU tensors).  ``shape`` is a tuple
+    whose None entries match any size."""
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch.Tensor")
-    if t.device.type != "cuda":
-        raise ValueError(f"{name} must be on the GPU (got {t.device}); libnx has no CPU path")
     if t.dtype != dtype:
         raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
-    if shape_tail is not None and (t.dim() != 2 or t.shape[1] != shape_tail):
-        raise ValueError(f"{name} must have shape (n, {shape_tail}) (got {tuple(t.shape)})")
+    if shape is not None and (t.dim() != len(shape) or any(
+            want is not None and got != want for got, want in zip(t.shape, shape))):
+        want = ", ".join("n" if v is None else str(v) for v in shape)
+        raise ValueError(f"{name} must have shape ({want}{',' if len(shape) == 1 else ''}) "
+                         f"(got {tuple(t.shape)})")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+    if t.is_conj():
+        raise ValueError(f"{name} is an unresolved conjugate view; call resolve_conj() first")
+
+
+def _on_gpu(**tensors):
+    """Every given tensor (None entries skipped) on one and the same GPU: the library
+    takes device pointers only and has no CPU path."""
+    dev = None
+    for name, t in tensors.items():
+        if t is None:
+            continue
+        if t.device.type != "cuda":
+            raise ValueError(f"{name} must be on the GPU (got {t.device}); libnx has no CPU path")
+        if dev is None:
+            dev = t.device
+        elif t.device != dev:
+            raise ValueError(f"{name} is on {t.device}, the other arguments on {dev}")
+
+
+def _seed_arg(gA: torch.Tensor, dtype) -> torch.Tensor:
+    """An adjoint seed as a plain contiguous tensor of `dtype`: autograd may hand
+    backward a lazy conjugate view (e.g. after A.conj()), which view_as_real refuses."""
+    return gA.resolve_conj().to(dtype).contiguous()
 
 
 def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
@@ -65,10 +92,12 @@ def _workspace(nbytes: int, device) -> Tuple[Optional[torch.Tensor], int]:
 def _f_arg(f: Optional[torch.Tensor], n: int, dtype):
     if f is None:
         return None
-    _need_gpu(f, "f", dtype)
-    if f.dim() != 1 or f.shape[0] != n:
-        raise ValueError(f"f must have shape ({n},) (got {tuple(f.shape)})")
-    return torch.view_as_real(f)
+    _need(f, "f", dtype, (n,))
+    return f
+
+
+def _real(t: Optional[torch.Tensor]) -> Optional[torch.Tensor]:
+    return None if t is None else torch.view_as_real(t)
 
 
 def workspace_bytes(n_atoms: int, n_points: int, mode="ph64", op=_lib.NX_OP_FWD,
@@ -83,18 +112,21 @@ def workspace_bytes(n_atoms: int, n_points: int, mode="ph64", op=_lib.NX_OP_FWD,
 def scatter_fwd(xyz: torch.Tensor, f: Optional[torch.Tensor], S: torch.Tensor, mode="ph64",
                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """A_k = sum_j f_j exp(2 i pi S_k . r_j) (Eq. 2).  xyz (N,3) float32, f (N,)
-    complex64 or None (f_j = 1), S (K,3) float32 -> A (K,) complex64."""
-    _need_gpu(xyz, "xyz", torch.float32, 3)
-    _need_gpu(S, "S", torch.float32, 3)
+    complex64 or None (f_j = 1), S (K,3) float32 -> A (K,) complex64 (written into
+    ``out`` when given: a contiguous (K,) complex64 tensor on the same GPU)."""
+    _need(xyz, "xyz", torch.float32, (None, 3))
+    _need(S, "S", torch.float32, (None, 3))
     n, k = xyz.shape[0], S.shape[0]
-    fr = _f_arg(f, n, torch.complex64)
+    _f_arg(f, n, torch.complex64)
+    if out is not None:
+        _need(out, "out", torch.complex64, (k,))
     m = _mode(mode)
+    _on_gpu(xyz=xyz, S=S, f=f, out=out)
     if out is None:
         out = torch.empty(k, dtype=torch.complex64, device=S.device)
     ws, wsb = _workspace(workspace_bytes(n, k, m, _lib.NX_OP_FWD, f is None), S.device)
-    _lib.check(_lib.nx_scatter_fwd(_ptr(xyz), _ptr(fr), n, _ptr(S), k,
-                                   _ptr(torch.view_as_real(out)), m, _ptr(ws), wsb,
-                                   _stream(S.device)))
+    _lib.check(_lib.nx_scatter_fwd(_ptr(xyz), _ptr(_real(f)), n, _ptr(S), k,
+                                   _ptr(_real(out)), m, _ptr(ws), wsb, _stream(S.device)))
     return out
 
 
@@ -102,52 +134,48 @@ def scatter_bwd(xyz: torch.Tensor, f: Optional[torch.Tensor], S: torch.Tensor, G
                 mode="ph64") -> torch.Tensor:
     """dL/dr_j = Re sum_k conj(G_k) f_j (2 i pi S_k) exp(2 i pi S_k . r_j) for the seed
     G = dL/dRe A + i dL/dIm A (K,) complex64 -> (N,3) float32."""
-    _need_gpu(xyz, "xyz", torch.float32, 3)
-    _need_gpu(S, "S", torch.float32, 3)
-    _need_gpu(G, "G", torch.complex64)
+    _need(xyz, "xyz", torch.float32, (None, 3))
+    _need(S, "S", torch.float32, (None, 3))
     n, k = xyz.shape[0], S.shape[0]
-    if G.dim() != 1 or G.shape[0] != k:
-        raise ValueError(f"G must have shape ({k},)")
-    fr = _f_arg(f, n, torch.complex64)
+    _need(G, "G", torch.complex64, (k,))
+    _f_arg(f, n, torch.complex64)
     m = _mode(mode)
+    _on_gpu(xyz=xyz, S=S, G=G, f=f)
     grad = torch.empty((n, 3), dtype=torch.float32, device=xyz.device)
     ws, wsb = _workspace(workspace_bytes(n, k, m, _lib.NX_OP_BWD, f is None), xyz.device)
-    _lib.check(_lib.nx_scatter_bwd(_ptr(xyz), _ptr(fr), n, _ptr(S), k,
-                                   _ptr(torch.view_as_real(G)), _ptr(grad), m, _ptr(ws), wsb,
-                                   _stream(xyz.device)))
+    _lib.check(_lib.nx_scatter_bwd(_ptr(xyz), _ptr(_real(f)), n, _ptr(S), k, _ptr(_real(G)),
+                                   _ptr(grad), m, _ptr(ws), wsb, _stream(xyz.device)))
     return grad
 
 
 def scatter_fwd_f64(xyz: torch.Tensor, f: Optional[torch.Tensor], S: torch.Tensor) -> torch.Tensor:
     """All-FP64 Eq. 2: xyz (N,3) float64, f (N,) complex128 or None, S (K,3) float64
     -> (K,) complex128."""
-    _need_gpu(xyz, "xyz", torch.float64, 3)
-    _need_gpu(S, "S", torch.float64, 3)
+    _need(xyz, "xyz", torch.float64, (None, 3))
+    _need(S, "S", torch.float64, (None, 3))
     n, k = xyz.shape[0], S.shape[0]
-    fr = _f_arg(f, n, torch.complex128)
+    _f_arg(f, n, torch.complex128)
+    _on_gpu(xyz=xyz, S=S, f=f)
     out = torch.empty(k, dtype=torch.complex128, device=S.device)
     ws, wsb = _workspace(workspace_bytes(n, k, 0, _lib.NX_OP_FWD_F64, f is None), S.device)
-    _lib.check(_lib.nx_scatter_fwd_f64(_ptr(xyz), _ptr(fr), n, _ptr(S), k,
-                                       _ptr(torch.view_as_real(out)), _ptr(ws), wsb,
-                                       _stream(S.device)))
+    _lib.check(_lib.nx_scatter_fwd_f64(_ptr(xyz), _ptr(_real(f)), n, _ptr(S), k, _ptr(_real(out)),
+                                       _ptr(ws), wsb, _stream(S.device)))
     return out
 
 
 def scatter_bwd_f64(xyz: torch.Tensor, f: Optional[torch.Tensor], S: torch.Tensor,
                     G: torch.Tensor) -> torch.Tensor:
     """All-FP64 adjoint: G (K,) complex128 -> (N,3) float64."""
-    _need_gpu(xyz, "xyz", torch.float64, 3)
-    _need_gpu(S, "S", torch.float64, 3)
-    _need_gpu(G, "G", torch.complex128)
+    _need(xyz, "xyz", torch.float64, (None, 3))
+    _need(S, "S", torch.float64, (None, 3))
     n, k = xyz.shape[0], S.shape[0]
-    if G.dim() != 1 or G.shape[0] != k:
-        raise ValueError(f"G must have shape ({k},)")
-    fr = _f_arg(f, n, torch.complex128)
+    _need(G, "G", torch.complex128, (k,))
+    _f_arg(f, n, torch.complex128)
+    _on_gpu(xyz=xyz, S=S, G=G, f=f)
     grad = torch.empty((n, 3), dtype=torch.float64, device=xyz.device)
     ws, wsb = _workspace(workspace_bytes(n, k, 0, _lib.NX_OP_BWD_F64, f is None), xyz.device)
-    _lib.check(_lib.nx_scatter_bwd_f64(_ptr(xyz), _ptr(fr), n, _ptr(S), k,
-                                       _ptr(torch.view_as_real(G)), _ptr(grad), _ptr(ws), wsb,
-                                       _stream(xyz.device)))
+    _lib.check(_lib.nx_scatter_bwd_f64(_ptr(xyz), _ptr(_real(f)), n, _ptr(S), k, _ptr(_real(G)),
+                                       _ptr(grad), _ptr(ws), wsb, _stream(xyz.device)))
     return grad
 
 
@@ -155,22 +183,20 @@ def scatter_bwd_ex(xyz: torch.Tensor, f: Optional[torch.Tensor], S: torch.Tensor
                    mode="ph64", want_xyz: bool = True, want_f: bool = True):
     """The adjoint with the factor gradient: returns (dL/dxyz (N,3) float32 or None,
     dL/df (N,) complex64 or None)."""
-    _need_gpu(xyz, "xyz", torch.float32, 3)
-    _need_gpu(S, "S", torch.float32, 3)
-    _need_gpu(G, "G", torch.complex64)
+    _need(xyz, "xyz", torch.float32, (None, 3))
+    _need(S, "S", torch.float32, (None, 3))
     n, k = xyz.shape[0], S.shape[0]
-    if G.dim() != 1 or G.shape[0] != k:
-        raise ValueError(f"G must have shape ({k},)")
-    fr = _f_arg(f, n, torch.complex64)
+    _need(G, "G", torch.complex64, (k,))
+    _f_arg(f, n, torch.complex64)
     m = _mode(mode)
+    _on_gpu(xyz=xyz, S=S, G=G, f=f)
     grad = torch.empty((n, 3), dtype=torch.float32, device=xyz.device) if want_xyz else None
     gradf = torch.empty(n, dtype=torch.complex64, device=xyz.device) if want_f else None
     op = _lib.NX_OP_BWD_GF if want_f else _lib.NX_OP_BWD
     ws, wsb = _workspace(workspace_bytes(n, k, m, op, f is None), xyz.device)
-    _lib.check(_lib.nx_scatter_bwd_ex(_ptr(xyz), _ptr(fr), n, _ptr(S), k,
-                                      _ptr(torch.view_as_real(G)), _ptr(grad),
-                                      None if gradf is None else _ptr(torch.view_as_real(gradf)),
-                                      m, _ptr(ws), wsb, _stream(xyz.device)))
+    _lib.check(_lib.nx_scatter_bwd_ex(_ptr(xyz), _ptr(_real(f)), n, _ptr(S), k, _ptr(_real(G)),
+                                      _ptr(grad), _ptr(_real(gradf)), m, _ptr(ws), wsb,
+                                      _stream(xyz.device)))
     return grad, gradf
 
 
@@ -178,21 +204,19 @@ def scatter_bwd_ex_f64(xyz: torch.Tensor, f: Optional[torch.Tensor], S: torch.Te
                        G: torch.Tensor, want_xyz: bool = True, want_f: bool = True):
     """All-FP64 adjoint with the factor gradient: (dL/dxyz float64 or None, dL/df complex128
     or None)."""
-    _need_gpu(xyz, "xyz", torch.float64, 3)
-    _need_gpu(S, "S", torch.float64, 3)
-    _need_gpu(G, "G", torch.complex128)
+    _need(xyz, "xyz", torch.float64, (None, 3))
+    _need(S, "S", torch.float64, (None, 3))
     n, k = xyz.shape[0], S.shape[0]
-    if G.dim() != 1 or G.shape[0] != k:
-        raise ValueError(f"G must have shape ({k},)")
-    fr = _f_arg(f, n, torch.complex128)
+    _need(G, "G", torch.complex128, (k,))
+    _f_arg(f, n, torch.complex128)
+    _on_gpu(xyz=xyz, S=S, G=G, f=f)
     grad = torch.empty((n, 3), dtype=torch.float64, device=xyz.device) if want_xyz else None
     gradf = torch.empty(n, dtype=torch.complex128, device=xyz.device) if want_f else None
     op = _lib.NX_OP_BWD_GF_F64 if want_f else _lib.NX_OP_BWD_F64
     ws, wsb = _workspace(workspace_bytes(n, k, 0, op, f is None), xyz.device)
-    _lib.check(_lib.nx_scatter_bwd_ex_f64(_ptr(xyz), _ptr(fr), n, _ptr(S), k,
-                                          _ptr(torch.view_as_real(G)), _ptr(grad),
-                                          None if gradf is None else _ptr(torch.view_as_real(gradf)),
-                                          _ptr(ws), wsb, _stream(xyz.device)))
+    _lib.check(_lib.nx_scatter_bwd_ex_f64(_ptr(xyz), _ptr(_real(f)), n, _ptr(S), k, _ptr(_real(G)),
+                                          _ptr(grad), _ptr(_real(gradf)), _ptr(ws), wsb,
+                                          _stream(xyz.device)))
     return grad, gradf
 
 
@@ -209,10 +233,8 @@ def _species_array(species_start: Sequence[int], n_atoms: int):
 def _fs_arg(fs: Optional[torch.Tensor], ns: int, k: int):
     if fs is None:
         return None
-    _need_gpu(fs, "fs", torch.complex64)
-    if tuple(fs.shape) != (ns, k):
-        raise ValueError(f"fs must have shape ({ns}, {k}) (got {tuple(fs.shape)})")
-    return torch.view_as_real(fs)
+    _need(fs, "fs", torch.complex64, (ns, k))
+    return fs
 
 
 def scatter_fwd_species(xyz: torch.Tensor, species_start: Sequence[int], fs: Optional[torch.Tensor],
@@ -221,22 +243,22 @@ def scatter_fwd_species(xyz: torch.Tensor, species_start: Sequence[int], fs: Opt
     listed species by species, species s = atoms [species_start[s], species_start[s+1]);
     fs (n_species, K) complex64 or None.  Returns A (K,) complex64, and the per-species
     sums (n_species, K) when return_species."""
-    _need_gpu(xyz, "xyz", torch.float32, 3)
-    _need_gpu(S, "S", torch.float32, 3)
+    _need(xyz, "xyz", torch.float32, (None, 3))
+    _need(S, "S", torch.float32, (None, 3))
     n, k = xyz.shape[0], S.shape[0]
     start, ns = _species_array(species_start, n)
-    fsr = _fs_arg(fs, ns, k)
+    _fs_arg(fs, ns, k)
     m = _mode(mode)
+    _on_gpu(xyz=xyz, S=S, fs=fs)
     A = torch.empty(k, dtype=torch.complex64, device=S.device)
     As = torch.empty((ns, k), dtype=torch.complex64, device=S.device) if return_species else None
     nb = _lib.nx_workspace_bytes_species(start, ns, k, m, 0)
     if _lib.last_error():
         raise _lib.NxError(_lib.NX_ERR_ARG, _lib.last_error())
     ws, wsb = _workspace(int(nb), S.device)
-    _lib.check(_lib.nx_scatter_fwd_species(_ptr(xyz), n, start, ns, _ptr(fsr), _ptr(S), k,
-                                           _ptr(torch.view_as_real(A)),
-                                           None if As is None else _ptr(torch.view_as_real(As)),
-                                           m, _ptr(ws), wsb, _stream(S.device)))
+    _lib.check(_lib.nx_scatter_fwd_species(_ptr(xyz), n, start, ns, _ptr(_real(fs)), _ptr(S), k,
+                                           _ptr(_real(A)), _ptr(_real(As)), m, _ptr(ws), wsb,
+                                           _stream(S.device)))
     return (A, As) if return_species else A
 
 
@@ -244,44 +266,41 @@ def scatter_bwd_species(xyz: torch.Tensor, species_start: Sequence[int], fs: Opt
                         S: torch.Tensor, G: torch.Tensor, A_species: Optional[torch.Tensor] = None,
                         mode="ph64", want_xyz: bool = True):
     """Adjoint of ``scatter_fwd_species``: (dL/dxyz (N,3) float32 or None, dL/dfs
-    (n_species, K) complex64 or None -- the latter when A_species is given)."""
-    _need_gpu(xyz, "xyz", torch.float32, 3)
-    _need_gpu(S, "S", torch.float32, 3)
-    _need_gpu(G, "G", torch.complex64)
+    (n_species, K) complex64 or None -- the latter when A_species, the per-species sums
+    (n_species, K) complex64 of the forward, is given)."""
+    _need(xyz, "xyz", torch.float32, (None, 3))
+    _need(S, "S", torch.float32, (None, 3))
     n, k = xyz.shape[0], S.shape[0]
+    _need(G, "G", torch.complex64, (k,))
     start, ns = _species_array(species_start, n)
-    fsr = _fs_arg(fs, ns, k)
-    m = _mode(mode)
-    Asr = None
+    _fs_arg(fs, ns, k)
     if A_species is not None:
-        _need_gpu(A_species, "A_species", torch.complex64)
-        Asr = torch.view_as_real(A_species)
+        _need(A_species, "A_species", torch.complex64, (ns, k))
+    m = _mode(mode)
+    _on_gpu(xyz=xyz, S=S, G=G, fs=fs, A_species=A_species)
     grad = torch.empty((n, 3), dtype=torch.float32, device=xyz.device) if want_xyz else None
     gfs = torch.empty((ns, k), dtype=torch.complex64, device=xyz.device) if A_species is not None else None
     nb = _lib.nx_workspace_bytes_species(start, ns, k, m, 1)
     if _lib.last_error():
         raise _lib.NxError(_lib.NX_ERR_ARG, _lib.last_error())
     ws, wsb = _workspace(int(nb), xyz.device)
-    _lib.check(_lib.nx_scatter_bwd_species(_ptr(xyz), n, start, ns, _ptr(fsr), _ptr(S), k,
-                                           _ptr(torch.view_as_real(G)), _ptr(Asr), _ptr(grad),
-                                           None if gfs is None else _ptr(torch.view_as_real(gfs)),
-                                           m, _ptr(ws), wsb, _stream(xyz.device)))
+    _lib.check(_lib.nx_scatter_bwd_species(_ptr(xyz), n, start, ns, _ptr(_real(fs)), _ptr(S), k,
+                                           _ptr(_real(G)), _ptr(_real(A_species)), _ptr(grad),
+                                           _ptr(_real(gfs)), m, _ptr(ws), wsb, _stream(xyz.device)))
     return grad, gfs
 
 
 def loss_grad(A: torch.Tensor, I: torch.Tensor, want_grad: bool = True):
     """L = sum_k (|A_k|^2 - I_k)^2 (float64 scalar tensor on the device) and the seed
     G = 4 (|A|^2 - I) A (complex64) or None."""
-    _need_gpu(A, "A", torch.complex64)
-    _need_gpu(I, "I", torch.float32)
+    _need(A, "A", torch.complex64, (None,))
     k = A.shape[0]
-    if A.dim() != 1 or I.dim() != 1 or I.shape[0] != k:
-        raise ValueError("A and I must be 1-D of the same length")
+    _need(I, "I", torch.float32, (k,))
+    _on_gpu(A=A, I=I)
     L = torch.empty((), dtype=torch.float64, device=A.device)
     G = torch.empty(k, dtype=torch.complex64, device=A.device) if want_grad else None
     ws, wsb = _workspace(workspace_bytes(0, k, 0, _lib.NX_OP_LOSS, True), A.device)
-    _lib.check(_lib.nx_loss_grad(_ptr(torch.view_as_real(A)), _ptr(I), k, _ptr(L),
-                                 None if G is None else _ptr(torch.view_as_real(G)),
+    _lib.check(_lib.nx_loss_grad(_ptr(_real(A)), _ptr(I), k, _ptr(L), _ptr(_real(G)),
                                  _ptr(ws), wsb, _stream(A.device)))
     return L, G
 
@@ -311,9 +330,9 @@ class ScatterFn(torch.autograd.Function):
         if not (want_x or want_f):
             return None, None, None, None
         if xyz.dtype == torch.float64:
-            gx, gf = scatter_bwd_ex_f64(xyz, f, S, gA.to(torch.complex128).contiguous(), want_x, want_f)
+            gx, gf = scatter_bwd_ex_f64(xyz, f, S, _seed_arg(gA, torch.complex128), want_x, want_f)
         else:
-            gx, gf = scatter_bwd_ex(xyz, f, S, gA.to(torch.complex64).contiguous(), ctx.mode,
+            gx, gf = scatter_bwd_ex(xyz, f, S, _seed_arg(gA, torch.complex64), ctx.mode,
                                     want_x, want_f)
         return gx, gf, None, None
 
@@ -339,7 +358,7 @@ class ScatterSpeciesFn(torch.autograd.Function):
             (xyz, S, As), fs = ctx.saved_tensors, None
         want_x = ctx.needs_input_grad[0]
         want_fs = ctx.has_fs and ctx.needs_input_grad[1]
-        gx, gfs = scatter_bwd_species(xyz, ctx.species_start, fs, S, gA.to(torch.complex64).contiguous(),
+        gx, gfs = scatter_bwd_species(xyz, ctx.species_start, fs, S, _seed_arg(gA, torch.complex64),
                                       As if want_fs else None, ctx.mode, want_x)
         return gx, gfs, None, None, None
 

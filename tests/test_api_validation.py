@@ -1,0 +1,76 @@
+"""The torch wrappers' argument checks, on the CPU.  Every shape, dtype and layout check
+runs before the device check, so wrongly shaped CPU tensors are refused with the shape
+error (on the GPU the same checks stand between the caller and the C ABI, which cannot
+see tensor sizes: a wrongly sized output would be written past its end).  No call reaches
+the library here."""
+import pytest
+import torch
+
+from paper_1010_2641_amd import api
+
+
+def z(*shape, dtype=torch.float32):
+    return torch.zeros(shape, dtype=dtype)
+
+
+def test_forward_out_is_checked():
+    x, S = z(5, 3), z(7, 3)
+    with pytest.raises(ValueError, match=r"out must have shape \(7,\)"):
+        api.scatter_fwd(x, None, S, out=z(6, dtype=torch.complex64))
+    with pytest.raises(ValueError, match="out must have shape"):
+        api.scatter_fwd(x, None, S, out=z(7, 1, dtype=torch.complex64))
+    with pytest.raises(TypeError, match="out must be torch.complex64"):
+        api.scatter_fwd(x, None, S, out=z(7, dtype=torch.complex128))
+    with pytest.raises(ValueError, match="out must be contiguous"):
+        api.scatter_fwd(x, None, S, out=z(14, dtype=torch.complex64)[::2])
+    # a well-formed call on CPU tensors reaches the device check and stops there
+    with pytest.raises(ValueError, match="must be on the GPU"):
+        api.scatter_fwd(x, None, S, out=z(7, dtype=torch.complex64))
+
+
+def test_input_shapes_and_dtypes():
+    x, S = z(5, 3), z(7, 3)
+    with pytest.raises(ValueError, match="xyz must have shape"):
+        api.scatter_fwd(z(5, 4), None, S)
+    with pytest.raises(ValueError, match="S must have shape"):
+        api.scatter_fwd(x, None, z(7))
+    with pytest.raises(ValueError, match=r"f must have shape \(5,\)"):
+        api.scatter_fwd(x, z(4, dtype=torch.complex64), S)
+    with pytest.raises(TypeError, match="f must be torch.complex64"):
+        api.scatter_fwd(x, z(5, dtype=torch.complex128), S)
+    with pytest.raises(ValueError, match=r"G must have shape \(7,\)"):
+        api.scatter_bwd(x, None, S, z(8, dtype=torch.complex64))
+    with pytest.raises(TypeError, match="xyz must be torch.float64"):
+        api.scatter_fwd_f64(x, None, S.double())
+    with pytest.raises(ValueError, match=r"I must have shape \(7,\)"):
+        api.loss_grad(z(7, dtype=torch.complex64), z(6))
+
+
+def test_species_arrays_are_checked():
+    x, S = z(4, 3), z(6, 3)
+    G = z(6, dtype=torch.complex64)
+    with pytest.raises(ValueError, match=r"A_species must have shape \(2, 6\)"):
+        api.scatter_bwd_species(x, [0, 2, 4], None, S, G, z(3, 6, dtype=torch.complex64))
+    with pytest.raises(ValueError, match=r"A_species must have shape \(2, 6\)"):
+        api.scatter_bwd_species(x, [0, 2, 4], None, S, G, z(2, 5, dtype=torch.complex64))
+    with pytest.raises(TypeError, match="A_species must be torch.complex64"):
+        api.scatter_bwd_species(x, [0, 2, 4], None, S, G, z(2, 6))
+    with pytest.raises(ValueError, match=r"fs must have shape \(2, 6\)"):
+        api.scatter_bwd_species(x, [0, 2, 4], z(2, 5, dtype=torch.complex64), S, G)
+    with pytest.raises(ValueError, match="must be on the GPU"):
+        api.scatter_bwd_species(x, [0, 2, 4], None, S, G, z(2, 6, dtype=torch.complex64))
+
+
+def test_conjugate_views():
+    g = torch.tensor([1 + 2j, -3 + 0.5j], dtype=torch.complex64)
+    lazy = g.conj()
+    assert lazy.is_conj()
+    # a lazy conjugate is refused as an input ...
+    with pytest.raises(ValueError, match="conjugate view"):
+        api._need(lazy, "G", torch.complex64, (2,))
+    # ... and backward's seed is resolved before it is marshalled
+    for dtype in (torch.complex64, torch.complex128):
+        seed = api._seed_arg(lazy, dtype)
+        assert not seed.is_conj() and seed.is_contiguous() and seed.dtype == dtype
+        assert torch.equal(torch.view_as_real(seed),
+                           torch.view_as_real(g.to(dtype)) * torch.tensor([1.0, -1.0], dtype=seed.real.dtype))

@@ -331,6 +331,32 @@ def test_autograd_matches_oracle():
     assert en <= M.T3_NORM_TOL and em <= M.T3_MAX_TOL
 
 
+def test_autograd_conjugate_view_seed():
+    """A graph that conjugates A before a function whose backward passes the gradient
+    through (here |conj A|) hands ScatterFn.backward a lazy conjugate view; the seed is
+    resolved before it reaches the C ABI, and since |conj A| = |A| the gradients equal
+    those of |A| bitwise, for the positions and (species path included) the factors."""
+    xyz, f, S = wl.random_problem(700, 900, seed=29, extent=12.0, s_range=2.0)
+    grads = []
+    for conj in (False, True):
+        x = dev(xyz).requires_grad_(True)
+        ff = dev(f).requires_grad_(True)
+        A = api.scatter(x, ff, dev(S), "ph64")
+        (A.conj() if conj else A).abs().sum().backward()
+        grads.append((x.grad.clone(), ff.grad.clone()))
+    assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
+    start = [0, 300, 700]
+    fs0 = torch.from_numpy(np.stack([np.full(900, 2 + 1j), np.full(900, 1 - 0.5j)]).astype(np.complex64))
+    sg = []
+    for conj in (False, True):
+        x = dev(xyz).requires_grad_(True)
+        fs = fs0.to(DEV).requires_grad_(True)
+        A = api.scatter_species(x, start, fs, dev(S), "ph64")
+        (A.conj() if conj else A).abs().sum().backward()
+        sg.append((x.grad.clone(), fs.grad.clone()))
+    assert torch.equal(sg[0][0], sg[1][0]) and torch.equal(sg[0][1], sg[1][1])
+
+
 def test_gradcheck_f64_path():
     """torch.autograd.gradcheck through the all-FP64 forward and adjoint kernels."""
     xyz, f, S = wl.random_problem(12, 20, seed=28, extent=4.0, s_range=1.0)
