@@ -1,0 +1,49 @@
+/*
+ * nx_micro.h -- C ABI of libnx_micro, the VALU issue-rate microbenchmarks behind the
+ * roofline of libnx's sums on gfx950 (MI355X).  Measurement support, not part of the
+ * scattering library.
+ *
+ * The sums of the direct scattering amplitude (Favre-Nicolin et al., J. Appl. Cryst.
+ * 2010, Section 2.1 Eq. 2) are bound by vector-ALU issue; the paper counts their work as
+ * 8 flop per atom-point pair (Section 2.2, Eq. 3).  Each kernel here repeats the
+ * per-pair instruction sequence of one sum on register operands only (no memory
+ * traffic), in two shapes: `wide` = 0 runs 4 (FP64-phase mixes) or 8 (FP32 mixes)
+ * independent pairs per lane at 8 waves per SIMD, `wide` = 1 twice as many at 4 waves per
+ * SIMD.  The better rate, in pairs per second, is the issue ceiling of that instruction
+ * mix on the chip under load.
+ *
+ * nxm_run queues one launch of n_blocks work-groups of nxm_threads_per_block() lanes,
+ * each lane computing iters * nxm_pairs_per_lane_iter(mix, wide) pairs, on `stream` (a
+ * hipStream_t, NULL = null stream).  `out` is a DEVICE array of n_blocks *
+ * nxm_threads_per_block() floats (overwritten with meaningless values).  Returns 0, -1 for
+ * invalid sizes, a NULL out or `wide` not 0 or 1, -2 for an unknown mix, -4 if the launch
+ * failed.  The call
+ * does not synchronise; time it with events on the same stream.
+ */
+#ifndef NX_MICRO_H
+#define NX_MICRO_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NXM_FWD_PH64_CF = 0,   /* forward, FP64 phase, complex f: 3 fma64, rint, sub64, cvt, cos, sin, 2 fma */
+  NXM_FWD_PH64_F1 = 1,   /* forward, FP64 phase, f = 1: the same with 2 adds */
+  NXM_BWD_PH64_CF = 2,   /* adjoint, FP64 phase, complex f: 3 fma64, add64, fract64, cvt, sin, 3 fma */
+  NXM_BWD_PH64_F1 = 3,   /* adjoint, FP64 phase, f = 1: without the add64 */
+  NXM_FWD_F32_CF = 4,    /* forward, FP32: 3 fma, fract, cos, sin, 4 fma */
+  NXM_FWD_F32_F1 = 5,    /* forward, FP32, f = 1: 3 fma, fract, cos, sin, 2 add */
+  NXM_BWD_F32_CF = 6,    /* adjoint, FP32, complex f: 3 fma, fract, cos, sin, 6 (w, v), 3 fma */
+  NXM_BWD_F32_F1 = 7     /* adjoint, FP32, f = 1: 3 fma, fract, cos, sin, 2 (Im w), 3 fma */
+} nxm_mix;
+
+int nxm_pairs_per_lane_iter(int mix, int wide);
+int nxm_threads_per_block(void);
+int nxm_run(int mix, int wide, int n_blocks, int iters, float* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NX_MICRO_H */

@@ -1,4 +1,5 @@
-"""Builds libnx.so (the gfx950 HIP library behind include/nx.h) in-tree with hipcc.
+"""Builds libnx.so (the gfx950 HIP library behind include/nx.h) and libnx_micro.so (the
+VALU issue-rate microbenchmarks behind include/nx_micro.h) in-tree with hipcc.
 
 Every HIP source is compiled for gfx950 only, with FMA contraction off (the kernels
 spell out their fused multiply-adds) and packed-FP32 instruction selection disabled.
@@ -14,10 +15,12 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libnx.so")
+LIB_MICRO = os.path.join(PKG, "libnx_micro.so")
 BUILD = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 
 SOURCES = ["nx_fwd.hip", "nx_bwd.hip", "nx_loss.hip", "nx_species.hip", "nx_api.cpp"]
+MICRO_SOURCES = ["nx_micro.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
@@ -46,16 +49,22 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build() -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+def _link(objs, lib):
+    tmp = lib + ".tmp"
     r = subprocess.run([_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs],
                        capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build() -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = SOURCES + MICRO_SOURCES
+    with cf.ThreadPoolExecutor(max_workers=len(srcs)) as ex:
+        objs = dict(zip(srcs, ex.map(_compile, srcs)))
+    _link([objs[s] for s in SOURCES], LIB)
+    _link([objs[s] for s in MICRO_SOURCES], LIB_MICRO)
     return LIB
 
 

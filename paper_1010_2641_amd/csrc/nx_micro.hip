@@ -1,0 +1,265 @@
+// nx_micro.hip -- VALU issue-rate microbenchmarks of gfx950 for the roofline of the sums.
+//
+// Each kernel repeats the per-pair instruction sequence of one of the library's sums
+// (the method's own work in the formulation the kernels use: phase, reduction, sin/cos,
+// multiply-adds; see the kernels in nx_fwd.hip and nx_bwd.hip) on register operands
+// only: no loads, no LDS, no barriers, no compensation and no loop overhead worth
+// counting.  The lane-constant operands (the lane's points or atoms) sit in VGPRs; the
+// values every lane shares (the other side of the pair) change every iteration and are
+// formed by the scalar unit from the loop counter, so each VALU instruction takes at
+// most one of them, as the sums do.  Each mix comes in two shapes, so that latency and
+// the scheduling of the half-rate transcendentals around other work cannot hold it back:
+// 4 (FP64 phase) or 8 (FP32) independent pairs per lane at 8 waves per SIMD, and twice
+// the pairs at 4 waves per SIMD.  The better of the two rates is the issue ceiling of
+// that instruction mix on this chip at the clock it runs under load.
+//
+// The results are stored once per lane so that nothing is optimised away; they mean
+// nothing.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "nx_micro.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+// Independent pairs per lane and iteration, narrow shape: 8 for the FP32 mixes, 4 for the
+// FP64-phase mixes (their lane operands are FP64; 8 would not fit 64 VGPRs and spill).
+// The wide shape doubles them at 4 waves per SIMD (128 VGPRs).
+constexpr int kPairs32 = 8;
+constexpr int kPairs64 = 4;
+
+// A double whose value changes with the (wave-uniform) iteration j: its high word is
+// offset by j, which moves the value by j * 2^-20 of its binade (scalar integer ops).
+__device__ __forceinline__ double uniform_f64(uint32_t hi, uint32_t lo, int j) {
+  return __hiloint2double(static_cast<int>(hi + static_cast<uint32_t>(j)), static_cast<int>(lo));
+}
+__device__ __forceinline__ float uniform_f32(uint32_t bits, int j) {
+  return __uint_as_float(bits + (static_cast<uint32_t>(j) << 4));
+}
+
+// Makes a lane value opaque to the compiler (an empty asm statement that "modifies" the
+// register), so that it stays in its register instead of being recomputed inside the loop
+// from the lane index (rematerialisation would add VALU work the sums do not do).
+template <typename T>
+__device__ __forceinline__ void opaque(T& v) {
+  asm volatile("" : "+v"(v));
+}
+
+// FP64-phase forward: psi = 3 FP64 fma; centred reduction (rint, subtract, cvt);
+// cos, sin; m (c + i s) with 2 FP32 fma (complex f) or 2 adds (f = 1).
+template <bool CF, int kPairs, int OCC>
+__global__ __launch_bounds__(kThreads, OCC) void mix_fwd_ph64(int iters, float* out) {
+  const double lane = static_cast<double>(threadIdx.x + blockIdx.x * kThreads);
+  double sx[kPairs], sy[kPairs], sz[kPairs], a0[kPairs];
+  float ar[kPairs], ai[kPairs];
+#pragma unroll
+  for (int p = 0; p < kPairs; ++p) {
+    sx[p] = 1.0 + 1e-7 * lane + 0.01 * p;
+    sy[p] = 0.5 - 2e-7 * lane + 0.02 * p;
+    sz[p] = 4.0 + 3e-7 * lane - 0.01 * p;
+    a0[p] = 1e-8 * lane + 0.125 * p;
+    ar[p] = 0.f;
+    ai[p] = 0.f;
+    opaque(sx[p]);
+    opaque(sy[p]);
+    opaque(sz[p]);
+    opaque(a0[p]);
+  }
+  for (int j = 0; j < iters; ++j) {
+    const double x = uniform_f64(0x40240000u, 0x9999999au, j);      // ~10
+    const double y = uniform_f64(0x40340000u, 0x33333333u, j);      // ~20
+    const double z = uniform_f64(0x403e0000u, 0xccccccccu, j);      // ~30
+    const float m = uniform_f32(0x41f80000u, j);                    // ~31
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) {
+      const double ph = __builtin_fma(sz[p], z, __builtin_fma(sy[p], y, __builtin_fma(sx[p], x, a0[p])));
+      const float t = static_cast<float>(ph - __builtin_rint(ph));
+      const float c = __builtin_amdgcn_cosf(t);
+      const float s = __builtin_amdgcn_sinf(t);
+      if constexpr (CF) {
+        ar[p] = __builtin_fmaf(m, c, ar[p]);
+        ai[p] = __builtin_fmaf(m, s, ai[p]);
+      } else {
+        ar[p] += c;
+        ai[p] += s;
+      }
+    }
+  }
+  float acc = 0.f;
+#pragma unroll
+  for (int p = 0; p < kPairs; ++p) acc += ar[p] - ai[p];
+  out[threadIdx.x + blockIdx.x * kThreads] = acc;
+}
+
+// FP64-phase adjoint: psi = 3 FP64 fma (+ 1 FP64 add of the atom's angle for complex f);
+// fract, cvt; sin; T_d += (|G| S_d) sin with 3 FP32 fma.
+template <bool CF, int kPairs, int OCC>
+__global__ __launch_bounds__(kThreads, OCC) void mix_bwd_ph64(int iters, float* out) {
+  const double lane = static_cast<double>(threadIdx.x + blockIdx.x * kThreads);
+  double x[kPairs], y[kPairs], z[kPairs], d0[kPairs], al[kPairs];
+  float t0[kPairs], t1[kPairs], t2[kPairs];
+#pragma unroll
+  for (int p = 0; p < kPairs; ++p) {
+    x[p] = 10.0 + 1e-6 * lane + 0.5 * p;
+    y[p] = 20.0 - 2e-6 * lane + 0.25 * p;
+    z[p] = 30.0 + 3e-6 * lane - 0.5 * p;
+    d0[p] = 1e-8 * lane + 0.1 * p;
+    al[p] = 0.3 - 2e-8 * lane - 0.05 * p;
+    t0[p] = t1[p] = t2[p] = 0.f;
+    opaque(x[p]);
+    opaque(y[p]);
+    opaque(z[p]);
+    opaque(d0[p]);
+    opaque(al[p]);
+  }
+  for (int j = 0; j < iters; ++j) {
+    const double sx = uniform_f64(0x3ff00000u, 0x9999999au, j);     // ~1
+    const double sy = uniform_f64(0x3fe00000u, 0x33333333u, j);     // ~0.5
+    const double sz = uniform_f64(0x40100000u, 0xccccccccu, j);     // ~4
+    const float gx = uniform_f32(0x3f800000u, j), gy = uniform_f32(0x3f000000u, j),
+                gz = uniform_f32(0x40800000u, j);
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) {
+      double ph = __builtin_fma(sz, z[p], __builtin_fma(sy, y[p], __builtin_fma(sx, x[p], d0[p])));
+      if constexpr (CF) ph += al[p];
+      const float t = static_cast<float>(__builtin_amdgcn_fract(ph));
+      const float s = __builtin_amdgcn_sinf(t);
+      t0[p] = __builtin_fmaf(s, gx, t0[p]);
+      t1[p] = __builtin_fmaf(s, gy, t1[p]);
+      t2[p] = __builtin_fmaf(s, gz, t2[p]);
+    }
+  }
+  float acc = 0.f;
+#pragma unroll
+  for (int p = 0; p < kPairs; ++p) acc += t0[p] - t1[p] + t2[p];
+  out[threadIdx.x + blockIdx.x * kThreads] = acc;
+}
+
+// The paper's FP32 arithmetic.  Forward: 3 FP32 fma, fract, cos, sin, then f (c + i s)
+// with 4 fma (complex f) or 2 adds (f = 1).
+template <bool CF, int kPairs, int OCC>
+__global__ __launch_bounds__(kThreads, OCC) void mix_fwd_f32(int iters, float* out) {
+  const float lane = static_cast<float>(threadIdx.x + blockIdx.x * kThreads);
+  float sx[kPairs], sy[kPairs], sz[kPairs], ar[kPairs], ai[kPairs];
+#pragma unroll
+  for (int p = 0; p < kPairs; ++p) {
+    sx[p] = 1.0f + 1e-7f * lane + 0.01f * p;
+    sy[p] = 0.5f - 2e-7f * lane + 0.02f * p;
+    sz[p] = 4.0f + 3e-7f * lane - 0.01f * p;
+    ar[p] = ai[p] = 0.f;
+    if constexpr (kPairs > kPairs32) {     // the wide shape: keep the lane values in registers
+      opaque(sx[p]);
+      opaque(sy[p]);
+      opaque(sz[p]);
+    }
+  }
+  for (int j = 0; j < iters; ++j) {
+    const float x = uniform_f32(0x41200000u, j), y = uniform_f32(0x41a00000u, j),
+                z = uniform_f32(0x41f00000u, j);
+    const float fr = uniform_f32(0x41f80000u, j), fi = uniform_f32(0x3f800000u, j);
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) {
+      const float ph = __builtin_fmaf(sz[p], z, __builtin_fmaf(sy[p], y, sx[p] * x));
+      const float u = __builtin_amdgcn_fractf(ph);
+      const float c = __builtin_amdgcn_cosf(u);
+      const float s = __builtin_amdgcn_sinf(u);
+      if constexpr (CF) {
+        ar[p] = __builtin_fmaf(-fi, s, __builtin_fmaf(fr, c, ar[p]));
+        ai[p] = __builtin_fmaf(fi, c, __builtin_fmaf(fr, s, ai[p]));
+      } else {
+        ar[p] += c;
+        ai[p] += s;
+      }
+    }
+  }
+  float acc = 0.f;
+#pragma unroll
+  for (int p = 0; p < kPairs; ++p) acc += ar[p] - ai[p];
+  out[threadIdx.x + blockIdx.x * kThreads] = acc;
+}
+
+// The paper's FP32 arithmetic, adjoint: 3 fma, fract, cos, sin; Im w = gr s - gi c (2),
+// Re w (2) and v = fr Im w + fi Re w (2) for complex f; T_d += S_d v (3).
+template <bool CF, int kPairs, int OCC>
+__global__ __launch_bounds__(kThreads, OCC) void mix_bwd_f32(int iters, float* out) {
+  const float lane = static_cast<float>(threadIdx.x + blockIdx.x * kThreads);
+  float x[kPairs], y[kPairs], z[kPairs], fr[kPairs], fi[kPairs], t0[kPairs], t1[kPairs], t2[kPairs];
+#pragma unroll
+  for (int p = 0; p < kPairs; ++p) {
+    x[p] = 10.f + 1e-6f * lane + 0.5f * p;
+    y[p] = 20.f - 2e-6f * lane + 0.25f * p;
+    z[p] = 30.f + 3e-6f * lane - 0.5f * p;
+    fr[p] = 31.f - p;
+    fi[p] = 1.f + p;
+    t0[p] = t1[p] = t2[p] = 0.f;
+    if constexpr (kPairs > kPairs32) {     // the wide shape: keep the lane values in registers
+      opaque(x[p]);
+      opaque(y[p]);
+      opaque(z[p]);
+    }
+  }
+  for (int j = 0; j < iters; ++j) {
+    const float sx = uniform_f32(0x3f800000u, j), sy = uniform_f32(0x3f000000u, j),
+                sz = uniform_f32(0x40800000u, j);
+    const float gr = uniform_f32(0x3f400000u, j), gi = uniform_f32(0x3e800000u, j);
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) {
+      const float ph = __builtin_fmaf(sz, z[p], __builtin_fmaf(sy, y[p], sx * x[p]));
+      const float u = __builtin_amdgcn_fractf(ph);
+      const float c = __builtin_amdgcn_cosf(u);
+      const float s = __builtin_amdgcn_sinf(u);
+      const float wim = __builtin_fmaf(-gi, c, gr * s);
+      float v = wim;
+      if constexpr (CF) {
+        const float wre = __builtin_fmaf(gi, s, gr * c);
+        v = __builtin_fmaf(fi[p], wre, fr[p] * wim);
+      }
+      t0[p] = __builtin_fmaf(v, sx, t0[p]);
+      t1[p] = __builtin_fmaf(v, sy, t1[p]);
+      t2[p] = __builtin_fmaf(v, sz, t2[p]);
+    }
+  }
+  float acc = 0.f;
+#pragma unroll
+  for (int p = 0; p < kPairs; ++p) acc += t0[p] - t1[p] + t2[p];
+  out[threadIdx.x + blockIdx.x * kThreads] = acc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nxm_pairs_per_lane_iter(int mix, int wide) {
+  const int np = (mix >= NXM_FWD_PH64_CF && mix <= NXM_BWD_PH64_F1) ? kPairs64 : kPairs32;
+  return wide ? 2 * np : np;
+}
+
+int nxm_threads_per_block(void) { return kThreads; }
+
+int nxm_run(int mix, int wide, int n_blocks, int iters, float* out, void* stream) {
+  if (n_blocks < 1 || iters < 1 || !out || (wide != 0 && wide != 1)) return -1;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const dim3 grid(static_cast<unsigned>(n_blocks));
+#define NXM_CASE(ID, KERNEL, CF, NP)                                                        \
+  case ID:                                                                                  \
+    if (wide) KERNEL<CF, 2 * NP, 4><<<grid, kThreads, 0, st>>>(iters, out);                 \
+    else KERNEL<CF, NP, 8><<<grid, kThreads, 0, st>>>(iters, out);                          \
+    break;
+  switch (mix) {
+    NXM_CASE(NXM_FWD_PH64_CF, mix_fwd_ph64, true, kPairs64)
+    NXM_CASE(NXM_FWD_PH64_F1, mix_fwd_ph64, false, kPairs64)
+    NXM_CASE(NXM_BWD_PH64_CF, mix_bwd_ph64, true, kPairs64)
+    NXM_CASE(NXM_BWD_PH64_F1, mix_bwd_ph64, false, kPairs64)
+    NXM_CASE(NXM_FWD_F32_CF, mix_fwd_f32, true, kPairs32)
+    NXM_CASE(NXM_FWD_F32_F1, mix_fwd_f32, false, kPairs32)
+    NXM_CASE(NXM_BWD_F32_CF, mix_bwd_f32, true, kPairs32)
+    NXM_CASE(NXM_BWD_F32_F1, mix_bwd_f32, false, kPairs32)
+    default: return -2;
+  }
+#undef NXM_CASE
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+}  // extern "C"

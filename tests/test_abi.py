@@ -31,6 +31,24 @@ def test_header_symbols_exported():
     assert sorted(_lib.SIGNATURES) == names
 
 
+def test_micro_header_symbols_exported():
+    """libnx_micro (the issue-ceiling microbenchmarks) exports what nx_micro.h declares and
+    refuses bad arguments before launching anything."""
+    from paper_1010_2641_amd import micro
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "nx_micro.h")).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(nxm_\w+)\s*\(", text)))
+    assert names == sorted(micro.SIGNATURES)
+    for name in names:
+        assert hasattr(micro.lib, name)
+    assert micro.nxm_threads_per_block() == 256
+    assert micro.nxm_pairs_per_lane_iter(0, 0) == 4 and micro.nxm_pairs_per_lane_iter(4, 0) == 8
+    assert micro.nxm_pairs_per_lane_iter(0, 1) == 8 and micro.nxm_pairs_per_lane_iter(4, 1) == 16
+    assert micro.nxm_run(99, 0, 1, 1, FAKE, None) == -2
+    assert micro.nxm_run(0, 0, 0, 1, FAKE, None) == -1
+    assert micro.nxm_run(0, 0, 1, 1, None, None) == -1
+    assert micro.nxm_run(0, 2, 1, 1, FAKE, None) == -1
+
+
 def test_version():
     assert _lib.nx_version() == 101
 

@@ -1,8 +1,10 @@
 """The gfx950 code the build produces, checked on the CPU (hipcc cross-compiles): no
 packed-FP32 instructions anywhere (their selection is disabled at compile time), no
-kernel that spills to scratch, and the two hot kernels of the default FP64-phase path
+kernel that spills to scratch, the two hot kernels of the default FP64-phase path
 at 8 waves per SIMD (the forward's LDS-tiled kernel with one point per lane and the
-split adjoint with two atoms per lane)."""
+split adjoint with two atoms per lane), and the issue-ceiling microbenchmarks' loops
+made of exactly the per-pair instruction counts the benchmark prices its sums with."""
+import collections
 import concurrent.futures as cf
 import os
 import re
@@ -14,7 +16,7 @@ import pytest
 
 from paper_1010_2641_amd import build
 
-HIP_SOURCES = [s for s in build.SOURCES if s.endswith(".hip")]
+HIP_SOURCES = [s for s in build.SOURCES + build.MICRO_SOURCES if s.endswith(".hip")]
 PACKED_FP32 = re.compile(r"\bv_pk_(fma|mul|add)_f32\b")
 
 pytestmark = pytest.mark.skipif(not os.path.exists(build._hipcc()) and shutil.which("hipcc") is None,
@@ -84,3 +86,53 @@ def test_hot_kernels_at_eight_waves(device_asm):
         found = [v for k, v in occ.items() if key in k]
         assert found, key
         assert min(found) >= o, (key, found)
+
+
+def loop_bodies(asm):
+    """{kernel symbol: Counter of the instructions of its loop} for kernels with one
+    loop (a label with a backward branch to it)."""
+    lines = asm.splitlines()
+    out, kern = {}, None
+    for i, line in enumerate(lines):
+        m = re.match(r"^(_Z\S+):", line)
+        if m:
+            kern = m.group(1)
+            continue
+        m = re.match(r"^(\.LBB\d+_\d+):", line)
+        if not (m and kern):
+            continue
+        body = []
+        for l in lines[i + 1:]:
+            l = l.strip()
+            if re.match(r"^_Z\S+:", l):
+                break
+            if re.match(r"s_c?branch\w* " + re.escape(m.group(1)) + "$", l):
+                c = collections.Counter(t.split()[0] for t in body
+                                        if t and not t.startswith((".", ";")) and not t.endswith(":"))
+                out.setdefault(kern, c)
+                break
+            body.append(l)
+    return out
+
+
+def test_micro_loops_are_the_priced_instruction_mixes(device_asm):
+    import bench
+    loops = loop_bodies(device_asm["nx_micro.hip"])
+    kinds = {"mix_fwd_ph64": ("ph64", "fwd"), "mix_bwd_ph64": ("ph64", "bwd"),
+             "mix_fwd_f32": ("f32", "fwd"), "mix_bwd_f32": ("f32", "bwd")}
+    seen = 0
+    for name, c in loops.items():
+        for key, (mode, op) in kinds.items():
+            m = re.search(key + r"ILb([01])ELi(\d+)ELi\d+E", name)
+            if not m:
+                continue
+            fkind = "complex" if m.group(1) == "1" else "unit"
+            pairs = int(m.group(2))
+            valu = sum(v for k, v in c.items() if k.startswith("v_"))
+            trans = c["v_sin_f32_e32"] + c["v_cos_f32_e32"]
+            assert valu == pairs * bench.ALG_SLOTS[(mode, op, fkind)], (name, dict(c))
+            assert trans == pairs * (1 if (mode, op) == ("ph64", "bwd") else 2), (name, dict(c))
+            assert not any(k.startswith(("scratch_", "global_load", "buffer_load", "ds_"))
+                           for k in c), (name, dict(c))
+            seen += 1
+    assert seen == 16
