@@ -5,16 +5,22 @@ the forward sum A_k = sum_j f_j exp(2 i pi S_k . r_j) (FP64 phase reduction,
 compensated FP32 sums), the intensity misfit L = sum (|A|^2 - I)^2 with its seed
 G = 4 (|A|^2 - I) A, and the adjoint dL/dr_j -- all in libnx's HIP kernels.
 
-Workload (default): the strained Ge-like truncated-pyramid dot on an fcc lattice,
-203,557 atoms with two complex scattering factors, on a 128^3 grid of points around
-(4,0,4) (2,097,152 points); the target intensity is that of the same dot with the
-strain scaled by 1.1, computed once before timing.
+Headline workload (default): the strained Ge-like truncated-pyramid dot on an fcc
+lattice, 203,557 atoms with two complex scattering factors, on a 128^3 grid of points
+around (4,0,4) (2,097,152 points); the target intensity is that of the same dot with
+the strain scaled by 1.1, computed once before timing.  The largest configuration,
+the 4,013,800-atom nanowire on 256^3 points (39 s per step), is measured in the same
+run as one timed step (the "c5" object of the line): the requested number of timed
+steps of it would not fit the run's time limit.
 
 Printed: one JSON line with the throughput in atom.point pairs per second of the
 whole step (N*K pairs per step), the forward-only and adjoint-only rates, the
 all-FP64 GPU path on the same step for comparison, the roofline of the dominant
-kernel (timed live with events on the launch stream), and the FP64 CPU oracle timed
-on a bounded sample of the same workload on this host's cores.
+kernel (timed live with events on the launch stream): the paper's count of 8 flop per
+pair against the FP32 peak, and beside it the VALU issue slots of the kernel's own
+instruction mix against the ceiling a register-only microbenchmark of that mix
+reaches in the same run; and the FP64 CPU oracle timed on a bounded sample of the
+same workload on this host's cores.
 """
 from __future__ import annotations
 
@@ -29,18 +35,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 3.93e13 full-rate VALU lane-ops/s;
-# counting each as one FMA (2 flop) gives 78.6 TFLOP/s (the unpacked FP32 and the
-# FP64 vector rate; the library is compiled without packed FP32 instructions).
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 3.93e13 full-rate VALU lane-ops/s
+# (nominal VALU issue slots; the library is compiled without packed FP32 instructions).
 VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
-PEAK_TFLOPS = 2 * VALU_SLOTS_PER_S / 1e12
 
 # Minimal VALU instruction count per (atom, point) pair of each kernel: the method's
 # own work on gfx950 in the formulation the kernels use (compensation, loads and loop
 # control excluded).  Phase S.r = 3 FP64 fma.  Forward: centred reduction mod 1 (rint,
 # subtract) and rounding to FP32 = 3; adjoint: fract and rounding = 2.  sin and cos count
-# one issue slot each, the strict bound: at half rate they keep the VALU busy for two
-# slots, partly overlapped with other work (the VALU counters give ~1.75 slots each).
+# one issue slot each (at half rate they keep the VALU busy longer; the microbenchmark
+# ceiling of the same mix prices that in).
 #   forward, complex f: f in polar form m exp(2 i pi a), a the addend of the phase's first
 #                       fma; m (cos + i sin) accumulated with 2 fma
 #   forward, f = 1:     (cos, sin) accumulated with 2 add
@@ -52,6 +56,7 @@ PEAK_TFLOPS = 2 * VALU_SLOTS_PER_S / 1e12
 #   forward: f (cos + i sin) with 4 fma, or 2 add for f = 1;
 #   adjoint: w = conj(G) exp(i theta) (2 for Im w, 4 with Re w), v = Im(f w) (2 for complex
 #            f), T_d += S_d v (3); sin and cos are both needed.
+# libnx_micro's kernels run exactly these sequences (tests/test_device_code.py counts them).
 ALG_SLOTS = {
     ("ph64", "fwd", "complex"): 3 + 3 + 2 + 2,
     ("ph64", "fwd", "unit"): 3 + 3 + 2 + 2,
@@ -62,11 +67,33 @@ ALG_SLOTS = {
     ("f32", "bwd", "complex"): 3 + 1 + 2 + 4 + 2 + 3,
     ("f32", "bwd", "unit"): 3 + 1 + 2 + 2 + 3,
 }
-PAPER_FLOP_PER_PAIR = 8       # the paper's count (3 mul, 4 add, 1 sincos)
-FP32_PEAK_TFLOPS = 157.3      # published FP32 vector peak (packed)
+# The paper's count of the work per pair (Eq. 3, Section 2.2: 3 mul, 4 add, 1 sincos) and
+# the published FP32 vector peak of the MI355X: the roofline's flop fraction.
+PAPER_FLOP_PER_PAIR = 8
+FP32_PEAK_TFLOPS = 157.3
 
 KERNEL_SOURCES = ["nx_fwd.hip", "nx_bwd.hip", "nx_loss.hip", "nx_species.hip", "nx_api.cpp",
                   "nx_internal.h"]
+
+WORKLOADS = {
+    "c1": "16^3 simple-cubic block, disorder 0.02, f=1, 64x64 map at l=4",
+    "c2": "Ge-like strained fcc truncated-pyramid dot, 203,557 atoms, 2 species "
+          "complex f, 128^3 grid around (4,0,4), fit step vs strain x1.1 target",
+    "c3": "100^3 simple-cubic crystal, disorder 0.01, 256^2 map near (8,8,8)",
+    "c4": "29^3-cell fcc cube, sinusoidal displacement, 64^3 grid around (2,2,0)",
+    "c5": "strained fcc nanowire, 4,013,800 atoms, 2 species, 256^3 grid at (0,0,4), "
+          "fit step vs strain x1.1 target",
+    "ewald": "the c2 dot on 2,097,152 area-detector points on Ewald's sphere "
+             "(128^2 pixels x 128 rocking frames around (4,0,4)), fit step vs strain "
+             "x1.1 target",
+    "cube41": "Section 4.1 cube, 1e6 atoms, 200x200 map around (004)",
+    "cube41s": "Section 4.1 strained cube, 1e6 atoms, 200x200 map around (004)",
+}
+
+# grid edge of the workloads whose points are a regular grid (h fastest): the oracle
+# sample always takes the grid lines through the map centre, where the strongest
+# intensity lies
+GRID_EDGE = {"c1": (64, 2), "c2": (128, 3), "c3": (256, 2), "c4": (64, 3), "c5": (256, 3)}
 
 
 def _code_only(text: str) -> str:
@@ -105,6 +132,11 @@ def parse():
                    help="skip the species-factorised step (workloads with several species)")
     p.add_argument("--cpu-seconds", type=float, default=20.0,
                    help="approximate CPU time budget of the oracle sample")
+    p.add_argument("--no-c5", action="store_true",
+                   help="skip the one-step measurement of the largest configuration (c5) that "
+                        "the headline line carries beside the default workload")
+    p.add_argument("--no-micro", action="store_true",
+                   help="skip the issue-ceiling microbenchmarks (the valu_issue fields)")
     p.add_argument("--copy-cal", type=int, default=0, metavar="BYTES",
                    help="only run a plain device-to-device copy of BYTES bytes three times "
                         "(the reference kernel that scales the HBM counters of a profile)")
@@ -122,26 +154,48 @@ def make_target(api, w, tf, tS, mode):
         tx = torch.from_numpy(w.target_xyz).cuda()
     else:                       # workloads without a target structure: a shifted copy
         tx = torch.from_numpy(w.xyz).cuda() * 1.001
-    return (api.scatter_fwd(tx, tf, tS, mode).abs() ** 2).float()
+    I = (api.scatter_fwd(tx, tf, tS, mode).abs() ** 2).float()
+    del tx
+    return I
 
 
-def cpu_baseline(w, A_gpu, g_gpu_fn, budget_s):
-    """The FP64 oracle on a bounded sample of the same workload: the forward on a
-    seeded sample of points (all atoms) and the adjoint on a seeded sample of atoms
-    (all points); the full-step time is extrapolated linearly.  Also returns the GPU's
-    error against the oracle on the sampled outputs."""
+def central_lines(name, n_points):
+    """Indices of the grid lines through the map centre (empty for unstructured points)."""
+    import numpy as np
+    if name not in GRID_EDGE:
+        return np.zeros(0, dtype=np.int64)
+    n, dims = GRID_EDGE[name]
+    c = n // 2
+    idx = [h + n * c + (n * n * c if dims == 3 else 0) for h in range(n)]
+    idx += [c + n * k + (n * n * c if dims == 3 else 0) for k in range(n)]
+    if dims == 3:
+        idx += [c + n * c + n * n * l for l in range(n)]
+    idx = np.unique(np.array(idx, dtype=np.int64))
+    assert idx.max() < n_points
+    return idx
+
+
+def cpu_baseline(name, w, A_gpu, G, g_gpu, budget_s):
+    """The FP64 oracle on a bounded sample of the same workload: the forward on the grid
+    lines through the map centre and then seeded random points (all atoms), for half the
+    budget, and the adjoint on seeded random atoms (all points) fed the step's own seed G,
+    for the other half; the full-step time is extrapolated linearly.  Also returns the
+    GPU's errors against the oracle on the sampled outputs (A_gpu: the step's amplitudes,
+    g_gpu: its gradient, both numpy)."""
     import numpy as np
 
     import oracle
-    from paper_1010_2641_amd import workloads as wl
 
     cores = oracle.threads()
     rng = np.random.default_rng(2024)
-    # forward on seeded batches of points (all atoms) until half the budget is spent,
-    # then the adjoint on seeded batches of atoms (all points) for the other half
-    order_p = rng.permutation(w.n_points)
+    lines = central_lines(name, w.n_points)
+    rest = rng.permutation(np.setdiff1d(np.arange(w.n_points), lines))
+    # grid-line and random points alternate, so that any cut of the budget holds both
+    nl = min(len(lines), len(rest))
+    mixed = np.empty(2 * nl, dtype=np.int64)
+    mixed[0::2], mixed[1::2] = lines[:nl], rest[:nl]
+    order_p = np.concatenate([mixed, lines[nl:], rest[nl:]])
     order_a = rng.permutation(w.n_atoms)
-    G = wl.random_seed_field(w.n_points, seed=2025, scale=1e-3)
     bp = max(1, min(w.n_points, int(2e8 // max(w.n_atoms, 1))))
     ba = max(1, min(w.n_atoms, int(2e8 // max(w.n_points, 1))))
     A_parts, n_pts, t_fwd = [], 0, 0.0
@@ -164,18 +218,19 @@ def cpu_baseline(w, A_gpu, g_gpu_fn, budget_s):
     g_ref = np.concatenate(g_parts)
     t_full = t_fwd * w.n_points / n_pts + t_bwd * w.n_atoms / n_at
     pairs = float(w.n_atoms) * float(w.n_points)
-    # GPU error on the same sampled outputs
     A_s = A_gpu[pts].astype(np.complex128)
     I, Ir = np.abs(A_s) ** 2, np.abs(A_ref) ** 2
     m = Ir >= 1e-6 * Ir.max()
-    g_gpu = g_gpu_fn(G)[atoms]
+    g_s = g_gpu[atoms].astype(np.float64)
     err = {
         "fwd_T1_rel_I": float(np.max(np.abs(I[m] - Ir[m]) / Ir[m])),
         "fwd_T2_rel_norm": float(np.linalg.norm(A_s - A_ref) / np.linalg.norm(A_ref)),
-        "bwd_T3_rel_norm": float(np.linalg.norm(g_gpu - g_ref) / np.linalg.norm(g_ref)),
-        "bwd_T3_rel_max": float(np.max(np.abs(g_gpu - g_ref)) / np.max(np.abs(g_ref))),
-        "sample": f"{n_pts} random points (forward) and {n_at} random atoms with a seeded "
-                  f"random seed G (adjoint)",
+        "bwd_T3_rel_norm": float(np.linalg.norm(g_s - g_ref) / np.linalg.norm(g_ref)),
+        "bwd_T3_rel_max": float(np.max(np.abs(g_s - g_ref)) / np.max(np.abs(g_ref))),
+        "tolerances": {"T1": 1e-5, "T2": 1e-6, "T3_norm": 1e-5, "T3_max": 1e-4},
+        "sample": f"{int(np.isin(pts, lines).sum())} grid-line and {int((~np.isin(pts, lines)).sum())} "
+                  f"random points (forward) and {n_at} random atoms with the step's own seed G "
+                  f"(adjoint)",
     }
     cpu_model = None
     try:
@@ -198,31 +253,110 @@ def cpu_baseline(w, A_gpu, g_gpu_fn, budget_s):
     return base, err
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the sum would shard along the points with no exchange)",
-              file=sys.stderr)
-        sys.exit(2)
+def saved_counters(name, dom, mode):
+    """Traffic (HBM bytes per call) and VALU counters of profiles/ for this kernel and
+    workload, used only while the kernel sources match the hash they were taken with."""
+    traffic = valu = None
+    tpath = os.path.join(ROOT, "profiles", f"{dom}_{name}_{mode}_traffic.json")
+    if os.path.exists(tpath):
+        with open(tpath) as fh:
+            tr = json.load(fh)
+        if tr.get("source_sha") == source_hash():
+            traffic = tr.get("hbm_bytes_per_launch")
+    vpath = os.path.join(ROOT, "profiles", f"{dom}_{name}_{mode}_valu.json")
+    if os.path.exists(vpath):
+        with open(vpath) as fh:
+            vr = json.load(fh)
+        if vr.get("source_sha") == source_hash():
+            valu = {k: vr[k] for k in ("valu_issue_util", "valu_busy", "valu_insts_per_pair",
+                                       "trans_insts_per_pair", "clock_ghz") if k in vr}
+    return traffic, valu
 
+
+def kernel_roofline(name, mode, fkind, pairs, t_fwd, t_bwd, ceilings):
+    """Roofline of the dominant kernel (the longer of the two sums): the paper's 8 flop
+    per pair (Eq. 3) against the published FP32 peak, and a separate VALU issue-slot
+    fraction against the measured ceiling of the kernel's own instruction mix.  Both
+    sums' figures are listed under "sums"."""
+    sums = {}
+    for dom, t in (("fwd", t_fwd), ("bwd", t_bwd)):
+        slots = ALG_SLOTS[(mode, dom, fkind)]
+        rate = pairs / t
+        ceil = ceilings.get((mode, dom, fkind)) if ceilings else None
+        sums[dom] = {
+            "launch_ms": t * 1e3,
+            "pairs_per_s": rate,
+            "paper_tflops": PAPER_FLOP_PER_PAIR * rate / 1e12,
+            "paper_flop_frac": PAPER_FLOP_PER_PAIR * rate / 1e12 / FP32_PEAK_TFLOPS,
+            "valu_issue": {
+                "unit": "VALU issue slots/s",
+                "alg_slots_per_pair": slots,
+                "achieved": slots * rate,
+                "ceiling": None if ceil is None else slots * ceil,
+                "ceiling_pairs_per_s": ceil,
+                "frac": None if ceil is None else rate / ceil,
+                "nominal": VALU_SLOTS_PER_S,
+                "frac_of_nominal": slots * rate / VALU_SLOTS_PER_S,
+            },
+        }
+    dom = "bwd" if t_bwd >= t_fwd else "fwd"
+    d = sums[dom]
+    traffic, valu = saved_counters(name, dom, mode)
+    return {"bound": "alu", "achieved": d["paper_tflops"], "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": d["paper_flop_frac"], "traffic": traffic,
+            "kernel": f"nx_scatter_{dom} ({mode}, {fkind} f)",
+            "launch": "one entry-point call (all of its dispatches and launch chunks)",
+            "flop_per_pair": PAPER_FLOP_PER_PAIR,
+            "flop_convention": "the paper's count per atom-point pair (Eq. 3, Section 2.2: "
+                               "3 mul, 4 add, 1 sincos) against the published FP32 vector peak",
+            "launch_ms": d["launch_ms"], "valu_issue": d["valu_issue"], "counters": valu,
+            "sums": sums}
+
+
+def issue_ceilings(mode, fkind):
+    """Pairs per second of the forward's and the adjoint's instruction mixes on register
+    operands (libnx_micro), measured now on this GPU."""
+    from paper_1010_2641_amd import micro
+    return {(mode, dom, fkind): micro.mix_rate(mode, dom, fkind) for dom in ("fwd", "bwd")}
+
+
+def f64_path(api, tx, tf, tS, G, n, k, pairs, stream):
+    """The all-FP64 GPU path on the same step (forward + adjoint, seed from the step);
+    very large steps time it on the first 1/16 of the points (its rate does not depend on
+    which points it is given)."""
+    import torch
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    k64 = k if pairs <= 2e12 else max(1, k // 16)
+    x64, S64 = tx.double(), tS[:k64].double().contiguous()
+    f64_ = None if tf is None else tf.to(torch.complex128)
+    G64 = G[:k64].to(torch.complex128).contiguous()
+    pairs64 = float(n) * float(k64)
+    if k64 == k:
+        api.scatter_fwd_f64(x64, f64_, S64)
+        torch.cuda.synchronize()
+    e = [ev() for _ in range(3)]
+    e[0].record(stream)
+    api.scatter_fwd_f64(x64, f64_, S64)
+    e[1].record(stream)
+    api.scatter_bwd_f64(x64, f64_, S64, G64)
+    e[2].record(stream)
+    torch.cuda.synchronize()
+    tf64, tb64 = e[0].elapsed_time(e[1]) / 1e3, e[1].elapsed_time(e[2]) / 1e3
+    return {"fwd_pairs_per_s": pairs64 / tf64, "bwd_pairs_per_s": pairs64 / tb64,
+            "step_pairs_per_s": pairs64 / (tf64 + tb64), "points_timed": k64}
+
+
+def measure(name, args, steps, warmup, ceilings, want_graph=False, want_species=True,
+            cpu_seconds=None):
+    """Times `steps` fit steps of workload `name` after `warmup` untimed ones and returns
+    the measured fields (rates, roofline, FP64 path, species path, oracle baseline)."""
     import numpy as np
     import torch
 
     from paper_1010_2641_amd import api, workloads as wl
 
-    if args.copy_cal:
-        src = torch.empty(args.copy_cal // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": args.copy_cal}), flush=True)
-        return
-
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    w = wl.named(args.workload)
+    w = wl.named(name)
     n, k = w.n_atoms, w.n_points
     pairs = float(n) * float(k)
     fkind = "unit" if w.f is None else "complex"
@@ -231,7 +365,7 @@ def main():
     tS = torch.from_numpy(w.S).to(dev)
     I = make_target(api, w, tf, tS, args.mode)
     torch.cuda.synchronize()
-    progress(f"workload {args.workload}: {n} atoms x {k} points, target intensity ready")
+    progress(f"workload {name}: {n} atoms x {k} points, target intensity ready")
 
     stream = torch.cuda.current_stream(dev)      # every libnx launch goes to this stream
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -248,27 +382,27 @@ def main():
         g = api.scatter_bwd(tx, tf, tS, G, args.mode)
         if rec is not None:
             rec[3].record(stream)
-        return L, A, g
+        return L, A, g, G
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    progress(f"{args.warmup} warm-up steps done")
+    progress(f"{name}: {warmup} warm-up steps done")
 
-    recs = [[ev() for _ in range(4)] for _ in range(args.steps)]
+    recs = [[ev() for _ in range(4)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         out = step(recs[i])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    progress(f"{args.steps} timed steps done, {wall / args.steps * 1e3:.1f} ms per step")
+    progress(f"{name}: {steps} timed steps done, {wall / steps * 1e3:.1f} ms per step")
 
     # the same step captured once in a HIP graph (the library issues kernels only: no
     # allocation, copy, memset or synchronisation), replayed for at least the timed steps
     # and at least 0.2 s; small problems are bound by launch latency, which replays cut
     graph = None
-    if args.graph:
+    if want_graph:
         side = torch.cuda.Stream()
         side.wait_stream(stream)
         with torch.cuda.stream(side):
@@ -277,9 +411,9 @@ def main():
         torch.cuda.synchronize()
         cg = torch.cuda.CUDAGraph()
         with torch.cuda.graph(cg):
-            _, gA, gg = step()
+            _, gA, gg, _ = step()
         torch.cuda.synchronize()
-        reps = max(args.steps, int(0.2 / max(wall / args.steps, 1e-9)) + 1)
+        reps = max(steps, int(0.2 / max(wall / steps, 1e-9)) + 1)
         cg.replay()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -290,71 +424,33 @@ def main():
         graph = {"ms_per_step": tg * 1e3, "pairs_per_s": pairs / tg, "replays": reps,
                  "bitwise_equal_to_eager": bool(torch.equal(gA, out[1]) and torch.equal(gg, out[2]))}
         del cg, gA, gg
-        progress(f"graph replays timed: {tg * 1e3:.3f} ms per step")
-    t_fwd = sum(r[0].elapsed_time(r[1]) for r in recs) / args.steps / 1e3
-    t_loss = sum(r[1].elapsed_time(r[2]) for r in recs) / args.steps / 1e3
-    t_bwd = sum(r[2].elapsed_time(r[3]) for r in recs) / args.steps / 1e3
-    ms_per_step = wall / args.steps * 1e3
-    value = pairs / (wall / args.steps)
+        progress(f"{name}: graph replays timed: {tg * 1e3:.3f} ms per step")
+    t_fwd = sum(r[0].elapsed_time(r[1]) for r in recs) / steps / 1e3
+    t_loss = sum(r[1].elapsed_time(r[2]) for r in recs) / steps / 1e3
+    t_bwd = sum(r[2].elapsed_time(r[3]) for r in recs) / steps / 1e3
+    res = {
+        "config": {"workload": WORKLOADS[name], "n_atoms": n, "n_points": k, "pairs_per_step": pairs,
+                   "precision": {"ph64": "FP64 phase reduction, FP32 sin/cos, compensated FP32 sums",
+                                 "f32": "plain FP32 (the paper's arithmetic)"}[args.mode]},
+        "steps": steps, "warmup": warmup,
+        "ms_per_step": wall / steps * 1e3,
+        "value": pairs / (wall / steps),
+        "fwd_pairs_per_s": pairs / t_fwd,
+        "bwd_pairs_per_s": pairs / t_bwd,
+        "loss_ms": t_loss * 1e3,
+        "graph_replay": graph,
+        "roofline": kernel_roofline(name, args.mode, fkind, pairs, t_fwd, t_bwd, ceilings),
+    }
 
-    # roofline of the dominant kernel (its launch sequence timed on the launch stream)
-    dom, t_dom = ("bwd", t_bwd) if t_bwd >= t_fwd else ("fwd", t_fwd)
-    slots = ALG_SLOTS[(args.mode, dom, fkind)]
-    achieved = pairs * 2 * slots / t_dom / 1e12
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", f"{dom}_{args.workload}_{args.mode}_traffic.json")
-    if os.path.exists(tpath):
-        with open(tpath) as fh:
-            tr = json.load(fh)
-        if tr.get("source_sha") == source_hash():
-            traffic = tr.get("hbm_bytes_per_launch")
-    valu = None
-    vpath = os.path.join(ROOT, "profiles", f"{dom}_{args.workload}_{args.mode}_valu.json")
-    if os.path.exists(vpath):
-        with open(vpath) as fh:
-            vr = json.load(fh)
-        if vr.get("source_sha") == source_hash():
-            valu = {k: vr[k] for k in ("valu_issue_util", "valu_busy", "valu_insts_per_pair",
-                                       "trans_insts_per_pair", "clock_ghz") if k in vr}
-    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_TFLOPS, "traffic": traffic,
-                "kernel": f"nx_scatter_{dom} ({args.mode}, {fkind} f)",
-                "launch": "one entry-point call (all of its dispatches and launch chunks)",
-                "alg_valu_slots_per_pair": slots, "launch_ms": t_dom * 1e3,
-                "counters": valu}
-
-    # all-FP64 GPU path on the same step (forward + adjoint, seed from this step)
-    f64 = None
+    L, A, g, G = out
     if not args.no_f64:
-        L, A, _ = out
-        _, G = api.loss_grad(A, I)
-        # very large steps: the FP64 path is timed on the first 1/16 of the points (its
-        # rate does not depend on which points it is given)
-        k64 = k if pairs <= 2e12 else max(1, k // 16)
-        x64, S64 = tx.double(), tS[:k64].double().contiguous()
-        f64_ = None if tf is None else tf.to(torch.complex128)
-        G64 = G[:k64].to(torch.complex128).contiguous()
-        pairs64 = float(n) * float(k64)
-        if k64 == k:
-            api.scatter_fwd_f64(x64, f64_, S64)
-            torch.cuda.synchronize()
-        e = [ev() for _ in range(3)]
-        e[0].record(stream)
-        api.scatter_fwd_f64(x64, f64_, S64)
-        e[1].record(stream)
-        api.scatter_bwd_f64(x64, f64_, S64, G64)
-        e[2].record(stream)
-        torch.cuda.synchronize()
-        tf64, tb64 = e[0].elapsed_time(e[1]) / 1e3, e[1].elapsed_time(e[2]) / 1e3
-        f64 = {"fwd_pairs_per_s": pairs64 / tf64, "bwd_pairs_per_s": pairs64 / tb64,
-               "step_pairs_per_s": pairs64 / (tf64 + tb64), "points_timed": k64}
-        del x64, S64, G64, f64_
-        progress(f"all-FP64 path timed on {k64} points")
+        res["f64_path"] = f64_path(api, tx, tf, tS, G, n, k, pairs, stream)
+        res["speedup_vs_f64_step"] = res["value"] / res["f64_path"]["step_pairs_per_s"]
+        progress(f"{name}: all-FP64 path timed on {res['f64_path']['points_timed']} points")
 
     # the same step with the species factored out of the sum (Section 4.2): one
     # unit-factor sum per species, atoms regrouped by species once, outside the timing
-    species = None
-    if not args.no_species and w.f is not None:
+    if want_species and w.f is not None:
         xs, start, vals, _ = wl.group_by_species(w.xyz, w.f)
         if len(vals) <= 16:
             txs = torch.from_numpy(xs).to(dev)
@@ -362,86 +458,109 @@ def main():
 
             def sstep(rec):
                 rec[0].record(stream)
-                A = api.scatter_fwd_species(txs, start, fs, tS, args.mode)
+                As = api.scatter_fwd_species(txs, start, fs, tS, args.mode)
                 rec[1].record(stream)
-                _, G = api.loss_grad(A, I)
+                _, Gs = api.loss_grad(As, I)
                 rec[2].record(stream)
-                api.scatter_bwd_species(txs, start, fs, tS, G, None, args.mode)
+                api.scatter_bwd_species(txs, start, fs, tS, Gs, None, args.mode)
                 rec[3].record(stream)
-                return A
+                return As
 
             sstep([ev() for _ in range(4)])
-            srecs = [[ev() for _ in range(4)] for _ in range(max(1, min(args.steps, 3)))]
+            srecs = [[ev() for _ in range(4)] for _ in range(max(1, min(steps, 3)))]
             torch.cuda.synchronize()
             for r in srecs:
                 A_sp = sstep(r)
             torch.cuda.synchronize()
             ts = [sum(r[a].elapsed_time(r[b]) for r in srecs) / len(srecs) / 1e3
                   for a, b in ((0, 1), (2, 3), (0, 3))]
-            Ad = out[1].cpu().numpy().astype(np.complex128)
+            Ad = A.cpu().numpy().astype(np.complex128)
             As_ = A_sp.cpu().numpy().astype(np.complex128)
-            progress("species-factorised step timed")
-            species = {"n_species": len(vals), "fwd_pairs_per_s": pairs / ts[0],
-                       "bwd_pairs_per_s": pairs / ts[1], "step_pairs_per_s": pairs / ts[2],
-                       "t2_vs_per_atom_step": float(np.linalg.norm(As_ - Ad) / np.linalg.norm(Ad))}
+            progress(f"{name}: species-factorised step timed")
+            res["species_path"] = {
+                "n_species": len(vals), "fwd_pairs_per_s": pairs / ts[0],
+                "bwd_pairs_per_s": pairs / ts[1], "step_pairs_per_s": pairs / ts[2],
+                "t2_vs_per_atom_step": float(np.linalg.norm(As_ - Ad) / np.linalg.norm(Ad))}
             del txs, fs
 
-    cpu = None
-    errs = None
     if not args.no_cpu:
-        A_np = out[1].cpu().numpy()
+        A_np = A.cpu().numpy()
+        G_np = G.cpu().numpy()
+        g_np = g.cpu().numpy()
+        res["cpu_baseline"], res["max_rel_err"] = cpu_baseline(
+            name, w, A_np, G_np, g_np, cpu_seconds or args.cpu_seconds)
+        progress(f"{name}: CPU oracle baseline done")
+    del tx, tf, tS, I, out, L, A, g, G
+    torch.cuda.empty_cache()
+    return res
 
-        def g_gpu_fn(G):
-            return api.scatter_bwd(tx, tf, tS, torch.from_numpy(G).to(dev), args.mode).cpu().numpy()
 
-        cpu, errs = cpu_baseline(w, A_np, g_gpu_fn, args.cpu_seconds)
-        progress("CPU oracle baseline done")
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the sum would shard along the points with no exchange)",
+              file=sys.stderr)
+        sys.exit(2)
 
+    import torch
+
+    if args.copy_cal:
+        src = torch.empty(args.copy_cal // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_cal}), flush=True)
+        return
+
+    from paper_1010_2641_amd import workloads as wl  # noqa: F401  (fails loudly without libnx)
+
+    torch.cuda.set_device(torch.device("cuda:0"))
+    fkind_of = {"c1": "unit", "c3": "unit", "c4": "unit", "cube41": "unit", "cube41s": "unit"}
+    ceilings = {}
+    if not args.no_micro:
+        for fk in {fkind_of.get(args.workload, "complex"), "complex"}:
+            ceilings.update(issue_ceilings(args.mode, fk))
+        progress("issue-ceiling microbenchmarks done: " + ", ".join(
+            f"{'/'.join(key)} {v:.3e} pairs/s" for key, v in sorted(ceilings.items())))
+
+    head = measure(args.workload, args, args.steps, args.warmup, ceilings, want_graph=args.graph,
+                   want_species=not args.no_species)
+    c5 = None
+    if args.workload == "c2" and not args.no_c5:
+        # the largest configuration, one timed step (its 39 s per step would take the
+        # requested timed steps past the run's time limit)
+        c5 = measure("c5", args, 1, 0, ceilings, want_species=False,
+                     cpu_seconds=2 * args.cpu_seconds)
+        progress("c5 leg done")
+
+    config = dict(head["config"])
+    if c5 is not None:
+        config["headline_choice"] = ("the 203,557-atom dot: the timed steps of the largest "
+                                     "configuration (4,013,800 atoms x 16,777,216 points, one "
+                                     "step per 39 s) would not fit the run's time limit; that "
+                                     "configuration is measured as one timed step in 'c5'")
     res = {
         "metric": "atom.point pairs/s of the fit step (forward + misfit + adjoint)",
-        "value": value,
+        "value": head["value"],
         "unit": "atom.point pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": {
-                "c1": "16^3 simple-cubic block, disorder 0.02, f=1, 64x64 map at l=4",
-                "c2": "Ge-like strained fcc truncated-pyramid dot, 203,557 atoms, 2 species "
-                      "complex f, 128^3 grid around (4,0,4), fit step vs strain x1.1 target",
-                "c3": "100^3 simple-cubic crystal, disorder 0.01, 256^2 map near (8,8,8)",
-                "c4": "29^3-cell fcc cube, sinusoidal displacement, 64^3 grid around (2,2,0)",
-                "c5": "strained fcc nanowire, 4,013,800 atoms, 2 species, 256^3 grid at (0,0,4)",
-                "ewald": "the c2 dot on 2,097,152 area-detector points on Ewald's sphere "
-                         "(128^2 pixels x 128 rocking frames around (4,0,4)), fit step vs strain "
-                         "x1.1 target",
-                "cube41": "Section 4.1 cube, 1e6 atoms, 200x200 map around (004)",
-                "cube41s": "Section 4.1 strained cube, 1e6 atoms, 200x200 map around (004)",
-            }[args.workload],
-            "n_atoms": n, "n_points": k, "pairs_per_step": pairs,
-            "precision": {"ph64": "FP64 phase reduction, FP32 sin/cos, compensated FP32 sums",
-                          "f32": "plain FP32 (the paper's arithmetic)"}[args.mode],
-        },
-        "fwd_pairs_per_s": pairs / t_fwd,
-        "bwd_pairs_per_s": pairs / t_bwd,
-        "loss_ms": t_loss * 1e3,
-        "f64_path": f64,
-        "species_path": species,
-        "graph_replay": graph,
-        "speedup_vs_f64_step": (value / f64["step_pairs_per_s"]) if f64 else None,
-        "max_rel_err": errs,
-        "paper_flop_convention": {"tflops": value * PAPER_FLOP_PER_PAIR / 1e12,
-                                  "frac_of_fp32_peak": value * PAPER_FLOP_PER_PAIR / 1e12 / FP32_PEAK_TFLOPS},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "source_sha": source_hash(),
+        "config": config,
     }
+    for key in ("fwd_pairs_per_s", "bwd_pairs_per_s", "loss_ms", "f64_path", "species_path",
+                "graph_replay", "speedup_vs_f64_step", "max_rel_err", "roofline", "cpu_baseline"):
+        res[key] = head.get(key)
+    res["c5"] = c5
+    res["source_sha"] = source_hash()
     print(json.dumps(res), flush=True)
 
 
