@@ -236,20 +236,28 @@ def test_species_python_validation():
 
 def test_c2_species_forward_and_fit_step():
     """C2 with its two species factored out: the species-factorised forward against the
-    oracle on sampled points (per-atom factors, the original atom order) and against the
-    per-atom-factor kernel on every point; the species adjoint against the per-atom
-    adjoint on sampled atoms."""
+    oracle on sampled points (per-atom factors, the original atom order), against the
+    all-FP64 path on every point at T1 <= 1e-5 (both the same Eq. 2 amplitude), and
+    against the per-atom-factor kernel on every point (two single-precision results, each
+    within T1 of the truth); the species adjoint against the per-atom adjoint on sampled
+    atoms."""
     w = wl.c2()
     xs, start, vals, order = wl.group_by_species(w.xyz, w.f)
     fs = np.repeat(vals[:, None], w.n_points, axis=1)
     tS = dev(w.S)
     A_sp = host(api.scatter_fwd_species(dev(xs), start, dev(fs), tS))
     A_pa = host(api.scatter_fwd(dev(w.xyz), dev(w.f), tS))
+    A64 = host(api.scatter_fwd_f64(dev(w.xyz.astype(np.float64)), dev(w.f.astype(np.complex128)),
+                                   tS.double()))
     idx = sample_points(w.n_points, 256, central_lines(128, 3), seed=7)
     A_ref = oracle.forward(w.xyz, w.f, w.S[idx])
     e1, e2 = M.t1(A_sp[idx], A_ref), M.t2(A_sp[idx], A_ref)
     print(f"c2 species sampled: T1={e1:.3e} T2={e2:.3e}", flush=True)
     assert e1 <= M.T1_TOL and e2 <= M.T2_TOL
+    assert M.t1(A64[idx], A_ref) <= M.F64_T1_TOL
+    f1, f2 = M.t1(A_sp, A64), M.t2(A_sp, A64)
+    print(f"c2 species vs f64 path, full grid: T1={f1:.3e} T2={f2:.3e}", flush=True)
+    assert f1 <= M.T1_TOL and f2 <= M.T2_TOL
     g1, g2 = M.t1(A_sp, A_pa), M.t2(A_sp, A_pa)
     print(f"c2 species vs per-atom kernel, full grid: T1={g1:.3e} T2={g2:.3e}", flush=True)
     assert g1 <= 2 * M.T1_TOL and g2 <= 2 * M.T2_TOL
