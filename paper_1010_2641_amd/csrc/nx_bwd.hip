@@ -483,27 +483,45 @@ __global__ __launch_bounds__(kThreads) void bwd_f64_kernel(
   }
 }
 
-// Combine the split partials of every atom in split order (deterministic).
-template <bool GF, bool POLAR>
+// Combine the split partials of every atom in a fixed order (deterministic): G lanes of
+// one wave serve one atom (G a power of two up to 64, about the number of splits); lane i
+// folds splits i, i + G, ... of each sum in sequence with Knuth's two-sum, then the lanes'
+// states meet in a butterfly in which both partners fold the lower lane's state first (a
+// fixed tree), and lane 0 writes the atom's outputs.  Few splits take G = 1.
+template <int G, bool GF, bool POLAR>
 __global__ __launch_bounds__(kThreads) void bwd_reduce_kernel(const float* __restrict__ part,
                                                               int nsplit, int64_t N,
                                                               const float* __restrict__ f,
                                                               float* __restrict__ grad,
                                                               float* __restrict__ gradf) {
+  static_assert(G >= 1 && G <= 64 && (G & (G - 1)) == 0, "G: a power of two within a wave");
   constexpr int NS = NSum<GF>::value;
-  const int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-  if (j >= N) return;
+  const int64_t t = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  const int64_t j = t / G;
+  const int lane = static_cast<int>(t % G);
   float T[NS];
 #pragma unroll
   for (int d = 0; d < NS; ++d) {
     float s = 0.f, cm = 0.f;
-    for (int sp = 0; sp < nsplit; ++sp) {
-      two_sum_acc(s, cm, part[((int64_t(sp) * NS + d) * 2 + 0) * N + j]);
-      cm += part[((int64_t(sp) * NS + d) * 2 + 1) * N + j];
+    if (j < N) {
+      for (int sp = lane; sp < nsplit; sp += G) {
+        two_sum_acc(s, cm, part[((int64_t(sp) * NS + d) * 2 + 0) * N + j]);
+        cm += part[((int64_t(sp) * NS + d) * 2 + 1) * N + j];
+      }
+    }
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) {
+      const float os = __shfl_xor(s, off), oc = __shfl_xor(cm, off);
+      const bool upper = (lane & off) != 0;    // the partner is the lower lane: fold it first
+      float a = upper ? os : s, ac = upper ? oc : cm;
+      const float b = upper ? s : os, bc = upper ? cm : oc;
+      two_sum_acc(a, ac, b);
+      s = a;
+      cm = ac + bc;
     }
     T[d] = s + cm;
   }
-  write_out<GF, POLAR>(grad, gradf, j, T, f);
+  if (j < N && lane == 0) write_out<GF, POLAR>(grad, gradf, j, T, f);
 }
 
 template <bool GF>
@@ -665,6 +683,16 @@ hipError_t bwd_f64_dispatch(const Plan& p, const BwdArgs& b, hipStream_t st) {
   return p.fk ? bwd_f64_launch<1, 1, GF>(p, b, st) : bwd_f64_launch<1, 0, GF>(p, b, st);
 }
 
+template <int G>
+void bwd_reduce_launch(bool gf, bool polar, int nsplit, int64_t N, const float* pa, const float* ff,
+                       float* g0, float* g1, hipStream_t st) {
+  const unsigned g = static_cast<unsigned>((N * G + kThreads - 1) / kThreads);
+  if (gf && polar) bwd_reduce_kernel<G, true, true><<<g, kThreads, 0, st>>>(pa, nsplit, N, ff, g0, g1);
+  else if (gf) bwd_reduce_kernel<G, true, false><<<g, kThreads, 0, st>>>(pa, nsplit, N, ff, g0, g1);
+  else if (polar) bwd_reduce_kernel<G, false, true><<<g, kThreads, 0, st>>>(pa, nsplit, N, ff, g0, g1);
+  else bwd_reduce_kernel<G, false, false><<<g, kThreads, 0, st>>>(pa, nsplit, N, ff, g0, g1);
+}
+
 }  // namespace
 
 hipError_t launch_pack_points(int mode, int red, const void* S, const void* G, int64_t k,
@@ -704,10 +732,13 @@ hipError_t launch_bwd_reduce(const Plan& p, const void* partial, const void* f, 
     auto* g0 = static_cast<float*>(grad);
     auto* g1 = static_cast<float*>(gradf);
     const bool polar = p.mode == kPH64 && p.fk;
-    if (p.gf && polar) bwd_reduce_kernel<true, true><<<g, kThreads, 0, st>>>(pa, p.nsplit, N, ff, g0, g1);
-    else if (p.gf) bwd_reduce_kernel<true, false><<<g, kThreads, 0, st>>>(pa, p.nsplit, N, ff, g0, g1);
-    else if (polar) bwd_reduce_kernel<false, true><<<g, kThreads, 0, st>>>(pa, p.nsplit, N, ff, g0, g1);
-    else bwd_reduce_kernel<false, false><<<g, kThreads, 0, st>>>(pa, p.nsplit, N, ff, g0, g1);
+    switch (reduce_lanes(p.nsplit)) {
+      case 64: bwd_reduce_launch<64>(p.gf, polar, p.nsplit, N, pa, ff, g0, g1, st); break;
+      case 32: bwd_reduce_launch<32>(p.gf, polar, p.nsplit, N, pa, ff, g0, g1, st); break;
+      case 16: bwd_reduce_launch<16>(p.gf, polar, p.nsplit, N, pa, ff, g0, g1, st); break;
+      case 8: bwd_reduce_launch<8>(p.gf, polar, p.nsplit, N, pa, ff, g0, g1, st); break;
+      default: bwd_reduce_launch<1>(p.gf, polar, p.nsplit, N, pa, ff, g0, g1, st); break;
+    }
   }
   return hipGetLastError();
 }

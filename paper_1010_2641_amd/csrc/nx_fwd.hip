@@ -384,21 +384,44 @@ __global__ __launch_bounds__(kThreads) void fwd_f64_kernel(
   }
 }
 
-// Combine the split partials of every point in split order (deterministic).
+// Combine the split partials of every point in a fixed order (deterministic): G lanes
+// of one wave serve one point (G a power of two up to 64, about the number of splits);
+// lane i folds splits i, i + G, i + 2G, ... in sequence with Knuth's two-sum, then the G
+// states are combined by a butterfly in which both partners fold the lower lane's state
+// first, so that every lane holds the same total and the order of the additions is a
+// fixed tree.  Few splits take G = 1 (one thread per point, splits in sequence).
+template <int G>
 __global__ __launch_bounds__(kThreads) void fwd_reduce_kernel(const float4* __restrict__ part,
                                                               int nsplit, int64_t K,
                                                               float2* __restrict__ A) {
-  const int64_t k = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-  if (k >= K) return;
+  static_assert(G >= 1 && G <= 64 && (G & (G - 1)) == 0, "G: a power of two within a wave");
+  const int64_t t = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  const int64_t k = t / G;
+  const int lane = static_cast<int>(t % G);
   float sr = 0.f, si = 0.f, cr = 0.f, ci = 0.f;
-  for (int sp = 0; sp < nsplit; ++sp) {
-    const float4 st = part[int64_t(sp) * K + k];
-    two_sum_acc(sr, cr, st.x);
-    two_sum_acc(si, ci, st.y);
-    cr += st.z;
-    ci += st.w;
+  if (k < K) {
+    for (int sp = lane; sp < nsplit; sp += G) {
+      const float4 st = part[int64_t(sp) * K + k];
+      two_sum_acc(sr, cr, st.x);
+      two_sum_acc(si, ci, st.y);
+      cr += st.z;
+      ci += st.w;
+    }
   }
-  A[k] = make_float2(sr + cr, si + ci);
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) {
+    const float osr = __shfl_xor(sr, off), osi = __shfl_xor(si, off);
+    const float ocr = __shfl_xor(cr, off), oci = __shfl_xor(ci, off);
+    const bool upper = (lane & off) != 0;      // the partner is the lower lane: fold it first
+    float ar = upper ? osr : sr, ai = upper ? osi : si, ac = upper ? ocr : cr, aci = upper ? oci : ci;
+    const float br = upper ? sr : osr, bi = upper ? si : osi, bc = upper ? cr : ocr, bci = upper ? ci : oci;
+    two_sum_acc(ar, ac, br);
+    two_sum_acc(ai, aci, bi);
+    sr = ar; si = ai;
+    cr = ac + bc;
+    ci = aci + bci;
+  }
+  if (k < K && lane == 0) A[k] = make_float2(sr + cr, si + ci);
 }
 
 __global__ __launch_bounds__(kThreads) void fwd_reduce_f64_kernel(const double2* __restrict__ part,
@@ -622,15 +645,31 @@ hipError_t launch_fwd_chunk(const Plan& p, const void* rec, int64_t a_begin, int
   return fwd_dispatch_p<kF32>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st);
 }
 
+namespace {
+template <int G>
+void fwd_reduce_launch(const Plan& p, const void* partial, void* A, hipStream_t st) {
+  const int64_t K = p.lanes;
+  const unsigned g = static_cast<unsigned>((K * G + kThreads - 1) / kThreads);
+  fwd_reduce_kernel<G><<<g, kThreads, 0, st>>>(static_cast<const float4*>(partial), p.nsplit, K,
+                                              static_cast<float2*>(A));
+}
+}  // namespace
+
 hipError_t launch_fwd_reduce(const Plan& p, const void* partial, void* A, hipStream_t st) {
   const int64_t K = p.lanes;
-  const unsigned g = static_cast<unsigned>((K + kThreads - 1) / kThreads);
-  if (p.mode == kF64)
+  if (p.mode == kF64) {
+    const unsigned g = static_cast<unsigned>((K + kThreads - 1) / kThreads);
     fwd_reduce_f64_kernel<<<g, kThreads, 0, st>>>(static_cast<const double2*>(partial), p.nsplit, K,
                                                  static_cast<double2*>(A));
-  else
-    fwd_reduce_kernel<<<g, kThreads, 0, st>>>(static_cast<const float4*>(partial), p.nsplit, K,
-                                             static_cast<float2*>(A));
+    return hipGetLastError();
+  }
+  switch (reduce_lanes(p.nsplit)) {
+    case 64: fwd_reduce_launch<64>(p, partial, A, st); break;
+    case 32: fwd_reduce_launch<32>(p, partial, A, st); break;
+    case 16: fwd_reduce_launch<16>(p, partial, A, st); break;
+    case 8: fwd_reduce_launch<8>(p, partial, A, st); break;
+    default: fwd_reduce_launch<1>(p, partial, A, st); break;
+  }
   return hipGetLastError();
 }
 

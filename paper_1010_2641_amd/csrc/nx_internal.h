@@ -148,6 +148,16 @@ enum Op : int { kOpFwd = 0, kOpBwd = 1, kOpFwdF64 = 2, kOpBwdF64 = 3, kOpLoss = 
 
 constexpr int kMaxSpecies = 16;   // species of the factorised entry points
 
+// Lanes that serve one output in the split reduction (a power of two, 1 to 64): about
+// the number of splits, so that each lane folds a few splits in sequence and the lanes'
+// states meet in a fixed butterfly; one lane per output (splits in sequence) below 8.
+inline int reduce_lanes(int nsplit) {
+  if (nsplit < 8) return 1;
+  int g = 8;
+  while (g < 64 && g < nsplit) g <<= 1;
+  return g;
+}
+
 // Builds the plan of (op, mode) for the sizes; pure host code, no HIP call.
 Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_null);
 
