@@ -115,6 +115,28 @@ int nx_scatter_fwd(const float* xyz, const float* f, int64_t n_atoms,
                    const float* S, int64_t n_points, float* A,
                    int mode, void* ws, size_t ws_bytes, void* stream);
 
+/* Bytes of the static device scratch of nx_scatter_fwd_noalloc (per GPU). */
+#define NX_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* Forward sum without allocation, for callers that cannot allocate device memory or
+ * pass a workspace (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): nx_scatter_fwd with the same arguments but no workspace.  Its
+ * workspace is a static device array of NX_NOALLOC_SCRATCH_BYTES (128 MiB) that every
+ * GPU the library runs on holds from the library's load until the process ends; the call
+ * itself allocates nothing.  The work is queued on `stream`, which must belong to the
+ * current device (the scratch used is the current device's).
+ * The launch plan is nx_scatter_fwd's, with fewer stream slices when its workspace would
+ * not fit the scratch: the result then differs from nx_scatter_fwd's only by rounding
+ * (the same tolerance), and is bitwise equal when the plan is the same.  Sizes that do not
+ * fit even with one slice (about n_atoms * 48 bytes of atom records, plus n_points * 16
+ * bytes when the atoms are cut into several launches) return NX_ERR_WORKSPACE before any
+ * HIP call.  Nothing in the scratch has to start at zero (each call writes what it reads
+ * back).  Every call on one GPU shares that GPU's scratch and leaves its contents behind:
+ * calls that overlap on one GPU (on different streams or threads) race and give wrong
+ * results; order them on one stream. */
+int nx_scatter_fwd_noalloc(const float* xyz, const float* f, int64_t n_atoms,
+                           const float* S, int64_t n_points, float* A, int mode, void* stream);
+
 /* Adjoint of the forward sum with respect to the positions (chain rule through Eq. 2).
  * For a real loss L(A) with seed G_k = dL/dRe A_k + i dL/dIm A_k (the complex gradient
  * convention of PyTorch):

@@ -16,6 +16,7 @@ NX_OP_FWD, NX_OP_BWD, NX_OP_FWD_F64, NX_OP_BWD_F64, NX_OP_LOSS = 0, 1, 2, 3, 4
 NX_OP_BWD_GF, NX_OP_BWD_GF_F64 = 5, 6
 NX_MAX_COUNT = 1 << 30
 NX_MAX_SPECIES = 16
+NX_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 # every symbol include/nx.h declares, with its ctypes signature
 _VP, _I64, _SZ, _I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t, ctypes.c_int
@@ -24,6 +25,7 @@ SIGNATURES = {
     "nx_last_error": ([], ctypes.c_char_p),
     "nx_workspace_bytes": ([_I64, _I64, _I, _I, _I], _SZ),
     "nx_scatter_fwd": ([_VP, _VP, _I64, _VP, _I64, _VP, _I, _VP, _SZ, _VP], _I),
+    "nx_scatter_fwd_noalloc": ([_VP, _VP, _I64, _VP, _I64, _VP, _I, _VP], _I),
     "nx_scatter_bwd": ([_VP, _VP, _I64, _VP, _I64, _VP, _VP, _I, _VP, _SZ, _VP], _I),
     "nx_scatter_fwd_f64": ([_VP, _VP, _I64, _VP, _I64, _VP, _VP, _SZ, _VP], _I),
     "nx_scatter_bwd_f64": ([_VP, _VP, _I64, _VP, _I64, _VP, _VP, _VP, _SZ, _VP], _I),
@@ -89,6 +91,7 @@ nx_version = lib.nx_version
 nx_last_error = lib.nx_last_error
 nx_workspace_bytes = lib.nx_workspace_bytes
 nx_scatter_fwd = lib.nx_scatter_fwd
+nx_scatter_fwd_noalloc = lib.nx_scatter_fwd_noalloc
 nx_scatter_bwd = lib.nx_scatter_bwd
 nx_scatter_fwd_f64 = lib.nx_scatter_fwd_f64
 nx_scatter_bwd_f64 = lib.nx_scatter_bwd_f64

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <mutex>
 #include <string>
 
 #include "nx_internal.h"
@@ -83,7 +84,8 @@ int device_error(const char* fn, hipError_t e) {
 
 namespace nx {
 
-Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_null) {
+Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_null,
+               int64_t max_split) {
   Plan p;
   p.fk = f_is_null ? 0 : 1;
   const bool fwd = (op == kOpFwd || op == kOpFwdF64);
@@ -144,6 +146,7 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
     if (maxs < 1) maxs = 1;
     if (want > maxs) want = maxs;
     if (want > kMaxSplit) want = kMaxSplit;
+    if (want > max_split) want = max_split < 1 ? 1 : max_split;
     p.nsplit = int(want);
   }
   // chunks of at most kLaunchPairs pairs, a whole number of groups per split
@@ -268,9 +271,73 @@ size_t species_ws(int op, int mode, int64_t n_points, const int64_t* start, int 
 
 }  // namespace
 
+namespace {
+
+// ---------------------------------------------------------------------------------
+// Scratch of nx_scatter_fwd_noalloc: the packed atom records and the split/chunk partial
+// sums of one call, as a static device array that every GPU the library runs on holds
+// until the process ends.  In host code `scratch` names a host-side stand-in, not device
+// memory: host code never passes it to a kernel or a copy.  Its device address is taken
+// with hipGetSymbolAddress once per device (with that device current, on the first call
+// there) and only that address is used.
+static __device__ __align__(256) unsigned char scratch[NX_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's scratch.
+int scratch_of_current_device(const char* fn, void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_error(fn, e);
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(NX_ERR_DEVICE, "%s: device %d outside the %d devices served", fn, dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return device_error(fn, e);
+    if (p == nullptr) return fail(NX_ERR_DEVICE, "%s: no device address for the scratch", fn);
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return NX_OK;
+}
+
+// nx_scatter_fwd's plan with its stream slices cut down, if need be, until its workspace
+// fits the scratch (the slice count is a function of the sizes only, so a call's plan and
+// result are reproducible).  False when even one slice does not fit.
+bool noalloc_plan(int mode, int64_t n_atoms, int64_t n_points, int f_is_null, nx::Plan* out) {
+  const size_t cap = NX_NOALLOC_SCRATCH_BYTES;
+  nx::Plan p = nx::make_plan(nx::kOpFwd, mode, n_atoms, n_points, f_is_null);
+  if (p.total() <= cap) {
+    *out = p;
+    return true;
+  }
+  int64_t lo = 1, hi = p.nsplit - 1, best = 0;     // workspace grows with the slice count
+  while (lo <= hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (nx::make_plan(nx::kOpFwd, mode, n_atoms, n_points, f_is_null, mid).total() <= cap) {
+      best = mid;
+      lo = mid + 1;
+    } else {
+      hi = mid - 1;
+    }
+  }
+  if (best == 0) {
+    *out = nx::make_plan(nx::kOpFwd, mode, n_atoms, n_points, f_is_null, 1);
+    return false;
+  }
+  *out = nx::make_plan(nx::kOpFwd, mode, n_atoms, n_points, f_is_null, best);
+  return true;
+}
+
+}  // namespace
+
 extern "C" {
 
-int nx_version(void) { return 101; }
+int nx_version(void) { return 102; }
 
 const char* nx_last_error(void) { return g_last_error.c_str(); }
 
@@ -303,6 +370,31 @@ int nx_scatter_fwd(const float* xyz, const float* f, int64_t n_atoms, const floa
     return fail(NX_ERR_ARG, "%s: A and f must be 8-byte aligned (complex64)", fn);
   const nx::Plan p = nx::make_plan(nx::kOpFwd, mode, n_atoms, n_points, f == nullptr);
   if (int r = check_ws(fn, p, ws, ws_bytes)) return r;
+  return run_sum(fn, p, true, xyz, f, S, nullptr, A, nullptr, ws, static_cast<hipStream_t>(stream));
+}
+
+int nx_scatter_fwd_noalloc(const float* xyz, const float* f, int64_t n_atoms, const float* S,
+                           int64_t n_points, float* A, int mode, void* stream) {
+  const char* fn = "nx_scatter_fwd_noalloc";
+  if (int r = check_counts(fn, n_atoms, n_points)) return r;
+  if (mode != NX_F32 && mode != NX_F32_PH64) return fail(NX_ERR_MODE, "%s: unknown mode %d", fn, mode);
+  if (n_points == 0) return ok();
+  if (!S || !A || (n_atoms > 0 && !xyz))
+    return fail(NX_ERR_ARG, "%s: NULL pointer (xyz=%p S=%p A=%p)", fn, (const void*)xyz,
+                (const void*)S, (void*)A);
+  if (!aligned(A, 8) || (f && !aligned(f, 8)))
+    return fail(NX_ERR_ARG, "%s: A and f must be 8-byte aligned (complex64)", fn);
+  nx::Plan p;
+  if (!noalloc_plan(mode, n_atoms, n_points, f == nullptr, &p))
+    return fail(NX_ERR_WORKSPACE,
+                "%s: %lld atoms over %lld points need %zu bytes of scratch even with one stream "
+                "slice; the static scratch holds %zu (use nx_scatter_fwd with a workspace)",
+                fn, (long long)n_atoms, (long long)n_points, p.total(),
+                (size_t)NX_NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  if (p.total() > 0) {
+    if (int r = scratch_of_current_device(fn, &ws)) return r;
+  }
   return run_sum(fn, p, true, xyz, f, S, nullptr, A, nullptr, ws, static_cast<hipStream_t>(stream));
 }
 

@@ -158,8 +158,10 @@ inline int reduce_lanes(int nsplit) {
   return g;
 }
 
-// Builds the plan of (op, mode) for the sizes; pure host code, no HIP call.
-Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_null);
+// Builds the plan of (op, mode) for the sizes; pure host code, no HIP call.  At most
+// max_split stream slices (kMaxSplit when omitted).
+Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_null,
+               int64_t max_split = kMaxSplit);
 
 // Per-launch stream range of chunk c: [begin, end) and the slice length per split.
 void chunk_range(const Plan& p, int64_t c, int64_t* begin, int64_t* end, int64_t* per_split);

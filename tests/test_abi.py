@@ -50,7 +50,7 @@ def test_micro_header_symbols_exported():
 
 
 def test_version():
-    assert _lib.nx_version() == 101
+    assert _lib.nx_version() == 102
 
 
 def fwd(n_atoms=8, n_points=8, xyz=FAKE, f=None, S=FAKE, A=FAKE, mode=1, ws=FAKE, wsb=1 << 40):
