@@ -97,7 +97,10 @@ def _f_arg(f: Optional[torch.Tensor], n: int, dtype):
 
 
 def _real(t: Optional[torch.Tensor]) -> Optional[torch.Tensor]:
-    return None if t is None else torch.view_as_real(t)
+    """A complex tensor for the C ABI's interleaved (re, im) arrays: a contiguous complex
+    tensor already is that array (its data pointer is the first real part), so it is
+    passed as it is, without building a view."""
+    return t
 
 
 def workspace_bytes(n_atoms: int, n_points: int, mode="ph64", op=_lib.NX_OP_FWD,

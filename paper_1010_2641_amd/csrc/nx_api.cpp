@@ -48,6 +48,10 @@ bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 //   NX_TUNE_LDS           FP64-phase sums: 1 stages record tiles in LDS (the forward's
 //                         atom records; the phase part of the adjoint's point records),
 //                         0 streams them through scalar loads (default: 1)
+//   NX_TUNE_FILL_BLOCKS   small problems: work-groups the slices may be shortened to reach
+//                         (default 1024); NX_TUNE_MIN_SLICE their shortest slice (32)
+//   NX_TUNE_INLINE        0: always pack the records in their own dispatch; 1: form them in
+//                         the sum kernel wherever that form exists (default: small calls)
 int64_t env_i64(const char* name, int64_t def) {
   const char* v = std::getenv(name);
   if (!v || !*v) return def;
@@ -146,8 +150,25 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
     if (maxs < 1) maxs = 1;
     if (want > maxs) want = maxs;
     if (want > kMaxSplit) want = kMaxSplit;
+    const int64_t fill_blocks = std::min<int64_t>(env_i64("NX_TUNE_FILL_BLOCKS", kFillBlocks), target);
+    const int64_t min_small = std::max<int64_t>(1, env_i64("NX_TUNE_MIN_SLICE", kMinStreamPerSplitSmall));
+    if (want * p.blocks < fill_blocks) {
+      int64_t fill = ceil_div(fill_blocks, p.blocks);
+      int64_t maxf = p.stream / min_small;
+      if (fill > maxf) fill = maxf;
+      if (fill > kMaxSplit) fill = kMaxSplit;
+      if (fill > want) want = fill;
+    }
     if (want > max_split) want = max_split < 1 ? 1 : max_split;
     p.nsplit = int(want);
+  }
+  // small calls: records formed in the sum kernel (the LDS forms with one lane item per
+  // lane and the default reduction variant); NX_TUNE_INLINE=0 turns this off, 1 forces it
+  // wherever that form exists
+  if (p.mode == kPH64 && p.lds && p.per_lane == 1 &&
+      (fwd ? (p.red == 0 && (p.grp == 8 || p.grp == 16)) : (p.red == 1 && p.grp == 64))) {
+    const int64_t ti = env_i64("NX_TUNE_INLINE", -1);
+    p.inl = (ti == 1 || (ti != 0 && p.blocks * p.stream <= kInlineMaxRecords)) ? 1 : 0;
   }
   // chunks of at most kLaunchPairs pairs, a whole number of groups per split
   const int64_t lane_pad = p.blocks * per_block;
@@ -208,17 +229,19 @@ int run_sum(const char* fn, const nx::Plan& p, bool fwd, const void* xyz, const 
   char* base = static_cast<char*>(ws);
   void* rec = base;
   void* partial = p.partial_bytes ? base + p.rec_bytes : nullptr;
-  hipError_t e;
-  if (fwd) e = nx::launch_pack_atoms(p.mode, p.red, p.grp, xyz, f, p.stream, rec, st);
-  else e = nx::launch_pack_points(p.mode, p.red, S, G, p.stream, rec, st);
+  hipError_t e = hipSuccess;
+  if (!p.inl) {          // small calls form their records in the sum kernel
+    if (fwd) e = nx::launch_pack_atoms(p.mode, p.red, p.grp, xyz, f, p.stream, rec, st);
+    else e = nx::launch_pack_points(p.mode, p.red, S, G, p.stream, rec, st);
+  }
   if (e != hipSuccess) return device_error(fn, e);
   for (int64_t c = 0; c < p.nchunks; ++c) {
     int64_t b, en, per;
     nx::chunk_range(p, c, &b, &en, &per);
     const int carry = c > 0 ? 1 : 0;
     const int direct = (p.nsplit == 1 && c == p.nchunks - 1) ? 1 : 0;
-    if (fwd) e = nx::launch_fwd_chunk(p, rec, b, en, per, S, partial, out, carry, direct, st);
-    else e = nx::launch_bwd_chunk(p, rec, b, en, per, xyz, f, partial, out, outf, carry, direct, st);
+    if (fwd) e = nx::launch_fwd_chunk(p, rec, b, en, per, S, partial, out, carry, direct, st, xyz, f);
+    else e = nx::launch_bwd_chunk(p, rec, b, en, per, xyz, f, partial, out, outf, carry, direct, st, S, G);
     if (e != hipSuccess) return device_error(fn, e);
   }
   if (p.nsplit > 1) {
@@ -551,9 +574,11 @@ int nx_scatter_fwd_species(const float* xyz, int64_t n_atoms, const int64_t* spe
   ss.n = n_species;
   for (int s = 0; s < n_species; ++s) {
     const int64_t a0 = species_start[s];
-    const nx::Plan ps = nx::make_plan(nx::kOpFwd, mode, species_start[s + 1] - a0, n_points, 1);
+    nx::Plan ps = nx::make_plan(nx::kOpFwd, mode, species_start[s + 1] - a0, n_points, 1);
     // each species' records are packed with its own plan (variant, group size), their
     // groups counted from the species' first atom; they sit at the species' place in ws
+    // (the kernels read them there: no records formed inside the kernel)
+    ps.inl = 0;
     e = nx::launch_pack_atoms(ps.mode, ps.red, ps.grp, xyz + 3 * a0, nullptr, ps.stream,
                               base + a0 * ps.rec_size, st);
     if (e != hipSuccess) return device_error(fn, e);

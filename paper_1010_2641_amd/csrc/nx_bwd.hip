@@ -121,6 +121,44 @@ __device__ __forceinline__ PtRegs load_point_split(const uint4* sd, int u,
   return r;
 }
 
+// The FP64-phase record of point k, with the seed in polar form conj(G) = |G| exp(2 i pi
+// delta): delta = -arg(G) / (2 pi) in FP64 (plus the reduction offset of the variant); |G| S
+// and |G| rounded once to FP32.  The pack kernel writes it to the workspace; the adjoint of
+// small calls forms it while staging its tile, so that both give the same record.
+__device__ __forceinline__ PointPH make_point_ph(const float* __restrict__ S,
+                                                const float* __restrict__ G, int64_t k,
+                                                double offset) {
+  PointPH r;
+  const double sx = S[3 * k], sy = S[3 * k + 1], sz = S[3 * k + 2];
+  const double gr = G[2 * k], gi = G[2 * k + 1];
+  const double m = sqrt(gr * gr + gi * gi);
+  r.sx = sx; r.sy = sy; r.sz = sz;
+  r.delta = -atan2(gi, gr) * 0.15915494309189533577 + offset;
+  r.gsx = static_cast<float>(m * sx);
+  r.gsy = static_cast<float>(m * sy);
+  r.gsz = static_cast<float>(m * sz);
+  r.gmag = static_cast<float>(m);
+  return r;
+}
+
+// A whole record from an LDS tile of 48-byte records (the inline form of small calls):
+// the phase part as two (double, double) pairs, the rest as one 16-byte word.
+__device__ __forceinline__ PtRegs load_point_lds(const uint4* sd, int u) {
+  const double2* sdd = reinterpret_cast<const double2*>(sd);
+  const double2 a = sdd[3 * u], b = sdd[3 * u + 1];
+  const uint4 c = sd[3 * u + 2];
+  PtRegs r;
+  r.sx = a.x;
+  r.delta = a.y;
+  r.sy = b.x;
+  r.sz = b.y;
+  r.gsx = __uint_as_float(c.x);
+  r.gsy = __uint_as_float(c.y);
+  r.gsz = __uint_as_float(c.z);
+  r.gmag = __uint_as_float(c.w);
+  return r;
+}
+
 // (c, s) of exp(2 i pi psi), psi = S.r + delta + alpha (delta includes the 1/2 of
 // RED == 1; alpha = arg f in cycles, absent for f = 1).  The seed angle enters as the
 // addend of the first fma, the atom's angle as one FP64 add.
@@ -315,16 +353,21 @@ __global__ __launch_bounds__(kThreads) void bwd_kernel(
 // staged in an LDS tile and the rest of the record (|G| S, |G|) read with scalar loads:
 // the phase's fma chain then takes its point values from VGPRs.  Groups and compensation are those of bwd_kernel
 // (tiles are whole groups), so the result is bitwise the same.
-template <int Q, int FK, int GRP, int RED, bool GF>
+//
+// INL (small calls): no packed records; each thread forms its whole record of the tile from
+// S and G while staging it (make_point_ph, as the pack kernel does) and every field is read
+// back from LDS, which saves the pack dispatch when few work-groups share each record.
+template <int Q, int FK, int GRP, int RED, bool GF, bool INL>
 __global__ __launch_bounds__(kThreads) void bwd_split_kernel(
     const PointPH* __restrict__ rec, int k_begin, int k_end, int per_split,
     const float* __restrict__ xyz, const float* __restrict__ f, int64_t N, int blocks_n,
     float* __restrict__ part, float* __restrict__ grad, float* __restrict__ gradf, int carry_in,
-    int direct) {
+    int direct, const float* __restrict__ S, const float* __restrict__ G) {
   static_assert(kThreads % GRP == 0, "tiles must hold whole groups");
   constexpr int NS = NSum<GF>::value;
   constexpr float SGN = (RED == 1) ? -1.f : 1.f;
-  __shared__ uint4 sd[2 * kThreads];
+  constexpr int W = INL ? 3 : 2;            // 16-byte words per point in the LDS tile
+  __shared__ uint4 sd[W * kThreads];
   const int lb = xcd_major_block(blockIdx.x, gridDim.x);
   const int nb = lb % blocks_n;
   const int sp = lb / blocks_n;
@@ -356,9 +399,17 @@ __global__ __launch_bounds__(kThreads) void bwd_split_kernel(
     const int nt = min(kThreads, k1 - t0);
     __syncthreads();                        // the previous tile is no longer read
     if (int(threadIdx.x) < nt) {
-      const uint4* w = reinterpret_cast<const uint4*>(rec + t0 + threadIdx.x);
-      sd[2 * threadIdx.x] = w[0];
-      sd[2 * threadIdx.x + 1] = w[1];
+      if constexpr (INL) {
+        const PointPH r = make_point_ph(S, G, t0 + threadIdx.x, RED == 1 ? 0.5 : 0.0);
+        const uint4* w = reinterpret_cast<const uint4*>(&r);
+        sd[3 * threadIdx.x] = w[0];
+        sd[3 * threadIdx.x + 1] = w[1];
+        sd[3 * threadIdx.x + 2] = w[2];
+      } else {
+        const uint4* w = reinterpret_cast<const uint4*>(rec + t0 + threadIdx.x);
+        sd[2 * threadIdx.x] = w[0];
+        sd[2 * threadIdx.x + 1] = w[1];
+      }
     }
     __syncthreads();
     for (int u0 = 0; u0 < nt; u0 += GRP) {
@@ -371,7 +422,7 @@ __global__ __launch_bounds__(kThreads) void bwd_split_kernel(
       if (ue - u0 == GRP) {
 #pragma unroll
         for (int u = 0; u < GRP; ++u) {
-          const PtRegs a = load_point_split(sd, u0 + u, rec, t0 + u0 + u);
+          const PtRegs a = INL ? load_point_lds(sd, u0 + u) : load_point_split(sd, u0 + u, rec, t0 + u0 + u);
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
             float c, s;
@@ -381,7 +432,7 @@ __global__ __launch_bounds__(kThreads) void bwd_split_kernel(
         }
       } else {
         for (int u = u0; u < ue; ++u) {
-          const PtRegs a = load_point_split(sd, u, rec, t0 + u);
+          const PtRegs a = INL ? load_point_lds(sd, u) : load_point_split(sd, u, rec, t0 + u);
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
             float c, s;
@@ -484,7 +535,7 @@ __global__ __launch_bounds__(kThreads) void bwd_f64_kernel(
 }
 
 // Combine the split partials of every atom in a fixed order (deterministic): G lanes of
-// one wave serve one atom (G a power of two up to 64, about the number of splits); lane i
+// one wave serve one atom (G a power of two up to 64, about a quarter of the splits); lane i
 // folds splits i, i + G, ... of each sum in sequence with Knuth's two-sum, then the lanes'
 // states meet in a butterfly in which both partners fold the lower lane's state first (a
 // fixed tree), and lane 0 writes the atom's outputs.  Few splits take G = 1.
@@ -504,6 +555,7 @@ __global__ __launch_bounds__(kThreads) void bwd_reduce_kernel(const float* __res
   for (int d = 0; d < NS; ++d) {
     float s = 0.f, cm = 0.f;
     if (j < N) {
+#pragma unroll 4
       for (int sp = lane; sp < nsplit; sp += G) {
         two_sum_acc(s, cm, part[((int64_t(sp) * NS + d) * 2 + 0) * N + j]);
         cm += part[((int64_t(sp) * NS + d) * 2 + 1) * N + j];
@@ -567,19 +619,7 @@ __global__ __launch_bounds__(kThreads) void pack_points_kernel(const void* __res
       const float* S = static_cast<const float*>(S_v);
       const float* G = static_cast<const float*>(G_v);
       if constexpr (MODE == kPH64) {
-        // conj(G) = |G| exp(2 i pi delta): delta = -arg(G) / (2 pi) in FP64 (plus the
-        // reduction offset of the variant); |G| S and |G| rounded once to FP32
-        PointPH r;
-        const double sx = S[3 * k], sy = S[3 * k + 1], sz = S[3 * k + 2];
-        const double gr = G[2 * k], gi = G[2 * k + 1];
-        const double m = sqrt(gr * gr + gi * gi);
-        r.sx = sx; r.sy = sy; r.sz = sz;
-        r.delta = -atan2(gi, gr) * 0.15915494309189533577 + offset;
-        r.gsx = static_cast<float>(m * sx);
-        r.gsy = static_cast<float>(m * sy);
-        r.gsz = static_cast<float>(m * sz);
-        r.gmag = static_cast<float>(m);
-        static_cast<PointPH*>(rec_v)[k] = r;
+        static_cast<PointPH*>(rec_v)[k] = make_point_ph(S, G, k, offset);
       } else {
         PointF32 r;
         r.sx = S[3 * k]; r.sy = S[3 * k + 1]; r.sz = S[3 * k + 2];
@@ -602,6 +642,7 @@ struct BwdArgs {
   const void* rec; int64_t k_begin, k_end, per_split;
   const void* xyz; const void* f; void* partial; void* grad; void* gradf;
   int carry_in, direct;
+  const void* S; const void* G;            // the inline form's record sources
 };
 
 template <int MODE, int Q, int FK, bool GF>
@@ -620,15 +661,23 @@ hipError_t bwd_dispatch(const Plan& p, const BwdArgs& b, hipStream_t st) {
         r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);
   } else {
     if (p.lds && p.red == 1 && (p.grp == 64 || p.grp == 32 || p.grp == 16)) {
+      if constexpr (Q == 1) {
+        if (p.inl && p.grp == 64) {       // records formed while staging (small calls)
+          bwd_split_kernel<1, FK, 64, 1, GF, true><<<grid, kThreads, 0, st>>>(
+              nullptr, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct,
+              static_cast<const float*>(b.S), static_cast<const float*>(b.G));
+          return hipGetLastError();
+        }
+      }
       if (p.grp == 64)
-        bwd_split_kernel<Q, FK, 64, 1, GF><<<grid, kThreads, 0, st>>>(
-            r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);
+        bwd_split_kernel<Q, FK, 64, 1, GF, false><<<grid, kThreads, 0, st>>>(
+            r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct, nullptr, nullptr);
       else if (p.grp == 32)
-        bwd_split_kernel<Q, FK, 32, 1, GF><<<grid, kThreads, 0, st>>>(
-            r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);
+        bwd_split_kernel<Q, FK, 32, 1, GF, false><<<grid, kThreads, 0, st>>>(
+            r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct, nullptr, nullptr);
       else
-        bwd_split_kernel<Q, FK, 16, 1, GF><<<grid, kThreads, 0, st>>>(
-            r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);
+        bwd_split_kernel<Q, FK, 16, 1, GF, false><<<grid, kThreads, 0, st>>>(
+            r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct, nullptr, nullptr);
       return hipGetLastError();
     }
     if (p.grp == 64 && p.red == 0)
@@ -708,8 +757,9 @@ hipError_t launch_pack_points(int mode, int red, const void* S, const void* G, i
 
 hipError_t launch_bwd_chunk(const Plan& p, const void* rec, int64_t k_begin, int64_t k_end,
                             int64_t per_split, const void* xyz, const void* f, void* partial,
-                            void* grad, void* gradf, int carry_in, int direct, hipStream_t st) {
-  const BwdArgs b{rec, k_begin, k_end, per_split, xyz, f, partial, grad, gradf, carry_in, direct};
+                            void* grad, void* gradf, int carry_in, int direct, hipStream_t st,
+                            const void* S, const void* G) {
+  const BwdArgs b{rec, k_begin, k_end, per_split, xyz, f, partial, grad, gradf, carry_in, direct, S, G};
   if (p.mode == kF64) return p.gf ? bwd_f64_dispatch<true>(p, b, st) : bwd_f64_dispatch<false>(p, b, st);
   if (p.mode == kPH64) return p.gf ? bwd_dispatch_q<kPH64, true>(p, b, st) : bwd_dispatch_q<kPH64, false>(p, b, st);
   return p.gf ? bwd_dispatch_q<kF32, true>(p, b, st) : bwd_dispatch_q<kF32, false>(p, b, st);
@@ -737,6 +787,7 @@ hipError_t launch_bwd_reduce(const Plan& p, const void* partial, const void* f, 
       case 32: bwd_reduce_launch<32>(p.gf, polar, p.nsplit, N, pa, ff, g0, g1, st); break;
       case 16: bwd_reduce_launch<16>(p.gf, polar, p.nsplit, N, pa, ff, g0, g1, st); break;
       case 8: bwd_reduce_launch<8>(p.gf, polar, p.nsplit, N, pa, ff, g0, g1, st); break;
+      case 4: bwd_reduce_launch<4>(p.gf, polar, p.nsplit, N, pa, ff, g0, g1, st); break;
       default: bwd_reduce_launch<1>(p.gf, polar, p.nsplit, N, pa, ff, g0, g1, st); break;
     }
   }

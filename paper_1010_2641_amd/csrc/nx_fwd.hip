@@ -69,6 +69,68 @@ __device__ __forceinline__ void kahan_rot(float& sr, float& cr, float& si, float
   si = ti;
 }
 
+// SplitMix64's output function (Steele, Lea and Flood, OOPSLA 2014): 64 pseudo-random
+// bits of a 64-bit key.  The atoms' roundings use keys 2j, the groups' turns keys 2g + 1.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// m >= 0 to FP32 by unbiased (stochastic) rounding: the FP32 value above m with
+// probability equal to the fraction of the gap by which m exceeds the value below it,
+// drawn from the top 53 bits of mix64(2 j).  The expected result is m, so the rounding
+// errors of atoms with equal factors are independent and add up incoherently instead
+// of as one relative error of their species' amplitude.
+__device__ __forceinline__ float round_unbiased(double m, int64_t j) {
+  float lo = static_cast<float>(m);
+  if (static_cast<double>(lo) > m) lo = __uint_as_float(__float_as_uint(lo) - 1u);
+  const float hi = __uint_as_float(__float_as_uint(lo) + 1u);
+  const double t = (m - static_cast<double>(lo)) / (static_cast<double>(hi) - static_cast<double>(lo));
+  const double u = static_cast<double>(mix64(2 * static_cast<uint64_t>(j)) >> 11) * 0x1.0p-53;
+  return u < t ? hi : lo;
+}
+
+// The FP64-phase record of atom j (indices counted from the first atom of a plan, which
+// starts the plan's first group):
+//   a  = arg f in cycles (0 for f = 1 or f = 0) + offset (the variant's 1/2) + k/8,
+//   m  = |f| from FP64, rounded without bias (1 for f = 1),
+//   (ck, sk) = sgn exp(-2 i pi k/8) in FP32, sgn = -1 for the fract variant,
+// with k = 0..7 the turn of the atom's group g = j / grp, from mix64(2 g + 1).  The pack
+// kernel writes it to the workspace; the forward of small calls forms it while staging
+// its tile, so that both give the same record.
+__device__ __forceinline__ AtomPH make_atom_ph(const float* __restrict__ xyz,
+                                               const float* __restrict__ f, int64_t j,
+                                               double offset, int grp, float sgn) {
+  AtomPH r;
+  r.x = xyz[3 * j]; r.y = xyz[3 * j + 1]; r.z = xyz[3 * j + 2];       // exact widening
+  double alpha = 0.0;
+  r.m = 1.f;
+  if (f) {
+    const double fr = f[2 * j], fi = f[2 * j + 1];
+    if (fr != 0.0 || fi != 0.0) alpha = atan2(fi, fr) * 0.15915494309189533577;
+    r.m = round_unbiased(sqrt(fr * fr + fi * fi), j);
+  }
+  const uint64_t g = static_cast<uint64_t>(j / grp);
+  const int k = static_cast<int>(mix64(2 * g + 1) & 7u);
+  r.a = alpha + offset + 0.125 * k;
+  r.ck = sgn * static_cast<float>(cospi(0.25 * k));
+  r.sk = -sgn * static_cast<float>(sinpi(0.25 * k));
+  r.pad = 0.f;
+  return r;
+}
+
+// FP64-phase atom records, grid-stride over the n atoms of one plan.
+__global__ __launch_bounds__(kThreads) void pack_atoms_ph_kernel(const float* __restrict__ xyz,
+                                                                 const float* __restrict__ f,
+                                                                 int64_t n, AtomPH* __restrict__ rec,
+                                                                 double offset, int grp, float sgn) {
+  for (int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x; j < n;
+       j += int64_t(gridDim.x) * kThreads)
+    rec[j] = make_atom_ph(xyz, f, j, offset, grp, sgn);
+}
+
 template <int MODE> struct AtomOf;
 template <> struct AtomOf<kF32> { using type = AtomF32; };
 template <> struct AtomOf<kPH64> { using type = AtomPH; };
@@ -244,11 +306,17 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(
 // (At least 5 waves per SIMD: without the bound the compiler keeps whole groups of
 // records in flight, up to 130 VGPRs for two points per lane, and three waves per SIMD
 // then hide the LDS latency worse; with it the same loop takes 52.)
-template <int P, int FK, int GRP, int RED>
-__global__ __launch_bounds__(kThreads, 5) void fwd_lds_kernel(
+//
+// INL (small calls): no packed records; each thread forms its record of the tile from
+// xyz and f while staging it (make_atom_ph, as the pack kernel does), which saves the pack
+// dispatch when few work-groups share each record.  The FP64 arctangent of the record
+// needs more registers than 5 waves per SIMD leave, so this form is built for 4.
+template <int P, int FK, int GRP, int RED, bool INL>
+__global__ __launch_bounds__(kThreads, INL ? 4 : 5) void fwd_lds_kernel(
     const AtomPH* __restrict__ rec, int a_begin, int a_end, int per_split,
     const float* __restrict__ S, int64_t K, int blocks_k, float4* __restrict__ part,
-    float2* __restrict__ A, int carry_in, int direct) {
+    float2* __restrict__ A, int carry_in, int direct, const float* __restrict__ xyz,
+    const float* __restrict__ f) {
   static_assert(kThreads % GRP == 0, "tiles must hold whole groups");
   using AT = AtomPH;
   __shared__ AT tile[kThreads];
@@ -277,7 +345,13 @@ __global__ __launch_bounds__(kThreads, 5) void fwd_lds_kernel(
   for (int t0 = j0; t0 < j1; t0 += kThreads) {
     const int nt = min(kThreads, j1 - t0);
     __syncthreads();                        // the previous tile is no longer read
-    if (int(threadIdx.x) < nt) tile[threadIdx.x] = rec[t0 + threadIdx.x];
+    if (int(threadIdx.x) < nt) {
+      if constexpr (INL)      // f = 1 (FK == 0): no factor to take apart
+        tile[threadIdx.x] = make_atom_ph(xyz, FK ? f : nullptr, t0 + threadIdx.x, RED == 1 ? 0.5 : 0.0,
+                                         GRP, RED == 1 ? -1.f : 1.f);
+      else
+        tile[threadIdx.x] = rec[t0 + threadIdx.x];
+    }
     __syncthreads();
     int u0 = 0;
     for (; u0 + GRP <= nt; u0 += GRP) {
@@ -385,7 +459,7 @@ __global__ __launch_bounds__(kThreads) void fwd_f64_kernel(
 }
 
 // Combine the split partials of every point in a fixed order (deterministic): G lanes
-// of one wave serve one point (G a power of two up to 64, about the number of splits);
+// of one wave serve one point (G a power of two up to 64, about a quarter of the splits);
 // lane i folds splits i, i + G, i + 2G, ... in sequence with Knuth's two-sum, then the G
 // states are combined by a butterfly in which both partners fold the lower lane's state
 // first, so that every lane holds the same total and the order of the additions is a
@@ -400,6 +474,7 @@ __global__ __launch_bounds__(kThreads) void fwd_reduce_kernel(const float4* __re
   const int lane = static_cast<int>(t % G);
   float sr = 0.f, si = 0.f, cr = 0.f, ci = 0.f;
   if (k < K) {
+#pragma unroll 4
     for (int sp = lane; sp < nsplit; sp += G) {
       const float4 st = part[int64_t(sp) * K + k];
       two_sum_acc(sr, cr, st.x);
@@ -467,60 +542,6 @@ __global__ __launch_bounds__(kThreads) void pack_atoms_kernel(const void* __rest
   }
 }
 
-// SplitMix64's output function (Steele, Lea and Flood, OOPSLA 2014): 64 pseudo-random
-// bits of a 64-bit key.  The atoms' roundings use keys 2j, the groups' turns keys 2g + 1.
-__device__ __forceinline__ uint64_t mix64(uint64_t z) {
-  z += 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
-// m >= 0 to FP32 by unbiased (stochastic) rounding: the FP32 value above m with
-// probability equal to the fraction of the gap by which m exceeds the value below it,
-// drawn from the top 53 bits of mix64(2 j).  The expected result is m, so the rounding
-// errors of atoms with equal factors are independent and add up incoherently instead
-// of as one relative error of their species' amplitude.
-__device__ __forceinline__ float round_unbiased(double m, int64_t j) {
-  float lo = static_cast<float>(m);
-  if (static_cast<double>(lo) > m) lo = __uint_as_float(__float_as_uint(lo) - 1u);
-  const float hi = __uint_as_float(__float_as_uint(lo) + 1u);
-  const double t = (m - static_cast<double>(lo)) / (static_cast<double>(hi) - static_cast<double>(lo));
-  const double u = static_cast<double>(mix64(2 * static_cast<uint64_t>(j)) >> 11) * 0x1.0p-53;
-  return u < t ? hi : lo;
-}
-
-// FP64-phase atom records (grid-stride over the n atoms of one plan, indices counted from
-// the first of them, which starts the plan's first group):
-//   a  = arg f in cycles (0 for f = 1 or f = 0) + offset (the variant's 1/2) + k/8,
-//   m  = |f| from FP64, rounded without bias (1 for f = 1),
-//   (ck, sk) = sgn exp(-2 i pi k/8) in FP32, sgn = -1 for the fract variant,
-// with k = 0..7 the turn of the atom's group g = j / grp, from mix64(2 g + 1).
-__global__ __launch_bounds__(kThreads) void pack_atoms_ph_kernel(const float* __restrict__ xyz,
-                                                                 const float* __restrict__ f,
-                                                                 int64_t n, AtomPH* __restrict__ rec,
-                                                                 double offset, int grp, float sgn) {
-  for (int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x; j < n;
-       j += int64_t(gridDim.x) * kThreads) {
-    AtomPH r;
-    r.x = xyz[3 * j]; r.y = xyz[3 * j + 1]; r.z = xyz[3 * j + 2];       // exact widening
-    double alpha = 0.0;
-    r.m = 1.f;
-    if (f) {
-      const double fr = f[2 * j], fi = f[2 * j + 1];
-      if (fr != 0.0 || fi != 0.0) alpha = atan2(fi, fr) * 0.15915494309189533577;
-      r.m = round_unbiased(sqrt(fr * fr + fi * fi), j);
-    }
-    const uint64_t g = static_cast<uint64_t>(j / grp);
-    const int k = static_cast<int>(mix64(2 * g + 1) & 7u);
-    r.a = alpha + offset + 0.125 * k;
-    r.ck = sgn * static_cast<float>(cospi(0.25 * k));
-    r.sk = -sgn * static_cast<float>(sinpi(0.25 * k));
-    r.pad = 0.f;
-    rec[j] = r;
-  }
-}
-
 unsigned grid_for(int64_t n) {
   int64_t b = (n + kThreads - 1) / kThreads;
   if (b < 1) b = 1;
@@ -531,7 +552,8 @@ unsigned grid_for(int64_t n) {
 template <int MODE, int P, int FK>
 hipError_t fwd_dispatch_red(const Plan& p, const void* rec, int64_t a_begin, int64_t a_end,
                             int64_t per_split, const void* S, void* partial, void* A,
-                            int carry_in, int direct, hipStream_t st, int red) {
+                            int carry_in, int direct, hipStream_t st, int red, const float* xyz,
+                            const float* f) {
   using AT = typename AtomOf<MODE>::type;
   const dim3 grid(static_cast<unsigned>(p.blocks * p.nsplit));
   const auto* r = static_cast<const AT*>(rec);
@@ -545,18 +567,35 @@ hipError_t fwd_dispatch_red(const Plan& p, const void* rec, int64_t a_begin, int
   }
   if constexpr (MODE == kPH64) {
     if (p.lds && (p.grp == 16 || p.grp == 8)) {
+      if constexpr (P == 1) {
+        if (p.inl && red == 0) {          // records formed while staging (small calls)
+          if (p.grp == 16)
+            fwd_lds_kernel<1, FK, 16, 0, true><<<grid, kThreads, 0, st>>>(
+                nullptr, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a,
+                carry_in, direct, xyz, f);
+          else
+            fwd_lds_kernel<1, FK, 8, 0, true><<<grid, kThreads, 0, st>>>(
+                nullptr, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a,
+                carry_in, direct, xyz, f);
+          return hipGetLastError();
+        }
+      }
       if (p.grp == 16 && red == 0)
-        fwd_lds_kernel<P, FK, 16, 0><<<grid, kThreads, 0, st>>>(
-            r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct);
+        fwd_lds_kernel<P, FK, 16, 0, false><<<grid, kThreads, 0, st>>>(
+            r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct,
+            nullptr, nullptr);
       else if (p.grp == 16)
-        fwd_lds_kernel<P, FK, 16, 1><<<grid, kThreads, 0, st>>>(
-            r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct);
+        fwd_lds_kernel<P, FK, 16, 1, false><<<grid, kThreads, 0, st>>>(
+            r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct,
+            nullptr, nullptr);
       else if (red == 0)
-        fwd_lds_kernel<P, FK, 8, 0><<<grid, kThreads, 0, st>>>(
-            r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct);
+        fwd_lds_kernel<P, FK, 8, 0, false><<<grid, kThreads, 0, st>>>(
+            r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct,
+            nullptr, nullptr);
       else
-        fwd_lds_kernel<P, FK, 8, 1><<<grid, kThreads, 0, st>>>(
-            r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct);
+        fwd_lds_kernel<P, FK, 8, 1, false><<<grid, kThreads, 0, st>>>(
+            r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct,
+            nullptr, nullptr);
       return hipGetLastError();
     }
   }
@@ -584,22 +623,22 @@ hipError_t fwd_dispatch_red(const Plan& p, const void* rec, int64_t a_begin, int
 template <int MODE, int P>
 hipError_t fwd_dispatch_fk(const Plan& p, const void* rec, int64_t a_begin, int64_t a_end,
                            int64_t per_split, const void* S, void* partial, void* A,
-                           int carry_in, int direct, hipStream_t st) {
+                           int carry_in, int direct, hipStream_t st, const float* xyz, const float* f) {
   if (p.fk)
     return fwd_dispatch_red<MODE, P, 1>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in,
-                                        direct, st, p.red);
+                                        direct, st, p.red, xyz, f);
   return fwd_dispatch_red<MODE, P, 0>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in,
-                                      direct, st, p.red);
+                                      direct, st, p.red, xyz, f);
 }
 
 template <int MODE>
 hipError_t fwd_dispatch_p(const Plan& p, const void* rec, int64_t a_begin, int64_t a_end,
                           int64_t per_split, const void* S, void* partial, void* A, int carry_in,
-                          int direct, hipStream_t st) {
+                          int direct, hipStream_t st, const float* xyz, const float* f) {
   switch (p.per_lane) {
-    case 4: return fwd_dispatch_fk<MODE, 4>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st);
-    case 2: return fwd_dispatch_fk<MODE, 2>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st);
-    default: return fwd_dispatch_fk<MODE, 1>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st);
+    case 4: return fwd_dispatch_fk<MODE, 4>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st, xyz, f);
+    case 2: return fwd_dispatch_fk<MODE, 2>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st, xyz, f);
+    default: return fwd_dispatch_fk<MODE, 1>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st, xyz, f);
   }
 }
 
@@ -632,7 +671,7 @@ hipError_t launch_pack_atoms(int mode, int red, int grp, const void* xyz, const 
 
 hipError_t launch_fwd_chunk(const Plan& p, const void* rec, int64_t a_begin, int64_t a_end,
                             int64_t per_split, const void* S, void* partial, void* A,
-                            int carry_in, int direct, hipStream_t st) {
+                            int carry_in, int direct, hipStream_t st, const void* xyz, const void* f) {
   if (p.mode == kF64) {
     if (p.per_lane == 2)
       return p.fk ? fwd_f64_launch<2, 1>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st)
@@ -641,8 +680,10 @@ hipError_t launch_fwd_chunk(const Plan& p, const void* rec, int64_t a_begin, int
                 : fwd_f64_launch<1, 0>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st);
   }
   if (p.mode == kPH64)
-    return fwd_dispatch_p<kPH64>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st);
-  return fwd_dispatch_p<kF32>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st);
+    return fwd_dispatch_p<kPH64>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st,
+                                 static_cast<const float*>(xyz), static_cast<const float*>(f));
+  return fwd_dispatch_p<kF32>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st,
+                              nullptr, nullptr);
 }
 
 namespace {
@@ -668,6 +709,7 @@ hipError_t launch_fwd_reduce(const Plan& p, const void* partial, void* A, hipStr
     case 32: fwd_reduce_launch<32>(p, partial, A, st); break;
     case 16: fwd_reduce_launch<16>(p, partial, A, st); break;
     case 8: fwd_reduce_launch<8>(p, partial, A, st); break;
+    case 4: fwd_reduce_launch<4>(p, partial, A, st); break;
     default: fwd_reduce_launch<1>(p, partial, A, st); break;
   }
   return hipGetLastError();

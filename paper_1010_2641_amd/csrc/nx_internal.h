@@ -111,6 +111,7 @@ struct Plan {
   int red = 0;           // phase reduction variant of the FP64-phase kernels (0 centred, 1 fract)
   int gf = 0;            // adjoint also returns dL/df
   int lds = 0;           // FP64-phase sums: record tiles staged in LDS instead of scalar loads
+  int inl = 0;           // small calls: records formed in the sum kernel, no pack dispatch
   int64_t lanes = 0;     // number of lane items
   int64_t stream = 0;    // number of stream items
   int64_t blocks = 0;    // work-groups over lane items
@@ -134,6 +135,16 @@ constexpr int64_t kTargetBlocks = 32768;
 // much below a few hundred items lose more than the fuller chip gains (64 took a
 // 1e5-atom, 1e4-point forward from 2.5e12 to 1.7e12 pairs/s at 820 splits).
 constexpr int64_t kMinStreamPerSplit = 256;
+// Small problems: when slices of kMinStreamPerSplit leave fewer than kFillBlocks
+// work-groups (4 waves per SIMD on the 1024 SIMDs), slices down to kMinStreamPerSplitSmall
+// items are allowed until the grid reaches kFillBlocks: with one wave per SIMD the sums
+// cannot hide their latencies, and the extra partial states of a small problem cost little.
+constexpr int64_t kFillBlocks = 1024;
+constexpr int64_t kMinStreamPerSplitSmall = 32;
+// Small calls form their packed records inside the sum kernel (no pack dispatch) when the
+// records formed in all (each work-group of lane items forms the records of its slices,
+// so every record is formed `blocks` times) are at most this many.
+constexpr int64_t kInlineMaxRecords = int64_t(1) << 17;
 constexpr int64_t kMaxSplit = 1024;
 constexpr int64_t kLaunchPairs = int64_t(1) << 39;   // pairs per launch (well under 1 s)
 // Forward: when one split's slice of packed atom records exceeds an XCD's 4 MiB L2, the
@@ -142,19 +153,22 @@ constexpr int64_t kLaunchPairs = int64_t(1) << 39;   // pairs per launch (well u
 constexpr int64_t kL2SliceBytes = int64_t(2) << 20;
 constexpr int64_t kL2Bytes = int64_t(4) << 20;
 constexpr int kLossBlocks = 1024;             // fixed grid of the loss reduction
+constexpr int64_t kLossSmall = 16384;         // up to this many points: one work-group
 
 enum Op : int { kOpFwd = 0, kOpBwd = 1, kOpFwdF64 = 2, kOpBwdF64 = 3, kOpLoss = 4,
                 kOpBwdGf = 5, kOpBwdGfF64 = 6 };
 
 constexpr int kMaxSpecies = 16;   // species of the factorised entry points
 
-// Lanes that serve one output in the split reduction (a power of two, 1 to 64): about
-// the number of splits, so that each lane folds a few splits in sequence and the lanes'
-// states meet in a fixed butterfly; one lane per output (splits in sequence) below 8.
+// Lanes that serve one output in the split reduction (a power of two, 4 to 64): about a
+// quarter of the number of splits, so that each lane folds about four splits in sequence
+// and the lanes' states meet in a short fixed butterfly; one lane per output (splits in
+// sequence) below 8 splits.
 inline int reduce_lanes(int nsplit) {
   if (nsplit < 8) return 1;
-  int g = 8;
-  while (g < 64 && g < nsplit) g <<= 1;
+  const int want = (nsplit + 3) / 4;
+  int g = 4;
+  while (g < 64 && g < want) g <<= 1;
   return g;
 }
 
@@ -175,18 +189,22 @@ hipError_t launch_pack_atoms(int mode, int red, int grp, const void* xyz, const 
 hipError_t launch_pack_points(int mode, int red, const void* S, const void* G, int64_t k,
                               void* rec, hipStream_t st);
 
-// One forward chunk over points (lane items) for atoms [a_begin, a_end).
+// One forward chunk over points (lane items) for atoms [a_begin, a_end).  With p.inl the
+// kernel forms the records itself from xyz and f (rec is then unused).
 hipError_t launch_fwd_chunk(const Plan& p, const void* rec, int64_t a_begin, int64_t a_end,
                             int64_t per_split, const void* S, void* partial, void* A,
-                            int carry_in, int direct, hipStream_t st);
+                            int carry_in, int direct, hipStream_t st, const void* xyz = nullptr,
+                            const void* f = nullptr);
 // Combine split partials into A.
 hipError_t launch_fwd_reduce(const Plan& p, const void* partial, void* A, hipStream_t st);
 
 // One adjoint chunk over atoms (lane items) for points [k_begin, k_end); grad and
 // gradf (only with p.gf) receive the outputs of the last chunk when `direct`.
+// With p.inl the kernel forms the point records itself from S and G (rec is then unused).
 hipError_t launch_bwd_chunk(const Plan& p, const void* rec, int64_t k_begin, int64_t k_end,
                             int64_t per_split, const void* xyz, const void* f, void* partial,
-                            void* grad, void* gradf, int carry_in, int direct, hipStream_t st);
+                            void* grad, void* gradf, int carry_in, int direct, hipStream_t st,
+                            const void* S = nullptr, const void* G = nullptr);
 // f: the atom factors (complex f in the FP64-phase mode scales and rotates the sums).
 hipError_t launch_bwd_reduce(const Plan& p, const void* partial, const void* f, void* grad,
                              void* gradf, hipStream_t st);

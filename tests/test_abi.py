@@ -43,10 +43,11 @@ def test_micro_header_symbols_exported():
     assert micro.nxm_threads_per_block() == 256
     assert micro.nxm_pairs_per_lane_iter(0, 0) == 4 and micro.nxm_pairs_per_lane_iter(4, 0) == 8
     assert micro.nxm_pairs_per_lane_iter(0, 1) == 8 and micro.nxm_pairs_per_lane_iter(4, 1) == 16
-    assert micro.nxm_run(99, 0, 1, 1, FAKE, None) == -2
-    assert micro.nxm_run(0, 0, 0, 1, FAKE, None) == -1
-    assert micro.nxm_run(0, 0, 1, 1, None, None) == -1
-    assert micro.nxm_run(0, 2, 1, 1, FAKE, None) == -1
+    assert micro.nxm_pairs_per_lane_iter(8, 0) == 32 and micro.nxm_pairs_per_lane_iter(10, 1) == 64
+    assert micro.nxm_run(99, 0, 1, 1, FAKE, None, None) == -2
+    assert micro.nxm_run(0, 0, 0, 1, FAKE, None, None) == -1
+    assert micro.nxm_run(0, 0, 1, 1, None, None, None) == -1
+    assert micro.nxm_run(0, 2, 1, 1, FAKE, None, None) == -1
 
 
 def test_version():
@@ -262,11 +263,18 @@ def test_plan_stream_splits_for_the_target_block_count(monkeypatch):
 def test_plan_stream_slices_are_at_least_256_items(monkeypatch):
     """Splits stop at slices of 256 stream items: a 100,000-atom forward over 10,000 points
     (40 work-groups) would want ceil(32768 / 40) = 820 slices, and gets 100000 // 256 =
-    390, each with one (sum, comp) float4 per point; 1,000 atoms over 1,000 points get 3."""
+    390, each with one (sum, comp) float4 per point.  Only when such slices leave fewer
+    than 1,024 work-groups (4 waves per SIMD) may they shrink to 32 items: 1,000 atoms over
+    1,000 points (4 work-groups of points) get 1000 // 32 = 31 slices instead of 3, and the
+    4,096 x 4,096 block (16 work-groups) 64 slices of 64 atoms instead of 16."""
     monkeypatch.delenv("NX_TUNE_TARGET_BLOCKS", raising=False)
     rec = 100_000 * 48
     assert _lib.nx_workspace_bytes(100_000, 10_000, 1, _lib.NX_OP_FWD, 1) == rec + 390 * 10_000 * 16
     a256 = lambda b: -(-b // 256) * 256
-    assert _lib.nx_workspace_bytes(1000, 1000, 1, _lib.NX_OP_FWD, 1) == a256(1000 * 48) + a256(3 * 1000 * 16)
+    assert _lib.nx_workspace_bytes(1000, 1000, 1, _lib.NX_OP_FWD, 1) == a256(1000 * 48) + a256(31 * 1000 * 16)
     # the FP32 mode's 32-byte records, same slices
-    assert _lib.nx_workspace_bytes(1000, 1000, 0, _lib.NX_OP_FWD, 1) == a256(1000 * 32) + a256(3 * 1000 * 16)
+    assert _lib.nx_workspace_bytes(1000, 1000, 0, _lib.NX_OP_FWD, 1) == a256(1000 * 32) + a256(31 * 1000 * 16)
+    assert _lib.nx_workspace_bytes(4096, 4096, 1, _lib.NX_OP_FWD, 1) == a256(4096 * 48) + a256(64 * 4096 * 16)
+    # a small target keeps the small grid (the knob the launch-shape tests use)
+    monkeypatch.setenv("NX_TUNE_TARGET_BLOCKS", "12")
+    assert _lib.nx_workspace_bytes(1000, 1000, 1, _lib.NX_OP_FWD, 1) == a256(1000 * 48) + a256(3 * 1000 * 16)

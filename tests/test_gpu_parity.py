@@ -278,8 +278,10 @@ def test_bwd_bitwise_deterministic():
 
 # ----------------------------------------------------------------------------- misfit and seed
 
-@pytest.mark.parametrize("k", [0, 1, 255, 100_003])
+@pytest.mark.parametrize("k", [0, 1, 255, 16_384, 16_385, 100_003])
 def test_loss_grad(k):
+    """Up to 16,384 points the misfit runs in one work-group, above in a fixed grid and one
+    ordered final pass: both as the oracle forms e and G, L to FP64 rounding."""
     A, I = wl.random_amplitudes(k, seed=23 + k)
     L_ref, G_ref = oracle.loss(A, I)
     L, G = api.loss_grad(dev(A), dev(I))
@@ -408,6 +410,25 @@ def test_degenerate_inputs(mode):
     assert np.all(run_bwd(xyz, f, S, G0, mode) == 0)
     Gz = np.where(zero_rows, (rng.normal(size=k) + 1j * rng.normal(size=k)), 0).astype(np.complex64)
     assert np.all(run_bwd(xyz, f, S, Gz, mode) == 0)
+
+
+@pytest.mark.parametrize("n,k", [(4096, 4096), (1000, 1000), (300, 257), (2500, 777), (64, 6000)])
+@pytest.mark.parametrize("cplx", [True, False])
+def test_inline_records_bitwise(n, k, cplx, monkeypatch):
+    """Small calls form the packed records inside the sum kernels instead of a pack dispatch;
+    the records are the pack kernel's, so the forward and the adjoint are bitwise equal
+    with that form forced off and on, and both meet the oracle."""
+    xyz, f, S = wl.random_problem(n, k, seed=3 * n + k, extent=25.0, s_range=2.5, complex_f=cplx)
+    G = wl.random_seed_field(k, seed=n + 7)
+    out = {}
+    for inl in ("0", "1"):
+        monkeypatch.setenv("NX_TUNE_INLINE", inl)
+        out[inl] = (run_fwd(xyz, f, S, "ph64"), run_bwd(xyz, f, S, G, "ph64"))
+    assert np.array_equal(out["0"][0], out["1"][0])
+    assert np.array_equal(out["0"][1], out["1"][1])
+    check_fwd(out["1"][0], oracle.forward(xyz, f, S), "ph64", f"inline fwd n={n} k={k}", f=f, n=n)
+    en, em = M.t3(out["1"][1], oracle.adjoint(xyz, f, S, G))
+    assert en <= M.T3_NORM_TOL and em <= M.T3_MAX_TOL
 
 
 @pytest.mark.parametrize("n,k", [(3001, 5003), (517, 12345), (40000, 300), (300000, 2000)])
