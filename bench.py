@@ -282,7 +282,7 @@ def kernel_roofline(name, mode, fkind, pairs, t_fwd, t_bwd, ceilings):
     for dom, t in (("fwd", t_fwd), ("bwd", t_bwd)):
         slots = ALG_SLOTS[(mode, dom, fkind)]
         rate = pairs / t
-        ceil = ceilings.get((mode, dom, fkind)) if ceilings else None
+        ceil, ceil_ghz = ceilings.get((mode, dom, fkind), (None, None)) if ceilings else (None, None)
         sums[dom] = {
             "launch_ms": t * 1e3,
             "pairs_per_s": rate,
@@ -294,6 +294,7 @@ def kernel_roofline(name, mode, fkind, pairs, t_fwd, t_bwd, ceilings):
                 "achieved": slots * rate,
                 "ceiling": None if ceil is None else slots * ceil,
                 "ceiling_pairs_per_s": ceil,
+                "ceiling_clock_ghz": ceil_ghz,
                 "frac": None if ceil is None else rate / ceil,
                 "nominal": VALU_SLOTS_PER_S,
                 "frac_of_nominal": slots * rate / VALU_SLOTS_PER_S,
@@ -314,10 +315,23 @@ def kernel_roofline(name, mode, fkind, pairs, t_fwd, t_bwd, ceilings):
 
 
 def issue_ceilings(mode, fkind):
-    """Pairs per second of the forward's and the adjoint's instruction mixes on register
-    operands (libnx_micro), measured now on this GPU."""
+    """(pairs per second, clock in GHz under that load) of the forward's and the adjoint's
+    instruction mixes on register operands (libnx_micro), measured now on this GPU."""
     from paper_1010_2641_amd import micro
     return {(mode, dom, fkind): micro.mix_rate(mode, dom, fkind) for dom in ("fwd", "bwd")}
+
+
+def op_costs():
+    """Cycles per wave64 instruction of single instruction kinds issued alone (FP32 and FP64
+    fma in the three-operand form with a scalar operand and in the two-operand accumulating
+    form, v_sin_f32), from their measured rate and the clock the same kernels read."""
+    from paper_1010_2641_amd import micro
+    out = {}
+    for kind in ("fma_f32", "fmac_f32", "fma_f64", "fmac_f64", "sin_f32"):
+        rate, ghz = micro.op_rate(kind)
+        out[kind] = {"insts_per_s_per_simd": rate, "clock_ghz": ghz,
+                     "cycles_per_inst": None if ghz is None else ghz * 1e9 / rate}
+    return out
 
 
 def f64_path(api, tx, tf, tS, G, n, k, pairs, stream):
@@ -424,6 +438,26 @@ def measure(name, args, steps, warmup, ceilings, want_graph=False, want_species=
         graph = {"ms_per_step": tg * 1e3, "pairs_per_s": pairs / tg, "replays": reps,
                  "bitwise_equal_to_eager": bool(torch.equal(gA, out[1]) and torch.equal(gg, out[2]))}
         del cg, gA, gg
+        # each sum on its own, captured and replayed (the GPU time of one call without the
+        # host's launch overhead, which dominates eager calls of small problems)
+        G0 = out[3]
+        for dom, fn in (("fwd", lambda: api.scatter_fwd(tx, tf, tS, args.mode)),
+                        ("bwd", lambda: api.scatter_bwd(tx, tf, tS, G0, args.mode))):
+            with torch.cuda.stream(side):
+                fn()
+            stream.wait_stream(side)
+            torch.cuda.synchronize()
+            cs = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(cs):
+                fn()
+            cs.replay()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                cs.replay()
+            torch.cuda.synchronize()
+            graph[f"{dom}_pairs_per_s"] = pairs / ((time.perf_counter() - t0) / reps)
+            del cs
         progress(f"{name}: graph replays timed: {tg * 1e3:.3f} ms per step")
     t_fwd = sum(r[0].elapsed_time(r[1]) for r in recs) / steps / 1e3
     t_loss = sum(r[1].elapsed_time(r[2]) for r in recs) / steps / 1e3
@@ -518,12 +552,13 @@ def main():
 
     torch.cuda.set_device(torch.device("cuda:0"))
     fkind_of = {"c1": "unit", "c3": "unit", "c4": "unit", "cube41": "unit", "cube41s": "unit"}
-    ceilings = {}
+    ceilings, costs = {}, None
     if not args.no_micro:
         for fk in {fkind_of.get(args.workload, "complex"), "complex"}:
             ceilings.update(issue_ceilings(args.mode, fk))
+        costs = op_costs()
         progress("issue-ceiling microbenchmarks done: " + ", ".join(
-            f"{'/'.join(key)} {v:.3e} pairs/s" for key, v in sorted(ceilings.items())))
+            f"{'/'.join(key)} {v[0]:.3e} pairs/s" for key, v in sorted(ceilings.items())))
 
     head = measure(args.workload, args, args.steps, args.warmup, ceilings, want_graph=args.graph,
                    want_species=not args.no_species)
@@ -560,6 +595,7 @@ def main():
                 "graph_replay", "speedup_vs_f64_step", "max_rel_err", "roofline", "cpu_baseline"):
         res[key] = head.get(key)
     res["c5"] = c5
+    res["valu_cycles_per_wave64_inst"] = costs
     res["source_sha"] = source_hash()
     print(json.dumps(res), flush=True)
 

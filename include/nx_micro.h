@@ -35,12 +35,26 @@ typedef enum {
   NXM_FWD_F32_CF = 4,    /* forward, FP32: 3 fma, fract, cos, sin, 4 fma */
   NXM_FWD_F32_F1 = 5,    /* forward, FP32, f = 1: 3 fma, fract, cos, sin, 2 add */
   NXM_BWD_F32_CF = 6,    /* adjoint, FP32, complex f: 3 fma, fract, cos, sin, 6 (w, v), 3 fma */
-  NXM_BWD_F32_F1 = 7     /* adjoint, FP32, f = 1: 3 fma, fract, cos, sin, 2 (Im w), 3 fma */
+  NXM_BWD_F32_F1 = 7,    /* adjoint, FP32, f = 1: 3 fma, fract, cos, sin, 2 (Im w), 3 fma */
+  NXM_OP_FMA_F32 = 8,    /* one instruction kind alone: FP32 fma, a scalar operand (v_fma_f32) */
+  NXM_OP_FMA_F64 = 9,    /*   FP64 fma, a scalar operand (v_fma_f64) */
+  NXM_OP_SIN_F32 = 10,   /*   v_sin_f32 */
+  NXM_OP_FMAC_F32 = 11,  /*   FP32 fma into its destination, vector operands (v_fmac_f32_e32) */
+  NXM_OP_FMAC_F64 = 12   /*   FP64 fma into its destination, vector operands (v_fmac_f64_e32) */
 } nxm_mix;
 
+/* Work items per lane and iteration: atom-point pairs for the mixes, instructions for the
+ * single-instruction kinds. */
 int nxm_pairs_per_lane_iter(int mix, int wide);
 int nxm_threads_per_block(void);
-int nxm_run(int mix, int wide, int n_blocks, int iters, float* out, void* stream);
+/* Rate of the real-time counter the kernels read (kHz), or -4. */
+int nxm_wallclock_khz(void);
+/* `clk`: DEVICE array of 2 * n_blocks counters or NULL; thread 0 of work-group b stores the
+ * shader-clock cycles (s_memtime) and real-time ticks (s_memrealtime) between its start and
+ * its end in clk[2 b] and clk[2 b + 1], so that cycles / ticks * nxm_wallclock_khz() is the
+ * clock under this load. */
+int nxm_run(int mix, int wide, int n_blocks, int iters, float* out, unsigned long long* clk,
+            void* stream);
 
 #ifdef __cplusplus
 }

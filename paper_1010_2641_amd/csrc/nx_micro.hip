@@ -47,10 +47,33 @@ __device__ __forceinline__ void opaque(T& v) {
   asm volatile("" : "+v"(v));
 }
 
+// The clock under load: thread 0 of every work-group reads the shader-clock counter
+// (s_memtime) and the constant-rate real-time counter (s_memrealtime) when it starts and
+// when it ends, and stores the two differences (vector stores) in clk[2 b], clk[2 b + 1].
+struct ClockMark {
+  uint64_t t0 = 0, r0 = 0;
+  __device__ __forceinline__ void start() {
+    if (threadIdx.x == 0) {
+      t0 = __builtin_amdgcn_s_memtime();
+      r0 = __builtin_amdgcn_s_memrealtime();
+    }
+  }
+  __device__ __forceinline__ void stop(unsigned long long* clk) {
+    if (clk && threadIdx.x == 0) {
+      const uint64_t t1 = __builtin_amdgcn_s_memtime();
+      const uint64_t r1 = __builtin_amdgcn_s_memrealtime();
+      clk[2 * blockIdx.x] = t1 - t0;
+      clk[2 * blockIdx.x + 1] = r1 - r0;
+    }
+  }
+};
+
 // FP64-phase forward: psi = 3 FP64 fma; centred reduction (rint, subtract, cvt);
 // cos, sin; m (c + i s) with 2 FP32 fma (complex f) or 2 adds (f = 1).
 template <bool CF, int kPairs, int OCC>
-__global__ __launch_bounds__(kThreads, OCC) void mix_fwd_ph64(int iters, float* out) {
+__global__ __launch_bounds__(kThreads, OCC) void mix_fwd_ph64(int iters, float* out, unsigned long long* clk) {
+  ClockMark cm;
+  cm.start();
   const double lane = static_cast<double>(threadIdx.x + blockIdx.x * kThreads);
   double sx[kPairs], sy[kPairs], sz[kPairs], a0[kPairs];
   float ar[kPairs], ai[kPairs];
@@ -91,12 +114,15 @@ __global__ __launch_bounds__(kThreads, OCC) void mix_fwd_ph64(int iters, float* 
 #pragma unroll
   for (int p = 0; p < kPairs; ++p) acc += ar[p] - ai[p];
   out[threadIdx.x + blockIdx.x * kThreads] = acc;
+  cm.stop(clk);
 }
 
 // FP64-phase adjoint: psi = 3 FP64 fma (+ 1 FP64 add of the atom's angle for complex f);
 // fract, cvt; sin; T_d += (|G| S_d) sin with 3 FP32 fma.
 template <bool CF, int kPairs, int OCC>
-__global__ __launch_bounds__(kThreads, OCC) void mix_bwd_ph64(int iters, float* out) {
+__global__ __launch_bounds__(kThreads, OCC) void mix_bwd_ph64(int iters, float* out, unsigned long long* clk) {
+  ClockMark cm;
+  cm.start();
   const double lane = static_cast<double>(threadIdx.x + blockIdx.x * kThreads);
   double x[kPairs], y[kPairs], z[kPairs], d0[kPairs], al[kPairs];
   float t0[kPairs], t1[kPairs], t2[kPairs];
@@ -135,12 +161,15 @@ __global__ __launch_bounds__(kThreads, OCC) void mix_bwd_ph64(int iters, float* 
 #pragma unroll
   for (int p = 0; p < kPairs; ++p) acc += t0[p] - t1[p] + t2[p];
   out[threadIdx.x + blockIdx.x * kThreads] = acc;
+  cm.stop(clk);
 }
 
 // The paper's FP32 arithmetic.  Forward: 3 FP32 fma, fract, cos, sin, then f (c + i s)
 // with 4 fma (complex f) or 2 adds (f = 1).
 template <bool CF, int kPairs, int OCC>
-__global__ __launch_bounds__(kThreads, OCC) void mix_fwd_f32(int iters, float* out) {
+__global__ __launch_bounds__(kThreads, OCC) void mix_fwd_f32(int iters, float* out, unsigned long long* clk) {
+  ClockMark cm;
+  cm.start();
   const float lane = static_cast<float>(threadIdx.x + blockIdx.x * kThreads);
   float sx[kPairs], sy[kPairs], sz[kPairs], ar[kPairs], ai[kPairs];
 #pragma unroll
@@ -178,12 +207,15 @@ __global__ __launch_bounds__(kThreads, OCC) void mix_fwd_f32(int iters, float* o
 #pragma unroll
   for (int p = 0; p < kPairs; ++p) acc += ar[p] - ai[p];
   out[threadIdx.x + blockIdx.x * kThreads] = acc;
+  cm.stop(clk);
 }
 
 // The paper's FP32 arithmetic, adjoint: 3 fma, fract, cos, sin; Im w = gr s - gi c (2),
 // Re w (2) and v = fr Im w + fi Re w (2) for complex f; T_d += S_d v (3).
 template <bool CF, int kPairs, int OCC>
-__global__ __launch_bounds__(kThreads, OCC) void mix_bwd_f32(int iters, float* out) {
+__global__ __launch_bounds__(kThreads, OCC) void mix_bwd_f32(int iters, float* out, unsigned long long* clk) {
+  ClockMark cm;
+  cm.start();
   const float lane = static_cast<float>(threadIdx.x + blockIdx.x * kThreads);
   float x[kPairs], y[kPairs], z[kPairs], fr[kPairs], fi[kPairs], t0[kPairs], t1[kPairs], t2[kPairs];
 #pragma unroll
@@ -225,6 +257,53 @@ __global__ __launch_bounds__(kThreads, OCC) void mix_bwd_f32(int iters, float* o
 #pragma unroll
   for (int p = 0; p < kPairs; ++p) acc += t0[p] - t1[p] + t2[p];
   out[threadIdx.x + blockIdx.x * kThreads] = acc;
+  cm.stop(clk);
+}
+
+// Single-instruction rates: NP independent chains per lane of one instruction kind, 4 steps
+// of each chain per iteration, for the cost of each kind per wave64 instruction: OP 0 FP32
+// fma with a scalar operand (the three-operand encoding, v_fma_f32), 1 FP64 fma likewise,
+// 2 v_sin_f32 on a turn in [-1/2, 1/2], 3 and 4 FP32 and FP64 fma accumulating into their
+// destination with vector operands only (the two-operand encodings v_fmac_f32_e32,
+// v_fmac_f64_e32, which the sums' inner loops mostly use).
+template <int OP, int NP>
+__global__ __launch_bounds__(kThreads, 8) void op_rate(int iters, float* out, unsigned long long* clk) {
+  ClockMark cm;
+  cm.start();
+  const float lane = static_cast<float>(threadIdx.x + blockIdx.x * kThreads);
+  float v[NP];
+  double w[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    v[i] = 1e-3f * lane + 0.01f * i;
+    w[i] = 1e-3 * lane + 0.01 * i;
+  }
+  float bv = 1.0f - 1e-9f * lane, cv = 1e-7f;
+  double bw = 1.0 - 1e-12 * lane, cw = 1e-7;
+  opaque(bv);
+  opaque(cv);
+  opaque(bw);
+  opaque(cw);
+  for (int j = 0; j < iters; ++j) {
+    const float a = uniform_f32(0x3f800000u, j & 7);      // ~1, changes with j (scalar ops)
+    const double ad = uniform_f64(0x3ff00000u, 0x00000001u, j & 7);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        if constexpr (OP == 0) v[i] = __builtin_fmaf(v[i], a, 1e-7f);
+        else if constexpr (OP == 1) w[i] = __builtin_fma(w[i], ad, 1e-7);
+        else if constexpr (OP == 2) v[i] = __builtin_amdgcn_sinf(v[i]);
+        else if constexpr (OP == 3) v[i] = __builtin_fmaf(bv, cv, v[i]);
+        else w[i] = __builtin_fma(bw, cw, w[i]);
+      }
+    }
+  }
+  float acc = 0.f;
+#pragma unroll
+  for (int i = 0; i < NP; ++i) acc += v[i] + static_cast<float>(w[i]);
+  out[threadIdx.x + blockIdx.x * kThreads] = acc;
+  cm.stop(clk);
 }
 
 }  // namespace
@@ -232,20 +311,34 @@ __global__ __launch_bounds__(kThreads, OCC) void mix_bwd_f32(int iters, float* o
 extern "C" {
 
 int nxm_pairs_per_lane_iter(int mix, int wide) {
+  if (mix >= NXM_OP_FMA_F32 && mix <= NXM_OP_FMAC_F64) return 4 * (wide ? 16 : 8);
   const int np = (mix >= NXM_FWD_PH64_CF && mix <= NXM_BWD_PH64_F1) ? kPairs64 : kPairs32;
   return wide ? 2 * np : np;
 }
 
 int nxm_threads_per_block(void) { return kThreads; }
 
-int nxm_run(int mix, int wide, int n_blocks, int iters, float* out, void* stream) {
+int nxm_wallclock_khz(void) {
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -4;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return -4;
+  return khz;
+}
+
+int nxm_run(int mix, int wide, int n_blocks, int iters, float* out, unsigned long long* clk,
+            void* stream) {
   if (n_blocks < 1 || iters < 1 || !out || (wide != 0 && wide != 1)) return -1;
   const hipStream_t st = static_cast<hipStream_t>(stream);
   const dim3 grid(static_cast<unsigned>(n_blocks));
 #define NXM_CASE(ID, KERNEL, CF, NP)                                                        \
   case ID:                                                                                  \
-    if (wide) KERNEL<CF, 2 * NP, 4><<<grid, kThreads, 0, st>>>(iters, out);                 \
-    else KERNEL<CF, NP, 8><<<grid, kThreads, 0, st>>>(iters, out);                          \
+    if (wide) KERNEL<CF, 2 * NP, 4><<<grid, kThreads, 0, st>>>(iters, out, clk);            \
+    else KERNEL<CF, NP, 8><<<grid, kThreads, 0, st>>>(iters, out, clk);                     \
+    break;
+#define NXM_OP(ID, OP)                                                                      \
+  case ID:                                                                                  \
+    if (wide) op_rate<OP, 16><<<grid, kThreads, 0, st>>>(iters, out, clk);                  \
+    else op_rate<OP, 8><<<grid, kThreads, 0, st>>>(iters, out, clk);                        \
     break;
   switch (mix) {
     NXM_CASE(NXM_FWD_PH64_CF, mix_fwd_ph64, true, kPairs64)
@@ -256,9 +349,15 @@ int nxm_run(int mix, int wide, int n_blocks, int iters, float* out, void* stream
     NXM_CASE(NXM_FWD_F32_F1, mix_fwd_f32, false, kPairs32)
     NXM_CASE(NXM_BWD_F32_CF, mix_bwd_f32, true, kPairs32)
     NXM_CASE(NXM_BWD_F32_F1, mix_bwd_f32, false, kPairs32)
+    NXM_OP(NXM_OP_FMA_F32, 0)
+    NXM_OP(NXM_OP_FMA_F64, 1)
+    NXM_OP(NXM_OP_SIN_F32, 2)
+    NXM_OP(NXM_OP_FMAC_F32, 3)
+    NXM_OP(NXM_OP_FMAC_F64, 4)
     default: return -2;
   }
 #undef NXM_CASE
+#undef NXM_OP
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 

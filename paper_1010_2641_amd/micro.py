@@ -14,6 +14,9 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnx_micro.so")
 
+# single instruction kinds of include/nx_micro.h
+OPS = {"fma_f32": 8, "fma_f64": 9, "sin_f32": 10, "fmac_f32": 11, "fmac_f64": 12}
+
 # (mode, sum, factor kind) -> mix id of include/nx_micro.h
 MIXES = {
     ("ph64", "fwd", "complex"): 0, ("ph64", "fwd", "unit"): 1,
@@ -25,8 +28,9 @@ MIXES = {
 SIGNATURES = {
     "nxm_pairs_per_lane_iter": ([ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "nxm_threads_per_block": ([], ctypes.c_int),
-    "nxm_run": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p],
-                ctypes.c_int),
+    "nxm_wallclock_khz": ([], ctypes.c_int),
+    "nxm_run": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                 ctypes.c_void_p], ctypes.c_int),
 }
 
 
@@ -46,31 +50,48 @@ lib = _load()
 
 nxm_pairs_per_lane_iter = lib.nxm_pairs_per_lane_iter
 nxm_threads_per_block = lib.nxm_threads_per_block
+nxm_wallclock_khz = lib.nxm_wallclock_khz
 nxm_run = lib.nxm_run
 
 
-def mix_rate(mode: str, op: str, fkind: str, n_blocks: int = 8192, iters: int = 2048,
-             reps: int = 3) -> float:
-    """Pairs per second of the (mode, op, fkind) instruction mix: the best of `reps` timed
-    launches of each of the two kernel shapes after one warm-up each, timed with events on
-    the current stream."""
+def _rate(mix: int, n_blocks: int, iters: int, reps: int):
+    """(best items per second over the two kernel shapes, clock in GHz of that launch):
+    `reps` timed launches of each shape after one warm-up, events on the current stream."""
     import torch
-    mix = MIXES[(mode, op, fkind)]
     threads = nxm_threads_per_block()
     out = torch.empty(n_blocks * threads, dtype=torch.float32, device="cuda")
+    clk = torch.zeros(2 * n_blocks, dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
-    best = 0.0
+    khz = nxm_wallclock_khz()
+    best, ghz = 0.0, None
     for wide in (0, 1):
         it = iters if not wide else iters // 2
-        pairs = float(n_blocks) * threads * it * nxm_pairs_per_lane_iter(mix, wide)
+        items = float(n_blocks) * threads * it * nxm_pairs_per_lane_iter(mix, wide)
         for r in range(reps + 1):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            rc = nxm_run(mix, wide, n_blocks, it, out.data_ptr(), stream.cuda_stream)
+            rc = nxm_run(mix, wide, n_blocks, it, out.data_ptr(), clk.data_ptr(), stream.cuda_stream)
             e1.record(stream)
             if rc != 0:
                 raise RuntimeError(f"nxm_run({mix}, {wide}) returned {rc}")
             e1.synchronize()
-            if r > 0:
-                best = max(best, pairs / (e0.elapsed_time(e1) / 1e3))
-    return best
+            rate = items / (e0.elapsed_time(e1) / 1e3)
+            if r > 0 and rate > best:
+                best = rate
+                c = clk.view(-1, 2).double().sum(0)
+                ghz = float(c[0] / c[1]) * khz / 1e6 if khz > 0 and c[1] > 0 else None
+    return best, ghz
+
+
+def mix_rate(mode: str, op: str, fkind: str, n_blocks: int = 8192, iters: int = 2048,
+             reps: int = 3):
+    """(pairs per second, clock in GHz) of the (mode, op, fkind) instruction mix: the
+    issue ceiling of that mix, the better of the two kernel shapes."""
+    return _rate(MIXES[(mode, op, fkind)], n_blocks, iters, reps)
+
+
+def op_rate(kind: str, n_blocks: int = 8192, iters: int = 1024, reps: int = 3):
+    """(wave64 instructions per second per SIMD, clock in GHz) of one instruction kind
+    (see OPS) issued alone; cycles per instruction = clock / that rate."""
+    rate, ghz = _rate(OPS[kind], n_blocks, iters, reps)
+    return rate / 64.0 / (256 * 4), ghz

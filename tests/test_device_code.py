@@ -78,8 +78,8 @@ def test_no_scratch_spills(device_asm):
 
 def test_hot_kernels_at_eight_waves(device_asm):
     occ = {name: o for asm in device_asm.values() for name, _, o in kernel_notes(asm)}
-    want = {"fwd_lds_kernelILi1ELi1ELi16ELi0E": 8,          # forward, complex f, 16-atom groups
-            "fwd_lds_kernelILi1ELi0ELi16ELi0E": 8,          # forward, f = 1
+    want = {"fwd_lds_kernelILi1ELi1ELi16ELi0ELb0E": 8,      # forward, complex f, 16-atom groups
+            "fwd_lds_kernelILi1ELi0ELi16ELi0ELb0E": 8,      # forward, f = 1
             "bwd_split_kernelILi2ELi1ELi64ELi1ELb0E": 8,    # adjoint, complex f
             "bwd_split_kernelILi2ELi0ELi64ELi1ELb0E": 8}    # adjoint, f = 1
     for key, o in want.items():
@@ -136,3 +136,16 @@ def test_micro_loops_are_the_priced_instruction_mixes(device_asm):
                            for k in c), (name, dict(c))
             seen += 1
     assert seen == 16
+    # the single-instruction kernels: 4 steps of NP chains of one kind per iteration
+    kinds = {"0": "v_fma_f32", "1": "v_fma", "2": "v_sin_f32", "3": "v_fmac_f32_e32", "4": "v_fmac_f64_e32"}
+    ops = 0
+    for name, c in loops.items():
+        m = re.search(r"op_rateILi(\d)ELi(\d+)E", name)
+        if not m:
+            continue
+        valu = sum(v for k, v in c.items() if k.startswith("v_"))
+        want = 4 * int(m.group(2))
+        kind = sum(v for k, v in c.items() if k.startswith(kinds[m.group(1)]))
+        assert valu == want and kind == want, (name, dict(c))
+        ops += 1
+    assert ops == 10
