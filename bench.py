@@ -135,6 +135,10 @@ def parse():
     p.add_argument("--no-c5", action="store_true",
                    help="skip the one-step measurement of the largest configuration (c5) that "
                         "the headline line carries beside the default workload")
+    p.add_argument("--staged", action="store_true",
+                   help="time the steps as three calls (forward, misfit, adjoint) instead of one "
+                        "nx_fit_step call (for one long step: the three calls also give the sums' "
+                        "own times, so the step is not run twice)")
     p.add_argument("--no-micro", action="store_true",
                    help="skip the issue-ceiling microbenchmarks (the valu_issue fields)")
     p.add_argument("--copy-cal", type=int, default=0, metavar="BYTES",
@@ -300,6 +304,15 @@ def kernel_roofline(name, mode, fkind, pairs, t_fwd, t_bwd, ceilings):
                 "frac_of_nominal": slots * rate / VALU_SLOTS_PER_S,
             },
         }
+    for dom in ("fwd", "bwd"):
+        # per cycle: the sum's clock under load from its committed counters (GRBM_GUI_ACTIVE
+        # over the kernel time), the ceiling's from the microbenchmark's own clock reading
+        _, v = saved_counters(name, dom, mode)
+        vi = sums[dom]["valu_issue"]
+        vi["kernel_clock_ghz"] = v.get("clock_ghz") if v else None
+        vi["frac_per_cycle"] = (vi["frac"] * vi["ceiling_clock_ghz"] / vi["kernel_clock_ghz"]
+                                if vi["frac"] and vi["ceiling_clock_ghz"] and vi["kernel_clock_ghz"]
+                                else None)
     dom = "bwd" if t_bwd >= t_fwd else "fwd"
     d = sums[dom]
     traffic, valu = saved_counters(name, dom, mode)
@@ -361,9 +374,11 @@ def f64_path(api, tx, tf, tS, G, n, k, pairs, stream):
 
 
 def measure(name, args, steps, warmup, ceilings, want_graph=False, want_species=True,
-            cpu_seconds=None):
+            cpu_seconds=None, staged_only=False):
     """Times `steps` fit steps of workload `name` after `warmup` untimed ones and returns
-    the measured fields (rates, roofline, FP64 path, species path, oracle baseline)."""
+    the measured fields (rates, roofline, FP64 path, species path, oracle baseline).  The
+    timed steps are one library call each (nx_fit_step); the same steps as three calls
+    with events between them give the forward's and the adjoint's own times."""
     import numpy as np
     import torch
 
@@ -384,18 +399,20 @@ def measure(name, args, steps, warmup, ceilings, want_graph=False, want_species=
     stream = torch.cuda.current_stream(dev)      # every libnx launch goes to this stream
     ev = lambda: torch.cuda.Event(enable_timing=True)
 
-    def step(rec=None):
-        if rec is not None:
-            rec[0].record(stream)
+    def step():
+        """The whole step, queued by one call into the library (nx_fit_step)."""
+        L, A, g, G = api.fit_step(tx, tf, tS, I, args.mode, return_seed=True)
+        return L, A, g, G
+
+    def staged(rec):
+        """The same step as three calls with events between them: the time of each sum."""
+        rec[0].record(stream)
         A = api.scatter_fwd(tx, tf, tS, args.mode)
-        if rec is not None:
-            rec[1].record(stream)
+        rec[1].record(stream)
         L, G = api.loss_grad(A, I)
-        if rec is not None:
-            rec[2].record(stream)
+        rec[2].record(stream)
         g = api.scatter_bwd(tx, tf, tS, G, args.mode)
-        if rec is not None:
-            rec[3].record(stream)
+        rec[3].record(stream)
         return L, A, g, G
 
     for _ in range(warmup):
@@ -403,14 +420,36 @@ def measure(name, args, steps, warmup, ceilings, want_graph=False, want_species=
     torch.cuda.synchronize()
     progress(f"{name}: {warmup} warm-up steps done")
 
-    recs = [[ev() for _ in range(4)] for _ in range(steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(steps):
-        out = step(recs[i])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    progress(f"{name}: {steps} timed steps done, {wall / steps * 1e3:.1f} ms per step")
+    if staged_only:
+        # long steps (seconds): the timed steps are the three calls themselves, which also
+        # give the sums' own times (the host's launch overhead is nothing against them)
+        recs = [[ev() for _ in range(4)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            out = staged(recs[i])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        n_staged = steps
+        progress(f"{name}: {steps} timed steps done (three calls), {wall / steps * 1e3:.1f} ms per step")
+    else:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            out = step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        progress(f"{name}: {steps} timed steps done, {wall / steps * 1e3:.1f} ms per step")
+        # the sums' own times: the step again as three calls, events on the launch stream
+        n_staged = steps
+        recs = [[ev() for _ in range(4)] for _ in range(n_staged)]
+        for i in range(n_staged):
+            staged_out = staged(recs[i])
+        torch.cuda.synchronize()
+        assert torch.equal(staged_out[1], out[1]) and torch.equal(staged_out[2], out[2]), \
+            "the one-call step and the three calls must agree bitwise"
+        del staged_out
+        progress(f"{name}: {n_staged} staged steps timed")
 
     # the same step captured once in a HIP graph (the library issues kernels only: no
     # allocation, copy, memset or synchronisation), replayed for at least the timed steps
@@ -459,14 +498,14 @@ def measure(name, args, steps, warmup, ceilings, want_graph=False, want_species=
             graph[f"{dom}_pairs_per_s"] = pairs / ((time.perf_counter() - t0) / reps)
             del cs
         progress(f"{name}: graph replays timed: {tg * 1e3:.3f} ms per step")
-    t_fwd = sum(r[0].elapsed_time(r[1]) for r in recs) / steps / 1e3
-    t_loss = sum(r[1].elapsed_time(r[2]) for r in recs) / steps / 1e3
-    t_bwd = sum(r[2].elapsed_time(r[3]) for r in recs) / steps / 1e3
+    t_fwd = sum(r[0].elapsed_time(r[1]) for r in recs) / len(recs) / 1e3
+    t_loss = sum(r[1].elapsed_time(r[2]) for r in recs) / len(recs) / 1e3
+    t_bwd = sum(r[2].elapsed_time(r[3]) for r in recs) / len(recs) / 1e3
     res = {
         "config": {"workload": WORKLOADS[name], "n_atoms": n, "n_points": k, "pairs_per_step": pairs,
                    "precision": {"ph64": "FP64 phase reduction, FP32 sin/cos, compensated FP32 sums",
                                  "f32": "plain FP32 (the paper's arithmetic)"}[args.mode]},
-        "steps": steps, "warmup": warmup,
+        "steps": steps, "warmup": warmup, "staged_steps": n_staged,
         "ms_per_step": wall / steps * 1e3,
         "value": pairs / (wall / steps),
         "fwd_pairs_per_s": pairs / t_fwd,
@@ -561,13 +600,13 @@ def main():
             f"{'/'.join(key)} {v[0]:.3e} pairs/s" for key, v in sorted(ceilings.items())))
 
     head = measure(args.workload, args, args.steps, args.warmup, ceilings, want_graph=args.graph,
-                   want_species=not args.no_species)
+                   want_species=not args.no_species, staged_only=args.staged)
     c5 = None
     if args.workload == "c2" and not args.no_c5:
         # the largest configuration, one timed step (its 39 s per step would take the
         # requested timed steps past the run's time limit)
         c5 = measure("c5", args, 1, 0, ceilings, want_species=False,
-                     cpu_seconds=2 * args.cpu_seconds)
+                     cpu_seconds=2 * args.cpu_seconds, staged_only=True)
         progress("c5 leg done")
 
     config = dict(head["config"])

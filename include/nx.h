@@ -89,7 +89,8 @@ typedef enum {
   NX_OP_BWD_F64 = 3,      /* nx_scatter_bwd_f64                              */
   NX_OP_LOSS = 4,         /* nx_loss_grad                                    */
   NX_OP_BWD_GF = 5,       /* nx_scatter_bwd_ex with grad_f                   */
-  NX_OP_BWD_GF_F64 = 6    /* nx_scatter_bwd_ex_f64 with grad_f               */
+  NX_OP_BWD_GF_F64 = 6,   /* nx_scatter_bwd_ex_f64 with grad_f               */
+  NX_OP_FIT = 7           /* nx_fit_step                                     */
 } nx_op;
 
 /* Most species accepted by the species-factorised entry points. */
@@ -176,6 +177,21 @@ int nx_scatter_bwd_f64(const double* xyz, const double* f, int64_t n_atoms,
  *   (may be NULL when only L is wanted).  n_points == 0 writes L = 0. */
 int nx_loss_grad(const float* A, const float* I, int64_t n_points, double* L, float* G,
                  void* ws, size_t ws_bytes, void* stream);
+
+/* One fitting step, queued by one call: the forward sum (Eq. 2), the intensity misfit
+ * and its seed (as nx_loss_grad), then the adjoint with respect to the positions (the
+ * chain rule through Eq. 2, as nx_scatter_bwd), on `stream`, in that order:
+ *     A = nx_scatter_fwd(xyz, f, S);  (L, G) = misfit(A, I);  grad_xyz = adjoint(G).
+ * The results are those of the three calls made one after the other (bitwise).  The one
+ * workspace serves the three stages in turn: nx_workspace_bytes(..., NX_OP_FIT, ...) is the
+ * largest of the three needs.  It exists for callers whose steps are short enough that
+ * three calls cost more host time than the GPU work (a few thousand atoms and points).
+ *   I float[n_points]; A float[n_points*2], L double[1], G float[n_points*2],
+ *   grad_xyz float[n_atoms*3]: outputs (device), overwritten.  Errors as for the three
+ *   calls; nothing is queued when the arguments are invalid. */
+int nx_fit_step(const float* xyz, const float* f, int64_t n_atoms, const float* S,
+                int64_t n_points, const float* I, float* A, double* L, float* G,
+                float* grad_xyz, int mode, void* ws, size_t ws_bytes, void* stream);
 
 /* Adjoint with the gradient with respect to the factors as well (for fitting
  * occupancies or compositions):

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libnx.so")
 NX_OK, NX_ERR_ARG, NX_ERR_MODE, NX_ERR_WORKSPACE, NX_ERR_DEVICE = 0, -1, -2, -3, -4
 NX_F32, NX_F32_PH64 = 0, 1
 NX_OP_FWD, NX_OP_BWD, NX_OP_FWD_F64, NX_OP_BWD_F64, NX_OP_LOSS = 0, 1, 2, 3, 4
-NX_OP_BWD_GF, NX_OP_BWD_GF_F64 = 5, 6
+NX_OP_BWD_GF, NX_OP_BWD_GF_F64, NX_OP_FIT = 5, 6, 7
 NX_MAX_COUNT = 1 << 30
 NX_MAX_SPECIES = 16
 NX_NOALLOC_SCRATCH_BYTES = 128 << 20
@@ -30,6 +30,7 @@ SIGNATURES = {
     "nx_scatter_fwd_f64": ([_VP, _VP, _I64, _VP, _I64, _VP, _VP, _SZ, _VP], _I),
     "nx_scatter_bwd_f64": ([_VP, _VP, _I64, _VP, _I64, _VP, _VP, _VP, _SZ, _VP], _I),
     "nx_loss_grad": ([_VP, _VP, _I64, _VP, _VP, _VP, _SZ, _VP], _I),
+    "nx_fit_step": ([_VP, _VP, _I64, _VP, _I64, _VP, _VP, _VP, _VP, _VP, _I, _VP, _SZ, _VP], _I),
     "nx_scatter_bwd_ex": ([_VP, _VP, _I64, _VP, _I64, _VP, _VP, _VP, _I, _VP, _SZ, _VP], _I),
     "nx_scatter_bwd_ex_f64": ([_VP, _VP, _I64, _VP, _I64, _VP, _VP, _VP, _VP, _SZ, _VP], _I),
     "nx_scatter_fwd_species": ([_VP, _I64, _VP, _I, _VP, _VP, _I64, _VP, _VP, _I, _VP, _SZ, _VP], _I),
@@ -96,6 +97,7 @@ nx_scatter_bwd = lib.nx_scatter_bwd
 nx_scatter_fwd_f64 = lib.nx_scatter_fwd_f64
 nx_scatter_bwd_f64 = lib.nx_scatter_bwd_f64
 nx_loss_grad = lib.nx_loss_grad
+nx_fit_step = lib.nx_fit_step
 nx_scatter_bwd_ex = lib.nx_scatter_bwd_ex
 nx_scatter_bwd_ex_f64 = lib.nx_scatter_bwd_ex_f64
 nx_scatter_fwd_species = lib.nx_scatter_fwd_species

@@ -387,10 +387,23 @@ def fit_step_species(xyz: torch.Tensor, species_start: Sequence[int], fs: Option
 
 
 def fit_step(xyz: torch.Tensor, f: Optional[torch.Tensor], S: torch.Tensor, I: torch.Tensor,
-             mode="ph64"):
-    """One fitting step's hot path on the current stream: A = Eq. 2, misfit L and seed
-    G, then dL/dxyz by the adjoint.  Returns (L, A, grad_xyz)."""
-    A = scatter_fwd(xyz, f, S, mode)
-    L, G = loss_grad(A, I)
-    grad = scatter_bwd(xyz, f, S, G, mode)
-    return L, A, grad
+             mode="ph64", return_seed: bool = False):
+    """One fitting step's hot path on the current stream, queued by one call into the
+    library (nx_fit_step): A = Eq. 2, misfit L and seed G, then dL/dxyz by the adjoint.
+    Returns (L, A, grad_xyz), and G as well when return_seed."""
+    _need(xyz, "xyz", torch.float32, (None, 3))
+    _need(S, "S", torch.float32, (None, 3))
+    n, k = xyz.shape[0], S.shape[0]
+    _f_arg(f, n, torch.complex64)
+    _need(I, "I", torch.float32, (k,))
+    m = _mode(mode)
+    _on_gpu(xyz=xyz, S=S, f=f, I=I)
+    dev = S.device
+    A = torch.empty(k, dtype=torch.complex64, device=dev)
+    G = torch.empty(k, dtype=torch.complex64, device=dev)
+    L = torch.empty((), dtype=torch.float64, device=dev)
+    grad = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    ws, wsb = _workspace(workspace_bytes(n, k, m, _lib.NX_OP_FIT, f is None), dev)
+    _lib.check(_lib.nx_fit_step(_ptr(xyz), _ptr(f), n, _ptr(S), k, _ptr(I), _ptr(A), _ptr(L),
+                                _ptr(G), _ptr(grad), m, _ptr(ws), wsb, _stream(dev)))
+    return (L, A, grad, G) if return_seed else (L, A, grad)

@@ -360,22 +360,26 @@ bool noalloc_plan(int mode, int64_t n_atoms, int64_t n_points, int f_is_null, nx
 
 extern "C" {
 
-int nx_version(void) { return 102; }
+int nx_version(void) { return 103; }
 
 const char* nx_last_error(void) { return g_last_error.c_str(); }
 
 size_t nx_workspace_bytes(int64_t n_atoms, int64_t n_points, int mode, int op, int f_is_null) {
   if (check_counts("nx_workspace_bytes", n_atoms, n_points) != NX_OK) return 0;
-  if (op < NX_OP_FWD || op > NX_OP_BWD_GF_F64) {
+  if (op < NX_OP_FWD || op > NX_OP_FIT) {
     fail(NX_ERR_MODE, "nx_workspace_bytes: unknown op %d", op);
     return 0;
   }
-  if ((op == NX_OP_FWD || op == NX_OP_BWD || op == NX_OP_BWD_GF) && mode != NX_F32 &&
-      mode != NX_F32_PH64) {
+  if ((op == NX_OP_FWD || op == NX_OP_BWD || op == NX_OP_BWD_GF || op == NX_OP_FIT) &&
+      mode != NX_F32 && mode != NX_F32_PH64) {
     fail(NX_ERR_MODE, "nx_workspace_bytes: unknown mode %d", mode);
     return 0;
   }
   ok();
+  if (op == NX_OP_FIT)   // the three stages use the workspace in turn
+    return std::max({nx::make_plan(nx::kOpFwd, mode, n_atoms, n_points, f_is_null).total(),
+                     nx::make_plan(nx::kOpLoss, mode, 0, n_points, 1).total(),
+                     nx::make_plan(nx::kOpBwd, mode, n_atoms, n_points, f_is_null).total()});
   return nx::make_plan(op, mode, n_atoms, n_points, f_is_null).total();
 }
 
@@ -484,6 +488,30 @@ int nx_loss_grad(const float* A, const float* I, int64_t n_points, double* L, fl
   hipError_t e = nx::launch_loss(A, I, n_points, L, G, static_cast<double*>(ws),
                                  static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_error(fn, e);
+  return ok();
+}
+
+int nx_fit_step(const float* xyz, const float* f, int64_t n_atoms, const float* S,
+                int64_t n_points, const float* I, float* A, double* L, float* G,
+                float* grad_xyz, int mode, void* ws, size_t ws_bytes, void* stream) {
+  const char* fn = "nx_fit_step";
+  if (int r = check_counts(fn, n_atoms, n_points)) return r;
+  if (mode != NX_F32 && mode != NX_F32_PH64) return fail(NX_ERR_MODE, "%s: unknown mode %d", fn, mode);
+  // everything the three stages check, before any of them queues work
+  if (!L || (n_points > 0 && (!S || !A || !I || !G)) || (n_atoms > 0 && (!xyz || !grad_xyz)))
+    return fail(NX_ERR_ARG, "%s: NULL pointer (xyz=%p S=%p I=%p A=%p L=%p G=%p grad_xyz=%p)", fn,
+                (const void*)xyz, (const void*)S, (const void*)I, (void*)A, (void*)L, (void*)G,
+                (void*)grad_xyz);
+  if ((A && !aligned(A, 8)) || (G && !aligned(G, 8)) || (f && !aligned(f, 8)) || !aligned(L, 8))
+    return fail(NX_ERR_ARG, "%s: A, G, f and L must be 8-byte aligned", fn);
+  const size_t need = nx_workspace_bytes(n_atoms, n_points, mode, NX_OP_FIT, f == nullptr);
+  if (need > 0 && (ws == nullptr || ws_bytes < need || !aligned(ws, 16)))
+    return fail(NX_ERR_WORKSPACE, "%s: workspace of %zu bytes (16-byte aligned) needed, %zu given",
+                fn, need, ws_bytes);
+  if (int r = nx_scatter_fwd(xyz, f, n_atoms, S, n_points, A, mode, ws, ws_bytes, stream)) return r;
+  if (int r = nx_loss_grad(A, I, n_points, L, G, ws, ws_bytes, stream)) return r;
+  if (int r = nx_scatter_bwd(xyz, f, n_atoms, S, n_points, G, grad_xyz, mode, ws, ws_bytes, stream))
+    return r;
   return ok();
 }
 

@@ -51,7 +51,7 @@ def test_micro_header_symbols_exported():
 
 
 def test_version():
-    assert _lib.nx_version() == 102
+    assert _lib.nx_version() == 103
 
 
 def fwd(n_atoms=8, n_points=8, xyz=FAKE, f=None, S=FAKE, A=FAKE, mode=1, ws=FAKE, wsb=1 << 40):
@@ -143,6 +143,23 @@ def test_python_wrappers_refuse_cpu_tensors():
         api.scatter_fwd(x, None, x)
     with pytest.raises(ValueError, match="unknown mode"):
         api._mode("fp16")
+
+
+def test_fit_step_checks_before_queueing():
+    """nx_fit_step checks what its three stages check before queueing any of them."""
+    fit = lambda n=8, k=8, xyz=FAKE, S=FAKE, I=FAKE, A=FAKE, L=FAKE, G=FAKE, g=FAKE, mode=1, ws=FAKE, \
+        wsb=1 << 40: _lib.nx_fit_step(xyz, None, n, S, k, I, A, L, G, g, mode, ws, wsb, None)
+    assert fit(n=-1) == _lib.NX_ERR_ARG
+    assert fit(mode=9) == _lib.NX_ERR_MODE
+    for kw in ("S", "I", "A", "L", "G", "g", "xyz"):
+        assert fit(**{kw: None}) == _lib.NX_ERR_ARG, kw
+        assert "nx_fit_step" in _lib.last_error()
+    assert fit(A=FAKE + 4) == _lib.NX_ERR_ARG
+    need = _lib.nx_workspace_bytes(1000, 3000, 1, _lib.NX_OP_FIT, 1)
+    assert need >= max(_lib.nx_workspace_bytes(1000, 3000, 1, op, 1)
+                       for op in (_lib.NX_OP_FWD, _lib.NX_OP_BWD, _lib.NX_OP_LOSS))
+    assert fit(n=1000, k=3000, wsb=need - 1) == _lib.NX_ERR_WORKSPACE
+    assert fit(n=1000, k=3000, ws=None) == _lib.NX_ERR_WORKSPACE
 
 
 def test_single_hip_runtime():

@@ -317,6 +317,22 @@ def test_fit_step_small(cplx):
     assert en <= M.T3_NORM_TOL and em <= M.T3_MAX_TOL
 
 
+@pytest.mark.parametrize("n,k,cplx", [(4096, 4096, False), (3001, 5003, True), (700, 0, True),
+                                      (0, 300, False), (20000, 70000, True)])
+def test_fit_step_one_call_equals_three(n, k, cplx):
+    """nx_fit_step queues the forward, the misfit and the adjoint in one call: A, L, G and
+    the gradient are bitwise those of the three calls, empty sizes included."""
+    xyz, f, S = wl.random_problem(n, k, seed=n + 2 * k, extent=20.0, s_range=2.0, complex_f=cplx)
+    I = (np.abs(wl.random_seed_field(k, seed=k + 1, scale=10.0)) ** 2).astype(np.float32)
+    tx, tf, tS, tI = dev(xyz), dev(f), dev(S), dev(I)
+    L1, A1, g1, G1 = api.fit_step(tx, tf, tS, tI, "ph64", return_seed=True)
+    A2 = api.scatter_fwd(tx, tf, tS, "ph64")
+    L2, G2 = api.loss_grad(A2, tI)
+    g2 = api.scatter_bwd(tx, tf, tS, G2, "ph64")
+    torch.cuda.synchronize()
+    assert torch.equal(A1, A2) and torch.equal(L1, L2) and torch.equal(G1, G2) and torch.equal(g1, g2)
+
+
 def test_autograd_matches_oracle():
     """torch autograd through ScatterFn: L computed with torch ops from A, gradient by
     the hand-written adjoint kernel."""
