@@ -41,10 +41,11 @@ VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 
 # Minimal VALU instruction count per (atom, point) pair of each kernel: the method's
 # own work on gfx950 in the formulation the kernels use (compensation, loads and loop
-# control excluded).  Phase S.r = 3 FP64 fma.  Forward: centred reduction mod 1 (rint,
-# subtract) and rounding to FP32 = 3; adjoint: fract and rounding = 2.  sin and cos count
-# one issue slot each (at half rate they keep the VALU busy longer; the microbenchmark
-# ceiling of the same mix prices that in).
+# control excluded).  Phase S.r = 3 FP64 fma, with the records' shift of 1.5 * 2^20 cycles
+# in the addend; reduction mod 1 = the low word of the phase read as a fixed-point turn:
+# integer to FP32 conversion and scaling by 2^-32 = 2.  sin and cos count one issue slot
+# each (at half rate they keep the VALU busy longer; the microbenchmark ceiling of the
+# same mix prices that in).
 #   forward, complex f: f in polar form m exp(2 i pi a), a the addend of the phase's first
 #                       fma; m (cos + i sin) accumulated with 2 fma
 #   forward, f = 1:     (cos, sin) accumulated with 2 add
@@ -58,8 +59,8 @@ VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 #            f), T_d += S_d v (3); sin and cos are both needed.
 # libnx_micro's kernels run exactly these sequences (tests/test_device_code.py counts them).
 ALG_SLOTS = {
-    ("ph64", "fwd", "complex"): 3 + 3 + 2 + 2,
-    ("ph64", "fwd", "unit"): 3 + 3 + 2 + 2,
+    ("ph64", "fwd", "complex"): 3 + 2 + 2 + 2,
+    ("ph64", "fwd", "unit"): 3 + 2 + 2 + 2,
     ("ph64", "bwd", "complex"): 3 + 1 + 2 + 1 + 3,
     ("ph64", "bwd", "unit"): 3 + 2 + 1 + 3,
     ("f32", "fwd", "complex"): 3 + 1 + 2 + 4,
@@ -142,7 +143,7 @@ def parse():
     p.add_argument("--no-micro", action="store_true",
                    help="skip the issue-ceiling microbenchmarks (the valu_issue fields)")
     p.add_argument("--copy-cal", type=int, default=0, metavar="BYTES",
-                   help="only run a plain device-to-device copy of BYTES bytes three times "
+                   help="only run a plain copy kernel over BYTES bytes (read once, written once) three times "
                         "(the reference kernel that scales the HBM counters of a profile)")
     return p.parse_args()
 
@@ -335,12 +336,15 @@ def issue_ceilings(mode, fkind):
 
 
 def op_costs():
-    """Cycles per wave64 instruction of single instruction kinds issued alone (FP32 and FP64
-    fma in the three-operand form with a scalar operand and in the two-operand accumulating
-    form, v_sin_f32), from their measured rate and the clock the same kernels read."""
+    """Cycles per wave64 instruction of the instruction kinds of the sums' loops, each
+    issued alone (FP32 fma in the three-operand form with a scalar or vector operands and
+    in the two-operand accumulating form, FP32 mul and add, FP64 fma in both forms, FP64
+    add, rint and fract, the integer-to-FP32 conversion, v_sin_f32, v_cos_f32), from their
+    measured rate and the clock the same kernels read."""
     from paper_1010_2641_amd import micro
     out = {}
-    for kind in ("fma_f32", "fmac_f32", "fma_f64", "fmac_f64", "sin_f32"):
+    for kind in ("fma_f32", "fma_f32_v", "fmac_f32", "mul_f32", "add_f32", "fma_f64", "fmac_f64",
+                 "add_f64", "rndne_f64", "fract_f64", "cvt_f32_i32", "sin_f32", "cos_f32"):
         rate, ghz = micro.op_rate(kind)
         out[kind] = {"insts_per_s_per_simd": rate, "clock_ghz": ghz,
                      "cycles_per_inst": None if ghz is None else ghz * 1e9 / rate}
@@ -581,8 +585,8 @@ def main():
     if args.copy_cal:
         src = torch.empty(args.copy_cal // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
         dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
+        for _ in range(3):     # an elementwise kernel (a device-to-device memcpy is no dispatch)
+            torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": args.copy_cal}), flush=True)
         return

@@ -102,16 +102,17 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
                                                                      : (mode == NX_F32_PH64 ? kPH64 : kF32);
   p.lanes = fwd ? n_points : n_atoms;
   p.stream = fwd ? n_atoms : n_points;
-  // Defaults from launch-shape and accuracy sweeps on MI355X.  Forward, FP64-phase
-  // mode: the centred reduction (its FP32 rounding of the reduced phase is half that of
-  // fract's, which decides the pointwise intensity error at the weakest points: fract is
-  // 8 % faster but took a strained 100^3 cube from 2.0e-6 to 7.7e-6), and 8-atom groups
-  // for few atoms (|A| peaks at N |f|, so each term weighs more), 16 above.
-  // Adjoint (judged normwise): fract, 64-point groups (1 % faster than 32 on C2-C4, same
-  // error), two atoms per lane.
+  // Defaults from launch-shape and accuracy sweeps on MI355X.  FP64-phase mode, both
+  // sums: the fixed-point reduction (the centred turn read from the low word of the
+  // shifted phase; the centred form's rounding, which decides the pointwise intensity
+  // error at the weakest points, with two instructions fewer than the centred form and
+  // one fewer than fract, whose rounding is twice as coarse: fract took a strained 100^3
+  // cube from 2.0e-6 to 7.7e-6).  Forward: 8-atom groups for few atoms (|A| peaks at
+  // N |f|, so each term weighs more), 16 above.  Adjoint (judged normwise): 64-point
+  // groups (1 % faster than 32 on C2-C4, same error), two atoms per lane.
   if (fwd) {
     const bool small = p.stream < 65536;
-    p.red = 0;
+    p.red = p.mode == kPH64 ? 2 : 0;
     // atom tiles staged in LDS: the records' phase addend would be a second scalar
     // operand of the first fma, which the scalar-load form has to copy to VGPRs
     p.lds = p.mode == kPH64 ? 1 : 0;
@@ -119,7 +120,7 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
     if (p.mode == kF64) p.per_lane = p.lanes >= 262144 ? 2 : 1;
     else p.per_lane = (p.lanes >= 32768 && p.lanes < 1048576) ? 2 : 1;
   } else {
-    p.red = p.mode == kPH64 ? 1 : 0;
+    p.red = p.mode == kPH64 ? 2 : 0;
     p.grp = p.mode == kPH64 ? 64 : 16;
     // the phase part of the point records from LDS tiles, the rest with scalar loads
     // (1.5-3 % faster than scalar loads alone, from 1e5 to 1e6 atoms)
@@ -135,10 +136,17 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
     if (p.mode == kPH64 && (fwd ? (tg == 8 || tg == 16 || tg == 32) : (tg == 16 || tg == 32 || tg == 64)))
       p.grp = int(tg);
     const int64_t tr = env_i64("NX_TUNE_RED", -1);
-    if (p.mode == kPH64 && (tr == 0 || tr == 1)) p.red = int(tr);
+    if (p.mode == kPH64 && (tr == 0 || tr == 1 || tr == 2)) p.red = int(tr);
     const int64_t tl = env_i64("NX_TUNE_LDS", -1);
     if (p.mode == kPH64 && (tl == 0 || tl == 1)) p.lds = int(tl);
   }
+  // the fixed-point reduction checks its range per LDS tile: the scalar-load forms (and
+  // the forward's 32-atom groups, which have no LDS form) take the centred one, and so do
+  // the forward's forms whose two tile loops do not fit their registers (four points per
+  // lane; two with 8-atom groups)
+  if (p.red == 2 && !(p.lds && (!fwd || ((p.grp == 8 || p.grp == 16) &&
+                                         (p.per_lane == 1 || (p.per_lane == 2 && p.grp == 16))))))
+    p.red = 0;
   const int64_t per_block = int64_t(kThreads) * p.per_lane;
   p.blocks = p.lanes > 0 ? ceil_div(p.lanes, per_block) : 0;
   p.nsplit = 1;
@@ -166,7 +174,7 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
   // lane and the default reduction variant); NX_TUNE_INLINE=0 turns this off, 1 forces it
   // wherever that form exists
   if (p.mode == kPH64 && p.lds && p.per_lane == 1 &&
-      (fwd ? (p.red == 0 && (p.grp == 8 || p.grp == 16)) : (p.red == 1 && p.grp == 64))) {
+      (fwd ? (p.red == 2 && (p.grp == 8 || p.grp == 16)) : (p.red == 2 && p.grp == 64))) {
     const int64_t ti = env_i64("NX_TUNE_INLINE", -1);
     p.inl = (ti == 1 || (ti != 0 && p.blocks * p.stream <= kInlineMaxRecords)) ? 1 : 0;
   }
@@ -192,8 +200,10 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
     p.chunk = chunk;
     p.nchunks = ceil_div(p.stream, chunk);
   }
-  // workspace: packed stream records, then the partial state
+  // workspace: packed stream records (with the FP64-phase adjoint's tile bounds), then
+  // the partial state
   p.rec_bytes = align_up(size_t(p.stream) * rec_size, 256);
+  if (!fwd && p.mode == kPH64) p.rec_bytes += point_bound_bytes(p.stream);
   const bool need_partial = p.lanes > 0 && (p.nsplit > 1 || p.nchunks > 1);
   if (need_partial) {
     size_t per_item;

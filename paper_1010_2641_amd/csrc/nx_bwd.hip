@@ -122,7 +122,8 @@ __device__ __forceinline__ PtRegs load_point_split(const uint4* sd, int u,
 }
 
 // The FP64-phase record of point k, with the seed in polar form conj(G) = |G| exp(2 i pi
-// delta): delta = -arg(G) / (2 pi) in FP64 (plus the reduction offset of the variant); |G| S
+// delta): delta = -arg(G) / (2 pi) in FP64 (plus kPhaseShift and the reduction offset of the
+// variant: `offset`); |G| S
 // and |G| rounded once to FP32.  The pack kernel writes it to the workspace; the adjoint of
 // small calls forms it while staging its tile, so that both give the same record.
 __device__ __forceinline__ PointPH make_point_ph(const float* __restrict__ S,
@@ -139,6 +140,19 @@ __device__ __forceinline__ PointPH make_point_ph(const float* __restrict__ S,
   r.gsz = static_cast<float>(m * sz);
   r.gmag = static_cast<float>(m);
   return r;
+}
+
+// |v| as FP32, +inf when v is not finite (the fixed-point tile bounds).
+__device__ __forceinline__ float bound_abs(double v) {
+  const float a = static_cast<float>(fabs(v));
+  return a <= 3.402823466e38f ? a : __builtin_inff();
+}
+
+// Largest v over the wavefront.
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
 }
 
 // A whole record from an LDS tile of 48-byte records (the inline form of small calls):
@@ -159,9 +173,11 @@ __device__ __forceinline__ PtRegs load_point_lds(const uint4* sd, int u) {
   return r;
 }
 
-// (c, s) of exp(2 i pi psi), psi = S.r + delta + alpha (delta includes the 1/2 of
-// RED == 1; alpha = arg f in cycles, absent for f = 1).  The seed angle enters as the
-// addend of the first fma, the atom's angle as one FP64 add.
+// (c, s) of exp(2 i pi psi), psi = S.r + delta + alpha (delta includes kPhaseShift and the
+// 1/2 of RED == 1; alpha = arg f in cycles, absent for f = 1).  The seed angle enters as
+// the addend of the first fma, the atom's angle as one FP64 add.  RED 0 centred, 1 fract,
+// 2 the fixed-point read of the low word (where the tile's bound holds; see kPhaseShift),
+// 3 its fallback: centred with rint, then the low word of the turn plus kPhaseShift.
 template <int RED, int FK>
 __device__ __forceinline__ void cis_ph64_pt(const PtRegs& a, double x, double y, double z,
                                             double al, float& c, float& s) {
@@ -169,7 +185,9 @@ __device__ __forceinline__ void cis_ph64_pt(const PtRegs& a, double x, double y,
   if constexpr (FK != 0) ph += al;
   float tf;
   if constexpr (RED == 0) tf = static_cast<float>(ph - __builtin_rint(ph));
-  else tf = static_cast<float>(__builtin_amdgcn_fract(ph));
+  else if constexpr (RED == 1) tf = static_cast<float>(__builtin_amdgcn_fract(ph));
+  else if constexpr (RED == 2) tf = static_cast<float>(__double2loint(ph)) * 0x1.0p-32f;
+  else tf = static_cast<float>(__double2loint((ph - __builtin_rint(ph)) + kPhaseShift)) * 0x1.0p-32f;
   c = __builtin_amdgcn_cosf(tf);
   s = __builtin_amdgcn_sinf(tf);
 }
@@ -354,26 +372,35 @@ __global__ __launch_bounds__(kThreads) void bwd_kernel(
 // the phase's fma chain then takes its point values from VGPRs.  Groups and compensation are those of bwd_kernel
 // (tiles are whole groups), so the result is bitwise the same.
 //
+// RED 2: each wave checks the fixed-point bound for every tile, (|x| + |y| + |z|) of its
+// atoms times the tile's largest |S| component (the bounds of the at most two pack blocks
+// the tile overlaps, `bnd`), and takes the fallback (variant 3, same records) for a tile
+// where some lane fails it.
+//
 // INL (small calls): no packed records; each thread forms its whole record of the tile from
 // S and G while staging it (make_point_ph, as the pack kernel does) and every field is read
-// back from LDS, which saves the pack dispatch when few work-groups share each record.
+// back from LDS, which saves the pack dispatch when few work-groups share each record; the
+// tile's bound is then reduced over its own points.
 template <int Q, int FK, int GRP, int RED, bool GF, bool INL>
 __global__ __launch_bounds__(kThreads) void bwd_split_kernel(
     const PointPH* __restrict__ rec, int k_begin, int k_end, int per_split,
     const float* __restrict__ xyz, const float* __restrict__ f, int64_t N, int blocks_n,
     float* __restrict__ part, float* __restrict__ grad, float* __restrict__ gradf, int carry_in,
-    int direct, const float* __restrict__ S, const float* __restrict__ G) {
+    int direct, const float* __restrict__ S, const float* __restrict__ G,
+    const float* __restrict__ bnd) {
   static_assert(kThreads % GRP == 0, "tiles must hold whole groups");
   constexpr int NS = NSum<GF>::value;
   constexpr float SGN = (RED == 1) ? -1.f : 1.f;
   constexpr int W = INL ? 3 : 2;            // 16-byte words per point in the LDS tile
   __shared__ uint4 sd[W * kThreads];
+  __shared__ float wmax[kThreads / 64];
   const int lb = xcd_major_block(blockIdx.x, gridDim.x);
   const int nb = lb % blocks_n;
   const int sp = lb / blocks_n;
   const int64_t j0 = int64_t(nb) * (kThreads * Q) + threadIdx.x;
   double x[Q], y[Q], z[Q], al[Q];
   float sum[Q][NS], cmp[Q][NS];
+  float r1 = 0.f;                           // the lane's |x| + |y| + |z| (largest over q)
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int64_t j = j0 + int64_t(q) * kThreads;
@@ -381,6 +408,7 @@ __global__ __launch_bounds__(kThreads) void bwd_split_kernel(
     x[q] = xyz[3 * jj];
     y[q] = xyz[3 * jj + 1];
     z[q] = xyz[3 * jj + 2];
+    r1 = fmaxf(r1, bound_abs(fabs(x[q]) + fabs(y[q]) + fabs(z[q])));
     al[q] = (FK && f) ? arg_cycles(f[2 * jj], f[2 * jj + 1]) : 0.0;
 #pragma unroll
     for (int d = 0; d < NS; ++d) {
@@ -393,25 +421,9 @@ __global__ __launch_bounds__(kThreads) void bwd_split_kernel(
       }
     }
   }
-  const int k0 = k_begin + sp * per_split;
-  const int k1 = min(k0 + per_split, k_end);
-  for (int t0 = k0; t0 < k1; t0 += kThreads) {
-    const int nt = min(kThreads, k1 - t0);
-    __syncthreads();                        // the previous tile is no longer read
-    if (int(threadIdx.x) < nt) {
-      if constexpr (INL) {
-        const PointPH r = make_point_ph(S, G, t0 + threadIdx.x, RED == 1 ? 0.5 : 0.0);
-        const uint4* w = reinterpret_cast<const uint4*>(&r);
-        sd[3 * threadIdx.x] = w[0];
-        sd[3 * threadIdx.x + 1] = w[1];
-        sd[3 * threadIdx.x + 2] = w[2];
-      } else {
-        const uint4* w = reinterpret_cast<const uint4*>(rec + t0 + threadIdx.x);
-        sd[2 * threadIdx.x] = w[0];
-        sd[2 * threadIdx.x + 1] = w[1];
-      }
-    }
-    __syncthreads();
+  // the groups of one tile (points t0 .. t0 + nt), reduced with the variant R
+  auto run_tile = [&](auto red_c, int t0, int nt) {
+    constexpr int R = decltype(red_c)::value;
     for (int u0 = 0; u0 < nt; u0 += GRP) {
       const int ue = (u0 + GRP <= nt) ? u0 + GRP : nt;
       float g[Q][NS];
@@ -426,7 +438,7 @@ __global__ __launch_bounds__(kThreads) void bwd_split_kernel(
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
             float c, s;
-            cis_ph64_pt<RED, FK>(a, x[q], y[q], z[q], al[q], c, s);
+            cis_ph64_pt<R, FK>(a, x[q], y[q], z[q], al[q], c, s);
             ph64_pair<GF>(g[q], a, c, s);
           }
         }
@@ -436,7 +448,7 @@ __global__ __launch_bounds__(kThreads) void bwd_split_kernel(
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
             float c, s;
-            cis_ph64_pt<RED, FK>(a, x[q], y[q], z[q], al[q], c, s);
+            cis_ph64_pt<R, FK>(a, x[q], y[q], z[q], al[q], c, s);
             ph64_pair<GF>(g[q], a, c, s);
           }
         }
@@ -445,6 +457,46 @@ __global__ __launch_bounds__(kThreads) void bwd_split_kernel(
       for (int q = 0; q < Q; ++q)
 #pragma unroll
         for (int d = 0; d < NS; ++d) kahan_acc(sum[q][d], cmp[q][d], SGN * g[q][d]);
+    }
+  };
+  const int k0 = k_begin + sp * per_split;
+  const int k1 = min(k0 + per_split, k_end);
+  for (int t0 = k0; t0 < k1; t0 += kThreads) {
+    const int nt = min(kThreads, k1 - t0);
+    __syncthreads();                        // the previous tile is no longer read
+    float sm = 0.f;
+    if (int(threadIdx.x) < nt) {
+      if constexpr (INL) {
+        const PointPH r = make_point_ph(S, G, t0 + threadIdx.x, kPhaseShift + (RED == 1 ? 0.5 : 0.0));
+        const uint4* w = reinterpret_cast<const uint4*>(&r);
+        sd[3 * threadIdx.x] = w[0];
+        sd[3 * threadIdx.x + 1] = w[1];
+        sd[3 * threadIdx.x + 2] = w[2];
+        sm = fmaxf(bound_abs(r.sx), fmaxf(bound_abs(r.sy), bound_abs(r.sz)));
+      } else {
+        const uint4* w = reinterpret_cast<const uint4*>(rec + t0 + threadIdx.x);
+        sd[2 * threadIdx.x] = w[0];
+        sd[2 * threadIdx.x + 1] = w[1];
+      }
+    }
+    if constexpr (INL && RED == 2) {
+      sm = wave_max(sm);
+      if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = sm;
+    }
+    __syncthreads();
+    if constexpr (RED == 2) {
+      float st;
+      if constexpr (INL) {
+        st = wmax[0];
+#pragma unroll
+        for (int w = 1; w < kThreads / 64; ++w) st = fmaxf(st, wmax[w]);
+      } else {
+        st = fmaxf(bnd[t0 / kThreads], bnd[(t0 + nt - 1) / kThreads]);
+      }
+      if (__all(r1 * st < kFixedPhaseBound)) run_tile(std::integral_constant<int, 2>{}, t0, nt);
+      else run_tile(std::integral_constant<int, 3>{}, t0, nt);
+    } else {
+      run_tile(std::integral_constant<int, RED>{}, t0, nt);
     }
   }
 #pragma unroll
@@ -538,7 +590,9 @@ __global__ __launch_bounds__(kThreads) void bwd_f64_kernel(
 // one wave serve one atom (G a power of two up to 64, about a quarter of the splits); lane i
 // folds splits i, i + G, ... of each sum in sequence with Knuth's two-sum, then the lanes'
 // states meet in a butterfly in which both partners fold the lower lane's state first (a
-// fixed tree), and lane 0 writes the atom's outputs.  Few splits take G = 1.
+// fixed tree), and lane 0 writes the atom's outputs.  Few splits take G = 1.  A wave
+// serves 64 / G consecutive atoms side by side (its lane w: atom w % (64 / G), split lane
+// w / (64 / G)), so that each load reads a run of consecutive atoms of G split rows.
 template <int G, bool GF, bool POLAR>
 __global__ __launch_bounds__(kThreads) void bwd_reduce_kernel(const float* __restrict__ part,
                                                               int nsplit, int64_t N,
@@ -547,9 +601,11 @@ __global__ __launch_bounds__(kThreads) void bwd_reduce_kernel(const float* __res
                                                               float* __restrict__ gradf) {
   static_assert(G >= 1 && G <= 64 && (G & (G - 1)) == 0, "G: a power of two within a wave");
   constexpr int NS = NSum<GF>::value;
+  constexpr int OPW = 64 / G;               // atoms per wave, side by side
   const int64_t t = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-  const int64_t j = t / G;
-  const int lane = static_cast<int>(t % G);
+  const int w = static_cast<int>(t & 63);
+  const int64_t j = (t >> 6) * OPW + (w % OPW);
+  const int lane = w / OPW;
   float T[NS];
 #pragma unroll
   for (int d = 0; d < NS; ++d) {
@@ -563,7 +619,7 @@ __global__ __launch_bounds__(kThreads) void bwd_reduce_kernel(const float* __res
     }
 #pragma unroll
     for (int off = 1; off < G; off <<= 1) {
-      const float os = __shfl_xor(s, off), oc = __shfl_xor(cm, off);
+      const float os = __shfl_xor(s, off * OPW), oc = __shfl_xor(cm, off * OPW);
       const bool upper = (lane & off) != 0;    // the partner is the lower lane: fold it first
       float a = upper ? os : s, ac = upper ? oc : cm;
       const float b = upper ? s : os, bc = upper ? cm : oc;
@@ -598,6 +654,35 @@ __global__ __launch_bounds__(kThreads) void bwd_reduce_f64_kernel(const double* 
   if constexpr (GF) {
     gradf[2 * j] = T[3];
     gradf[2 * j + 1] = -T[4];
+  }
+}
+
+// FP64-phase point records, grid-stride over blocks of 256 points, with each block's
+// largest |S| component in bnd[block] (the adjoint's tile bound).
+__global__ __launch_bounds__(kThreads) void pack_points_ph_kernel(const float* __restrict__ S,
+                                                                  const float* __restrict__ G,
+                                                                  int64_t n, PointPH* __restrict__ rec,
+                                                                  float* __restrict__ bnd,
+                                                                  double offset) {
+  __shared__ float wmax[kThreads / 64];
+  for (int64_t b = blockIdx.x; b * kThreads < n; b += gridDim.x) {
+    const int64_t k = b * kThreads + threadIdx.x;
+    float sm = 0.f;
+    if (k < n) {
+      const PointPH r = make_point_ph(S, G, k, offset);
+      rec[k] = r;
+      sm = fmaxf(bound_abs(r.sx), fmaxf(bound_abs(r.sy), bound_abs(r.sz)));
+    }
+    sm = wave_max(sm);
+    __syncthreads();                      // wmax of the previous block is read
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = sm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float bm = wmax[0];
+#pragma unroll
+      for (int w = 1; w < kThreads / 64; ++w) bm = fmaxf(bm, wmax[w]);
+      bnd[b] = bm;
+    }
   }
 }
 
@@ -660,24 +745,36 @@ hipError_t bwd_dispatch(const Plan& p, const BwdArgs& b, hipStream_t st) {
     bwd_kernel<MODE, Q, FK, 16, 0, GF><<<grid, kThreads, 0, st>>>(
         r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct);
   } else {
-    if (p.lds && p.red == 1 && (p.grp == 64 || p.grp == 32 || p.grp == 16)) {
+    if (p.lds && (p.red == 1 || p.red == 2) && (p.grp == 64 || p.grp == 32 || p.grp == 16)) {
+      const float* bnd = (p.inl || !r) ? nullptr
+          : reinterpret_cast<const float*>(reinterpret_cast<const char*>(r) + point_bound_offset(p.stream));
+      const auto* S = static_cast<const float*>(b.S);
+      const auto* G = static_cast<const float*>(b.G);
+      auto launch = [&](auto grp_c, auto red_c, auto inl_c) {
+        constexpr bool I = decltype(inl_c)::value;
+        bwd_split_kernel<I ? 1 : Q, FK, decltype(grp_c)::value, decltype(red_c)::value, GF, I>
+            <<<grid, kThreads, 0, st>>>(I ? nullptr : r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf,
+                                        b.carry_in, b.direct, I ? S : nullptr, I ? G : nullptr, bnd);
+      };
+      using R1 = std::integral_constant<int, 1>;
+      using R2 = std::integral_constant<int, 2>;
+      using NoInl = std::integral_constant<bool, false>;
       if constexpr (Q == 1) {
-        if (p.inl && p.grp == 64) {       // records formed while staging (small calls)
-          bwd_split_kernel<1, FK, 64, 1, GF, true><<<grid, kThreads, 0, st>>>(
-              nullptr, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct,
-              static_cast<const float*>(b.S), static_cast<const float*>(b.G));
+        if (p.inl && p.grp == 64 && p.red == 2) {       // records formed while staging (small calls)
+          launch(std::integral_constant<int, 64>{}, R2{}, std::integral_constant<bool, true>{});
           return hipGetLastError();
         }
       }
-      if (p.grp == 64)
-        bwd_split_kernel<Q, FK, 64, 1, GF, false><<<grid, kThreads, 0, st>>>(
-            r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct, nullptr, nullptr);
-      else if (p.grp == 32)
-        bwd_split_kernel<Q, FK, 32, 1, GF, false><<<grid, kThreads, 0, st>>>(
-            r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct, nullptr, nullptr);
-      else
-        bwd_split_kernel<Q, FK, 16, 1, GF, false><<<grid, kThreads, 0, st>>>(
-            r, k0, k1, per, x, ff, p.lanes, nblk, pa, g, gf, b.carry_in, b.direct, nullptr, nullptr);
+      if (p.grp == 64) {
+        if (p.red == 2) launch(std::integral_constant<int, 64>{}, R2{}, NoInl{});
+        else launch(std::integral_constant<int, 64>{}, R1{}, NoInl{});
+      } else if (p.grp == 32) {
+        if (p.red == 2) launch(std::integral_constant<int, 32>{}, R2{}, NoInl{});
+        else launch(std::integral_constant<int, 32>{}, R1{}, NoInl{});
+      } else {
+        if (p.red == 2) launch(std::integral_constant<int, 16>{}, R2{}, NoInl{});
+        else launch(std::integral_constant<int, 16>{}, R1{}, NoInl{});
+      }
       return hipGetLastError();
     }
     if (p.grp == 64 && p.red == 0)
@@ -735,7 +832,8 @@ hipError_t bwd_f64_dispatch(const Plan& p, const BwdArgs& b, hipStream_t st) {
 template <int G>
 void bwd_reduce_launch(bool gf, bool polar, int nsplit, int64_t N, const float* pa, const float* ff,
                        float* g0, float* g1, hipStream_t st) {
-  const unsigned g = static_cast<unsigned>((N * G + kThreads - 1) / kThreads);
+  const int64_t waves = (N + 64 / G - 1) / (64 / G);
+  const unsigned g = static_cast<unsigned>((waves * 64 + kThreads - 1) / kThreads);
   if (gf && polar) bwd_reduce_kernel<G, true, true><<<g, kThreads, 0, st>>>(pa, nsplit, N, ff, g0, g1);
   else if (gf) bwd_reduce_kernel<G, true, false><<<g, kThreads, 0, st>>>(pa, nsplit, N, ff, g0, g1);
   else if (polar) bwd_reduce_kernel<G, false, true><<<g, kThreads, 0, st>>>(pa, nsplit, N, ff, g0, g1);
@@ -748,9 +846,12 @@ hipError_t launch_pack_points(int mode, int red, const void* S, const void* G, i
                               void* rec, hipStream_t st) {
   if (k <= 0) return hipSuccess;
   const unsigned g = grid_for(k);
-  const double offset = red == 1 ? 0.5 : 0.0;
+  const double offset = kPhaseShift + (red == 1 ? 0.5 : 0.0);
   if (mode == kF64) pack_points_kernel<kF64><<<g, kThreads, 0, st>>>(S, G, k, rec, 0.0);
-  else if (mode == kPH64) pack_points_kernel<kPH64><<<g, kThreads, 0, st>>>(S, G, k, rec, offset);
+  else if (mode == kPH64)
+    pack_points_ph_kernel<<<g, kThreads, 0, st>>>(
+        static_cast<const float*>(S), static_cast<const float*>(G), k, static_cast<PointPH*>(rec),
+        reinterpret_cast<float*>(static_cast<char*>(rec) + point_bound_offset(k)), offset);
   else pack_points_kernel<kF32><<<g, kThreads, 0, st>>>(S, G, k, rec, 0.0);
   return hipGetLastError();
 }
@@ -782,7 +883,7 @@ hipError_t launch_bwd_reduce(const Plan& p, const void* partial, const void* f, 
     auto* g0 = static_cast<float*>(grad);
     auto* g1 = static_cast<float*>(gradf);
     const bool polar = p.mode == kPH64 && p.fk;
-    switch (reduce_lanes(p.nsplit)) {
+    switch (reduce_lanes(p.nsplit, N)) {
       case 64: bwd_reduce_launch<64>(p.gf, polar, p.nsplit, N, pa, ff, g0, g1, st); break;
       case 32: bwd_reduce_launch<32>(p.gf, polar, p.nsplit, N, pa, ff, g0, g1, st); break;
       case 16: bwd_reduce_launch<16>(p.gf, polar, p.nsplit, N, pa, ff, g0, g1, st); break;

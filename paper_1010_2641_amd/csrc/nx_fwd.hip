@@ -94,7 +94,8 @@ __device__ __forceinline__ float round_unbiased(double m, int64_t j) {
 
 // The FP64-phase record of atom j (indices counted from the first atom of a plan, which
 // starts the plan's first group):
-//   a  = arg f in cycles (0 for f = 1 or f = 0) + offset (the variant's 1/2) + k/8,
+//   a  = arg f in cycles (0 for f = 1 or f = 0) + offset (kPhaseShift, plus 1/2 for the
+//        fract variant) + k/8,
 //   m  = |f| from FP64, rounded without bias (1 for f = 1),
 //   (ck, sk) = sgn exp(-2 i pi k/8) in FP32, sgn = -1 for the fract variant,
 // with k = 0..7 the turn of the atom's group g = j / grp, from mix64(2 g + 1).  The pack
@@ -117,18 +118,51 @@ __device__ __forceinline__ AtomPH make_atom_ph(const float* __restrict__ xyz,
   r.a = alpha + offset + 0.125 * k;
   r.ck = sgn * static_cast<float>(cospi(0.25 * k));
   r.sk = -sgn * static_cast<float>(sinpi(0.25 * k));
-  r.pad = 0.f;
+  r.rmax = 0.f;
   return r;
 }
 
-// FP64-phase atom records, grid-stride over the n atoms of one plan.
+// |v| as FP32, +inf when v is not finite: the tile bounds of the fixed-point reduction
+// treat coordinates that are not finite as unbounded (their tiles take the centred form).
+__device__ __forceinline__ float bound_abs(double v) {
+  const float a = static_cast<float>(fabs(v));
+  return a <= 3.402823466e38f ? a : __builtin_inff();
+}
+
+// Largest v over the wavefront (the tile bounds).
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
+// FP64-phase atom records, grid-stride over the blocks of 256 atoms of one plan; every
+// record of a block carries the block's largest coordinate magnitude (rmax).
 __global__ __launch_bounds__(kThreads) void pack_atoms_ph_kernel(const float* __restrict__ xyz,
                                                                  const float* __restrict__ f,
                                                                  int64_t n, AtomPH* __restrict__ rec,
                                                                  double offset, int grp, float sgn) {
-  for (int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x; j < n;
-       j += int64_t(gridDim.x) * kThreads)
-    rec[j] = make_atom_ph(xyz, f, j, offset, grp, sgn);
+  __shared__ float wmax[kThreads / 64];
+  for (int64_t b = blockIdx.x; b * kThreads < n; b += gridDim.x) {
+    const int64_t j = b * kThreads + threadIdx.x;
+    AtomPH r;
+    float am = 0.f;
+    if (j < n) {
+      r = make_atom_ph(xyz, f, j, offset, grp, sgn);
+      am = fmaxf(bound_abs(r.x), fmaxf(bound_abs(r.y), bound_abs(r.z)));
+    }
+    am = wave_max(am);
+    __syncthreads();                      // wmax of the previous block is read
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = am;
+    __syncthreads();
+    float bm = wmax[0];
+#pragma unroll
+    for (int w = 1; w < kThreads / 64; ++w) bm = fmaxf(bm, wmax[w]);
+    if (j < n) {
+      r.rmax = bm;
+      rec[j] = r;
+    }
+  }
 }
 
 template <int MODE> struct AtomOf;
@@ -136,19 +170,27 @@ template <> struct AtomOf<kF32> { using type = AtomF32; };
 template <> struct AtomOf<kPH64> { using type = AtomPH; };
 
 // exp(2 i pi psi) for the FP64-phase mode as (c, s) in FP32, psi = S.r + arg f + k/8 (the
-// group's eighth turn); the record's addend is a = arg f + k/8 + the variant's offset:
+// group's eighth turn); the record's addend is a = arg f + k/8 + kPhaseShift (an integer)
+// + the variant's offset:
 //   RED 0 (offset 0):   t = (S.r + a) - rint(S.r + a) in [-1/2, 1/2] (exact), rounded once
 //                       to FP32;
 //   RED 1 (offset 1/2): u = fract(S.r + a) = fract(psi + 1/2) in [0, 1) (exact), rounded
 //                       once to FP32, so that exp(2 i pi u) = -exp(2 i pi psi); the records'
-//                       turn-back factor carries the -1.
+//                       turn-back factor carries the -1;
+//   RED 2 (offset 0):   t from the low word of S.r + a read as a 32-bit fixed-point turn
+//                       (see kPhaseShift): the RED 0 value but at exactly half a turn, where
+//                       the tile's bound holds (the kernels check it per tile);
+//   3 (RED 2's fallback for tiles out of that range): t = (S.r + a) - rint(S.r + a), then
+//                       the low word of t + kPhaseShift read in the same way.
 template <int RED>
 __device__ __forceinline__ void cis_ph64(double sx, double sy, double sz, const AtomPH& a, float& c,
                                          float& s) {
   const double ph = __builtin_fma(sz, a.z, __builtin_fma(sy, a.y, __builtin_fma(sx, a.x, a.a)));
   float tf;
   if constexpr (RED == 0) tf = static_cast<float>(ph - __builtin_rint(ph));
-  else tf = static_cast<float>(__builtin_amdgcn_fract(ph));
+  else if constexpr (RED == 1) tf = static_cast<float>(__builtin_amdgcn_fract(ph));
+  else if constexpr (RED == 2) tf = static_cast<float>(__double2loint(ph)) * 0x1.0p-32f;
+  else tf = static_cast<float>(__double2loint((ph - __builtin_rint(ph)) + kPhaseShift)) * 0x1.0p-32f;
   c = __builtin_amdgcn_cosf(tf);
   s = __builtin_amdgcn_sinf(tf);
 }
@@ -307,10 +349,16 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(
 // records in flight, up to 130 VGPRs for two points per lane, and three waves per SIMD
 // then hide the LDS latency worse; with it the same loop takes 52.)
 //
+// RED 2: each wave checks the fixed-point bound for every tile, (|Sx| + |Sy| + |Sz|) of
+// its points times the tile's largest coordinate magnitude (the rmax of the tile's first
+// and last records, which cover the at most two pack blocks the tile overlaps), and
+// takes the fallback (variant 3, same records) for a tile where some lane fails it.
+//
 // INL (small calls): no packed records; each thread forms its record of the tile from
 // xyz and f while staging it (make_atom_ph, as the pack kernel does), which saves the pack
-// dispatch when few work-groups share each record.  The FP64 arctangent of the record
-// needs more registers than 5 waves per SIMD leave, so this form is built for 4.
+// dispatch when few work-groups share each record; the tile's bound is then reduced over
+// its own records.  The FP64 arctangent of the record needs more registers than 5 waves
+// per SIMD leave, so this form is built for 4.
 template <int P, int FK, int GRP, int RED, bool INL>
 __global__ __launch_bounds__(kThreads, INL ? 4 : 5) void fwd_lds_kernel(
     const AtomPH* __restrict__ rec, int a_begin, int a_end, int per_split,
@@ -320,12 +368,14 @@ __global__ __launch_bounds__(kThreads, INL ? 4 : 5) void fwd_lds_kernel(
   static_assert(kThreads % GRP == 0, "tiles must hold whole groups");
   using AT = AtomPH;
   __shared__ AT tile[kThreads];
+  __shared__ float wmax[kThreads / 64];
   const int lb = xcd_major_block(blockIdx.x, gridDim.x);
   const int kb = lb % blocks_k;
   const int sp = lb / blocks_k;
   const int64_t k0 = int64_t(kb) * (kThreads * P) + threadIdx.x;
   double sx[P], sy[P], sz[P];
   float sr[P], si[P], cr[P], ci[P];
+  float s1 = 0.f;                           // the lane's |Sx| + |Sy| + |Sz| (largest over p)
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     const int64_t k = k0 + int64_t(p) * kThreads;
@@ -333,6 +383,7 @@ __global__ __launch_bounds__(kThreads, INL ? 4 : 5) void fwd_lds_kernel(
     sx[p] = S[3 * kk];
     sy[p] = S[3 * kk + 1];
     sz[p] = S[3 * kk + 2];
+    s1 = fmaxf(s1, bound_abs(fabs(sx[p]) + fabs(sy[p]) + fabs(sz[p])));
     if (carry_in && k < K) {
       const float4 st = part[int64_t(sp) * K + k];
       sr[p] = st.x; si[p] = st.y; cr[p] = st.z; ci[p] = st.w;
@@ -340,19 +391,9 @@ __global__ __launch_bounds__(kThreads, INL ? 4 : 5) void fwd_lds_kernel(
       sr[p] = 0.f; si[p] = 0.f; cr[p] = 0.f; ci[p] = 0.f;
     }
   }
-  const int j0 = a_begin + sp * per_split;
-  const int j1 = min(j0 + per_split, a_end);
-  for (int t0 = j0; t0 < j1; t0 += kThreads) {
-    const int nt = min(kThreads, j1 - t0);
-    __syncthreads();                        // the previous tile is no longer read
-    if (int(threadIdx.x) < nt) {
-      if constexpr (INL)      // f = 1 (FK == 0): no factor to take apart
-        tile[threadIdx.x] = make_atom_ph(xyz, FK ? f : nullptr, t0 + threadIdx.x, RED == 1 ? 0.5 : 0.0,
-                                         GRP, RED == 1 ? -1.f : 1.f);
-      else
-        tile[threadIdx.x] = rec[t0 + threadIdx.x];
-    }
-    __syncthreads();
+  // the groups of one tile, reduced with the variant R
+  auto run_tile = [&](auto red_c, int nt) {
+    constexpr int R = decltype(red_c)::value;
     int u0 = 0;
     for (; u0 + GRP <= nt; u0 += GRP) {
       const float ck = tile[u0].ck, sk = tile[u0].sk;
@@ -366,7 +407,7 @@ __global__ __launch_bounds__(kThreads, INL ? 4 : 5) void fwd_lds_kernel(
 #pragma unroll
           for (int p = 0; p < P; ++p) {
             float c, s;
-            cis_ph64<RED>(sx[p], sy[p], sz[p], a, c, s);
+            cis_ph64<R>(sx[p], sy[p], sz[p], a, c, s);
             if (u == 0) first_term<FK>(a, c, s, qr[p], qi[p]);
             else add_term<FK>(a, c, s, qr[p], qi[p]);
           }
@@ -390,12 +431,48 @@ __global__ __launch_bounds__(kThreads, INL ? 4 : 5) void fwd_lds_kernel(
 #pragma unroll
         for (int p = 0; p < P; ++p) {
           float c, s;
-          cis_ph64<RED>(sx[p], sy[p], sz[p], a, c, s);
+          cis_ph64<R>(sx[p], sy[p], sz[p], a, c, s);
           add_term<FK>(a, c, s, gr[p], gi[p]);
         }
       }
 #pragma unroll
       for (int p = 0; p < P; ++p) kahan_rot(sr[p], cr[p], si[p], ci[p], gr[p], gi[p], ck, sk);
+    }
+  };
+  const int j0 = a_begin + sp * per_split;
+  const int j1 = min(j0 + per_split, a_end);
+  for (int t0 = j0; t0 < j1; t0 += kThreads) {
+    const int nt = min(kThreads, j1 - t0);
+    __syncthreads();                        // the previous tile is no longer read
+    float am = 0.f;
+    if (int(threadIdx.x) < nt) {
+      if constexpr (INL) {    // f = 1 (FK == 0): no factor to take apart
+        const AT r = make_atom_ph(xyz, FK ? f : nullptr, t0 + threadIdx.x,
+                                  kPhaseShift + (RED == 1 ? 0.5 : 0.0), GRP, RED == 1 ? -1.f : 1.f);
+        tile[threadIdx.x] = r;
+        am = fmaxf(bound_abs(r.x), fmaxf(bound_abs(r.y), bound_abs(r.z)));
+      } else {
+        tile[threadIdx.x] = rec[t0 + threadIdx.x];
+      }
+    }
+    if constexpr (INL && RED == 2) {
+      am = wave_max(am);
+      if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = am;
+    }
+    __syncthreads();
+    if constexpr (RED == 2) {
+      float rt;
+      if constexpr (INL) {
+        rt = wmax[0];
+#pragma unroll
+        for (int w = 1; w < kThreads / 64; ++w) rt = fmaxf(rt, wmax[w]);
+      } else {
+        rt = fmaxf(tile[0].rmax, tile[nt - 1].rmax);
+      }
+      if (__all(s1 * rt < kFixedPhaseBound)) run_tile(std::integral_constant<int, 2>{}, nt);
+      else run_tile(std::integral_constant<int, 3>{}, nt);
+    } else {
+      run_tile(std::integral_constant<int, RED>{}, nt);
     }
   }
 #pragma unroll
@@ -463,15 +540,19 @@ __global__ __launch_bounds__(kThreads) void fwd_f64_kernel(
 // lane i folds splits i, i + G, i + 2G, ... in sequence with Knuth's two-sum, then the G
 // states are combined by a butterfly in which both partners fold the lower lane's state
 // first, so that every lane holds the same total and the order of the additions is a
-// fixed tree.  Few splits take G = 1 (one thread per point, splits in sequence).
+// fixed tree.  Few splits take G = 1 (one thread per point, splits in sequence).  A wave
+// serves 64 / G consecutive points side by side (its lane w: point w % (64 / G), split
+// lane w / (64 / G)), so that each load reads whole runs of consecutive partial states.
 template <int G>
 __global__ __launch_bounds__(kThreads) void fwd_reduce_kernel(const float4* __restrict__ part,
                                                               int nsplit, int64_t K,
                                                               float2* __restrict__ A) {
   static_assert(G >= 1 && G <= 64 && (G & (G - 1)) == 0, "G: a power of two within a wave");
+  constexpr int OPW = 64 / G;               // outputs per wave, side by side
   const int64_t t = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-  const int64_t k = t / G;
-  const int lane = static_cast<int>(t % G);
+  const int w = static_cast<int>(t & 63);
+  const int64_t k = (t >> 6) * OPW + (w % OPW);
+  const int lane = w / OPW;
   float sr = 0.f, si = 0.f, cr = 0.f, ci = 0.f;
   if (k < K) {
 #pragma unroll 4
@@ -485,8 +566,8 @@ __global__ __launch_bounds__(kThreads) void fwd_reduce_kernel(const float4* __re
   }
 #pragma unroll
   for (int off = 1; off < G; off <<= 1) {
-    const float osr = __shfl_xor(sr, off), osi = __shfl_xor(si, off);
-    const float ocr = __shfl_xor(cr, off), oci = __shfl_xor(ci, off);
+    const float osr = __shfl_xor(sr, off * OPW), osi = __shfl_xor(si, off * OPW);
+    const float ocr = __shfl_xor(cr, off * OPW), oci = __shfl_xor(ci, off * OPW);
     const bool upper = (lane & off) != 0;      // the partner is the lower lane: fold it first
     float ar = upper ? osr : sr, ai = upper ? osi : si, ac = upper ? ocr : cr, aci = upper ? oci : ci;
     const float br = upper ? sr : osr, bi = upper ? si : osi, bc = upper ? cr : ocr, bci = upper ? ci : oci;
@@ -567,38 +648,53 @@ hipError_t fwd_dispatch_red(const Plan& p, const void* rec, int64_t a_begin, int
   }
   if constexpr (MODE == kPH64) {
     if (p.lds && (p.grp == 16 || p.grp == 8)) {
+      // records formed while staging (small calls): one point per lane, the fixed-point
+      // reduction
+      const bool inl = P == 1 && p.inl && red == 2;
+      auto launch = [&](auto grp_c, auto red_c, auto inl_c) {
+        fwd_lds_kernel<P, FK, decltype(grp_c)::value, decltype(red_c)::value, decltype(inl_c)::value>
+            <<<grid, kThreads, 0, st>>>(decltype(inl_c)::value ? nullptr : r, int(a_begin), int(a_end),
+                                        int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in,
+                                        direct, xyz, f);
+      };
+      using I16 = std::integral_constant<int, 16>;
+      using I8 = std::integral_constant<int, 8>;
+      using R0 = std::integral_constant<int, 0>;
+      using R1 = std::integral_constant<int, 1>;
+      using R2 = std::integral_constant<int, 2>;
+      using NoInl = std::integral_constant<bool, false>;
       if constexpr (P == 1) {
-        if (p.inl && red == 0) {          // records formed while staging (small calls)
-          if (p.grp == 16)
-            fwd_lds_kernel<1, FK, 16, 0, true><<<grid, kThreads, 0, st>>>(
-                nullptr, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a,
-                carry_in, direct, xyz, f);
-          else
-            fwd_lds_kernel<1, FK, 8, 0, true><<<grid, kThreads, 0, st>>>(
-                nullptr, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a,
-                carry_in, direct, xyz, f);
+        if (inl) {
+          if (p.grp == 16) launch(I16{}, R2{}, std::integral_constant<bool, true>{});
+          else launch(I8{}, R2{}, std::integral_constant<bool, true>{});
           return hipGetLastError();
         }
       }
-      if (p.grp == 16 && red == 0)
-        fwd_lds_kernel<P, FK, 16, 0, false><<<grid, kThreads, 0, st>>>(
-            r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct,
-            nullptr, nullptr);
-      else if (p.grp == 16)
-        fwd_lds_kernel<P, FK, 16, 1, false><<<grid, kThreads, 0, st>>>(
-            r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct,
-            nullptr, nullptr);
-      else if (red == 0)
-        fwd_lds_kernel<P, FK, 8, 0, false><<<grid, kThreads, 0, st>>>(
-            r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct,
-            nullptr, nullptr);
-      else
-        fwd_lds_kernel<P, FK, 8, 1, false><<<grid, kThreads, 0, st>>>(
-            r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct,
-            nullptr, nullptr);
+      // the fixed-point forms exist where their two tile loops fit the registers (the
+      // plan sends the others to the centred form)
+      if (p.grp == 16) {
+        if constexpr (P <= 2) {
+          if (red == 2) {
+            launch(I16{}, R2{}, NoInl{});
+            return hipGetLastError();
+          }
+        }
+        if (red == 1) launch(I16{}, R1{}, NoInl{});
+        else launch(I16{}, R0{}, NoInl{});
+      } else {
+        if constexpr (P == 1) {
+          if (red == 2) {
+            launch(I8{}, R2{}, NoInl{});
+            return hipGetLastError();
+          }
+        }
+        if (red == 1) launch(I8{}, R1{}, NoInl{});
+        else launch(I8{}, R0{}, NoInl{});
+      }
       return hipGetLastError();
     }
   }
+  if (red == 2) red = 0;         // the scalar-load form has no per-tile bound: centred
   if (p.grp == 16 && red == 0)
     fwd_kernel<MODE, P, FK, 16, 0><<<grid, kThreads, 0, st>>>(
         r, int(a_begin), int(a_end), int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in, direct);
@@ -663,7 +759,8 @@ hipError_t launch_pack_atoms(int mode, int red, int grp, const void* xyz, const 
   if (mode == kF64) pack_atoms_kernel<kF64><<<g, kThreads, 0, st>>>(xyz, f, n, rec);
   else if (mode == kPH64)
     pack_atoms_ph_kernel<<<g, kThreads, 0, st>>>(static_cast<const float*>(xyz), static_cast<const float*>(f), n,
-                                                 static_cast<AtomPH*>(rec), red == 1 ? 0.5 : 0.0, grp,
+                                                 static_cast<AtomPH*>(rec),
+                                                 kPhaseShift + (red == 1 ? 0.5 : 0.0), grp,
                                                  red == 1 ? -1.f : 1.f);
   else pack_atoms_kernel<kF32><<<g, kThreads, 0, st>>>(xyz, f, n, rec);
   return hipGetLastError();
@@ -690,7 +787,8 @@ namespace {
 template <int G>
 void fwd_reduce_launch(const Plan& p, const void* partial, void* A, hipStream_t st) {
   const int64_t K = p.lanes;
-  const unsigned g = static_cast<unsigned>((K * G + kThreads - 1) / kThreads);
+  const int64_t waves = (K + 64 / G - 1) / (64 / G);
+  const unsigned g = static_cast<unsigned>((waves * 64 + kThreads - 1) / kThreads);
   fwd_reduce_kernel<G><<<g, kThreads, 0, st>>>(static_cast<const float4*>(partial), p.nsplit, K,
                                               static_cast<float2*>(A));
 }
@@ -704,7 +802,7 @@ hipError_t launch_fwd_reduce(const Plan& p, const void* partial, void* A, hipStr
                                                  static_cast<double2*>(A));
     return hipGetLastError();
   }
-  switch (reduce_lanes(p.nsplit)) {
+  switch (reduce_lanes(p.nsplit, K)) {
     case 64: fwd_reduce_launch<64>(p, partial, A, st); break;
     case 32: fwd_reduce_launch<32>(p, partial, A, st); break;
     case 16: fwd_reduce_launch<16>(p, partial, A, st); break;

@@ -19,24 +19,58 @@ constexpr int kThreads = 256;          // work-group size of every sum kernel (4
 // Atom for the FP32 mode: coordinates and factor in FP32.
 struct alignas(16) AtomF32 { float x, y, z, fr, fi, pad0, pad1, pad2; };            // 32 B
 // Atom for the FP64-phase mode (f = 1 and complex f alike): coordinates widened (exactly)
-// to FP64; a (FP64, cycles) = arg f + the reduction offset of the variant + the eighth
-// turn k/8 of the atom's compensated group; m (FP32) = |f| rounded without bias
-// (stochastic rounding keyed by the atom index; 1 for f = 1); (ck, sk) = the group's
-// turn-back factor exp(-2 i pi k/8), negated for the fract variant.
-struct alignas(16) AtomPH { double x, y, z, a; float m, ck, sk, pad; };              // 48 B
+// to FP64; a (FP64, cycles) = arg f + kPhaseShift + the reduction offset of the variant +
+// the eighth turn k/8 of the atom's compensated group; m (FP32) = |f| rounded without
+// bias (stochastic rounding keyed by the atom index; 1 for f = 1); (ck, sk) = the group's
+// turn-back factor exp(-2 i pi k/8), negated for the fract variant; rmax = the largest
+// |x|, |y| or |z| among the 256 records of the record's block of the pack (+inf if any is
+// not finite), the tile bound of the fixed-point reduction.
+struct alignas(16) AtomPH { double x, y, z, a; float m, ck, sk, rmax; };             // 48 B
 // Atom for the all-FP64 path.
 struct alignas(16) AtomF64 { double x, y, z, fr, fi, pad; };                         // 48 B
 // Point for the FP32-mode adjoint: S and the seed G.
 struct alignas(16) PointF32 { float sx, sy, sz, gr, gi, pad0, pad1, pad2; };         // 32 B
 // Point for the FP64-phase adjoint, with the seed in polar form conj(G) =
-// |G| exp(2 i pi delta): S (FP64) and delta (cycles, FP64, plus the reduction offset of
-// the variant) for the phase in the first 32 bytes, |G| S and |G| (FP32) for the
+// |G| exp(2 i pi delta): S (FP64) and delta (cycles, FP64, plus kPhaseShift and the
+// reduction offset of the variant) for the phase in the first 32 bytes, |G| S and |G| (FP32) for the
 // multiply-adds into the per-atom sums in the last 16.  sx and delta come first: they
 // are the two point values of the phase's first fma, which the adjoint reads from an
 // LDS tile (an fma takes at most one scalar operand), the rest with scalar loads.
 struct alignas(16) PointPH { double sx, delta, sy, sz; float gsx, gsy, gsz, gmag; }; // 48 B
 // Point for the all-FP64 adjoint.
 struct alignas(16) PointF64 { double sx, sy, sz, gr, gi, pad; };                     // 48 B
+
+// The FP64-phase reductions of the phase psi = S.r + addend to a turn in [-1/2, 1/2]:
+//   0 centred: t = psi - rint(psi), exact in FP64, rounded once to FP32;
+//   1 fract:   u = fract(psi + 1/2) in [0, 1), rounded once to FP32 (the terms change sign);
+//   2 fixed point: every record's addend carries kPhaseShift = 1.5 * 2^20 cycles, an
+//     integer, so psi modulo one is unchanged.  While |psi - kPhaseShift| < 2^19, psi lies
+//     in [2^20, 2^21), where the last bit of an FP64 is worth 2^-32 cycles, and the low 32
+//     bits of its encoding are psi modulo one in 32-bit fixed point; read as a signed
+//     integer they are t * 2^32 with t the centred turn in [-1/2, 1/2).  One integer to
+//     FP32 conversion (rounded as the FP64 to FP32 one of the centred form) and a scaling
+//     by 2^-32 replace the rounding, the subtraction and the FP64 to FP32 conversion.  The
+//     three fma of the phase round at 2^-33 cycles each in that range (against about 2^-26
+//     for the FP32 rounding of the turn), and the terms are those of the centred form but at
+//     exactly half a turn (-1/2 here, +-1/2 after rint).  Every tile of records checks
+//     the range first: (|Sx| + |Sy| + |Sz|) max(|x|, |y|, |z|) < kFixedPhaseBound for every
+//     lane of the wave (the addends stay below 2 cycles from kPhaseShift), and a wave whose
+//     check fails reduces that tile's phases with rint and reads the low word of the reduced
+//     phase plus kPhaseShift (variant 3: the centred turn rounded to 2^-32 cycles, an extra
+//     error below 2^-33 cycles where the phase was finer; the same loop shape as variant 2,
+//     so the fallback does not raise the kernel's register count), on the same records.
+constexpr double kPhaseShift = 1572864.0;
+constexpr float kFixedPhaseBound = 524224.0f;     // 2^19 - 64
+
+// Tile bounds of the packed FP64-phase point records of the adjoint: one float per 256
+// records (the largest |Sx|, |Sy| or |Sz| of those points, +inf if any is not finite),
+// stored after the records.
+inline size_t point_bound_offset(int64_t n) {
+  return (static_cast<size_t>(n) * sizeof(PointPH) + 255) / 256 * 256;
+}
+inline size_t point_bound_bytes(int64_t n) {
+  return (static_cast<size_t>((n + kThreads - 1) / kThreads) * sizeof(float) + 255) / 256 * 256;
+}
 
 // Running state of one output lane item (a point for the forward, one component of
 // an atom's sum for the adjoint) kept between launches and across splits.
@@ -108,7 +142,7 @@ struct Plan {
   int per_lane = 1;      // lane items per lane (P points or Q atoms)
   int grp = 16;          // stream items per compensated group
   int fk = 0;            // 0: f_j = 1, 1: complex f_j
-  int red = 0;           // phase reduction variant of the FP64-phase kernels (0 centred, 1 fract)
+  int red = 0;           // phase reduction of the FP64-phase kernels (0 centred, 1 fract, 2 fixed point)
   int gf = 0;            // adjoint also returns dL/df
   int lds = 0;           // FP64-phase sums: record tiles staged in LDS instead of scalar loads
   int inl = 0;           // small calls: records formed in the sum kernel, no pack dispatch
@@ -163,9 +197,14 @@ constexpr int kMaxSpecies = 16;   // species of the factorised entry points
 // Lanes that serve one output in the split reduction (a power of two, 4 to 64): about a
 // quarter of the number of splits, so that each lane folds about four splits in sequence
 // and the lanes' states meet in a short fixed butterfly; one lane per output (splits in
-// sequence) below 8 splits.
-inline int reduce_lanes(int nsplit) {
+// sequence) below 8 splits.  A wave holds 64 / G outputs side by side (consecutive lanes,
+// consecutive outputs), so that one load reads 64 / G consecutive entries of G split rows:
+// with many outputs (kReduceWideOutputs and up, which fill the chip with 4 lanes each) G
+// stays at 4, whole 64-byte lines per row, instead of over-fetching lines for a few bytes.
+constexpr int64_t kReduceWideOutputs = 16384;
+inline int reduce_lanes(int nsplit, int64_t outputs) {
   if (nsplit < 8) return 1;
+  if (outputs >= kReduceWideOutputs) return 4;
   const int want = (nsplit + 3) / 4;
   int g = 4;
   while (g < 64 && g < want) g <<= 1;

@@ -68,8 +68,13 @@ struct ClockMark {
   }
 };
 
-// FP64-phase forward: psi = 3 FP64 fma; centred reduction (rint, subtract, cvt);
-// cos, sin; m (c + i s) with 2 FP32 fma (complex f) or 2 adds (f = 1).
+// The phase shift of the FP64-phase records (1.5 * 2^20 cycles): the phase then lies in
+// [2^20, 2^21), and its low word is the centred turn in 32-bit fixed point.
+constexpr double kShift = 1572864.0;
+
+// FP64-phase forward: psi = 3 FP64 fma (the shift in the addend); the fixed-point turn
+// (v_cvt_f32_i32 of the low word, scaled by 2^-32); cos, sin; m (c + i s) with 2 FP32 fma
+// (complex f) or 2 adds (f = 1).
 template <bool CF, int kPairs, int OCC>
 __global__ __launch_bounds__(kThreads, OCC) void mix_fwd_ph64(int iters, float* out, unsigned long long* clk) {
   ClockMark cm;
@@ -82,7 +87,7 @@ __global__ __launch_bounds__(kThreads, OCC) void mix_fwd_ph64(int iters, float* 
     sx[p] = 1.0 + 1e-7 * lane + 0.01 * p;
     sy[p] = 0.5 - 2e-7 * lane + 0.02 * p;
     sz[p] = 4.0 + 3e-7 * lane - 0.01 * p;
-    a0[p] = 1e-8 * lane + 0.125 * p;
+    a0[p] = kShift + 1e-8 * lane + 0.125 * p;
     ar[p] = 0.f;
     ai[p] = 0.f;
     opaque(sx[p]);
@@ -98,7 +103,7 @@ __global__ __launch_bounds__(kThreads, OCC) void mix_fwd_ph64(int iters, float* 
 #pragma unroll
     for (int p = 0; p < kPairs; ++p) {
       const double ph = __builtin_fma(sz[p], z, __builtin_fma(sy[p], y, __builtin_fma(sx[p], x, a0[p])));
-      const float t = static_cast<float>(ph - __builtin_rint(ph));
+      const float t = static_cast<float>(__double2loint(ph)) * 0x1.0p-32f;
       const float c = __builtin_amdgcn_cosf(t);
       const float s = __builtin_amdgcn_sinf(t);
       if constexpr (CF) {
@@ -117,8 +122,9 @@ __global__ __launch_bounds__(kThreads, OCC) void mix_fwd_ph64(int iters, float* 
   cm.stop(clk);
 }
 
-// FP64-phase adjoint: psi = 3 FP64 fma (+ 1 FP64 add of the atom's angle for complex f);
-// fract, cvt; sin; T_d += (|G| S_d) sin with 3 FP32 fma.
+// FP64-phase adjoint: psi = 3 FP64 fma (+ 1 FP64 add of the atom's angle for complex f;
+// the shift in the point's addend); the fixed-point turn (v_cvt_f32_i32 of the low word,
+// scaled); sin; T_d += (|G| S_d) sin with 3 FP32 fma.
 template <bool CF, int kPairs, int OCC>
 __global__ __launch_bounds__(kThreads, OCC) void mix_bwd_ph64(int iters, float* out, unsigned long long* clk) {
   ClockMark cm;
@@ -131,7 +137,7 @@ __global__ __launch_bounds__(kThreads, OCC) void mix_bwd_ph64(int iters, float* 
     x[p] = 10.0 + 1e-6 * lane + 0.5 * p;
     y[p] = 20.0 - 2e-6 * lane + 0.25 * p;
     z[p] = 30.0 + 3e-6 * lane - 0.5 * p;
-    d0[p] = 1e-8 * lane + 0.1 * p;
+    d0[p] = kShift + 1e-8 * lane + 0.1 * p;
     al[p] = 0.3 - 2e-8 * lane - 0.05 * p;
     t0[p] = t1[p] = t2[p] = 0.f;
     opaque(x[p]);
@@ -150,7 +156,7 @@ __global__ __launch_bounds__(kThreads, OCC) void mix_bwd_ph64(int iters, float* 
     for (int p = 0; p < kPairs; ++p) {
       double ph = __builtin_fma(sz, z[p], __builtin_fma(sy, y[p], __builtin_fma(sx, x[p], d0[p])));
       if constexpr (CF) ph += al[p];
-      const float t = static_cast<float>(__builtin_amdgcn_fract(ph));
+      const float t = static_cast<float>(__double2loint(ph)) * 0x1.0p-32f;
       const float s = __builtin_amdgcn_sinf(t);
       t0[p] = __builtin_fmaf(s, gx, t0[p]);
       t1[p] = __builtin_fmaf(s, gy, t1[p]);
@@ -161,6 +167,90 @@ __global__ __launch_bounds__(kThreads, OCC) void mix_bwd_ph64(int iters, float* 
 #pragma unroll
   for (int p = 0; p < kPairs; ++p) acc += t0[p] - t1[p] + t2[p];
   out[threadIdx.x + blockIdx.x * kThreads] = acc;
+  cm.stop(clk);
+}
+
+// The same FP64-phase sequences in the sums' own shape: few lane items (1 point for the
+// forward, 2 atoms for the adjoint) and kTile wave-uniform stream items per iteration,
+// unrolled, as the sums' inner loops walk a group of records.
+constexpr int kTile = 16;
+
+template <bool CF>
+__global__ __launch_bounds__(kThreads, 8) void mix_fwd_ph64_tile(int iters, float* out, unsigned long long* clk) {
+  ClockMark cm;
+  cm.start();
+  const double lane = static_cast<double>(threadIdx.x + blockIdx.x * kThreads);
+  double sx = 1.0 + 1e-7 * lane, sy = 0.5 - 2e-7 * lane, sz = 4.0 + 3e-7 * lane;
+  float ar = 0.f, ai = 0.f;
+  opaque(sx);
+  opaque(sy);
+  opaque(sz);
+  for (int j = 0; j < iters; ++j) {
+#pragma unroll
+    for (int t = 0; t < kTile; ++t) {
+      const double x = uniform_f64(0x40240000u + t, 0x9999999au, j);      // ~10
+      const double y = uniform_f64(0x40340000u + t, 0x33333333u, j);      // ~20
+      const double z = uniform_f64(0x403e0000u + t, 0xccccccccu, j);      // ~30
+      const double a = kShift + 0.125 * t;
+      const float m = uniform_f32(0x41f80000u + (t << 8), j);              // ~31
+      const double ph = __builtin_fma(sz, z, __builtin_fma(sy, y, __builtin_fma(sx, x, a)));
+      const float tt = static_cast<float>(__double2loint(ph)) * 0x1.0p-32f;
+      const float c = __builtin_amdgcn_cosf(tt);
+      const float s = __builtin_amdgcn_sinf(tt);
+      if constexpr (CF) {
+        ar = __builtin_fmaf(m, c, ar);
+        ai = __builtin_fmaf(m, s, ai);
+      } else {
+        ar += c;
+        ai += s;
+      }
+    }
+  }
+  out[threadIdx.x + blockIdx.x * kThreads] = ar - ai;
+  cm.stop(clk);
+}
+
+template <bool CF>
+__global__ __launch_bounds__(kThreads, 8) void mix_bwd_ph64_tile(int iters, float* out, unsigned long long* clk) {
+  ClockMark cm;
+  cm.start();
+  const double lane = static_cast<double>(threadIdx.x + blockIdx.x * kThreads);
+  double x[2], y[2], z[2], al[2];
+  float t0[2], t1[2], t2[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    x[q] = 10.0 + 1e-6 * lane + 0.5 * q;
+    y[q] = 20.0 - 2e-6 * lane + 0.25 * q;
+    z[q] = 30.0 + 3e-6 * lane - 0.5 * q;
+    al[q] = 0.3 - 2e-8 * lane - 0.05 * q;
+    t0[q] = t1[q] = t2[q] = 0.f;
+    opaque(x[q]);
+    opaque(y[q]);
+    opaque(z[q]);
+    opaque(al[q]);
+  }
+  for (int j = 0; j < iters; ++j) {
+#pragma unroll
+    for (int t = 0; t < kTile; ++t) {
+      const double sx = uniform_f64(0x3ff00000u + t, 0x9999999au, j);     // ~1
+      const double sy = uniform_f64(0x3fe00000u + t, 0x33333333u, j);     // ~0.5
+      const double sz = uniform_f64(0x40100000u + t, 0xccccccccu, j);     // ~4
+      const double d0 = kShift + 0.1 * t;
+      const float gx = uniform_f32(0x3f800000u + (t << 8), j), gy = uniform_f32(0x3f000000u + (t << 8), j),
+                  gz = uniform_f32(0x40800000u + (t << 8), j);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        double ph = __builtin_fma(sz, z[q], __builtin_fma(sy, y[q], __builtin_fma(sx, x[q], d0)));
+        if constexpr (CF) ph += al[q];
+        const float tt = static_cast<float>(__double2loint(ph)) * 0x1.0p-32f;
+        const float s = __builtin_amdgcn_sinf(tt);
+        t0[q] = __builtin_fmaf(s, gx, t0[q]);
+        t1[q] = __builtin_fmaf(s, gy, t1[q]);
+        t2[q] = __builtin_fmaf(s, gz, t2[q]);
+      }
+    }
+  }
+  out[threadIdx.x + blockIdx.x * kThreads] = t0[0] - t1[0] + t2[0] + t0[1] - t1[1] + t2[1];
   cm.stop(clk);
 }
 
@@ -265,7 +355,13 @@ __global__ __launch_bounds__(kThreads, OCC) void mix_bwd_f32(int iters, float* o
 // fma with a scalar operand (the three-operand encoding, v_fma_f32), 1 FP64 fma likewise,
 // 2 v_sin_f32 on a turn in [-1/2, 1/2], 3 and 4 FP32 and FP64 fma accumulating into their
 // destination with vector operands only (the two-operand encodings v_fmac_f32_e32,
-// v_fmac_f64_e32, which the sums' inner loops mostly use).
+// v_fmac_f64_e32, which the sums' inner loops mostly use), then the other kinds of the
+// sums' loops: 5 v_add_f64, 6 v_rndne_f64, 7 v_fract_f64, 8 v_cvt_f32_i32 (on the bits of
+// the previous result, a chain the compiler cannot fold), 9 v_cos_f32, 10 v_mul_f32_e32,
+// 11 FP32 fma with vector operands only in the three-operand encoding (v_fma_f32,
+// destination not the addend), 12 v_add_f32_e32.  The roundings, whose repetition the
+// compiler could fold, pass their result through opaque() at every step, which adds no
+// instruction.
 template <int OP, int NP>
 __global__ __launch_bounds__(kThreads, 8) void op_rate(int iters, float* out, unsigned long long* clk) {
   ClockMark cm;
@@ -295,7 +391,15 @@ __global__ __launch_bounds__(kThreads, 8) void op_rate(int iters, float* out, un
         else if constexpr (OP == 1) w[i] = __builtin_fma(w[i], ad, 1e-7);
         else if constexpr (OP == 2) v[i] = __builtin_amdgcn_sinf(v[i]);
         else if constexpr (OP == 3) v[i] = __builtin_fmaf(bv, cv, v[i]);
-        else w[i] = __builtin_fma(bw, cw, w[i]);
+        else if constexpr (OP == 4) w[i] = __builtin_fma(bw, cw, w[i]);
+        else if constexpr (OP == 5) w[i] = w[i] + cw;
+        else if constexpr (OP == 6) { w[i] = __builtin_rint(w[i]); opaque(w[i]); }
+        else if constexpr (OP == 7) { w[i] = __builtin_amdgcn_fract(w[i]); opaque(w[i]); }
+        else if constexpr (OP == 8) v[i] = static_cast<float>(__float_as_int(v[i]));
+        else if constexpr (OP == 9) v[i] = __builtin_amdgcn_cosf(v[i]);
+        else if constexpr (OP == 10) v[i] = v[i] * bv;
+        else if constexpr (OP == 11) v[i] = __builtin_fmaf(v[i], bv, cv);
+        else v[i] = v[i] + cv;
       }
     }
   }
@@ -311,8 +415,14 @@ __global__ __launch_bounds__(kThreads, 8) void op_rate(int iters, float* out, un
 extern "C" {
 
 int nxm_pairs_per_lane_iter(int mix, int wide) {
-  if (mix >= NXM_OP_FMA_F32 && mix <= NXM_OP_FMAC_F64) return 4 * (wide ? 16 : 8);
-  const int np = (mix >= NXM_FWD_PH64_CF && mix <= NXM_BWD_PH64_F1) ? kPairs64 : kPairs32;
+  if (wide < 0 || wide > 2) return 0;
+  if (mix >= NXM_OP_FMA_F32 && mix <= NXM_OP_ADD_F32) return wide == 2 ? 0 : 4 * (wide ? 16 : 8);
+  const bool ph64 = mix >= NXM_FWD_PH64_CF && mix <= NXM_BWD_PH64_F1;
+  if (wide == 2) {     // the sums' shape: FP64-phase mixes only
+    if (!ph64) return 0;
+    return (mix == NXM_BWD_PH64_CF || mix == NXM_BWD_PH64_F1) ? 2 * kTile : kTile;
+  }
+  const int np = ph64 ? kPairs64 : kPairs32;
   return wide ? 2 * np : np;
 }
 
@@ -327,7 +437,20 @@ int nxm_wallclock_khz(void) {
 
 int nxm_run(int mix, int wide, int n_blocks, int iters, float* out, unsigned long long* clk,
             void* stream) {
-  if (n_blocks < 1 || iters < 1 || !out || (wide != 0 && wide != 1)) return -1;
+  if (n_blocks < 1 || iters < 1 || !out || wide < 0 || wide > 2) return -1;
+  if (wide == 2 && mix >= NXM_OP_FMA_F32) return -1;
+  if (wide == 2) {
+    const dim3 g(static_cast<unsigned>(n_blocks));
+    const hipStream_t s2 = static_cast<hipStream_t>(stream);
+    switch (mix) {
+      case NXM_FWD_PH64_CF: mix_fwd_ph64_tile<true><<<g, kThreads, 0, s2>>>(iters, out, clk); break;
+      case NXM_FWD_PH64_F1: mix_fwd_ph64_tile<false><<<g, kThreads, 0, s2>>>(iters, out, clk); break;
+      case NXM_BWD_PH64_CF: mix_bwd_ph64_tile<true><<<g, kThreads, 0, s2>>>(iters, out, clk); break;
+      case NXM_BWD_PH64_F1: mix_bwd_ph64_tile<false><<<g, kThreads, 0, s2>>>(iters, out, clk); break;
+      default: return -1;      // the FP32 mixes have no such shape
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -4;
+  }
   const hipStream_t st = static_cast<hipStream_t>(stream);
   const dim3 grid(static_cast<unsigned>(n_blocks));
 #define NXM_CASE(ID, KERNEL, CF, NP)                                                        \
@@ -354,6 +477,14 @@ int nxm_run(int mix, int wide, int n_blocks, int iters, float* out, unsigned lon
     NXM_OP(NXM_OP_SIN_F32, 2)
     NXM_OP(NXM_OP_FMAC_F32, 3)
     NXM_OP(NXM_OP_FMAC_F64, 4)
+    NXM_OP(NXM_OP_ADD_F64, 5)
+    NXM_OP(NXM_OP_RNDNE_F64, 6)
+    NXM_OP(NXM_OP_FRACT_F64, 7)
+    NXM_OP(NXM_OP_CVT_F32_I32, 8)
+    NXM_OP(NXM_OP_COS_F32, 9)
+    NXM_OP(NXM_OP_MUL_F32, 10)
+    NXM_OP(NXM_OP_FMA_F32_V, 11)
+    NXM_OP(NXM_OP_ADD_F32, 12)
     default: return -2;
   }
 #undef NXM_CASE

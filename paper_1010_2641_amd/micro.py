@@ -15,7 +15,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnx_micro.so")
 
 # single instruction kinds of include/nx_micro.h
-OPS = {"fma_f32": 8, "fma_f64": 9, "sin_f32": 10, "fmac_f32": 11, "fmac_f64": 12}
+OPS = {"fma_f32": 8, "fma_f64": 9, "sin_f32": 10, "fmac_f32": 11, "fmac_f64": 12,
+       "add_f64": 13, "rndne_f64": 14, "fract_f64": 15, "cvt_f32_i32": 16, "cos_f32": 17,
+       "mul_f32": 18, "fma_f32_v": 19, "add_f32": 20}
 
 # (mode, sum, factor kind) -> mix id of include/nx_micro.h
 MIXES = {
@@ -55,8 +57,9 @@ nxm_run = lib.nxm_run
 
 
 def _rate(mix: int, n_blocks: int, iters: int, reps: int):
-    """(best items per second over the two kernel shapes, clock in GHz of that launch):
-    `reps` timed launches of each shape after one warm-up, events on the current stream."""
+    """(best items per second over the kernel shapes, clock in GHz of that launch): `reps`
+    timed launches of each shape the mix has after one warm-up, events on the current
+    stream; every shape runs about the same number of items per lane."""
     import torch
     threads = nxm_threads_per_block()
     out = torch.empty(n_blocks * threads, dtype=torch.float32, device="cuda")
@@ -64,9 +67,13 @@ def _rate(mix: int, n_blocks: int, iters: int, reps: int):
     stream = torch.cuda.current_stream()
     khz = nxm_wallclock_khz()
     best, ghz = 0.0, None
-    for wide in (0, 1):
-        it = iters if not wide else iters // 2
-        items = float(n_blocks) * threads * it * nxm_pairs_per_lane_iter(mix, wide)
+    base = nxm_pairs_per_lane_iter(mix, 0)
+    for wide in (0, 1, 2):
+        per = nxm_pairs_per_lane_iter(mix, wide)
+        if per <= 0:
+            continue
+        it = max(1, iters * base // per)
+        items = float(n_blocks) * threads * it * per
         for r in range(reps + 1):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)

@@ -47,7 +47,13 @@ def test_micro_header_symbols_exported():
     assert micro.nxm_run(99, 0, 1, 1, FAKE, None, None) == -2
     assert micro.nxm_run(0, 0, 0, 1, FAKE, None, None) == -1
     assert micro.nxm_run(0, 0, 1, 1, None, None, None) == -1
-    assert micro.nxm_run(0, 2, 1, 1, FAKE, None, None) == -1
+    assert micro.nxm_run(0, 3, 1, 1, FAKE, None, None) == -1
+    # the sums' shape exists for the FP64-phase mixes only: refused before any launch
+    assert micro.nxm_pairs_per_lane_iter(0, 2) == 16 and micro.nxm_pairs_per_lane_iter(2, 2) == 32
+    assert micro.nxm_pairs_per_lane_iter(4, 2) == 0 and micro.nxm_pairs_per_lane_iter(8, 2) == 0
+    assert micro.nxm_pairs_per_lane_iter(0, 3) == 0
+    assert micro.nxm_run(4, 2, 1, 1, FAKE, None, None) == -1
+    assert micro.nxm_run(8, 2, 1, 1, FAKE, None, None) == -1
 
 
 def test_version():
@@ -268,9 +274,11 @@ def test_plan_launch_chunks_and_splits(monkeypatch):
 def test_plan_stream_splits_for_the_target_block_count(monkeypatch):
     """The adjoint of a 203,557-atom, 2,097,152-point fit: 398 work-groups of 512 atoms are
     too few, so the points are cut into ceil(32768 / 398) = 83 slices, each with its own
-    (sum, comp) state of the 3 position sums per atom (24 bytes)."""
+    (sum, comp) state of the 3 position sums per atom (24 bytes).  The 48-byte point records
+    are followed by one float per 256 points (the tiles' bound of the fixed-point phase
+    reduction)."""
     n, k = 203_557, 2_097_152
-    rec = -(-k * 48 // 256) * 256
+    rec = -(-k * 48 // 256) * 256 + -(-(-(-k // 256)) * 4 // 256) * 256
     part = -(-83 * n * 24 // 256) * 256
     assert _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_BWD, 0) == rec + part
     monkeypatch.setenv("NX_TUNE_TARGET_BLOCKS", "4096")              # ceil(4096 / 398) = 11

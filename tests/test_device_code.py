@@ -1,8 +1,11 @@
 """The gfx950 code the build produces, checked on the CPU (hipcc cross-compiles): no
 packed-FP32 instructions anywhere (their selection is disabled at compile time), no
-kernel that spills to scratch, the two hot kernels of the default FP64-phase path
-at 8 waves per SIMD (the forward's LDS-tiled kernel with one point per lane and the
-split adjoint with two atoms per lane), and the issue-ceiling microbenchmarks' loops
+kernel that spills to scratch, the two hot kernels of the default FP64-phase path at
+their occupancy (the forward's LDS-tiled kernel with one point per lane at 8 waves per
+SIMD; the split adjoint with two atoms per lane at 6, the register cost of its per-tile
+fallback loop: a build without that loop ran at 8 waves and no faster, 102.3 against
+101.9 ms on the 203,557-atom, 2,097,152-point adjoint), and the issue-ceiling
+microbenchmarks' loops
 made of exactly the per-pair instruction counts the benchmark prices its sums with."""
 import collections
 import concurrent.futures as cf
@@ -76,12 +79,12 @@ def test_no_scratch_spills(device_asm):
     assert n > 100          # every instantiation was seen
 
 
-def test_hot_kernels_at_eight_waves(device_asm):
+def test_hot_kernels_occupancy(device_asm):
     occ = {name: o for asm in device_asm.values() for name, _, o in kernel_notes(asm)}
-    want = {"fwd_lds_kernelILi1ELi1ELi16ELi0ELb0E": 8,      # forward, complex f, 16-atom groups
-            "fwd_lds_kernelILi1ELi0ELi16ELi0ELb0E": 8,      # forward, f = 1
-            "bwd_split_kernelILi2ELi1ELi64ELi1ELb0E": 8,    # adjoint, complex f
-            "bwd_split_kernelILi2ELi0ELi64ELi1ELb0E": 8}    # adjoint, f = 1
+    want = {"fwd_lds_kernelILi1ELi1ELi16ELi2ELb0E": 8,      # forward, complex f, 16-atom groups
+            "fwd_lds_kernelILi1ELi0ELi16ELi2ELb0E": 8,      # forward, f = 1
+            "bwd_split_kernelILi2ELi1ELi64ELi2ELb0ELb0E": 6,    # adjoint, complex f
+            "bwd_split_kernelILi2ELi0ELi64ELi2ELb0ELb0E": 6}    # adjoint, f = 1
     for key, o in want.items():
         found = [v for k, v in occ.items() if key in k]
         assert found, key
@@ -136,11 +139,29 @@ def test_micro_loops_are_the_priced_instruction_mixes(device_asm):
                            for k in c), (name, dict(c))
             seen += 1
     assert seen == 16
+    # the sums' own shape: 1 point (forward) or 2 atoms (adjoint) x 16 stream items
+    tiles = 0
+    for name, c in loops.items():
+        m = re.search(r"mix_(fwd|bwd)_ph64_tileILb([01])E", name)
+        if not m:
+            continue
+        op, fkind = m.group(1), "complex" if m.group(2) == "1" else "unit"
+        pairs = 16 * (2 if op == "bwd" else 1)
+        valu = sum(v for k, v in c.items() if k.startswith("v_"))
+        trans = c["v_sin_f32_e32"] + c["v_cos_f32_e32"]
+        assert valu == pairs * bench.ALG_SLOTS[("ph64", op, fkind)], (name, dict(c))
+        assert trans == pairs * (1 if op == "bwd" else 2), (name, dict(c))
+        assert not any(k.startswith(("scratch_", "global_load", "buffer_load", "ds_")) for k in c)
+        tiles += 1
+    assert tiles == 4
     # the single-instruction kernels: 4 steps of NP chains of one kind per iteration
-    kinds = {"0": "v_fma_f32", "1": "v_fma", "2": "v_sin_f32", "3": "v_fmac_f32_e32", "4": "v_fmac_f64_e32"}
+    kinds = {"0": "v_fma_f32", "1": "v_fma_f64", "2": "v_sin_f32", "3": "v_fmac_f32_e32",
+             "4": "v_fmac_f64_e32", "5": "v_add_f64", "6": "v_rndne_f64", "7": "v_fract_f64",
+             "8": "v_cvt_f32_i32", "9": "v_cos_f32", "10": "v_mul_f32_e32", "11": "v_fma_f32",
+             "12": "v_add_f32_e32"}
     ops = 0
     for name, c in loops.items():
-        m = re.search(r"op_rateILi(\d)ELi(\d+)E", name)
+        m = re.search(r"op_rateILi(\d+)ELi(\d+)E", name)
         if not m:
             continue
         valu = sum(v for k, v in c.items() if k.startswith("v_"))
@@ -148,4 +169,4 @@ def test_micro_loops_are_the_priced_instruction_mixes(device_asm):
         kind = sum(v for k, v in c.items() if k.startswith(kinds[m.group(1)]))
         assert valu == want and kind == want, (name, dict(c))
         ops += 1
-    assert ops == 10
+    assert ops == 26

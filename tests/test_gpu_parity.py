@@ -117,13 +117,14 @@ def test_fwd_chunked_launches(mode, monkeypatch):
     check_fwd(A, A_ref, mode, "chunked", f=f, n=len(xyz))
 
 
-@pytest.mark.parametrize("red", ["0", "1"])
+@pytest.mark.parametrize("red", ["0", "1", "2"])
 @pytest.mark.parametrize("grp", ["8", "16", "32"])
 @pytest.mark.parametrize("cplx", [True, False])
 def test_fwd_variants(red, grp, cplx, monkeypatch):
-    """Both phase-reduction variants and every group size meet the tolerances, for complex
-    f and f = 1 (the records' eighth turns and offsets follow the plan's variant and
-    group size; 32-atom groups run in the scalar-load form)."""
+    """Every phase-reduction variant (centred, fract, fixed point) and every group size
+    meet the tolerances, for complex f and f = 1 (the records' eighth turns and offsets
+    follow the plan's variant and group size; 32-atom groups run in the scalar-load form,
+    which takes the centred reduction for the fixed-point one)."""
     monkeypatch.setenv("NX_TUNE_RED", red)
     monkeypatch.setenv("NX_TUNE_GRP", grp)
     xyz, f, S = wl.random_problem(3001, 2100, seed=12, extent=80.0, s_range=6.0, complex_f=cplx)
@@ -256,7 +257,7 @@ def test_bwd_slice_length_boundaries(k, mode):
         assert en <= M.F64_T3_TOL
 
 
-@pytest.mark.parametrize("red", ["0", "1"])
+@pytest.mark.parametrize("red", ["0", "1", "2"])
 @pytest.mark.parametrize("grp", ["16", "32", "64"])
 def test_bwd_variants(red, grp, monkeypatch):
     monkeypatch.setenv("NX_TUNE_RED", red)
