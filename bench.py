@@ -225,7 +225,12 @@ def cpu_baseline(name, w, A_gpu, G, g_gpu, budget_s):
     pairs = float(w.n_atoms) * float(w.n_points)
     A_s = A_gpu[pts].astype(np.complex128)
     I, Ir = np.abs(A_s) ** 2, np.abs(A_ref) ** 2
-    m = Ir >= 1e-6 * Ir.max()
+    # T1's floor is 1e-6 of the map's strongest intensity, taken from the step's own
+    # amplitudes over every point (a threshold: the FP64-phase error does not move it);
+    # the sample alone may miss the strongest point (the Ewald scan's sample has no grid
+    # line through the reflection), which would admit points a thousand times weaker
+    Imax = max(float(Ir.max()), float(np.max(np.abs(A_gpu.astype(np.complex128)) ** 2)))
+    m = Ir >= 1e-6 * Imax
     g_s = g_gpu[atoms].astype(np.float64)
     err = {
         "fwd_T1_rel_I": float(np.max(np.abs(I[m] - Ir[m]) / Ir[m])),
