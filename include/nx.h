@@ -193,6 +193,46 @@ int nx_fit_step(const float* xyz, const float* f, int64_t n_atoms, const float* 
                 int64_t n_points, const float* I, float* A, double* L, float* G,
                 float* grad_xyz, int mode, void* ws, size_t ws_bytes, void* stream);
 
+/* A regular grid of reciprocal-space points, given exactly (FP64, r.l.u.): point
+ * (i1, i2, i3), 0 <= i_a < n_a, is S = origin + i1 step1 + i2 step2 + i3 step3, and the points
+ * are listed with i1 fastest, k = i1 + n1 (i2 + n2 i3) (the order of A, G and I).  The maps
+ * of reciprocal space around a reflection (Section 4's examples) are such grids.  The
+ * grid entry points compute the same sums as their point-list counterparts over these
+ * points, in the FP64-phase mode only (mode NX_F32_PH64; other modes: NX_ERR_MODE).  Where
+ * n1 is a multiple of 64 they walk the grid by rows: the phase S.r_j is i1 (step1.r_j)
+ * plus a row term formed once per atom and row, one FP64 fma per atom-point pair instead of
+ * three; otherwise they form every grid point in FP64 and run the point-list kernels.
+ * Counts: n_a >= 0, n1 n2 n3 <= NX_MAX_COUNT; origin and steps finite (else NX_ERR_ARG). */
+typedef struct nx_grid {
+  double origin[3], step1[3], step2[3], step3[3];
+  int64_t n1, n2, n3;
+} nx_grid;
+
+/* Workspace (bytes) of the grid entry points for op NX_OP_FWD (nx_scatter_fwd_grid),
+ * NX_OP_BWD (nx_scatter_bwd_grid) or NX_OP_FIT (nx_fit_step_grid); 0 with the error set
+ * for invalid arguments. */
+size_t nx_workspace_bytes_grid(int64_t n_atoms, const nx_grid* grid, int op, int f_is_null);
+
+/* Forward sum (Eq. 2) over the points of `grid` (host pointer):
+ *   A_k = sum_j f_j exp(2 i pi S_k . r_j),  S_k the grid's k-th point in FP64.
+ * xyz, f, A as for nx_scatter_fwd (A float[n1 n2 n3 * 2], device, overwritten). */
+int nx_scatter_fwd_grid(const float* xyz, const float* f, int64_t n_atoms, const nx_grid* grid,
+                        float* A, int mode, void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint with respect to the positions over the points of `grid` (the chain rule through
+ * Eq. 2, as nx_scatter_bwd): G float[n1 n2 n3 * 2] (device), grad_xyz float[n_atoms * 3]
+ * (device, overwritten; zero for an empty grid). */
+int nx_scatter_bwd_grid(const float* xyz, const float* f, int64_t n_atoms, const nx_grid* grid,
+                        const float* G, float* grad_xyz, int mode, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* One fitting step over the points of `grid`, queued by one call: nx_scatter_fwd_grid, the
+ * misfit of nx_loss_grad, nx_scatter_bwd_grid, on one workspace (op NX_OP_FIT of
+ * nx_workspace_bytes_grid); bitwise the three calls.  Arguments as nx_fit_step's. */
+int nx_fit_step_grid(const float* xyz, const float* f, int64_t n_atoms, const nx_grid* grid,
+                     const float* I, float* A, double* L, float* G, float* grad_xyz, int mode,
+                     void* ws, size_t ws_bytes, void* stream);
+
 /* Adjoint with the gradient with respect to the factors as well (for fitting
  * occupancies or compositions):
  *     grad_f_j = dL/dRe f_j + i dL/dIm f_j = conj( sum_k conj(G_k) exp(2 i pi S_k . r_j) )

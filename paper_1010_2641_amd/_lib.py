@@ -18,8 +18,19 @@ NX_MAX_COUNT = 1 << 30
 NX_MAX_SPECIES = 16
 NX_NOALLOC_SCRATCH_BYTES = 128 << 20
 
+
+
+class nx_grid(ctypes.Structure):
+    """struct nx_grid: point (i1, i2, i3) is origin + i1 step1 + i2 step2 + i3 step3 (FP64),
+    listed with i1 fastest."""
+    _fields_ = [("origin", ctypes.c_double * 3), ("step1", ctypes.c_double * 3),
+                ("step2", ctypes.c_double * 3), ("step3", ctypes.c_double * 3),
+                ("n1", ctypes.c_int64), ("n2", ctypes.c_int64), ("n3", ctypes.c_int64)]
+
+
 # every symbol include/nx.h declares, with its ctypes signature
 _VP, _I64, _SZ, _I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t, ctypes.c_int
+_GP = ctypes.POINTER(nx_grid)
 SIGNATURES = {
     "nx_version": ([], _I),
     "nx_last_error": ([], ctypes.c_char_p),
@@ -37,6 +48,10 @@ SIGNATURES = {
     "nx_scatter_bwd_species": ([_VP, _I64, _VP, _I, _VP, _VP, _I64, _VP, _VP, _VP, _VP, _I, _VP, _SZ,
                                 _VP], _I),
     "nx_workspace_bytes_species": ([_VP, _I, _I64, _I, _I], _SZ),
+    "nx_workspace_bytes_grid": ([_I64, _GP, _I, _I], _SZ),
+    "nx_scatter_fwd_grid": ([_VP, _VP, _I64, _GP, _VP, _I, _VP, _SZ, _VP], _I),
+    "nx_scatter_bwd_grid": ([_VP, _VP, _I64, _GP, _VP, _VP, _I, _VP, _SZ, _VP], _I),
+    "nx_fit_step_grid": ([_VP, _VP, _I64, _GP, _VP, _VP, _VP, _VP, _VP, _I, _VP, _SZ, _VP], _I),
 }
 
 
@@ -103,3 +118,7 @@ nx_scatter_bwd_ex_f64 = lib.nx_scatter_bwd_ex_f64
 nx_scatter_fwd_species = lib.nx_scatter_fwd_species
 nx_scatter_bwd_species = lib.nx_scatter_bwd_species
 nx_workspace_bytes_species = lib.nx_workspace_bytes_species
+nx_workspace_bytes_grid = lib.nx_workspace_bytes_grid
+nx_scatter_fwd_grid = lib.nx_scatter_fwd_grid
+nx_scatter_bwd_grid = lib.nx_scatter_bwd_grid
+nx_fit_step_grid = lib.nx_fit_step_grid

@@ -12,11 +12,14 @@ library (include/nx.h), which does all the arithmetic.
 * ``scatter_fwd_species`` / ``scatter_bwd_species`` -- the species-factorised sum of
   Section 4.2 (unit-factor sums per species times S-dependent species factors);
 * ``scatter``, ``scatter_species``          -- differentiable forwards (autograd.Function);
-* ``fit_step``, ``fit_step_species``        -- forward, misfit and adjoint in one call.
+* ``fit_step``, ``fit_step_species``        -- forward, misfit and adjoint in one call;
+* ``Grid``, ``scatter_fwd_grid``, ``scatter_bwd_grid``, ``fit_step_grid`` -- the same sums
+  over a regular grid of points given exactly (FP64 origin and steps), walked by rows.
 """
 from __future__ import annotations
 
 import ctypes
+from dataclasses import dataclass
 from typing import Optional, Sequence, Tuple
 
 import torch
@@ -406,4 +409,112 @@ def fit_step(xyz: torch.Tensor, f: Optional[torch.Tensor], S: torch.Tensor, I: t
     ws, wsb = _workspace(workspace_bytes(n, k, m, _lib.NX_OP_FIT, f is None), dev)
     _lib.check(_lib.nx_fit_step(_ptr(xyz), _ptr(f), n, _ptr(S), k, _ptr(I), _ptr(A), _ptr(L),
                                 _ptr(G), _ptr(grad), m, _ptr(ws), wsb, _stream(dev)))
+    return (L, A, grad, G) if return_seed else (L, A, grad)
+
+
+@dataclass(frozen=True)
+class Grid:
+    """A regular grid of reciprocal-space points (r.l.u., FP64): point (i1, i2, i3) is
+    origin + i1 step1 + i2 step2 + i3 step3, 0 <= i_a < n_a, listed with i1 fastest
+    (k = i1 + n1 (i2 + n2 i3)), the order of A, G and I in the grid calls."""
+    origin: Tuple[float, float, float]
+    step1: Tuple[float, float, float]
+    step2: Tuple[float, float, float]
+    step3: Tuple[float, float, float]
+    n1: int
+    n2: int = 1
+    n3: int = 1
+
+    @property
+    def size(self) -> int:
+        return int(self.n1) * int(self.n2) * int(self.n3)
+
+
+
+def _grid_arg(grid) -> Tuple[_lib.nx_grid, int]:
+    """The nx_grid struct and point count of a Grid (or of any object with the same
+    fields, such as a workload's grid)."""
+    try:
+        parts = {name: tuple(float(x) for x in getattr(grid, name))
+                 for name in ("origin", "step1", "step2", "step3")}
+        counts = tuple(int(getattr(grid, name)) for name in ("n1", "n2", "n3"))
+    except (AttributeError, TypeError):
+        raise TypeError("grid must be a Grid (origin, step1, step2, step3, n1, n2, n3)") from None
+    g = _lib.nx_grid()
+    for name, v in parts.items():
+        if len(v) != 3:
+            raise ValueError(f"grid {name} must have 3 components (got {len(v)})")
+        getattr(g, name)[:] = v
+    if min(counts) < 0:
+        raise ValueError(f"grid counts must be >= 0 (got {counts})")
+    g.n1, g.n2, g.n3 = counts
+    return g, counts[0] * counts[1] * counts[2]
+
+
+def workspace_bytes_grid(n_atoms: int, grid: Grid, op=_lib.NX_OP_FWD, f_is_null: bool = False) -> int:
+    g, _ = _grid_arg(grid)
+    n = _lib.nx_workspace_bytes_grid(n_atoms, ctypes.byref(g), op, int(bool(f_is_null)))
+    msg = _lib.last_error()
+    if msg:
+        raise _lib.NxError(_lib.NX_ERR_ARG, msg)
+    return int(n)
+
+
+def scatter_fwd_grid(xyz: torch.Tensor, f: Optional[torch.Tensor], grid: Grid,
+                     out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Eq. 2 over the points of ``grid`` (FP64-phase mode): xyz (N,3) float32, f (N,)
+    complex64 or None -> A (grid.size,) complex64, in the grid's order."""
+    _need(xyz, "xyz", torch.float32, (None, 3))
+    g, k = _grid_arg(grid)
+    n = xyz.shape[0]
+    _f_arg(f, n, torch.complex64)
+    if out is not None:
+        _need(out, "out", torch.complex64, (k,))
+    _on_gpu(xyz=xyz, f=f, out=out)
+    nbytes = workspace_bytes_grid(n, grid, _lib.NX_OP_FWD, f is None)    # validates the grid
+    if out is None:
+        out = torch.empty(k, dtype=torch.complex64, device=xyz.device)
+    ws, wsb = _workspace(nbytes, xyz.device)
+    _lib.check(_lib.nx_scatter_fwd_grid(_ptr(xyz), _ptr(f), n, ctypes.byref(g), _ptr(out),
+                                        _lib.NX_F32_PH64, _ptr(ws), wsb, _stream(xyz.device)))
+    return out
+
+
+def scatter_bwd_grid(xyz: torch.Tensor, f: Optional[torch.Tensor], grid: Grid,
+                     G: torch.Tensor) -> torch.Tensor:
+    """The position adjoint over the points of ``grid``: seed G (grid.size,) complex64 ->
+    dL/dxyz (N,3) float32 (as scatter_bwd)."""
+    _need(xyz, "xyz", torch.float32, (None, 3))
+    g, k = _grid_arg(grid)
+    n = xyz.shape[0]
+    _need(G, "G", torch.complex64, (k,))
+    _f_arg(f, n, torch.complex64)
+    _on_gpu(xyz=xyz, G=G, f=f)
+    nbytes = workspace_bytes_grid(n, grid, _lib.NX_OP_BWD, f is None)
+    grad = torch.empty((n, 3), dtype=torch.float32, device=xyz.device)
+    ws, wsb = _workspace(nbytes, xyz.device)
+    _lib.check(_lib.nx_scatter_bwd_grid(_ptr(xyz), _ptr(f), n, ctypes.byref(g), _ptr(G), _ptr(grad),
+                                        _lib.NX_F32_PH64, _ptr(ws), wsb, _stream(xyz.device)))
+    return grad
+
+
+def fit_step_grid(xyz: torch.Tensor, f: Optional[torch.Tensor], grid: Grid, I: torch.Tensor,
+                  return_seed: bool = False):
+    """fit_step over the points of ``grid`` (nx_fit_step_grid): I (grid.size,) float32.
+    Returns (L, A, grad_xyz), and G as well when return_seed."""
+    _need(xyz, "xyz", torch.float32, (None, 3))
+    g, k = _grid_arg(grid)
+    n = xyz.shape[0]
+    _f_arg(f, n, torch.complex64)
+    _need(I, "I", torch.float32, (k,))
+    _on_gpu(xyz=xyz, f=f, I=I)
+    dev = xyz.device
+    nbytes = workspace_bytes_grid(n, grid, _lib.NX_OP_FIT, f is None)
+    A = torch.empty(k, dtype=torch.complex64, device=dev)
+    G = torch.empty(k, dtype=torch.complex64, device=dev)
+    L = torch.empty((), dtype=torch.float64, device=dev)
+    grad = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    ws, wsb = _workspace(nbytes, dev)
+    _lib.check(_lib.nx_fit_step_grid(_ptr(xyz), _ptr(f), n, ctypes.byref(g), _ptr(I), _ptr(A), _ptr(L),
+                                     _ptr(G), _ptr(grad), _lib.NX_F32_PH64, _ptr(ws), wsb, _stream(dev)))
     return (L, A, grad, G) if return_seed else (L, A, grad)

@@ -4,6 +4,7 @@
 #include "nx.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -89,7 +90,7 @@ int device_error(const char* fn, hipError_t e) {
 namespace nx {
 
 Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_null,
-               int64_t max_split) {
+               int64_t max_split, int grid) {
   Plan p;
   p.fk = f_is_null ? 0 : 1;
   const bool fwd = (op == kOpFwd || op == kOpFwdF64);
@@ -140,6 +141,20 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
     const int64_t tl = env_i64("NX_TUNE_LDS", -1);
     if (p.mode == kPH64 && (tl == 0 || tl == 1)) p.lds = int(tl);
   }
+  // a grid walked by rows (its own kernels): one point per lane in the forward, so that
+  // every wave's 64 points lie in one row; where its kernels do not exist for the plan
+  // the general kernels take the grid's points
+  // (NX_TUNE_GRID=1 sends every grid to the general kernels)
+  if (grid == 2 && env_i64("NX_TUNE_GRID", -1) == 1) grid = 1;
+  // a grid's forward: one point per lane, LDS tiles and the fixed-point reduction, the
+  // forms built to walk grid rows (grid 2) or to form each lane's FP64 grid point
+  // (grid 1), whatever the knobs say
+  if (grid != 0 && fwd && p.mode == kPH64) {
+    p.per_lane = 1;
+    p.red = 2;
+    p.lds = 1;
+    if (p.grp != 8) p.grp = 16;
+  }
   // the fixed-point reduction checks its range per LDS tile: the scalar-load forms (and
   // the forward's 32-atom groups, which have no LDS form) take the centred one, and so do
   // the forward's forms whose two tile loops do not fit their registers (four points per
@@ -147,6 +162,9 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
   if (p.red == 2 && !(p.lds && (!fwd || ((p.grp == 8 || p.grp == 16) &&
                                          (p.per_lane == 1 || (p.per_lane == 2 && p.grp == 16))))))
     p.red = 0;
+  if (grid == 2 && !(p.mode == kPH64 && p.red == 2 && p.lds && (fwd ? p.per_lane == 1 : p.grp == 64)))
+    grid = 1;
+  p.grid = p.mode == kPH64 ? grid : 0;
   const int64_t per_block = int64_t(kThreads) * p.per_lane;
   p.blocks = p.lanes > 0 ? ceil_div(p.lanes, per_block) : 0;
   p.nsplit = 1;
@@ -173,7 +191,8 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
   // small calls: records formed in the sum kernel (the LDS forms with one lane item per
   // lane and the default reduction variant); NX_TUNE_INLINE=0 turns this off, 1 forces it
   // wherever that form exists
-  if (p.mode == kPH64 && p.lds && p.per_lane == 1 &&
+  // (grids: records always packed)
+  if (p.mode == kPH64 && p.lds && p.per_lane == 1 && p.grid == 0 &&
       (fwd ? (p.red == 2 && (p.grp == 8 || p.grp == 16)) : (p.red == 2 && p.grp == 64))) {
     const int64_t ti = env_i64("NX_TUNE_INLINE", -1);
     p.inl = (ti == 1 || (ti != 0 && p.blocks * p.stream <= kInlineMaxRecords)) ? 1 : 0;
@@ -185,6 +204,7 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
   if (launch_pairs < 1) launch_pairs = kLaunchPairs;
   size_t rec_size;
   if (fwd) rec_size = p.mode == kF64 ? sizeof(AtomF64) : (p.mode == kPH64 ? sizeof(AtomPH) : sizeof(AtomF32));
+  else if (p.grid == 2) rec_size = sizeof(PointGrid);
   else rec_size = p.mode == kF64 ? sizeof(PointF64) : (p.mode == kPH64 ? sizeof(PointPH) : sizeof(PointF32));
   p.rec_size = rec_size;
   int64_t chunk = lane_pad > 0 ? launch_pairs / lane_pad : p.stream;
@@ -257,6 +277,91 @@ int run_sum(const char* fn, const nx::Plan& p, bool fwd, const void* xyz, const 
   if (p.nsplit > 1) {
     if (fwd) e = nx::launch_fwd_reduce(p, partial, out, st);
     else e = nx::launch_bwd_reduce(p, partial, f, out, outf, st);
+    if (e != hipSuccess) return device_error(fn, e);
+  }
+  return ok();
+}
+
+// Grid entry points: the grid's point count (n1 n2 n3), or -1 after setting the error for
+// a NULL grid, a negative or too large count, or a value that is not finite.
+int64_t grid_points(const char* fn, const nx_grid* g) {
+  if (!g) {
+    fail(NX_ERR_ARG, "%s: NULL grid", fn);
+    return -1;
+  }
+  const int64_t n[3] = {g->n1, g->n2, g->n3};
+  int64_t k = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] < 0 || n[a] > NX_MAX_COUNT) {
+      fail(NX_ERR_ARG, "%s: grid count n%d = %lld outside [0, %lld]", fn, a + 1, (long long)n[a],
+           (long long)NX_MAX_COUNT);
+      return -1;
+    }
+    if (n[a] == 0) k = 0;
+    else if (k > NX_MAX_COUNT / n[a]) k = NX_MAX_COUNT + 1;
+    else k *= n[a];
+  }
+  if (k > NX_MAX_COUNT) {
+    fail(NX_ERR_ARG, "%s: grid of %lld x %lld x %lld points exceeds %lld", fn, (long long)g->n1,
+         (long long)g->n2, (long long)g->n3, (long long)NX_MAX_COUNT);
+    return -1;
+  }
+  const double* v[4] = {g->origin, g->step1, g->step2, g->step3};
+  for (int a = 0; a < 4; ++a)
+    for (int d = 0; d < 3; ++d)
+      if (!std::isfinite(v[a][d])) {
+        fail(NX_ERR_ARG, "%s: grid origin and steps must be finite", fn);
+        return -1;
+      }
+  return k;
+}
+
+nx::GridDef grid_def(const nx_grid* g) {
+  nx::GridDef d;
+  for (int a = 0; a < 3; ++a) {
+    d.o[a] = g->origin[a];
+    d.e1[a] = g->step1[a];
+    d.e2[a] = g->step2[a];
+    d.e3[a] = g->step3[a];
+  }
+  d.n1 = g->n1;
+  d.n2 = g->n2;
+  d.n3 = g->n3;
+  return d;
+}
+
+// The grid kernels walk rows of n1 points; they need n1 to be a multiple of 64.
+int grid_kind(const nx_grid* g) { return (g->n1 % 64 == 0) ? 2 : 1; }
+
+// The launch sequence of run_sum over the points of a grid (FP64-phase mode): grid records
+// packed, the chunks, the split reduce.  `out` is A (forward) or grad_xyz (adjoint).
+int run_sum_grid(const char* fn, const nx::Plan& p, bool fwd, const float* xyz, const float* f,
+                 const nx::GridDef& gd, const float* G, float* out, void* ws, hipStream_t st) {
+  char* base = static_cast<char*>(ws);
+  void* rec = base;
+  void* partial = p.partial_bytes ? base + p.rec_bytes : nullptr;
+  hipError_t e = hipSuccess;
+  if (fwd) {
+    if (!p.inl) e = nx::launch_pack_atoms_grid(p, xyz, f, p.stream, gd, rec, st);
+  } else {
+    e = nx::launch_pack_points_grid(p, gd, G, rec, st);
+  }
+  if (e != hipSuccess) return device_error(fn, e);
+  for (int64_t c = 0; c < p.nchunks; ++c) {
+    int64_t b, en, per;
+    nx::chunk_range(p, c, &b, &en, &per);
+    const int carry = c > 0 ? 1 : 0;
+    const int direct = (p.nsplit == 1 && c == p.nchunks - 1) ? 1 : 0;
+    if (fwd)
+      e = nx::launch_fwd_chunk(p, rec, b, en, per, nullptr, partial, out, carry, direct, st, xyz, f, &gd);
+    else
+      e = nx::launch_bwd_chunk(p, rec, b, en, per, xyz, f, partial, out, nullptr, carry, direct, st,
+                               nullptr, nullptr, &gd);
+    if (e != hipSuccess) return device_error(fn, e);
+  }
+  if (p.nsplit > 1) {
+    if (fwd) e = nx::launch_fwd_reduce(p, partial, out, st);
+    else e = nx::launch_bwd_reduce(p, partial, f, out, nullptr, st);
     if (e != hipSuccess) return device_error(fn, e);
   }
   return ok();
@@ -370,7 +475,7 @@ bool noalloc_plan(int mode, int64_t n_atoms, int64_t n_points, int f_is_null, nx
 
 extern "C" {
 
-int nx_version(void) { return 103; }
+int nx_version(void) { return 104; }
 
 const char* nx_last_error(void) { return g_last_error.c_str(); }
 
@@ -561,6 +666,88 @@ int nx_scatter_bwd_ex_f64(const double* xyz, const double* f, int64_t n_atoms, c
   const nx::Plan p = nx::make_plan(nx::kOpBwdGfF64, 0, n_atoms, n_points, f == nullptr);
   if (int r = check_ws(fn, p, ws, ws_bytes)) return r;
   return run_sum(fn, p, false, xyz, f, S, G, grad_xyz, grad_f, ws, static_cast<hipStream_t>(stream));
+}
+
+size_t nx_workspace_bytes_grid(int64_t n_atoms, const nx_grid* grid, int op, int f_is_null) {
+  const char* fn = "nx_workspace_bytes_grid";
+  const int64_t k = grid_points(fn, grid);
+  if (k < 0) return 0;
+  if (check_counts(fn, n_atoms, k) != NX_OK) return 0;
+  if (op != NX_OP_FWD && op != NX_OP_BWD && op != NX_OP_FIT) {
+    fail(NX_ERR_MODE, "%s: op must be NX_OP_FWD, NX_OP_BWD or NX_OP_FIT, got %d", fn, op);
+    return 0;
+  }
+  ok();
+  const int g = grid_kind(grid);
+  const size_t fw = nx::make_plan(nx::kOpFwd, NX_F32_PH64, n_atoms, k, f_is_null, nx::kMaxSplit, g).total();
+  const size_t bw = nx::make_plan(nx::kOpBwd, NX_F32_PH64, n_atoms, k, f_is_null, nx::kMaxSplit, g).total();
+  if (op == NX_OP_FWD) return fw;
+  if (op == NX_OP_BWD) return bw;
+  return std::max({fw, bw, nx::make_plan(nx::kOpLoss, NX_F32_PH64, 0, k, 1).total()});
+}
+
+int nx_scatter_fwd_grid(const float* xyz, const float* f, int64_t n_atoms, const nx_grid* grid,
+                        float* A, int mode, void* ws, size_t ws_bytes, void* stream) {
+  const char* fn = "nx_scatter_fwd_grid";
+  const int64_t k = grid_points(fn, grid);
+  if (k < 0) return NX_ERR_ARG;
+  if (int r = check_counts(fn, n_atoms, k)) return r;
+  if (mode != NX_F32_PH64)
+    return fail(NX_ERR_MODE, "%s: mode %d: grids take the FP64-phase mode (NX_F32_PH64)", fn, mode);
+  if (k == 0) return ok();
+  if (!A || (n_atoms > 0 && !xyz))
+    return fail(NX_ERR_ARG, "%s: NULL pointer (xyz=%p A=%p)", fn, (const void*)xyz, (void*)A);
+  if (!aligned(A, 8) || (f && !aligned(f, 8)))
+    return fail(NX_ERR_ARG, "%s: A and f must be 8-byte aligned (complex64)", fn);
+  const nx::Plan p = nx::make_plan(nx::kOpFwd, mode, n_atoms, k, f == nullptr, nx::kMaxSplit, grid_kind(grid));
+  if (int r = check_ws(fn, p, ws, ws_bytes)) return r;
+  return run_sum_grid(fn, p, true, xyz, f, grid_def(grid), nullptr, A, ws, static_cast<hipStream_t>(stream));
+}
+
+int nx_scatter_bwd_grid(const float* xyz, const float* f, int64_t n_atoms, const nx_grid* grid,
+                        const float* G, float* grad_xyz, int mode, void* ws, size_t ws_bytes,
+                        void* stream) {
+  const char* fn = "nx_scatter_bwd_grid";
+  const int64_t k = grid_points(fn, grid);
+  if (k < 0) return NX_ERR_ARG;
+  if (int r = check_counts(fn, n_atoms, k)) return r;
+  if (mode != NX_F32_PH64)
+    return fail(NX_ERR_MODE, "%s: mode %d: grids take the FP64-phase mode (NX_F32_PH64)", fn, mode);
+  if (n_atoms == 0) return ok();
+  if (!xyz || !grad_xyz || (k > 0 && !G))
+    return fail(NX_ERR_ARG, "%s: NULL pointer (xyz=%p G=%p grad_xyz=%p)", fn, (const void*)xyz,
+                (const void*)G, (void*)grad_xyz);
+  if ((G && !aligned(G, 8)) || (f && !aligned(f, 8)))
+    return fail(NX_ERR_ARG, "%s: G and f must be 8-byte aligned (complex64)", fn);
+  // (no points: the kernel runs over an empty range and writes a zero gradient)
+  const nx::Plan p = nx::make_plan(nx::kOpBwd, mode, n_atoms, k, f == nullptr, nx::kMaxSplit, grid_kind(grid));
+  if (int r = check_ws(fn, p, ws, ws_bytes)) return r;
+  return run_sum_grid(fn, p, false, xyz, f, grid_def(grid), G, grad_xyz, ws, static_cast<hipStream_t>(stream));
+}
+
+int nx_fit_step_grid(const float* xyz, const float* f, int64_t n_atoms, const nx_grid* grid,
+                     const float* I, float* A, double* L, float* G, float* grad_xyz, int mode,
+                     void* ws, size_t ws_bytes, void* stream) {
+  const char* fn = "nx_fit_step_grid";
+  const int64_t k = grid_points(fn, grid);
+  if (k < 0) return NX_ERR_ARG;
+  if (int r = check_counts(fn, n_atoms, k)) return r;
+  if (mode != NX_F32_PH64)
+    return fail(NX_ERR_MODE, "%s: mode %d: grids take the FP64-phase mode (NX_F32_PH64)", fn, mode);
+  if (!L || (k > 0 && (!A || !I || !G)) || (n_atoms > 0 && (!xyz || !grad_xyz)))
+    return fail(NX_ERR_ARG, "%s: NULL pointer (xyz=%p I=%p A=%p L=%p G=%p grad_xyz=%p)", fn,
+                (const void*)xyz, (const void*)I, (void*)A, (void*)L, (void*)G, (void*)grad_xyz);
+  if ((A && !aligned(A, 8)) || (G && !aligned(G, 8)) || (f && !aligned(f, 8)) || !aligned(L, 8))
+    return fail(NX_ERR_ARG, "%s: A, G, f and L must be 8-byte aligned", fn);
+  const size_t need = nx_workspace_bytes_grid(n_atoms, grid, NX_OP_FIT, f == nullptr);
+  if (need > 0 && (ws == nullptr || ws_bytes < need || !aligned(ws, 16)))
+    return fail(NX_ERR_WORKSPACE, "%s: workspace of %zu bytes (16-byte aligned) needed, %zu given",
+                fn, need, ws_bytes);
+  if (int r = nx_scatter_fwd_grid(xyz, f, n_atoms, grid, A, mode, ws, ws_bytes, stream)) return r;
+  if (int r = nx_loss_grad(A, I, k, L, G, ws, ws_bytes, stream)) return r;
+  if (int r = nx_scatter_bwd_grid(xyz, f, n_atoms, grid, G, grad_xyz, mode, ws, ws_bytes, stream))
+    return r;
+  return ok();
 }
 
 size_t nx_workspace_bytes_species(const int64_t* species_start, int n_species, int64_t n_points,

@@ -178,11 +178,8 @@ __device__ __forceinline__ PtRegs load_point_lds(const uint4* sd, int u) {
 // the addend of the first fma, the atom's angle as one FP64 add.  RED 0 centred, 1 fract,
 // 2 the fixed-point read of the low word (where the tile's bound holds; see kPhaseShift),
 // 3 its fallback: centred with rint, then the low word of the turn plus kPhaseShift.
-template <int RED, int FK>
-__device__ __forceinline__ void cis_ph64_pt(const PtRegs& a, double x, double y, double z,
-                                            double al, float& c, float& s) {
-  double ph = __builtin_fma(a.sz, z, __builtin_fma(a.sy, y, __builtin_fma(a.sx, x, a.delta)));
-  if constexpr (FK != 0) ph += al;
+template <int RED>
+__device__ __forceinline__ void cis_turn_pt(double ph, float& c, float& s) {
   float tf;
   if constexpr (RED == 0) tf = static_cast<float>(ph - __builtin_rint(ph));
   else if constexpr (RED == 1) tf = static_cast<float>(__builtin_amdgcn_fract(ph));
@@ -190,6 +187,13 @@ __device__ __forceinline__ void cis_ph64_pt(const PtRegs& a, double x, double y,
   else tf = static_cast<float>(__double2loint((ph - __builtin_rint(ph)) + kPhaseShift)) * 0x1.0p-32f;
   c = __builtin_amdgcn_cosf(tf);
   s = __builtin_amdgcn_sinf(tf);
+}
+template <int RED, int FK>
+__device__ __forceinline__ void cis_ph64_pt(const PtRegs& a, double x, double y, double z,
+                                            double al, float& c, float& s) {
+  double ph = __builtin_fma(a.sz, z, __builtin_fma(a.sy, y, __builtin_fma(a.sx, x, a.delta)));
+  if constexpr (FK != 0) ph += al;
+  cis_turn_pt<RED>(ph, c, s);
 }
 
 // One point's contribution to the FP64-phase group partials g[0..NS).
@@ -519,6 +523,128 @@ __global__ __launch_bounds__(kThreads) void bwd_split_kernel(
   }
 }
 
+// FP64-phase adjoint over a grid whose rows hold a multiple of 64 points, with 64-point
+// compensated groups: every group lies in one row (its first point is a multiple of 64
+// from the grid's start), so that with c0 = o.r + arg f / 2 pi and c_d = e_d.r (per lane
+// atom, FP64) the phase of point (i1, i2, i3) is fma(i1, c1, b) + delta with the row term
+// b = c0 + i2 c2 + i3 c3, formed once per group (two fma per atom): one fma and one add per
+// pair instead of three fma and one add.  The tile holds (i1, delta) of each point (16 B),
+// the rest of the record comes with scalar loads.  Groups, compensation and outputs are
+// those of bwd_split_kernel; the reduction is the fixed-point read with the per-tile range
+// check ((|x| + |y| + |z|) of the lane's atoms times the tile's bound, which covers the
+// row parts) and variant 3 for tiles out of range.
+template <int Q, int FK>
+__global__ __launch_bounds__(kThreads) void bwd_grid_kernel(
+    const PointGrid* __restrict__ rec, int k_begin, int k_end, int per_split,
+    const float* __restrict__ xyz, const float* __restrict__ f, int64_t N, int blocks_n,
+    float* __restrict__ part, float* __restrict__ grad, int carry_in, int direct, GridDef g,
+    const float* __restrict__ bnd) {
+  constexpr int GRP = 64;
+  constexpr int NS = 3;
+  __shared__ double2 sd[kThreads];          // (i1, delta) of the tile's points
+  const int lb = xcd_major_block(blockIdx.x, gridDim.x);
+  const int nb = lb % blocks_n;
+  const int sp = lb / blocks_n;
+  const int64_t j0 = int64_t(nb) * (kThreads * Q) + threadIdx.x;
+  double c0[Q], c1[Q], c2[Q], c3[Q];
+  float sum[Q][NS], cmp[Q][NS];
+  float r1 = 0.f;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t j = j0 + int64_t(q) * kThreads;
+    const int64_t jj = j < N ? j : N - 1;
+    const double x = xyz[3 * jj], y = xyz[3 * jj + 1], z = xyz[3 * jj + 2];
+    r1 = fmaxf(r1, bound_abs(fabs(x) + fabs(y) + fabs(z)));
+    const double al = (FK && f) ? arg_cycles(f[2 * jj], f[2 * jj + 1]) : 0.0;
+    c0[q] = __builtin_fma(g.o[2], z, __builtin_fma(g.o[1], y, __builtin_fma(g.o[0], x, al)));
+    c1[q] = __builtin_fma(g.e1[2], z, __builtin_fma(g.e1[1], y, g.e1[0] * x));
+    c2[q] = __builtin_fma(g.e2[2], z, __builtin_fma(g.e2[1], y, g.e2[0] * x));
+    c3[q] = __builtin_fma(g.e3[2], z, __builtin_fma(g.e3[1], y, g.e3[0] * x));
+#pragma unroll
+    for (int d = 0; d < NS; ++d) {
+      if (carry_in && j < N) {
+        sum[q][d] = part[((int64_t(sp) * NS + d) * 2 + 0) * N + j];
+        cmp[q][d] = part[((int64_t(sp) * NS + d) * 2 + 1) * N + j];
+      } else {
+        sum[q][d] = 0.f;
+        cmp[q][d] = 0.f;
+      }
+    }
+  }
+  auto run_tile = [&](auto red_c, int t0, int nt) {
+    constexpr int R = decltype(red_c)::value;
+    for (int u0 = 0; u0 < nt; u0 += GRP) {
+      const int ue = (u0 + GRP <= nt) ? u0 + GRP : nt;
+      const uint32_t row = static_cast<uint32_t>(t0 + u0) / static_cast<uint32_t>(g.n1);
+      const double d2 = static_cast<double>(row % static_cast<uint32_t>(g.n2)),
+                   d3 = static_cast<double>(row / static_cast<uint32_t>(g.n2));
+      double b[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) b[q] = __builtin_fma(d3, c3[q], __builtin_fma(d2, c2[q], c0[q]));
+      float gq[Q][NS];
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int d = 0; d < NS; ++d) gq[q][d] = 0.f;
+      auto pair_step = [&](int u) {
+        const double2 pd = sd[u];
+        const uint4 w = reinterpret_cast<const uint4*>(rec + t0 + u)[1];
+        const float gsx = __uint_as_float(w.x), gsy = __uint_as_float(w.y), gsz = __uint_as_float(w.z);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          float c, s;
+          cis_turn_pt<R>(__builtin_fma(pd.x, c1[q], b[q]) + pd.y, c, s);
+          gq[q][0] = __builtin_fmaf(s, gsx, gq[q][0]);
+          gq[q][1] = __builtin_fmaf(s, gsy, gq[q][1]);
+          gq[q][2] = __builtin_fmaf(s, gsz, gq[q][2]);
+        }
+      };
+      if (ue - u0 == GRP) {
+#pragma unroll
+        for (int u = 0; u < GRP; ++u) pair_step(u0 + u);
+      } else {
+        for (int u = u0; u < ue; ++u) pair_step(u);
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int d = 0; d < NS; ++d) kahan_acc(sum[q][d], cmp[q][d], gq[q][d]);
+    }
+  };
+  const int k0 = k_begin + sp * per_split;
+  const int k1 = min(k0 + per_split, k_end);
+  for (int t0 = k0; t0 < k1; t0 += kThreads) {
+    const int nt = min(kThreads, k1 - t0);
+    __syncthreads();                        // the previous tile is no longer read
+    if (int(threadIdx.x) < nt) {
+      const PointGrid r = rec[t0 + threadIdx.x];
+      sd[threadIdx.x] = make_double2(r.i1, r.delta);
+    }
+    __syncthreads();
+    const float st = fmaxf(bnd[t0 / kThreads], bnd[(t0 + nt - 1) / kThreads]);
+    if (__all(r1 * st < kFixedPhaseBound)) run_tile(std::integral_constant<int, 2>{}, t0, nt);
+    else run_tile(std::integral_constant<int, 3>{}, t0, nt);
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t j = j0 + int64_t(q) * kThreads;
+    if (j < N) {
+      if (direct) {
+        float T[NS];
+#pragma unroll
+        for (int d = 0; d < NS; ++d) T[d] = sum[q][d] + cmp[q][d];
+        write_out<false, FK != 0>(grad, nullptr, j, T, f);
+      } else {
+#pragma unroll
+        for (int d = 0; d < NS; ++d) {
+          part[((int64_t(sp) * NS + d) * 2 + 0) * N + j] = sum[q][d];
+          part[((int64_t(sp) * NS + d) * 2 + 1) * N + j] = cmp[q][d];
+        }
+      }
+    }
+  }
+}
+
 // All-FP64 adjoint.  part layout: [sp][sum index][N] doubles.
 template <int Q, int FK, bool GF>
 __global__ __launch_bounds__(kThreads) void bwd_f64_kernel(
@@ -672,6 +798,78 @@ __global__ __launch_bounds__(kThreads) void pack_points_ph_kernel(const float* _
       const PointPH r = make_point_ph(S, G, k, offset);
       rec[k] = r;
       sm = fmaxf(bound_abs(r.sx), fmaxf(bound_abs(r.sy), bound_abs(r.sz)));
+    }
+    sm = wave_max(sm);
+    __syncthreads();                      // wmax of the previous block is read
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = sm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float bm = wmax[0];
+#pragma unroll
+      for (int w = 1; w < kThreads / 64; ++w) bm = fmaxf(bm, wmax[w]);
+      bnd[b] = bm;
+    }
+  }
+}
+
+// Point k of a grid with its seed: S (FP64, from the grid), the row part R = o + i2 e2 +
+// i3 e3, delta = -arg(G) / (2 pi) + kPhaseShift, |G|.
+struct GridPoint { double S[3], R[3], i1, delta, m; };
+__device__ __forceinline__ GridPoint grid_point_seed(const GridDef& g, const float* __restrict__ G,
+                                                    int64_t k) {
+  GridPoint p;
+  // (counts and indices stay below 2^30: 32-bit index arithmetic)
+  const uint32_t ku = static_cast<uint32_t>(k), n1 = static_cast<uint32_t>(g.n1),
+                 n2 = static_cast<uint32_t>(g.n2);
+  const uint32_t row = ku / n1;
+  const double d1 = static_cast<double>(ku - row * n1), d2 = static_cast<double>(row % n2),
+               d3 = static_cast<double>(row / n2);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    p.R[d] = __builtin_fma(d3, g.e3[d], __builtin_fma(d2, g.e2[d], g.o[d]));
+    p.S[d] = __builtin_fma(d1, g.e1[d], p.R[d]);
+  }
+  const double gr = G[2 * k], gi = G[2 * k + 1];
+  p.m = sqrt(gr * gr + gi * gi);
+  p.delta = -atan2(gi, gr) * 0.15915494309189533577 + kPhaseShift;
+  p.i1 = d1;
+  return p;
+}
+
+// Point records of a grid, grid-stride over blocks of 256 points: PointGrid (ROWS, the grid
+// kernels) or PointPH (the general kernels, with the FP64 grid point), and each block's
+// bound in bnd[block]: the largest |S| component, for PointGrid also of the row part.
+template <bool ROWS>
+__global__ __launch_bounds__(kThreads) void pack_points_grid_kernel(GridDef g, const float* __restrict__ G,
+                                                                    int64_t n, void* __restrict__ rec_v,
+                                                                    float* __restrict__ bnd) {
+  __shared__ float wmax[kThreads / 64];
+  for (int64_t b = blockIdx.x; b * kThreads < n; b += gridDim.x) {
+    const int64_t k = b * kThreads + threadIdx.x;
+    float sm = 0.f;
+    if (k < n) {
+      const GridPoint q = grid_point_seed(g, G, k);
+      sm = fmaxf(bound_abs(q.S[0]), fmaxf(bound_abs(q.S[1]), bound_abs(q.S[2])));
+      if constexpr (ROWS) {
+        sm = fmaxf(sm, fmaxf(bound_abs(q.R[0]), fmaxf(bound_abs(q.R[1]), bound_abs(q.R[2]))));
+        PointGrid r;
+        r.i1 = q.i1;
+        r.delta = q.delta;
+        r.gsx = static_cast<float>(q.m * q.S[0]);
+        r.gsy = static_cast<float>(q.m * q.S[1]);
+        r.gsz = static_cast<float>(q.m * q.S[2]);
+        r.gmag = static_cast<float>(q.m);
+        static_cast<PointGrid*>(rec_v)[k] = r;
+      } else {
+        PointPH r;
+        r.sx = q.S[0]; r.sy = q.S[1]; r.sz = q.S[2];
+        r.delta = q.delta;
+        r.gsx = static_cast<float>(q.m * q.S[0]);
+        r.gsy = static_cast<float>(q.m * q.S[1]);
+        r.gsz = static_cast<float>(q.m * q.S[2]);
+        r.gmag = static_cast<float>(q.m);
+        static_cast<PointPH*>(rec_v)[k] = r;
+      }
     }
     sm = wave_max(sm);
     __syncthreads();                      // wmax of the previous block is read
@@ -856,10 +1054,51 @@ hipError_t launch_pack_points(int mode, int red, const void* S, const void* G, i
   return hipGetLastError();
 }
 
+hipError_t launch_pack_points_grid(const Plan& p, const GridDef& g, const float* G, void* rec,
+                                   hipStream_t st) {
+  const int64_t k = p.stream;
+  if (k <= 0) return hipSuccess;
+  float* bnd = reinterpret_cast<float*>(static_cast<char*>(rec) + point_bound_offset(k, p.rec_size));
+  if (p.grid == 2) pack_points_grid_kernel<true><<<grid_for(k), kThreads, 0, st>>>(g, G, k, rec, bnd);
+  else pack_points_grid_kernel<false><<<grid_for(k), kThreads, 0, st>>>(g, G, k, rec, bnd);
+  return hipGetLastError();
+}
+
+namespace {
+template <int Q, int FK>
+void bwd_grid_launch(const Plan& p, const void* rec, int64_t k_begin, int64_t k_end, int64_t per_split,
+                     const void* xyz, const void* f, void* partial, void* grad, int carry_in, int direct,
+                     const GridDef& g, hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>(p.blocks * p.nsplit));
+  const auto* r = static_cast<const PointGrid*>(rec);
+  const float* bnd = reinterpret_cast<const float*>(static_cast<const char*>(rec) +
+                                                    point_bound_offset(p.stream, sizeof(PointGrid)));
+  bwd_grid_kernel<Q, FK><<<grid, kThreads, 0, st>>>(
+      r, int(k_begin), int(k_end), int(per_split), static_cast<const float*>(xyz),
+      static_cast<const float*>(f), p.lanes, int(p.blocks), static_cast<float*>(partial),
+      static_cast<float*>(grad), carry_in, direct, g, bnd);
+}
+}  // namespace
+
 hipError_t launch_bwd_chunk(const Plan& p, const void* rec, int64_t k_begin, int64_t k_end,
                             int64_t per_split, const void* xyz, const void* f, void* partial,
                             void* grad, void* gradf, int carry_in, int direct, hipStream_t st,
-                            const void* S, const void* G) {
+                            const void* S, const void* G, const GridDef* gd) {
+  if (p.mode == kPH64 && p.grid == 2 && gd && !p.gf) {
+#define NX_GRID_BWD(Q, FK) \
+  bwd_grid_launch<Q, FK>(p, rec, k_begin, k_end, per_split, xyz, f, partial, grad, carry_in, direct, *gd, st)
+    if (p.fk) {
+      if (p.per_lane == 4) NX_GRID_BWD(4, 1);
+      else if (p.per_lane == 2) NX_GRID_BWD(2, 1);
+      else NX_GRID_BWD(1, 1);
+    } else {
+      if (p.per_lane == 4) NX_GRID_BWD(4, 0);
+      else if (p.per_lane == 2) NX_GRID_BWD(2, 0);
+      else NX_GRID_BWD(1, 0);
+    }
+#undef NX_GRID_BWD
+    return hipGetLastError();
+  }
   const BwdArgs b{rec, k_begin, k_end, per_split, xyz, f, partial, grad, gradf, carry_in, direct, S, G};
   if (p.mode == kF64) return p.gf ? bwd_f64_dispatch<true>(p, b, st) : bwd_f64_dispatch<false>(p, b, st);
   if (p.mode == kPH64) return p.gf ? bwd_dispatch_q<kPH64, true>(p, b, st) : bwd_dispatch_q<kPH64, false>(p, b, st);

@@ -183,9 +183,7 @@ template <> struct AtomOf<kPH64> { using type = AtomPH; };
 //   3 (RED 2's fallback for tiles out of that range): t = (S.r + a) - rint(S.r + a), then
 //                       the low word of t + kPhaseShift read in the same way.
 template <int RED>
-__device__ __forceinline__ void cis_ph64(double sx, double sy, double sz, const AtomPH& a, float& c,
-                                         float& s) {
-  const double ph = __builtin_fma(sz, a.z, __builtin_fma(sy, a.y, __builtin_fma(sx, a.x, a.a)));
+__device__ __forceinline__ void cis_turn(double ph, float& c, float& s) {
   float tf;
   if constexpr (RED == 0) tf = static_cast<float>(ph - __builtin_rint(ph));
   else if constexpr (RED == 1) tf = static_cast<float>(__builtin_amdgcn_fract(ph));
@@ -193,6 +191,26 @@ __device__ __forceinline__ void cis_ph64(double sx, double sy, double sz, const 
   else tf = static_cast<float>(__double2loint((ph - __builtin_rint(ph)) + kPhaseShift)) * 0x1.0p-32f;
   c = __builtin_amdgcn_cosf(tf);
   s = __builtin_amdgcn_sinf(tf);
+}
+template <int RED>
+__device__ __forceinline__ void cis_ph64(double sx, double sy, double sz, const AtomPH& a, float& c,
+                                         float& s) {
+  cis_turn<RED>(__builtin_fma(sz, a.z, __builtin_fma(sy, a.y, __builtin_fma(sx, a.x, a.a))), c, s);
+}
+
+// Point (i1, i2, i3) of a grid, and the row part o + i2 e2 + i3 e3, in FP64.
+// (Counts and indices stay below 2^30, so the index arithmetic is 32-bit.)
+__device__ __forceinline__ void grid_point(const GridDef& g, int64_t k, double* S, double* R) {
+  const uint32_t ku = static_cast<uint32_t>(k), n1 = static_cast<uint32_t>(g.n1),
+                 n2 = static_cast<uint32_t>(g.n2);
+  const uint32_t row = ku / n1;
+  const double d1 = static_cast<double>(ku - row * n1), d2 = static_cast<double>(row % n2),
+               d3 = static_cast<double>(row / n2);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    R[d] = __builtin_fma(d3, g.e3[d], __builtin_fma(d2, g.e2[d], g.o[d]));
+    S[d] = __builtin_fma(d1, g.e1[d], R[d]);
+  }
 }
 
 // FP64-phase terms: the first term of a running sum, and the sum plus one more term.
@@ -359,12 +377,14 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(
 // dispatch when few work-groups share each record; the tile's bound is then reduced over
 // its own records.  The FP64 arctangent of the record needs more registers than 5 waves
 // per SIMD leave, so this form is built for 4.
-template <int P, int FK, int GRP, int RED, bool INL>
+//
+// GRID: the points are those of a grid (gd), formed in FP64 by each lane, instead of S.
+template <int P, int FK, int GRP, int RED, bool INL, bool GRID = false>
 __global__ __launch_bounds__(kThreads, INL ? 4 : 5) void fwd_lds_kernel(
     const AtomPH* __restrict__ rec, int a_begin, int a_end, int per_split,
     const float* __restrict__ S, int64_t K, int blocks_k, float4* __restrict__ part,
     float2* __restrict__ A, int carry_in, int direct, const float* __restrict__ xyz,
-    const float* __restrict__ f) {
+    const float* __restrict__ f, GridDef gd) {
   static_assert(kThreads % GRP == 0, "tiles must hold whole groups");
   using AT = AtomPH;
   __shared__ AT tile[kThreads];
@@ -380,9 +400,17 @@ __global__ __launch_bounds__(kThreads, INL ? 4 : 5) void fwd_lds_kernel(
   for (int p = 0; p < P; ++p) {
     const int64_t k = k0 + int64_t(p) * kThreads;
     const int64_t kk = k < K ? k : K - 1;
-    sx[p] = S[3 * kk];
-    sy[p] = S[3 * kk + 1];
-    sz[p] = S[3 * kk + 2];
+    if constexpr (GRID) {    // the points of a grid, in FP64
+      double G3[3], R3[3];
+      grid_point(gd, kk, G3, R3);
+      sx[p] = G3[0];
+      sy[p] = G3[1];
+      sz[p] = G3[2];
+    } else {
+      sx[p] = S[3 * kk];
+      sy[p] = S[3 * kk + 1];
+      sz[p] = S[3 * kk + 2];
+    }
     s1 = fmaxf(s1, bound_abs(fabs(sx[p]) + fabs(sy[p]) + fabs(sz[p])));
     if (carry_in && k < K) {
       const float4 st = part[int64_t(sp) * K + k];
@@ -482,6 +510,159 @@ __global__ __launch_bounds__(kThreads, INL ? 4 : 5) void fwd_lds_kernel(
       if (direct) A[k] = make_float2(sr[p] + cr[p], si[p] + ci[p]);
       else part[int64_t(sp) * K + k] = make_float4(sr[p], si[p], cr[p], ci[p]);
     }
+  }
+}
+
+// Grid atom records (AtomGrid): the AtomPH record of atom j (same addend, factor, turn
+// and rounding) with its position folded into c0 = o.r + a and c_d = e_d.r, in FP64; rmax
+// as in pack_atoms_ph_kernel.
+__global__ __launch_bounds__(kThreads) void pack_atoms_grid_kernel(const float* __restrict__ xyz,
+                                                                   const float* __restrict__ f,
+                                                                   int64_t n, AtomGrid* __restrict__ rec,
+                                                                   GridDef g, int grp) {
+  __shared__ float wmax[kThreads / 64];
+  for (int64_t b = blockIdx.x; b * kThreads < n; b += gridDim.x) {
+    const int64_t j = b * kThreads + threadIdx.x;
+    AtomGrid r;
+    float am = 0.f;
+    if (j < n) {
+      const AtomPH a = make_atom_ph(xyz, f, j, kPhaseShift, grp, 1.f);
+      r.c0 = __builtin_fma(g.o[2], a.z, __builtin_fma(g.o[1], a.y, __builtin_fma(g.o[0], a.x, a.a)));
+      r.c1 = __builtin_fma(g.e1[2], a.z, __builtin_fma(g.e1[1], a.y, g.e1[0] * a.x));
+      r.c2 = __builtin_fma(g.e2[2], a.z, __builtin_fma(g.e2[1], a.y, g.e2[0] * a.x));
+      r.c3 = __builtin_fma(g.e3[2], a.z, __builtin_fma(g.e3[1], a.y, g.e3[0] * a.x));
+      r.m = a.m;
+      r.ck = a.ck;
+      r.sk = a.sk;
+      am = fmaxf(bound_abs(a.x), fmaxf(bound_abs(a.y), bound_abs(a.z)));
+    }
+    am = wave_max(am);
+    __syncthreads();                      // wmax of the previous block is read
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = am;
+    __syncthreads();
+    float bm = wmax[0];
+#pragma unroll
+    for (int w = 1; w < kThreads / 64; ++w) bm = fmaxf(bm, wmax[w]);
+    if (j < n) {
+      r.rmax = bm;
+      rec[j] = r;
+    }
+  }
+}
+
+// FP64-phase forward over a grid whose rows hold a multiple of 64 points, one point per
+// lane: every wave's 64 points lie in one row (i2, i3), at i1 = i1_0 .. i1_0 + 63.  The phase
+// of atom j at point (i1, i2, i3) is i1 c1_j + b_j,row with the row term b = c0 + i2 c2 + i3 c3:
+// the thread that stages atom j into the LDS tile forms b for the rows of the work-group's
+// 4 waves (two fma each), and every pair then costs one FP64 fma instead of three.  Groups,
+// quads, eighth turns and compensation are those of fwd_lds_kernel; the reduction is the
+// fixed-point read, with the per-tile range check (the lane's |S|_1 and that of its row
+// part o + i2 e2 + i3 e3, so that the row term stays in range too) and variant 3 for tiles
+// out of range.  Built for 8 waves per SIMD (62 VGPRs, no spills).
+template <int FK, int GRP>
+__global__ __launch_bounds__(kThreads, 8) void fwd_grid_kernel(
+    const AtomGrid* __restrict__ rec, int a_begin, int a_end, int per_split, GridDef g, int64_t K,
+    int blocks_k, float4* __restrict__ part, float2* __restrict__ A, int carry_in, int direct) {
+  static_assert(kThreads % GRP == 0, "tiles must hold whole groups");
+  struct Tile { double c1; float m, ck, sk, rmax; };   // 24 B
+  __shared__ Tile tile[kThreads];
+  __shared__ double rowb[kThreads / 64][kThreads];   // the row term per wave and atom
+  const int lb = xcd_major_block(blockIdx.x, gridDim.x);
+  const int kb = lb % blocks_k;
+  const int sp = lb / blocks_k;
+  const int wave = threadIdx.x >> 6;
+  const int64_t k = int64_t(kb) * kThreads + threadIdx.x;
+  const int64_t kk = k < K ? k : K - 1;
+  const double di1 = static_cast<double>(static_cast<uint32_t>(kk) % static_cast<uint32_t>(g.n1));
+  float s1;
+  {
+    double S3[3], R3[3];
+    grid_point(g, kk, S3, R3);
+    s1 = fmaxf(bound_abs(fabs(S3[0]) + fabs(S3[1]) + fabs(S3[2])),
+               bound_abs(fabs(R3[0]) + fabs(R3[1]) + fabs(R3[2])));
+  }
+  // the rows of the work-group's waves (that of each wave's first point)
+  double d2w[kThreads / 64], d3w[kThreads / 64];
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) {
+    int64_t kw = int64_t(kb) * kThreads + 64 * w;
+    if (kw > K - 1) kw = K - 1;
+    const uint32_t row = static_cast<uint32_t>(kw) / static_cast<uint32_t>(g.n1);
+    d2w[w] = static_cast<double>(row % static_cast<uint32_t>(g.n2));
+    d3w[w] = static_cast<double>(row / static_cast<uint32_t>(g.n2));
+  }
+  float sr = 0.f, si = 0.f, cr = 0.f, ci = 0.f;
+  if (carry_in && k < K) {
+    const float4 st = part[int64_t(sp) * K + k];
+    sr = st.x; si = st.y; cr = st.z; ci = st.w;
+  }
+  auto run_tile = [&](auto red_c, int nt) {
+    constexpr int R = decltype(red_c)::value;
+    const double* bw = rowb[wave];
+    int u0 = 0;
+    for (; u0 + GRP <= nt; u0 += GRP) {
+      const float ck = tile[u0].ck, sk = tile[u0].sk;
+      float gr = 0.f, gi = 0.f;
+#pragma unroll
+      for (int q = 0; q < GRP / 4; ++q) {
+        float qr = 0.f, qi = 0.f;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int uu = u0 + 4 * q + u;
+          const double ph = __builtin_fma(di1, tile[uu].c1, bw[uu]);
+          float c, s;
+          cis_turn<R>(ph, c, s);
+          const float m = tile[uu].m;
+          if constexpr (FK == 0) {
+            if (u == 0) { qr = c; qi = s; } else { qr += c; qi += s; }
+          } else {
+            if (u == 0) { qr = m * c; qi = m * s; }
+            else { qr = __builtin_fmaf(m, c, qr); qi = __builtin_fmaf(m, s, qi); }
+          }
+        }
+        if (q == 0) { gr = qr; gi = qi; } else { gr += qr; gi += qi; }
+      }
+      kahan_rot(sr, cr, si, ci, gr, gi, ck, sk);
+    }
+    if (u0 < nt) {    // the split's last, partial group
+      const float ck = tile[u0].ck, sk = tile[u0].sk;
+      float gr = 0.f, gi = 0.f;
+      for (int uu = u0; uu < nt; ++uu) {
+        const double ph = __builtin_fma(di1, tile[uu].c1, bw[uu]);
+        float c, s;
+        cis_turn<R>(ph, c, s);
+        if constexpr (FK == 0) {
+          gr += c;
+          gi += s;
+        } else {
+          const float m = tile[uu].m;
+          gr = __builtin_fmaf(m, c, gr);
+          gi = __builtin_fmaf(m, s, gi);
+        }
+      }
+      kahan_rot(sr, cr, si, ci, gr, gi, ck, sk);
+    }
+  };
+  const int j0 = a_begin + sp * per_split;
+  const int j1 = min(j0 + per_split, a_end);
+  for (int t0 = j0; t0 < j1; t0 += kThreads) {
+    const int nt = min(kThreads, j1 - t0);
+    __syncthreads();                        // the previous tile is no longer read
+    if (int(threadIdx.x) < nt) {
+      const AtomGrid a = rec[t0 + threadIdx.x];
+      tile[threadIdx.x] = Tile{a.c1, a.m, a.ck, a.sk, a.rmax};
+#pragma unroll
+      for (int w = 0; w < kThreads / 64; ++w)
+        rowb[w][threadIdx.x] = __builtin_fma(d3w[w], a.c3, __builtin_fma(d2w[w], a.c2, a.c0));
+    }
+    __syncthreads();
+    const float rt = fmaxf(tile[0].rmax, tile[nt - 1].rmax);
+    if (__all(s1 * rt < kFixedPhaseBound)) run_tile(std::integral_constant<int, 2>{}, nt);
+    else run_tile(std::integral_constant<int, 3>{}, nt);
+  }
+  if (k < K) {
+    if (direct) A[k] = make_float2(sr + cr, si + ci);
+    else part[int64_t(sp) * K + k] = make_float4(sr, si, cr, ci);
   }
 }
 
@@ -634,7 +815,7 @@ template <int MODE, int P, int FK>
 hipError_t fwd_dispatch_red(const Plan& p, const void* rec, int64_t a_begin, int64_t a_end,
                             int64_t per_split, const void* S, void* partial, void* A,
                             int carry_in, int direct, hipStream_t st, int red, const float* xyz,
-                            const float* f) {
+                            const float* f, const GridDef* gd) {
   using AT = typename AtomOf<MODE>::type;
   const dim3 grid(static_cast<unsigned>(p.blocks * p.nsplit));
   const auto* r = static_cast<const AT*>(rec);
@@ -647,6 +828,20 @@ hipError_t fwd_dispatch_red(const Plan& p, const void* rec, int64_t a_begin, int
     return hipGetLastError();
   }
   if constexpr (MODE == kPH64) {
+    if (gd) {       // grid points: the plan takes one point per lane, LDS tiles, RED 2
+      if constexpr (P == 1) {
+        if (p.grp == 16)
+          fwd_lds_kernel<1, FK, 16, 2, false, true><<<grid, kThreads, 0, st>>>(
+              r, int(a_begin), int(a_end), int(per_split), nullptr, p.lanes, int(p.blocks), pa, a,
+              carry_in, direct, nullptr, nullptr, *gd);
+        else
+          fwd_lds_kernel<1, FK, 8, 2, false, true><<<grid, kThreads, 0, st>>>(
+              r, int(a_begin), int(a_end), int(per_split), nullptr, p.lanes, int(p.blocks), pa, a,
+              carry_in, direct, nullptr, nullptr, *gd);
+        return hipGetLastError();
+      }
+      return hipErrorInvalidValue;
+    }
     if (p.lds && (p.grp == 16 || p.grp == 8)) {
       // records formed while staging (small calls): one point per lane, the fixed-point
       // reduction
@@ -655,7 +850,7 @@ hipError_t fwd_dispatch_red(const Plan& p, const void* rec, int64_t a_begin, int
         fwd_lds_kernel<P, FK, decltype(grp_c)::value, decltype(red_c)::value, decltype(inl_c)::value>
             <<<grid, kThreads, 0, st>>>(decltype(inl_c)::value ? nullptr : r, int(a_begin), int(a_end),
                                         int(per_split), s, p.lanes, int(p.blocks), pa, a, carry_in,
-                                        direct, xyz, f);
+                                        direct, xyz, f, GridDef{});
       };
       using I16 = std::integral_constant<int, 16>;
       using I8 = std::integral_constant<int, 8>;
@@ -719,22 +914,24 @@ hipError_t fwd_dispatch_red(const Plan& p, const void* rec, int64_t a_begin, int
 template <int MODE, int P>
 hipError_t fwd_dispatch_fk(const Plan& p, const void* rec, int64_t a_begin, int64_t a_end,
                            int64_t per_split, const void* S, void* partial, void* A,
-                           int carry_in, int direct, hipStream_t st, const float* xyz, const float* f) {
+                           int carry_in, int direct, hipStream_t st, const float* xyz, const float* f,
+                           const GridDef* gd) {
   if (p.fk)
     return fwd_dispatch_red<MODE, P, 1>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in,
-                                        direct, st, p.red, xyz, f);
+                                        direct, st, p.red, xyz, f, gd);
   return fwd_dispatch_red<MODE, P, 0>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in,
-                                      direct, st, p.red, xyz, f);
+                                      direct, st, p.red, xyz, f, gd);
 }
 
 template <int MODE>
 hipError_t fwd_dispatch_p(const Plan& p, const void* rec, int64_t a_begin, int64_t a_end,
                           int64_t per_split, const void* S, void* partial, void* A, int carry_in,
-                          int direct, hipStream_t st, const float* xyz, const float* f) {
+                          int direct, hipStream_t st, const float* xyz, const float* f,
+                           const GridDef* gd) {
   switch (p.per_lane) {
-    case 4: return fwd_dispatch_fk<MODE, 4>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st, xyz, f);
-    case 2: return fwd_dispatch_fk<MODE, 2>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st, xyz, f);
-    default: return fwd_dispatch_fk<MODE, 1>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st, xyz, f);
+    case 4: return fwd_dispatch_fk<MODE, 4>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st, xyz, f, gd);
+    case 2: return fwd_dispatch_fk<MODE, 2>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st, xyz, f, gd);
+    default: return fwd_dispatch_fk<MODE, 1>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st, xyz, f, gd);
   }
 }
 
@@ -766,9 +963,37 @@ hipError_t launch_pack_atoms(int mode, int red, int grp, const void* xyz, const 
   return hipGetLastError();
 }
 
+hipError_t launch_pack_atoms_grid(const Plan& p, const float* xyz, const float* f, int64_t n,
+                                  const GridDef& g, void* rec, hipStream_t st) {
+  if (p.grid != 2) return launch_pack_atoms(p.mode, p.red, p.grp, xyz, f, n, rec, st);
+  if (n <= 0) return hipSuccess;
+  pack_atoms_grid_kernel<<<grid_for(n), kThreads, 0, st>>>(xyz, f, n, static_cast<AtomGrid*>(rec), g,
+                                                           p.grp);
+  return hipGetLastError();
+}
+
 hipError_t launch_fwd_chunk(const Plan& p, const void* rec, int64_t a_begin, int64_t a_end,
                             int64_t per_split, const void* S, void* partial, void* A,
-                            int carry_in, int direct, hipStream_t st, const void* xyz, const void* f) {
+                            int carry_in, int direct, hipStream_t st, const void* xyz, const void* f,
+                            const GridDef* gd) {
+  if (p.mode == kPH64 && p.grid == 2 && gd) {
+    const dim3 grid(static_cast<unsigned>(p.blocks * p.nsplit));
+    const auto* r = static_cast<const AtomGrid*>(rec);
+    auto* pa = static_cast<float4*>(partial);
+    auto* a = static_cast<float2*>(A);
+#define NX_GRID_FWD(FK, GRP)                                                                    \
+  fwd_grid_kernel<FK, GRP><<<grid, kThreads, 0, st>>>(r, int(a_begin), int(a_end), int(per_split), \
+                                                      *gd, p.lanes, int(p.blocks), pa, a, carry_in, direct)
+    if (p.fk) {
+      if (p.grp == 16) NX_GRID_FWD(1, 16);
+      else NX_GRID_FWD(1, 8);
+    } else {
+      if (p.grp == 16) NX_GRID_FWD(0, 16);
+      else NX_GRID_FWD(0, 8);
+    }
+#undef NX_GRID_FWD
+    return hipGetLastError();
+  }
   if (p.mode == kF64) {
     if (p.per_lane == 2)
       return p.fk ? fwd_f64_launch<2, 1>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st)
@@ -778,9 +1003,10 @@ hipError_t launch_fwd_chunk(const Plan& p, const void* rec, int64_t a_begin, int
   }
   if (p.mode == kPH64)
     return fwd_dispatch_p<kPH64>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st,
-                                 static_cast<const float*>(xyz), static_cast<const float*>(f));
+                                 static_cast<const float*>(xyz), static_cast<const float*>(f),
+                                 p.grid ? gd : nullptr);
   return fwd_dispatch_p<kF32>(p, rec, a_begin, a_end, per_split, S, partial, A, carry_in, direct, st,
-                              nullptr, nullptr);
+                              nullptr, nullptr, nullptr);
 }
 
 namespace {

@@ -63,14 +63,33 @@ constexpr double kPhaseShift = 1572864.0;
 constexpr float kFixedPhaseBound = 524224.0f;     // 2^19 - 64
 
 // Tile bounds of the packed FP64-phase point records of the adjoint: one float per 256
-// records (the largest |Sx|, |Sy| or |Sz| of those points, +inf if any is not finite),
-// stored after the records.
-inline size_t point_bound_offset(int64_t n) {
-  return (static_cast<size_t>(n) * sizeof(PointPH) + 255) / 256 * 256;
+// records (the largest |Sx|, |Sy| or |Sz| of those points, +inf if any is not finite; for
+// grid records also of the row's part o + i2 e2 + i3 e3), stored after the records.
+inline size_t point_bound_offset(int64_t n, size_t rec_size = sizeof(PointPH)) {
+  return (static_cast<size_t>(n) * rec_size + 255) / 256 * 256;
 }
 inline size_t point_bound_bytes(int64_t n) {
   return (static_cast<size_t>((n + kThreads - 1) / kThreads) * sizeof(float) + 255) / 256 * 256;
 }
+
+// A regular grid of points given exactly: S(i1, i2, i3) = o + i1 e1 + i2 e2 + i3 e3 in
+// FP64, 0 <= i_a < n_a, point k = i1 + n1 (i2 + n2 i3) (i1 fastest).  Passed to the
+// kernels by value.
+struct GridDef {
+  double o[3], e1[3], e2[3], e3[3];
+  int64_t n1, n2, n3;
+};
+
+// Forward atom record of the grid sums: with r the atom's position and a its FP64-phase
+// addend (as in AtomPH), c0 = o.r + a and c_d = e_d.r, so that the phase of point
+// (i1, i2, i3) is i1 c1 + (c0 + i2 c2 + i3 c3); the bracket is one value per atom and grid
+// row.  m, ck, sk, rmax as in AtomPH.
+struct alignas(16) AtomGrid { double c0, c1, c2, c3; float m, ck, sk, rmax; };      // 48 B
+// Adjoint point record of the grid sums: i1 (FP64, exact) and delta (the seed's phase plus
+// kPhaseShift) for the phase, |G| S and |G| in FP32 (S the FP64 grid point).
+struct alignas(16) PointGrid { double i1, delta; float gsx, gsy, gsz, gmag; };      // 32 B
+// (the plan sizes the forward's records as AtomPH for both)
+static_assert(sizeof(AtomGrid) == sizeof(AtomPH), "grid atom records replace AtomPH in place");
 
 // Running state of one output lane item (a point for the forward, one component of
 // an atom's sum for the adjoint) kept between launches and across splits.
@@ -146,6 +165,8 @@ struct Plan {
   int gf = 0;            // adjoint also returns dL/df
   int lds = 0;           // FP64-phase sums: record tiles staged in LDS instead of scalar loads
   int inl = 0;           // small calls: records formed in the sum kernel, no pack dispatch
+  int grid = 0;          // points: 0 a list, 1 a grid (general kernels, FP64 points from the
+                         // grid), 2 a grid walked by rows (the grid kernels)
   int64_t lanes = 0;     // number of lane items
   int64_t stream = 0;    // number of stream items
   int64_t blocks = 0;    // work-groups over lane items
@@ -213,8 +234,12 @@ inline int reduce_lanes(int nsplit, int64_t outputs) {
 
 // Builds the plan of (op, mode) for the sizes; pure host code, no HIP call.  At most
 // max_split stream slices (kMaxSplit when omitted).
+// `grid`: 0 for a list of points; for a grid (FP64-phase mode), 2 asks for the grid kernels
+// and 1 for the general ones; the plan keeps 2 only where the grid kernels exist for it
+// (rows of n1 points, n1 a multiple of 64, the fixed-point reduction; one point per lane in
+// the forward, 64-point groups in the adjoint) and holds the kind it chose in p.grid.
 Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_null,
-               int64_t max_split = kMaxSplit);
+               int64_t max_split = kMaxSplit, int grid = 0);
 
 // Per-launch stream range of chunk c: [begin, end) and the slice length per split.
 void chunk_range(const Plan& p, int64_t c, int64_t* begin, int64_t* end, int64_t* per_split);
@@ -227,13 +252,20 @@ hipError_t launch_pack_atoms(int mode, int red, int grp, const void* xyz, const 
                              void* rec, hipStream_t st);
 hipError_t launch_pack_points(int mode, int red, const void* S, const void* G, int64_t k,
                               void* rec, hipStream_t st);
+// Grid records (FP64-phase mode): the atoms as AtomGrid (plan grid 2; grid 1 packs AtomPH
+// with launch_pack_atoms), the points of the grid with the seed G as PointGrid (grid 2) or
+// PointPH (grid 1), followed by the tile bounds as after launch_pack_points.
+hipError_t launch_pack_atoms_grid(const Plan& p, const float* xyz, const float* f, int64_t n,
+                                  const GridDef& g, void* rec, hipStream_t st);
+hipError_t launch_pack_points_grid(const Plan& p, const GridDef& g, const float* G, void* rec,
+                                   hipStream_t st);
 
 // One forward chunk over points (lane items) for atoms [a_begin, a_end).  With p.inl the
 // kernel forms the records itself from xyz and f (rec is then unused).
 hipError_t launch_fwd_chunk(const Plan& p, const void* rec, int64_t a_begin, int64_t a_end,
                             int64_t per_split, const void* S, void* partial, void* A,
                             int carry_in, int direct, hipStream_t st, const void* xyz = nullptr,
-                            const void* f = nullptr);
+                            const void* f = nullptr, const GridDef* grid = nullptr);
 // Combine split partials into A.
 hipError_t launch_fwd_reduce(const Plan& p, const void* partial, void* A, hipStream_t st);
 
@@ -243,7 +275,8 @@ hipError_t launch_fwd_reduce(const Plan& p, const void* partial, void* A, hipStr
 hipError_t launch_bwd_chunk(const Plan& p, const void* rec, int64_t k_begin, int64_t k_end,
                             int64_t per_split, const void* xyz, const void* f, void* partial,
                             void* grad, void* gradf, int carry_in, int direct, hipStream_t st,
-                            const void* S = nullptr, const void* G = nullptr);
+                            const void* S = nullptr, const void* G = nullptr,
+                            const GridDef* grid = nullptr);
 // f: the atom factors (complex f in the FP64-phase mode scales and rotates the sums).
 hipError_t launch_bwd_reduce(const Plan& p, const void* partial, const void* f, void* grad,
                              void* gradf, hipStream_t st);

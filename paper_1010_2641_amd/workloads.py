@@ -47,15 +47,59 @@ F_SPECIES_0 = complex(31.0, 1.0)
 F_SPECIES_1 = complex(22.0, 3.5)
 
 
+@dataclass(frozen=True)
+class RegularGrid:
+    """A regular grid of points given exactly: point (i1, i2, i3) is origin + i1 step1 +
+    i2 step2 + i3 step3 (float64), 0 <= i_a < n_a, listed with i1 fastest."""
+    origin: tuple
+    step1: tuple
+    step2: tuple
+    step3: tuple
+    n1: int
+    n2: int = 1
+    n3: int = 1
+
+    @property
+    def size(self) -> int:
+        return self.n1 * self.n2 * self.n3
+
+    def points(self, idx=None) -> np.ndarray:
+        """The grid points (or those of the flat indices idx), float64 (K, 3)."""
+        k = np.arange(self.size, dtype=np.int64) if idx is None else np.asarray(idx, dtype=np.int64)
+        i1 = (k % self.n1).astype(np.float64)
+        i2 = ((k // self.n1) % self.n2).astype(np.float64)
+        i3 = (k // (self.n1 * self.n2)).astype(np.float64)
+        return (np.asarray(self.origin, np.float64)[None, :] + i1[:, None] * np.asarray(self.step1)[None, :]
+                + i2[:, None] * np.asarray(self.step2)[None, :] + i3[:, None] * np.asarray(self.step3)[None, :])
+
+
+def axis_grid(h, k, l) -> RegularGrid:
+    """The grid of grid_points(h, k, l) for axes given as (start, step, count) or as a
+    single value: h along x (fastest), k along y, l along z."""
+    axes = []
+    for v in (h, k, l):
+        axes.append((float(v[0]), float(v[1]), int(v[2])) if isinstance(v, tuple) else (float(v), 0.0, 1))
+    (h0, dh, nh), (k0, dk, nk), (l0, dl, nl) = axes
+    return RegularGrid((h0, k0, l0), (dh, 0.0, 0.0), (0.0, dk, 0.0), (0.0, 0.0, dl), nh, nk, nl)
+
+
+def linspace_axis(lo: float, hi: float, n: int, centre: float = 0.0):
+    """(start, step, count) of centre + linspace(lo, hi, n)."""
+    return (centre + lo, (hi - lo) / (n - 1), n)
+
+
 @dataclass
 class Workload:
-    """One synthetic problem: atoms, factors, points (all float32 / complex64)."""
+    """One synthetic problem: atoms, factors, points (all float32 / complex64).  Where the
+    points are a regular grid, ``grid`` gives it exactly (S is that grid rounded to
+    float32, the list the point-list calls take)."""
     name: str
     xyz: np.ndarray                      # (N, 3) float32
     f: Optional[np.ndarray]              # (N,) complex64 or None for f_j = 1
     S: np.ndarray                        # (K, 3) float32
     target_xyz: Optional[np.ndarray] = None   # (N, 3) float32: structure whose |A|^2 is fitted
     meta: dict = field(default_factory=dict)
+    grid: Optional[RegularGrid] = None
 
     @property
     def n_atoms(self) -> int:
@@ -104,7 +148,9 @@ def c1(seed: int = 1001, sigma: float = 0.02) -> Workload:
         p = p + rng.normal(0.0, sigma, size=p.shape)
     d = np.linspace(-0.5, 0.5, 64)
     S = grid_points(d, d, 4.0)
-    return Workload("c1", _f32(p), None, _f32(S), meta=dict(sigma=sigma, seed=seed))
+    a = linspace_axis(-0.5, 0.5, 64)
+    return Workload("c1", _f32(p), None, _f32(S), meta=dict(sigma=sigma, seed=seed),
+                    grid=axis_grid(a, a, 4.0))
 
 
 def _pyramid_mask(p):
@@ -138,7 +184,9 @@ def c2(seed: int = 1002, n_grid: int = 128, strain: float = 0.04) -> Workload:
     d = np.linspace(-0.05, 0.05, n_grid)
     S = grid_points(4.0 + d, d, 4.0 + d)
     return Workload("c2", _f32(p), f, _f32(S), target_xyz=_f32(pt),
-                    meta=dict(seed=seed, strain=strain))
+                    meta=dict(seed=seed, strain=strain),
+                    grid=axis_grid(linspace_axis(-0.05, 0.05, n_grid, 4.0), linspace_axis(-0.05, 0.05, n_grid),
+                                   linspace_axis(-0.05, 0.05, n_grid, 4.0)))
 
 
 def c3(seed: int = 1003, sigma: float = 0.01, n_side: int = 100, n_grid: int = 256) -> Workload:
@@ -150,7 +198,9 @@ def c3(seed: int = 1003, sigma: float = 0.01, n_side: int = 100, n_grid: int = 2
         p = p + rng.normal(0.0, sigma, size=p.shape)
     d = np.linspace(-0.05, 0.05, n_grid)
     S = grid_points(8.0 + d, 8.0 + d, 8.0)
-    return Workload("c3", _f32(p), None, _f32(S), meta=dict(seed=seed, sigma=sigma))
+    a = linspace_axis(-0.05, 0.05, n_grid, 8.0)
+    return Workload("c3", _f32(p), None, _f32(S), meta=dict(seed=seed, sigma=sigma),
+                    grid=axis_grid(a, a, 8.0))
 
 
 def _sine_field(p0, amp, phase):
@@ -170,7 +220,9 @@ def c4(seed: int = 1004, n_cells: int = 29, n_grid: int = 64) -> Workload:
     pt = p0 + _sine_field(p0, 0.033, 0.3)
     d = np.linspace(-0.08, 0.08, n_grid)
     S = grid_points(2.0 + d, 2.0 + d, d)
-    return Workload("c4", _f32(p), None, _f32(S), target_xyz=_f32(pt), meta=dict(seed=seed))
+    a = linspace_axis(-0.08, 0.08, n_grid, 2.0)
+    return Workload("c4", _f32(p), None, _f32(S), target_xyz=_f32(pt), meta=dict(seed=seed),
+                    grid=axis_grid(a, a, linspace_axis(-0.08, 0.08, n_grid)))
 
 
 def _wire_displacement(p0, scale):
@@ -199,7 +251,9 @@ def c5(seed: int = 1005, n_grid: int = 256) -> Workload:
     pt = p0 + _wire_displacement(p0, 1.1)
     d = np.linspace(-0.05, 0.05, n_grid)
     S = grid_points(d, d, 4.0 + d)
-    return Workload("c5", _f32(p), f, _f32(S), target_xyz=_f32(pt), meta=dict(seed=seed))
+    a = linspace_axis(-0.05, 0.05, n_grid)
+    return Workload("c5", _f32(p), f, _f32(S), target_xyz=_f32(pt), meta=dict(seed=seed),
+                    grid=axis_grid(a, a, linspace_axis(-0.05, 0.05, n_grid, 4.0)))
 
 
 # ----------------------------------------------------------------------------- unstructured points
@@ -288,7 +342,8 @@ def cube41(strained: bool = False) -> Workload:
     l = np.arange(3.9, 4.1, 0.001)[:200]
     S = grid_points(h, 0.0, l)
     return Workload("cube41s" if strained else "cube41", _f32(p), None, _f32(S),
-                    meta=dict(strained=strained))
+                    meta=dict(strained=strained),
+                    grid=axis_grid((-0.1, 0.001, 200), 0.0, (3.9, 0.001, 200)))
 
 
 NAMED = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "ewald": ewald, "cube41": cube41,

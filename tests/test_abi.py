@@ -57,7 +57,7 @@ def test_micro_header_symbols_exported():
 
 
 def test_version():
-    assert _lib.nx_version() == 103
+    assert _lib.nx_version() == 104
 
 
 def fwd(n_atoms=8, n_points=8, xyz=FAKE, f=None, S=FAKE, A=FAKE, mode=1, ws=FAKE, wsb=1 << 40):
@@ -303,3 +303,107 @@ def test_plan_stream_slices_are_at_least_256_items(monkeypatch):
     # a small target keeps the small grid (the knob the launch-shape tests use)
     monkeypatch.setenv("NX_TUNE_TARGET_BLOCKS", "12")
     assert _lib.nx_workspace_bytes(1000, 1000, 1, _lib.NX_OP_FWD, 1) == a256(1000 * 48) + a256(3 * 1000 * 16)
+
+
+def grid_struct(n1=64, n2=2, n3=3, origin=(3.95, -0.05, 3.95), step=1e-3):
+    g = _lib.nx_grid()
+    g.origin[:] = origin
+    g.step1[:] = (step, 0.0, 0.0)
+    g.step2[:] = (0.0, step, 0.0)
+    g.step3[:] = (0.0, 0.0, step)
+    g.n1, g.n2, g.n3 = n1, n2, n3
+    return g
+
+
+def fwd_grid(g, n_atoms=8, xyz=FAKE, f=None, A=FAKE, mode=1, ws=FAKE, wsb=1 << 40):
+    return _lib.nx_scatter_fwd_grid(xyz, f, n_atoms, ctypes.byref(g) if g is not None else None, A,
+                                    mode, ws, wsb, None)
+
+
+def bwd_grid(g, n_atoms=8, xyz=FAKE, f=None, G=FAKE, grad=FAKE, mode=1, ws=FAKE, wsb=1 << 40):
+    return _lib.nx_scatter_bwd_grid(xyz, f, n_atoms, ctypes.byref(g) if g is not None else None, G,
+                                    grad, mode, ws, wsb, None)
+
+
+def test_grid_struct_layout():
+    """struct nx_grid: 12 doubles, then three int64 counts (120 bytes)."""
+    assert ctypes.sizeof(_lib.nx_grid) == 120
+    assert _lib.nx_grid.n1.offset == 96 and _lib.nx_grid.n3.offset == 112
+
+
+def test_grid_argument_checks():
+    assert fwd_grid(None) == _lib.NX_ERR_ARG and "NULL grid" in _lib.last_error()
+    assert bwd_grid(None) == _lib.NX_ERR_ARG
+    assert fwd_grid(grid_struct(n2=-1)) == _lib.NX_ERR_ARG and "n2" in _lib.last_error()
+    assert fwd_grid(grid_struct(n1=1 << 11, n2=1 << 10, n3=1 << 10)) == _lib.NX_ERR_ARG
+    assert "exceeds" in _lib.last_error()
+    assert fwd_grid(grid_struct(n1=1 << 40)) == _lib.NX_ERR_ARG
+    assert fwd_grid(grid_struct(origin=(float("nan"), 0.0, 0.0))) == _lib.NX_ERR_ARG
+    assert "finite" in _lib.last_error()
+    g = grid_struct()
+    g.step3[2] = float("inf")
+    assert bwd_grid(g) == _lib.NX_ERR_ARG
+    # FP64-phase mode only
+    assert fwd_grid(grid_struct(), mode=0) == _lib.NX_ERR_MODE and "NX_F32_PH64" in _lib.last_error()
+    assert bwd_grid(grid_struct(), mode=0) == _lib.NX_ERR_MODE
+    # NULL pointers and alignment
+    assert fwd_grid(grid_struct(), A=None) == _lib.NX_ERR_ARG
+    assert fwd_grid(grid_struct(), xyz=None) == _lib.NX_ERR_ARG
+    assert bwd_grid(grid_struct(), G=None) == _lib.NX_ERR_ARG
+    assert bwd_grid(grid_struct(), grad=None) == _lib.NX_ERR_ARG
+    assert fwd_grid(grid_struct(), A=FAKE + 4) == _lib.NX_ERR_ARG
+    assert fwd_grid(grid_struct(), f=FAKE + 4) == _lib.NX_ERR_ARG
+    # workspace too small or missing
+    assert fwd_grid(grid_struct(), ws=None, wsb=0) == _lib.NX_ERR_WORKSPACE
+    assert bwd_grid(grid_struct(), wsb=16) == _lib.NX_ERR_WORKSPACE
+    assert fwd_grid(grid_struct(), n_atoms=-1) == _lib.NX_ERR_ARG
+
+
+def test_grid_empty_calls_queue_nothing():
+    """An empty grid forward and a zero-atom adjoint return before any launch."""
+    assert fwd_grid(grid_struct(n3=0), A=None, xyz=None, ws=None, wsb=0) == _lib.NX_OK
+    assert bwd_grid(grid_struct(), n_atoms=0, xyz=None, grad=None, G=None, ws=None, wsb=0) == _lib.NX_OK
+
+
+def test_grid_fit_step_checks_before_queueing():
+    g = grid_struct()
+    args = lambda **kw: [kw.get("xyz", FAKE), None, 8, ctypes.byref(g), kw.get("I", FAKE), kw.get("A", FAKE),
+                         kw.get("L", FAKE), kw.get("G", FAKE), kw.get("grad", FAKE), kw.get("mode", 1),
+                         kw.get("ws", FAKE), kw.get("wsb", 1 << 40), None]
+    assert _lib.nx_fit_step_grid(*args(L=None)) == _lib.NX_ERR_ARG
+    assert _lib.nx_fit_step_grid(*args(I=None)) == _lib.NX_ERR_ARG
+    assert _lib.nx_fit_step_grid(*args(mode=0)) == _lib.NX_ERR_MODE
+    assert _lib.nx_fit_step_grid(*args(L=FAKE + 4)) == _lib.NX_ERR_ARG
+    assert _lib.nx_fit_step_grid(*args(ws=None, wsb=0)) == _lib.NX_ERR_WORKSPACE
+    # the step's workspace covers its three stages
+    fit = _lib.nx_workspace_bytes_grid(8, ctypes.byref(g), _lib.NX_OP_FIT, 1)
+    stages = [_lib.nx_workspace_bytes_grid(8, ctypes.byref(g), op, 1) for op in (_lib.NX_OP_FWD, _lib.NX_OP_BWD)]
+    stages.append(_lib.nx_workspace_bytes(0, 384, 1, _lib.NX_OP_LOSS, 1))
+    assert fit == max(stages)
+
+
+def test_grid_workspace(monkeypatch):
+    """Rows of a multiple of 64 points: 48-byte atom records (forward) and 32-byte point
+    records (i1, the phase addend, |G| S and |G|; adjoint), each followed as in the
+    point-list calls by the tiles' bounds; other grids take the point-list records (48 B).
+    Unknown ops are refused."""
+    monkeypatch.delenv("NX_TUNE_GRID", raising=False)
+    a256 = lambda b: -(-b // 256) * 256
+    g = grid_struct(n1=128, n2=128, n3=128)          # 2,097,152 points
+    n, k = 203_557, 128 ** 3
+    bwd_rows = _lib.nx_workspace_bytes_grid(n, ctypes.byref(g), _lib.NX_OP_BWD, 0)
+    bwd_list = _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_BWD, 0)
+    assert bwd_list - bwd_rows == a256(k * 48) - a256(k * 32)
+    # the forward: one point per lane, same records as the list
+    fw = _lib.nx_workspace_bytes_grid(n, ctypes.byref(g), _lib.NX_OP_FWD, 0)
+    assert fw % 256 == 0 and fw >= a256(n * 48)
+    # a row of 50 points takes the general kernels and their records
+    g50 = grid_struct(n1=50, n2=40, n3=3)
+    assert (_lib.nx_workspace_bytes_grid(1000, ctypes.byref(g50), _lib.NX_OP_BWD, 1)
+            == _lib.nx_workspace_bytes(1000, 6000, 1, _lib.NX_OP_BWD, 1))
+    # and so does every grid under NX_TUNE_GRID=1
+    monkeypatch.setenv("NX_TUNE_GRID", "1")
+    assert _lib.nx_workspace_bytes_grid(n, ctypes.byref(g), _lib.NX_OP_BWD, 0) == bwd_list
+    assert _lib.nx_workspace_bytes_grid(8, ctypes.byref(g), 3, 1) == 0
+    assert "op must be" in _lib.last_error()
+    assert _lib.nx_workspace_bytes_grid(8, None, _lib.NX_OP_FWD, 1) == 0

@@ -84,7 +84,11 @@ def test_hot_kernels_occupancy(device_asm):
     want = {"fwd_lds_kernelILi1ELi1ELi16ELi2ELb0E": 8,      # forward, complex f, 16-atom groups
             "fwd_lds_kernelILi1ELi0ELi16ELi2ELb0E": 8,      # forward, f = 1
             "bwd_split_kernelILi2ELi1ELi64ELi2ELb0ELb0E": 6,    # adjoint, complex f
-            "bwd_split_kernelILi2ELi0ELi64ELi2ELb0ELb0E": 6}    # adjoint, f = 1
+            "bwd_split_kernelILi2ELi0ELi64ELi2ELb0ELb0E": 6,    # adjoint, f = 1
+            "fwd_grid_kernelILi1ELi16E": 8,                      # grids walked by rows
+            "fwd_grid_kernelILi0ELi16E": 8,
+            "bwd_grid_kernelILi2ELi1E": 6,
+            "bwd_grid_kernelILi2ELi0E": 6}
     for key, o in want.items():
         found = [v for k, v in occ.items() if key in k]
         assert found, key

@@ -1,0 +1,220 @@
+"""The grid entry points (nx_scatter_fwd_grid, nx_scatter_bwd_grid, nx_fit_step_grid): the
+sums of Eq. 2 and its adjoint over a regular grid of points given exactly (FP64 origin and
+steps), against the FP64 oracle evaluated at the same FP64 grid points.
+
+* Rows of a multiple of 64 points take the row-walking kernels: the phase is i1 (step1.r)
+  plus a row term formed once per atom and row.  Other grids take the point-list kernels
+  with every grid point formed in FP64.  Both meet the point-list calls' tolerances
+  (random atoms: pointwise error against sqrt(sum |f|^2); adjoint: T3).
+* Oblique steps, complex and unit factors, ragged point and atom counts, chunked
+  launches and stream splits, empty calls, tiles beyond the fixed-point range.
+* The fit step in one call equals its three calls bitwise.
+* C2 at full size (203,557 atoms, 128^3 points) in the launch configuration of a full call,
+  on sampled points and atoms."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1010_2641_amd import api, workloads as wl
+from tests import metrics as M
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def dev(a):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def oblique(n1, n2, n3, origin=(3.9, 0.1, 4.1)):
+    return wl.RegularGrid(origin, (0.013, 0.004, -0.002), (-0.003, 0.011, 0.001), (0.002, -0.001, 0.017),
+                          n1, n2, n3)
+
+
+def fwd(xyz, f, grid):
+    A = api.scatter_fwd_grid(dev(xyz), dev(f), grid)
+    torch.cuda.synchronize()
+    return A.cpu().numpy().astype(np.complex128)
+
+
+def bwd(xyz, f, grid, G):
+    g = api.scatter_bwd_grid(dev(xyz), dev(f), grid, dev(G.astype(np.complex64)))
+    torch.cuda.synchronize()
+    return g.cpu().numpy().astype(np.float64)
+
+
+SHAPES = [((128, 5, 3), 3001, True),      # rows of 128: the row kernels
+          ((64, 5, 1), 777, False),       # 320 points: a partly filled last work-group
+          ((64, 1, 1), 70_000, True),     # one row, many atoms: stream splits
+          ((50, 7, 3), 2500, True),       # rows of 50: the point-list kernels
+          ((1, 3, 200), 1200, False),     # one-point rows
+          ((192, 2, 2), 1, True)]         # a single atom
+
+
+@pytest.mark.parametrize("shape,n,cplx", SHAPES)
+def test_fwd_grid_vs_oracle(shape, n, cplx):
+    grid = oblique(*shape)
+    xyz, f, _ = wl.random_problem(n, 1, seed=n + shape[0], extent=60.0, s_range=1.0, complex_f=cplx)
+    print(f"case fwd grid {shape} N={n} complex={cplx}", flush=True)
+    A = fwd(xyz, f, grid)
+    ref = oracle.forward(xyz, f, grid.points())
+    e = M.incoherent(A, ref, f, n)
+    print(f"  pointwise/sqrt(sum|f|^2) = {e:.3e}", flush=True)
+    assert e <= M.INC_TOL
+
+
+@pytest.mark.parametrize("shape,n,cplx", SHAPES)
+def test_bwd_grid_vs_oracle(shape, n, cplx):
+    grid = oblique(*shape)
+    xyz, f, _ = wl.random_problem(n, 1, seed=2 * n + shape[1], extent=60.0, s_range=1.0, complex_f=cplx)
+    G = wl.random_seed_field(grid.size, seed=n + 5)
+    print(f"case bwd grid {shape} N={n} complex={cplx}", flush=True)
+    g = bwd(xyz, f, grid, G)
+    en, em = M.t3(g, oracle.adjoint(xyz, f, grid.points(), G))
+    print(f"  T3 norm={en:.3e} max={em:.3e}", flush=True)
+    assert en <= M.T3_NORM_TOL and em <= M.T3_MAX_TOL
+
+
+@pytest.mark.parametrize("cplx", [True, False])
+def test_row_kernels_agree_with_point_list_kernels(cplx, monkeypatch):
+    """The same grid through the row kernels and (NX_TUNE_GRID=1) through the point-list
+    kernels with FP64 grid points: the phases round differently (i1 (e1.r) + row term
+    against S.r), so the results agree to rounding, not bitwise."""
+    grid = oblique(256, 3, 2)
+    n = 5000
+    xyz, f, _ = wl.random_problem(n, 1, seed=71, extent=50.0, s_range=1.0, complex_f=cplx)
+    G = wl.random_seed_field(grid.size, seed=72)
+    print(f"case rows vs point-list kernels complex={cplx}", flush=True)
+    A_rows, g_rows = fwd(xyz, f, grid), bwd(xyz, f, grid, G)
+    monkeypatch.setenv("NX_TUNE_GRID", "1")
+    A_list, g_list = fwd(xyz, f, grid), bwd(xyz, f, grid, G)
+    e = M.incoherent(A_rows, A_list, f, n)
+    en, em = M.t3(g_rows, g_list)
+    print(f"  fwd gap {e:.3e}, adjoint T3 norm={en:.3e} max={em:.3e}", flush=True)
+    assert e <= M.INC_TOL and en <= M.T3_NORM_TOL and em <= M.T3_MAX_TOL
+
+
+def test_chunked_launches(monkeypatch):
+    """Small launch chunks: several forward and adjoint launches carry their state."""
+    grid = oblique(128, 4, 2)
+    n = 9000
+    xyz, f, _ = wl.random_problem(n, 1, seed=73, extent=40.0, s_range=1.0)
+    G = wl.random_seed_field(grid.size, seed=74)
+    monkeypatch.setenv("NX_TUNE_LAUNCH_PAIRS", str(1 << 20))
+    print("case grid chunked launches", flush=True)
+    A = fwd(xyz, f, grid)
+    g = bwd(xyz, f, grid, G)
+    P = grid.points()
+    assert M.incoherent(A, oracle.forward(xyz, f, P), f, n) <= M.INC_TOL
+    en, em = M.t3(g, oracle.adjoint(xyz, f, P, G))
+    assert en <= M.T3_NORM_TOL and em <= M.T3_MAX_TOL
+
+
+def test_empty_and_degenerate():
+    grid = oblique(64, 2, 1)
+    xyz, f, _ = wl.random_problem(10, 1, seed=75)
+    print("case grid empty calls", flush=True)
+    # no atoms: A = 0
+    A = api.scatter_fwd_grid(torch.zeros((0, 3), dtype=torch.float32, device=DEV), None, grid)
+    torch.cuda.synchronize()
+    assert A.shape == (128,) and bool((A == 0).all())
+    # no points: zero gradient, written by the library
+    empty = oblique(64, 0, 1)
+    g = api.scatter_bwd_grid(dev(xyz), dev(f), empty, torch.zeros(0, dtype=torch.complex64, device=DEV))
+    torch.cuda.synchronize()
+    assert g.shape == (10, 3) and bool((g == 0).all())
+    assert api.scatter_fwd_grid(dev(xyz), dev(f), empty).numel() == 0
+    # a zero step: every point of a row is the same point
+    flat = wl.RegularGrid((1.0, 2.0, 3.0), (0.0, 0.0, 0.0), (0.1, 0.0, 0.0), (0.0, 0.0, 0.0), 64, 3, 1)
+    A = fwd(xyz, f, flat).reshape(3, 64)
+    assert np.all(A == A[:, :1])
+    assert M.incoherent(A.ravel(), oracle.forward(xyz, f, flat.points()), f, 10) <= M.INC_TOL
+
+
+@pytest.mark.parametrize("n,cplx", [(2000, True), (1500, False)])
+def test_fit_step_grid_one_call_equals_three(n, cplx):
+    grid = oblique(128, 6, 2)
+    xyz, f, _ = wl.random_problem(n, 1, seed=76 + n, extent=40.0, s_range=1.0, complex_f=cplx)
+    I = dev((np.abs(oracle.forward(xyz, f, grid.points())) ** 2).astype(np.float32) * 1.1)
+    x, fd = dev(xyz), dev(f)
+    print(f"case fit step grid N={n} complex={cplx}", flush=True)
+    L, A, g, G = api.fit_step_grid(x, fd, grid, I, return_seed=True)
+    A3 = api.scatter_fwd_grid(x, fd, grid)
+    L3, G3 = api.loss_grad(A3, I)
+    g3 = api.scatter_bwd_grid(x, fd, grid, G3)
+    torch.cuda.synchronize()
+    assert torch.equal(A, A3) and torch.equal(G, G3) and torch.equal(g, g3)
+    assert float(L) == float(L3)
+
+
+def test_tiles_beyond_the_fixed_point_range():
+    """Every other block of 700 atoms 300,000 lattice units out (their tiles exceed the
+    fixed-point range: 300,000 x |S|_1 > 2^19) and every other group of points with
+    |S_x| near 30,000 (the adjoint's tiles beyond the range for atoms within 40 units):
+    those tiles reduce with rint and still meet the tolerances."""
+    n = 3000
+    xyz, f, _ = wl.random_problem(n, 1, seed=77, extent=40.0, s_range=1.0)
+    far = (np.arange(n) // 700) % 2 == 1
+    xyz = xyz.copy()
+    xyz[far, 0] += np.float32(300_000.0)
+    grid = oblique(128, 4, 2, origin=(3.0, 0.0, 0.0))
+    print("case grid forward, out-of-range atom tiles", flush=True)
+    A = fwd(xyz, f, grid)
+    assert M.incoherent(A, oracle.forward(xyz, f, grid.points()), f, n) <= M.INC_TOL
+    # points: the second half of the grid's rows far out along x
+    n2 = 1000
+    xa, fa, _ = wl.random_problem(n2, 1, seed=78, extent=40.0, s_range=1.0)
+    gfar = wl.RegularGrid((30_000.0, 0.0, 0.0), (0.013, 0.004, 0.0), (-29_997.0, 0.011, 0.0),
+                          (0.0, 0.0, 0.017), 64, 2, 3)
+    G = wl.random_seed_field(gfar.size, seed=79)
+    print("case grid adjoint, out-of-range point tiles", flush=True)
+    g = bwd(xa, fa, gfar, G)
+    en, em = M.t3(g, oracle.adjoint(xa, fa, gfar.points(), G))
+    print(f"  T3 norm={en:.3e} max={em:.3e}", flush=True)
+    assert en <= M.T3_NORM_TOL and em <= M.T3_MAX_TOL
+
+
+def central_lines(n):
+    c = n // 2
+    idx = [h + n * c + n * n * c for h in range(n)] + [c + n * k + n * n * c for k in range(n)]
+    idx += [c + n * c + n * n * l for l in range(n)]
+    return np.unique(np.array(idx, dtype=np.int64))
+
+
+def test_c2_grid_fit_step_at_full_size():
+    """C2's fit step over its exact 128^3 grid (one call, the benchmark's configuration):
+    sampled A against the oracle at the FP64 grid points (T1, T2), L against an FP64
+    recomputation from the returned A, the adjoint against the oracle on 24 sampled atoms
+    and against the all-FP64 GPU adjoint fed the same seed on 4,096."""
+    w = wl.c2()
+    grid = w.grid
+    P = grid.points()
+    tx, tf = dev(w.xyz), dev(w.f)
+    I = (api.scatter_fwd_grid(dev(w.target_xyz), tf, grid).abs() ** 2).float()
+    print(f"case c2 grid fit step: {w.n_atoms} atoms x {grid.size} points", flush=True)
+    L, A, g, G = api.fit_step_grid(tx, tf, grid, I, return_seed=True)
+    torch.cuda.synchronize()
+    A_np = A.cpu().numpy()
+    rng = np.random.default_rng(81)
+    idx = np.unique(np.concatenate([rng.choice(grid.size, 256, replace=False), central_lines(128)]))
+    ref = oracle.forward(w.xyz, w.f, P[idx])
+    e1, e2 = M.t1(A_np[idx], ref), M.t2(A_np[idx], ref)
+    print(f"  fwd sampled T1={e1:.3e} T2={e2:.3e}", flush=True)
+    assert e1 <= M.T1_TOL and e2 <= M.T2_TOL
+    Ad = A_np.astype(np.complex128)
+    e = np.abs(Ad) ** 2 - I.cpu().numpy().astype(np.float64)
+    assert abs(float(L.cpu()) - np.sum(e * e)) <= 1e-12 * np.sum(e * e)
+    G_np = G.cpu().numpy()
+    g_np = g.cpu().numpy()
+    atoms = np.sort(rng.choice(w.n_atoms, size=24, replace=False))
+    en, em = M.t3(g_np[atoms], oracle.adjoint(w.xyz[atoms], w.f[atoms], P, G_np))
+    print(f"  adjoint vs oracle (24 atoms): T3 norm={en:.3e} max={em:.3e}", flush=True)
+    assert en <= M.T3_NORM_TOL and em <= M.T3_MAX_TOL
+    atoms = np.sort(rng.choice(w.n_atoms, size=4096, replace=False))
+    g64 = api.scatter_bwd_f64(dev(w.xyz[atoms].astype(np.float64)), dev(w.f[atoms].astype(np.complex128)),
+                              dev(P), G.to(torch.complex128)).cpu().numpy()
+    en, em = M.t3(g_np[atoms], g64)
+    print(f"  adjoint vs all-FP64 path (4096 atoms): T3 norm={en:.3e} max={em:.3e}", flush=True)
+    assert en <= M.T3_NORM_TOL and em <= M.T3_MAX_TOL
