@@ -8,7 +8,10 @@ G = 4 (|A|^2 - I) A, and the adjoint dL/dr_j -- all in libnx's HIP kernels.
 Headline workload (default): the strained Ge-like truncated-pyramid dot on an fcc
 lattice, 203,557 atoms with two complex scattering factors, on a 128^3 grid of points
 around (4,0,4) (2,097,152 points); the target intensity is that of the same dot with
-the strain scaled by 1.1, computed once before timing.  The largest configuration,
+the strain scaled by 1.1, computed once before timing.  The grid goes to the grid entry
+points exactly (FP64 origin and steps; nx_fit_step_grid, whose kernels walk it by rows);
+the same step through the point-list entry points (the points rounded to FP32) is timed
+beside it ("list_path"), and --points list makes that the timed step.  The largest configuration,
 the 4,013,800-atom nanowire on 256^3 points (39 s per step), is measured in the same
 run as one timed step (the "c5" object of the line): the requested number of timed
 steps of it would not fit the run's time limit.
@@ -67,6 +70,14 @@ ALG_SLOTS = {
     ("f32", "fwd", "unit"): 3 + 1 + 2 + 2,
     ("f32", "bwd", "complex"): 3 + 1 + 2 + 4 + 2 + 3,
     ("f32", "bwd", "unit"): 3 + 1 + 2 + 2 + 3,
+    # grids walked by rows (FP64-phase mode): the phase is fma(i1, step1.r, b), b the atom's
+    # row term (formed once per atom and row), 1 FP64 fma instead of 3; the adjoint adds the
+    # point's addend (the seed phase and the shift) with 1 FP64 add, the factor's angle
+    # being folded into b
+    ("grid", "fwd", "complex"): 1 + 2 + 2 + 2,
+    ("grid", "fwd", "unit"): 1 + 2 + 2 + 2,
+    ("grid", "bwd", "complex"): 2 + 2 + 1 + 3,
+    ("grid", "bwd", "unit"): 2 + 2 + 1 + 3,
 }
 # The paper's count of the work per pair (Eq. 3, Section 2.2: 3 mul, 4 add, 1 sincos) and
 # the published FP32 vector peak of the MI355X: the roofline's flop fraction.
@@ -124,6 +135,11 @@ def parse():
     p.add_argument("--workload", default="c2",
                    choices=["c1", "c2", "c3", "c4", "c5", "ewald", "cube41", "cube41s"])
     p.add_argument("--mode", default="ph64", choices=["ph64", "f32"])
+    p.add_argument("--points", default="grid", choices=["grid", "list"],
+                   help="grid: a workload whose points are a regular grid passes that grid exactly "
+                        "(FP64 origin and steps) to the grid entry points, which walk it by rows "
+                        "(FP64-phase mode); list: its points rounded to FP32 go to the point-list "
+                        "entry points (the default for unstructured points and the FP32 mode)")
     p.add_argument("--no-f64", action="store_true", help="skip the all-FP64 comparison")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--graph", action="store_true",
@@ -153,13 +169,14 @@ def progress(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
-def make_target(api, w, tf, tS, mode):
+def make_target(w, fwd):
+    """|A|^2 of the workload's target structure (fwd: the forward of the points in use)."""
     import torch
     if w.target_xyz is not None:
         tx = torch.from_numpy(w.target_xyz).cuda()
     else:                       # workloads without a target structure: a shifted copy
         tx = torch.from_numpy(w.xyz).cuda() * 1.001
-    I = (api.scatter_fwd(tx, tf, tS, mode).abs() ** 2).float()
+    I = (fwd(tx).abs() ** 2).float()
     del tx
     return I
 
@@ -180,16 +197,19 @@ def central_lines(name, n_points):
     return idx
 
 
-def cpu_baseline(name, w, A_gpu, G, g_gpu, budget_s):
+def cpu_baseline(name, w, A_gpu, G, g_gpu, budget_s, S_eval=None):
     """The FP64 oracle on a bounded sample of the same workload: the forward on the grid
     lines through the map centre and then seeded random points (all atoms), for half the
     budget, and the adjoint on seeded random atoms (all points) fed the step's own seed G,
     for the other half; the full-step time is extrapolated linearly.  Also returns the
     GPU's errors against the oracle on the sampled outputs (A_gpu: the step's amplitudes,
-    g_gpu: its gradient, both numpy)."""
+    g_gpu: its gradient, both numpy).  S_eval: the points the GPU evaluated ((K, 3); the
+    FP64 grid points for the grid entry points), by default the FP32 list w.S."""
     import numpy as np
 
     import oracle
+
+    S_all = w.S if S_eval is None else S_eval
 
     cores = oracle.threads()
     rng = np.random.default_rng(2024)
@@ -207,14 +227,14 @@ def cpu_baseline(name, w, A_gpu, G, g_gpu, budget_s):
     while n_pts < w.n_points and t_fwd < 0.5 * budget_s:
         idx = order_p[n_pts:n_pts + bp]
         t0 = time.perf_counter()
-        A_parts.append(oracle.forward(w.xyz, w.f, w.S[idx]))
+        A_parts.append(oracle.forward(w.xyz, w.f, S_all[idx]))
         t_fwd += time.perf_counter() - t0
         n_pts += len(idx)
     g_parts, n_at, t_bwd = [], 0, 0.0
     while n_at < w.n_atoms and t_bwd < 0.5 * budget_s:
         idx = order_a[n_at:n_at + ba]
         t0 = time.perf_counter()
-        g_parts.append(oracle.adjoint(w.xyz[idx], None if w.f is None else w.f[idx], w.S, G))
+        g_parts.append(oracle.adjoint(w.xyz[idx], None if w.f is None else w.f[idx], S_all, G))
         t_bwd += time.perf_counter() - t0
         n_at += len(idx)
     pts = order_p[:n_pts]
@@ -287,7 +307,8 @@ def kernel_roofline(name, mode, fkind, pairs, t_fwd, t_bwd, ceilings):
     """Roofline of the dominant kernel (the longer of the two sums): the paper's 8 flop
     per pair (Eq. 3) against the published FP32 peak, and a separate VALU issue-slot
     fraction against the measured ceiling of the kernel's own instruction mix.  Both
-    sums' figures are listed under "sums"."""
+    sums' figures are listed under "sums".  mode: "ph64", "f32" or "grid" (the FP64-phase
+    sums over grid rows)."""
     sums = {}
     for dom, t in (("fwd", t_fwd), ("bwd", t_bwd)):
         slots = ALG_SLOTS[(mode, dom, fkind)]
@@ -324,7 +345,8 @@ def kernel_roofline(name, mode, fkind, pairs, t_fwd, t_bwd, ceilings):
     traffic, valu = saved_counters(name, dom, mode)
     return {"bound": "alu", "achieved": d["paper_tflops"], "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": d["paper_flop_frac"], "traffic": traffic,
-            "kernel": f"nx_scatter_{dom} ({mode}, {fkind} f)",
+            "kernel": (f"nx_scatter_{dom}_grid (ph64, {fkind} f, rows of the grid)" if mode == "grid"
+                       else f"nx_scatter_{dom} ({mode}, {fkind} f)"),
             "launch": "one entry-point call (all of its dispatches and launch chunks)",
             "flop_per_pair": PAPER_FLOP_PER_PAIR,
             "flop_convention": "the paper's count per atom-point pair (Eq. 3, Section 2.2: "
@@ -382,12 +404,39 @@ def f64_path(api, tx, tf, tS, G, n, k, pairs, stream):
             "step_pairs_per_s": pairs64 / (tf64 + tb64), "points_timed": k64}
 
 
+def uses_grid(args, w) -> bool:
+    """Whether the workload's points go to the grid entry points (see --points)."""
+    return args.points == "grid" and args.mode == "ph64" and w.grid is not None
+
+
+def list_path(api, tx, tf, tS, I, mode, pairs, stream, reps=3):
+    """The same step through the point-list entry points (the grid's points rounded to
+    FP32): one warm-up, then `reps` steps as three calls with events between them."""
+    import torch
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    recs = [[ev() for _ in range(4)] for _ in range(reps + 1)]
+    for r in recs:
+        r[0].record(stream)
+        A = api.scatter_fwd(tx, tf, tS, mode)
+        r[1].record(stream)
+        _, G = api.loss_grad(A, I)
+        r[2].record(stream)
+        api.scatter_bwd(tx, tf, tS, G, mode)
+        r[3].record(stream)
+    torch.cuda.synchronize()
+    t = [sum(r[a].elapsed_time(r[b]) for r in recs[1:]) / reps / 1e3 for a, b in ((0, 1), (2, 3), (0, 3))]
+    return {"entry_points": "nx_scatter_fwd, nx_loss_grad, nx_scatter_bwd (FP32 point list)",
+            "fwd_pairs_per_s": pairs / t[0], "bwd_pairs_per_s": pairs / t[1],
+            "step_pairs_per_s": pairs / t[2], "ms_per_step": t[2] * 1e3, "steps": reps}
+
+
 def measure(name, args, steps, warmup, ceilings, want_graph=False, want_species=True,
-            cpu_seconds=None, staged_only=False):
+            cpu_seconds=None, staged_only=False, want_list=False):
     """Times `steps` fit steps of workload `name` after `warmup` untimed ones and returns
     the measured fields (rates, roofline, FP64 path, species path, oracle baseline).  The
-    timed steps are one library call each (nx_fit_step); the same steps as three calls
-    with events between them give the forward's and the adjoint's own times."""
+    timed steps are one library call each (nx_fit_step, or nx_fit_step_grid for a grid);
+    the same steps as three calls with events between them give the forward's and the
+    adjoint's own times."""
     import numpy as np
     import torch
 
@@ -398,29 +447,40 @@ def measure(name, args, steps, warmup, ceilings, want_graph=False, want_species=
     n, k = w.n_atoms, w.n_points
     pairs = float(n) * float(k)
     fkind = "unit" if w.f is None else "complex"
+    grid = w.grid if uses_grid(args, w) else None
+    kind = "grid" if grid is not None else args.mode       # the sums' instruction mix
     tx = torch.from_numpy(w.xyz).to(dev)
     tf = None if w.f is None else torch.from_numpy(w.f).to(dev)
     tS = torch.from_numpy(w.S).to(dev)
-    I = make_target(api, w, tf, tS, args.mode)
+    if grid is not None:
+        fwd = lambda x: api.scatter_fwd_grid(x, tf, grid)
+        bwd = lambda G: api.scatter_bwd_grid(tx, tf, grid, G)
+        fit = lambda: api.fit_step_grid(tx, tf, grid, I, return_seed=True)
+    else:
+        fwd = lambda x: api.scatter_fwd(x, tf, tS, args.mode)
+        bwd = lambda G: api.scatter_bwd(tx, tf, tS, G, args.mode)
+        fit = lambda: api.fit_step(tx, tf, tS, I, args.mode, return_seed=True)
+    I = make_target(w, fwd)
     torch.cuda.synchronize()
-    progress(f"workload {name}: {n} atoms x {k} points, target intensity ready")
+    progress(f"workload {name}: {n} atoms x {k} points ({'exact grid' if grid else 'point list'}), "
+             "target intensity ready")
 
     stream = torch.cuda.current_stream(dev)      # every libnx launch goes to this stream
     ev = lambda: torch.cuda.Event(enable_timing=True)
 
     def step():
-        """The whole step, queued by one call into the library (nx_fit_step)."""
-        L, A, g, G = api.fit_step(tx, tf, tS, I, args.mode, return_seed=True)
+        """The whole step, queued by one call into the library (nx_fit_step[_grid])."""
+        L, A, g, G = fit()
         return L, A, g, G
 
     def staged(rec):
         """The same step as three calls with events between them: the time of each sum."""
         rec[0].record(stream)
-        A = api.scatter_fwd(tx, tf, tS, args.mode)
+        A = fwd(tx)
         rec[1].record(stream)
         L, G = api.loss_grad(A, I)
         rec[2].record(stream)
-        g = api.scatter_bwd(tx, tf, tS, G, args.mode)
+        g = bwd(G)
         rec[3].record(stream)
         return L, A, g, G
 
@@ -489,8 +549,7 @@ def measure(name, args, steps, warmup, ceilings, want_graph=False, want_species=
         # each sum on its own, captured and replayed (the GPU time of one call without the
         # host's launch overhead, which dominates eager calls of small problems)
         G0 = out[3]
-        for dom, fn in (("fwd", lambda: api.scatter_fwd(tx, tf, tS, args.mode)),
-                        ("bwd", lambda: api.scatter_bwd(tx, tf, tS, G0, args.mode))):
+        for dom, fn in (("fwd", lambda: fwd(tx)), ("bwd", lambda: bwd(G0))):
             with torch.cuda.stream(side):
                 fn()
             stream.wait_stream(side)
@@ -512,6 +571,8 @@ def measure(name, args, steps, warmup, ceilings, want_graph=False, want_species=
     t_bwd = sum(r[2].elapsed_time(r[3]) for r in recs) / len(recs) / 1e3
     res = {
         "config": {"workload": WORKLOADS[name], "n_atoms": n, "n_points": k, "pairs_per_step": pairs,
+                   "points": ("the workload's grid given exactly (FP64 origin and steps), nx_fit_step_grid"
+                              if grid is not None else "point list (FP32), nx_fit_step"),
                    "precision": {"ph64": "FP64 phase reduction, FP32 sin/cos, compensated FP32 sums",
                                  "f32": "plain FP32 (the paper's arithmetic)"}[args.mode]},
         "steps": steps, "warmup": warmup, "staged_steps": n_staged,
@@ -521,18 +582,24 @@ def measure(name, args, steps, warmup, ceilings, want_graph=False, want_species=
         "bwd_pairs_per_s": pairs / t_bwd,
         "loss_ms": t_loss * 1e3,
         "graph_replay": graph,
-        "roofline": kernel_roofline(name, args.mode, fkind, pairs, t_fwd, t_bwd, ceilings),
+        "roofline": kernel_roofline(name, kind, fkind, pairs, t_fwd, t_bwd, ceilings),
     }
 
     L, A, g, G = out
+    S_eval = grid.points() if grid is not None else None       # the FP64 grid points
+    if want_list and grid is not None:
+        res["list_path"] = list_path(api, tx, tf, tS, I, args.mode, pairs, stream)
+        progress(f"{name}: the point-list step timed")
     if not args.no_f64:
-        res["f64_path"] = f64_path(api, tx, tf, tS, G, n, k, pairs, stream)
+        tS64 = torch.from_numpy(S_eval).to(dev) if grid is not None else tS
+        res["f64_path"] = f64_path(api, tx, tf, tS64, G, n, k, pairs, stream)
+        del tS64
         res["speedup_vs_f64_step"] = res["value"] / res["f64_path"]["step_pairs_per_s"]
         progress(f"{name}: all-FP64 path timed on {res['f64_path']['points_timed']} points")
 
     # the same step with the species factored out of the sum (Section 4.2): one
     # unit-factor sum per species, atoms regrouped by species once, outside the timing
-    if want_species and w.f is not None:
+    if want_species and w.f is not None and grid is None:
         xs, start, vals, _ = wl.group_by_species(w.xyz, w.f)
         if len(vals) <= 16:
             txs = torch.from_numpy(xs).to(dev)
@@ -570,7 +637,7 @@ def measure(name, args, steps, warmup, ceilings, want_graph=False, want_species=
         G_np = G.cpu().numpy()
         g_np = g.cpu().numpy()
         res["cpu_baseline"], res["max_rel_err"] = cpu_baseline(
-            name, w, A_np, G_np, g_np, cpu_seconds or args.cpu_seconds)
+            name, w, A_np, G_np, g_np, cpu_seconds or args.cpu_seconds, S_eval)
         progress(f"{name}: CPU oracle baseline done")
     del tx, tf, tS, I, out, L, A, g, G
     torch.cuda.empty_cache()
@@ -602,14 +669,18 @@ def main():
     fkind_of = {"c1": "unit", "c3": "unit", "c4": "unit", "cube41": "unit", "cube41s": "unit"}
     ceilings, costs = {}, None
     if not args.no_micro:
-        for fk in {fkind_of.get(args.workload, "complex"), "complex"}:
-            ceilings.update(issue_ceilings(args.mode, fk))
+        kinds = {args.mode}
+        if args.mode == "ph64" and args.points == "grid":
+            kinds.add("grid")           # the ceilings of the grid sums' own mixes too
+        for kind in sorted(kinds):
+            for fk in {fkind_of.get(args.workload, "complex"), "complex"}:
+                ceilings.update(issue_ceilings(kind, fk))
         costs = op_costs()
         progress("issue-ceiling microbenchmarks done: " + ", ".join(
             f"{'/'.join(key)} {v[0]:.3e} pairs/s" for key, v in sorted(ceilings.items())))
 
     head = measure(args.workload, args, args.steps, args.warmup, ceilings, want_graph=args.graph,
-                   want_species=not args.no_species, staged_only=args.staged)
+                   want_species=not args.no_species, staged_only=args.staged, want_list=True)
     c5 = None
     if args.workload == "c2" and not args.no_c5:
         # the largest configuration, one timed step (its 39 s per step would take the
@@ -639,7 +710,7 @@ def main():
         "data": "synthetic",
         "config": config,
     }
-    for key in ("fwd_pairs_per_s", "bwd_pairs_per_s", "loss_ms", "f64_path", "species_path",
+    for key in ("fwd_pairs_per_s", "bwd_pairs_per_s", "loss_ms", "list_path", "f64_path", "species_path",
                 "graph_replay", "speedup_vs_f64_step", "max_rel_err", "roofline", "cpu_baseline"):
         res[key] = head.get(key)
     res["c5"] = c5

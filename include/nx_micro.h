@@ -11,7 +11,8 @@
  * mixes) independent pairs per lane at 8 waves per SIMD, `wide` = 1 twice as many at 4
  * waves per SIMD, and `wide` = 2 (FP64-phase mixes only) the sums' own shape, 1 point
  * (forward) or 2 atoms (adjoint) per lane against 16 wave-uniform stream items per
- * iteration.  The best rate, in pairs per second, is the issue ceiling of that instruction
+ * iteration; the mixes of the sums over grid rows (Eq. 2 over a regular grid, the phase
+ * formed from the point's index along the row) exist in that shape only.  The best rate, in pairs per second, is the issue ceiling of that instruction
  * mix on the chip under load.
  *
  * nxm_run queues one launch of n_blocks work-groups of nxm_threads_per_block() lanes,
@@ -50,7 +51,11 @@ typedef enum {
   NXM_OP_COS_F32 = 17,   /*   v_cos_f32 */
   NXM_OP_MUL_F32 = 18,   /*   v_mul_f32_e32 */
   NXM_OP_FMA_F32_V = 19, /*   FP32 fma, vector operands, three-operand encoding (v_fma_f32) */
-  NXM_OP_ADD_F32 = 20    /*   v_add_f32_e32 */
+  NXM_OP_ADD_F32 = 20,   /*   v_add_f32_e32 */
+  NXM_FWD_GRID_CF = 21,  /* forward over grid rows, complex f: 1 fma64, cvt_i32, mul, cos, sin, 2 fma */
+  NXM_FWD_GRID_F1 = 22,  /* forward over grid rows, f = 1: the same with 2 adds */
+  NXM_BWD_GRID_CF = 23,  /* adjoint over grid rows: 1 fma64, add64, cvt_i32, mul, sin, 3 fma */
+  NXM_BWD_GRID_F1 = 24   /* adjoint over grid rows, f = 1: the same sequence */
 } nxm_mix;
 
 /* Work items per lane and iteration: atom-point pairs for the mixes, instructions for the

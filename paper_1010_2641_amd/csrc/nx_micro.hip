@@ -254,6 +254,90 @@ __global__ __launch_bounds__(kThreads, 8) void mix_bwd_ph64_tile(int iters, floa
   cm.stop(clk);
 }
 
+// The grid kernels' sequences (a grid walked by rows), in the sums' shape.  Forward: the
+// phase is fma(i1, c1, b) (i1 the lane's point index along the row, c1 = step1.r and b the
+// atom's row term, both shared by the wave), then the fixed-point turn, cos, sin and the
+// accumulation as above.  The shared operands come from LDS in the kernel (vector
+// registers); here the tile's row terms b stay in registers and c1 is formed by the
+// scalar unit, which changes it every iteration (an addend from the scalar unit would
+// have to be copied to vector registers first: the accumulating form of the FP64 fma
+// overwrites its addend).
+template <bool CF>
+__global__ __launch_bounds__(kThreads, 8) void mix_fwd_grid_tile(int iters, float* out, unsigned long long* clk) {
+  ClockMark cm;
+  cm.start();
+  double di1 = static_cast<double>((threadIdx.x + blockIdx.x * kThreads) & 127);
+  double b[kTile];
+#pragma unroll
+  for (int t = 0; t < kTile; ++t) {
+    b[t] = kShift + 12.5 + 0.125 * t;
+    opaque(b[t]);
+  }
+  opaque(di1);
+  float ar = 0.f, ai = 0.f;
+  for (int j = 0; j < iters; ++j) {
+#pragma unroll
+    for (int t = 0; t < kTile; ++t) {
+      const double c1 = uniform_f64(0x3f340000u + (t << 8), 0x9999999au, j);   // ~3e-4
+      const float m = uniform_f32(0x41f80000u + (t << 8), j);              // ~31
+      const double ph = __builtin_fma(di1, c1, b[t]);
+      const float tt = static_cast<float>(__double2loint(ph)) * 0x1.0p-32f;
+      const float c = __builtin_amdgcn_cosf(tt);
+      const float s = __builtin_amdgcn_sinf(tt);
+      if constexpr (CF) {
+        ar = __builtin_fmaf(m, c, ar);
+        ai = __builtin_fmaf(m, s, ai);
+      } else {
+        ar += c;
+        ai += s;
+      }
+    }
+  }
+  out[threadIdx.x + blockIdx.x * kThreads] = ar - ai;
+  cm.stop(clk);
+}
+
+// Adjoint over grid rows: the phase is fma(i1, c1, b) + delta (c1 = step1.r and b the row
+// term of the lane's atom, the factor's angle folded into b; i1 and delta those of the
+// point, shared by the wave), then the fixed-point turn, sin and T_d += (|G| S_d) sin.  The
+// same sequence for complex f and f = 1.  Two atoms per lane, 16 points per iteration.
+template <bool CF>
+__global__ __launch_bounds__(kThreads, 8) void mix_bwd_grid_tile(int iters, float* out, unsigned long long* clk) {
+  ClockMark cm;
+  cm.start();
+  const double lane = static_cast<double>(threadIdx.x + blockIdx.x * kThreads);
+  double c1[2], b[2];
+  float t0[2], t1[2], t2[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    c1[q] = 3e-4 + 1e-9 * lane + 1e-5 * q;
+    b[q] = 12.5 - 1e-6 * lane + 0.25 * q;
+    t0[q] = t1[q] = t2[q] = 0.f;
+    opaque(c1[q]);
+    opaque(b[q]);
+  }
+  for (int j = 0; j < iters; ++j) {
+#pragma unroll
+    for (int t = 0; t < kTile; ++t) {
+      const double i1 = uniform_f64(0x40500000u + t, 0x00000000u, j);      // ~64
+      const double d0 = uniform_f64(0x41380000u + t, 0x33333333u, j);      // ~1.57e6
+      const float gx = uniform_f32(0x3f800000u + (t << 8), j), gy = uniform_f32(0x3f000000u + (t << 8), j),
+                  gz = uniform_f32(0x40800000u + (t << 8), j);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const double ph = __builtin_fma(i1, c1[q], b[q]) + d0;
+        const float tt = static_cast<float>(__double2loint(ph)) * 0x1.0p-32f;
+        const float s = __builtin_amdgcn_sinf(tt);
+        t0[q] = __builtin_fmaf(s, gx, t0[q]);
+        t1[q] = __builtin_fmaf(s, gy, t1[q]);
+        t2[q] = __builtin_fmaf(s, gz, t2[q]);
+      }
+    }
+  }
+  out[threadIdx.x + blockIdx.x * kThreads] = t0[0] - t1[0] + t2[0] + t0[1] - t1[1] + t2[1];
+  cm.stop(clk);
+}
+
 // The paper's FP32 arithmetic.  Forward: 3 FP32 fma, fract, cos, sin, then f (c + i s)
 // with 4 fma (complex f) or 2 adds (f = 1).
 template <bool CF, int kPairs, int OCC>
@@ -417,6 +501,11 @@ extern "C" {
 int nxm_pairs_per_lane_iter(int mix, int wide) {
   if (wide < 0 || wide > 2) return 0;
   if (mix >= NXM_OP_FMA_F32 && mix <= NXM_OP_ADD_F32) return wide == 2 ? 0 : 4 * (wide ? 16 : 8);
+  if (mix >= NXM_FWD_GRID_CF && mix <= NXM_BWD_GRID_F1) {    // the sums' shape only
+    if (wide != 2) return 0;
+    return mix >= NXM_BWD_GRID_CF ? 2 * kTile : kTile;
+  }
+  if (mix < NXM_FWD_PH64_CF || mix > NXM_BWD_F32_F1) return 0;
   const bool ph64 = mix >= NXM_FWD_PH64_CF && mix <= NXM_BWD_PH64_F1;
   if (wide == 2) {     // the sums' shape: FP64-phase mixes only
     if (!ph64) return 0;
@@ -437,8 +526,8 @@ int nxm_wallclock_khz(void) {
 
 int nxm_run(int mix, int wide, int n_blocks, int iters, float* out, unsigned long long* clk,
             void* stream) {
-  if (n_blocks < 1 || iters < 1 || !out || wide < 0 || wide > 2) return -1;
-  if (wide == 2 && mix >= NXM_OP_FMA_F32) return -1;
+  if (mix < NXM_FWD_PH64_CF || mix > NXM_BWD_GRID_F1) return -2;
+  if (n_blocks < 1 || iters < 1 || !out || nxm_pairs_per_lane_iter(mix, wide) <= 0) return -1;
   if (wide == 2) {
     const dim3 g(static_cast<unsigned>(n_blocks));
     const hipStream_t s2 = static_cast<hipStream_t>(stream);
@@ -447,6 +536,10 @@ int nxm_run(int mix, int wide, int n_blocks, int iters, float* out, unsigned lon
       case NXM_FWD_PH64_F1: mix_fwd_ph64_tile<false><<<g, kThreads, 0, s2>>>(iters, out, clk); break;
       case NXM_BWD_PH64_CF: mix_bwd_ph64_tile<true><<<g, kThreads, 0, s2>>>(iters, out, clk); break;
       case NXM_BWD_PH64_F1: mix_bwd_ph64_tile<false><<<g, kThreads, 0, s2>>>(iters, out, clk); break;
+      case NXM_FWD_GRID_CF: mix_fwd_grid_tile<true><<<g, kThreads, 0, s2>>>(iters, out, clk); break;
+      case NXM_FWD_GRID_F1: mix_fwd_grid_tile<false><<<g, kThreads, 0, s2>>>(iters, out, clk); break;
+      case NXM_BWD_GRID_CF: mix_bwd_grid_tile<true><<<g, kThreads, 0, s2>>>(iters, out, clk); break;
+      case NXM_BWD_GRID_F1: mix_bwd_grid_tile<false><<<g, kThreads, 0, s2>>>(iters, out, clk); break;
       default: return -1;      // the FP32 mixes have no such shape
     }
     return hipGetLastError() == hipSuccess ? 0 : -4;

@@ -25,6 +25,8 @@ MIXES = {
     ("ph64", "bwd", "complex"): 2, ("ph64", "bwd", "unit"): 3,
     ("f32", "fwd", "complex"): 4, ("f32", "fwd", "unit"): 5,
     ("f32", "bwd", "complex"): 6, ("f32", "bwd", "unit"): 7,
+    ("grid", "fwd", "complex"): 21, ("grid", "fwd", "unit"): 22,
+    ("grid", "bwd", "complex"): 23, ("grid", "bwd", "unit"): 24,
 }
 
 SIGNATURES = {
@@ -67,7 +69,10 @@ def _rate(mix: int, n_blocks: int, iters: int, reps: int):
     stream = torch.cuda.current_stream()
     khz = nxm_wallclock_khz()
     best, ghz = 0.0, None
-    base = nxm_pairs_per_lane_iter(mix, 0)
+    # the pairs per lane of the mix's first shape set the work of every shape
+    base = next((b for b in (nxm_pairs_per_lane_iter(mix, w) for w in (0, 1, 2)) if b > 0), 0)
+    if base <= 0:
+        raise ValueError(f"mix {mix} has no kernel shape")
     for wide in (0, 1, 2):
         per = nxm_pairs_per_lane_iter(mix, wide)
         if per <= 0:

@@ -54,6 +54,12 @@ def test_micro_header_symbols_exported():
     assert micro.nxm_pairs_per_lane_iter(0, 3) == 0
     assert micro.nxm_run(4, 2, 1, 1, FAKE, None, None) == -1
     assert micro.nxm_run(8, 2, 1, 1, FAKE, None, None) == -1
+    # the mixes of the sums over grid rows: the sums' shape only
+    assert micro.nxm_pairs_per_lane_iter(21, 2) == 16 and micro.nxm_pairs_per_lane_iter(24, 2) == 32
+    assert micro.nxm_pairs_per_lane_iter(21, 0) == 0 and micro.nxm_pairs_per_lane_iter(23, 1) == 0
+    assert micro.nxm_run(22, 0, 1, 1, FAKE, None, None) == -1
+    assert micro.nxm_run(25, 2, 1, 1, FAKE, None, None) == -2
+    assert micro.nxm_pairs_per_lane_iter(25, 2) == 0
 
 
 def test_version():

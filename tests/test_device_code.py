@@ -158,6 +158,22 @@ def test_micro_loops_are_the_priced_instruction_mixes(device_asm):
         assert not any(k.startswith(("scratch_", "global_load", "buffer_load", "ds_")) for k in c)
         tiles += 1
     assert tiles == 4
+    # the sums over grid rows, same shape
+    grids = 0
+    for name, c in loops.items():
+        m = re.search(r"mix_(fwd|bwd)_grid_tileILb([01])E", name)
+        if not m:
+            continue
+        op, fkind = m.group(1), "complex" if m.group(2) == "1" else "unit"
+        pairs = 16 * (2 if op == "bwd" else 1)
+        valu = sum(v for k, v in c.items() if k.startswith("v_"))
+        trans = c["v_sin_f32_e32"] + c["v_cos_f32_e32"]
+        assert valu == pairs * bench.ALG_SLOTS[("grid", op, fkind)], (name, dict(c))
+        assert trans == pairs * (1 if op == "bwd" else 2), (name, dict(c))
+        assert c["v_fma_f64"] + c["v_fmac_f64_e32"] == pairs, (name, dict(c))
+        assert not any(k.startswith(("scratch_", "global_load", "buffer_load", "ds_", "v_mov")) for k in c)
+        grids += 1
+    assert grids == 4
     # the single-instruction kernels: 4 steps of NP chains of one kind per iteration
     kinds = {"0": "v_fma_f32", "1": "v_fma_f64", "2": "v_sin_f32", "3": "v_fmac_f32_e32",
              "4": "v_fmac_f64_e32", "5": "v_add_f64", "6": "v_rndne_f64", "7": "v_fract_f64",
