@@ -141,29 +141,37 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
     const int64_t tl = env_i64("NX_TUNE_LDS", -1);
     if (p.mode == kPH64 && (tl == 0 || tl == 1)) p.lds = int(tl);
   }
-  // a grid walked by rows (its own kernels): one point per lane in the forward, so that
-  // every wave's 64 points lie in one row; where its kernels do not exist for the plan
-  // the general kernels take the grid's points
+  // a grid walked by rows (its own kernels): every wave's points lie in one row; where its
+  // kernels do not exist for the plan the general kernels take the grid's points
   // (NX_TUNE_GRID=1 sends every grid to the general kernels)
+  const int rows_lane = grid == 4 ? 4 : grid == 3 ? 2 : 1;   // points per lane over rows
+  if (grid >= 3) grid = 2;
   if (grid == 2 && env_i64("NX_TUNE_GRID", -1) == 1) grid = 1;
-  // a grid's forward: one point per lane, LDS tiles and the fixed-point reduction, the
-  // forms built to walk grid rows (grid 2) or to form each lane's FP64 grid point
-  // (grid 1), whatever the knobs say
+  // a grid's forward: LDS tiles and the fixed-point reduction, the forms built to walk
+  // grid rows (grid 2) or to form each lane's FP64 grid point (grid 1), whatever the knobs
+  // say; over rows of a multiple of 128 points two consecutive points per lane, over such
+  // rows in pairs a 2 x 2 block (the others' phase factors stepped from the first's;
+  // NX_TUNE_P=1 or 2 caps the points per lane), else one
   if (grid != 0 && fwd && p.mode == kPH64) {
-    p.per_lane = 1;
+    const int64_t tp = env_i64("NX_TUNE_P", -1);
+    p.per_lane = grid == 2 ? ((tp == 1 || tp == 2) ? std::min<int>(int(tp), rows_lane) : rows_lane) : 1;
     p.red = 2;
     p.lds = 1;
     if (p.grp != 8) p.grp = 16;
+    if (p.per_lane == 4 && p.grp != 16) p.per_lane = 2;     // (the block form has 16-atom groups)
   }
   // the fixed-point reduction checks its range per LDS tile: the scalar-load forms (and
   // the forward's 32-atom groups, which have no LDS form) take the centred one, and so do
   // the forward's forms whose two tile loops do not fit their registers (four points per
   // lane; two with 8-atom groups)
-  if (p.red == 2 && !(p.lds && (!fwd || ((p.grp == 8 || p.grp == 16) &&
-                                         (p.per_lane == 1 || (p.per_lane == 2 && p.grp == 16))))))
+  // (a grid's forward has the fixed-point forms for all of its shapes)
+  if (p.red == 2 && !(grid != 0 && fwd) &&
+      !(p.lds && (!fwd || ((p.grp == 8 || p.grp == 16) &&
+                           (p.per_lane == 1 || (p.per_lane == 2 && p.grp == 16))))))
     p.red = 0;
-  if (grid == 2 && !(p.mode == kPH64 && p.red == 2 && p.lds && (fwd ? p.per_lane == 1 : p.grp == 64)))
+  if (grid == 2 && !(p.mode == kPH64 && p.red == 2 && p.lds && (fwd || p.grp == 64)))
     grid = 1;
+  if (grid == 1 && fwd) p.per_lane = 1;
   p.grid = p.mode == kPH64 ? grid : 0;
   const int64_t per_block = int64_t(kThreads) * p.per_lane;
   p.blocks = p.lanes > 0 ? ceil_div(p.lanes, per_block) : 0;
@@ -203,8 +211,9 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
   int64_t launch_pairs = env_i64("NX_TUNE_LAUNCH_PAIRS", kLaunchPairs);
   if (launch_pairs < 1) launch_pairs = kLaunchPairs;
   size_t rec_size;
-  if (fwd) rec_size = p.mode == kF64 ? sizeof(AtomF64) : (p.mode == kPH64 ? sizeof(AtomPH) : sizeof(AtomF32));
-  else if (p.grid == 2) rec_size = sizeof(PointGrid);
+  if (fwd && p.grid == 2) rec_size = sizeof(AtomGrid);
+  else if (fwd) rec_size = p.mode == kF64 ? sizeof(AtomF64) : (p.mode == kPH64 ? sizeof(AtomPH) : sizeof(AtomF32));
+  else if (p.grid == 2) rec_size = sizeof(PointRow);
   else rec_size = p.mode == kF64 ? sizeof(PointF64) : (p.mode == kPH64 ? sizeof(PointPH) : sizeof(PointF32));
   p.rec_size = rec_size;
   int64_t chunk = lane_pad > 0 ? launch_pairs / lane_pad : p.stream;
@@ -224,6 +233,7 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
   // the partial state
   p.rec_bytes = align_up(size_t(p.stream) * rec_size, 256);
   if (!fwd && p.mode == kPH64) p.rec_bytes += point_bound_bytes(p.stream);
+  if (!fwd && p.grid == 2) p.rec_bytes += row_group_bytes(p.stream);
   const bool need_partial = p.lanes > 0 && (p.nsplit > 1 || p.nchunks > 1);
   if (need_partial) {
     size_t per_item;
@@ -330,8 +340,12 @@ nx::GridDef grid_def(const nx_grid* g) {
   return d;
 }
 
-// The grid kernels walk rows of n1 points; they need n1 to be a multiple of 64.
-int grid_kind(const nx_grid* g) { return (g->n1 % 64 == 0) ? 2 : 1; }
+// The grid kernels walk rows of n1 points; they need n1 to be a multiple of 64 (3: of 128,
+// where the forward takes two points per lane; 4: of 128 with n2 even, a 2 x 2 block).
+int grid_kind(const nx_grid* g) {
+  if (g->n1 % 128 == 0) return g->n2 % 2 == 0 ? 4 : 3;
+  return g->n1 % 64 == 0 ? 2 : 1;
+}
 
 // The launch sequence of run_sum over the points of a grid (FP64-phase mode): grid records
 // packed, the chunks, the split reduce.  `out` is A (forward) or grad_xyz (adjoint).

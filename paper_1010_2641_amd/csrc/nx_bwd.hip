@@ -523,30 +523,32 @@ __global__ __launch_bounds__(kThreads) void bwd_split_kernel(
   }
 }
 
-// FP64-phase adjoint over a grid whose rows hold a multiple of 64 points, with 64-point
-// compensated groups: every group lies in one row (its first point is a multiple of 64
-// from the grid's start), so that with c0 = o.r + arg f / 2 pi and c_d = e_d.r (per lane
-// atom, FP64) the phase of point (i1, i2, i3) is fma(i1, c1, b) + delta with the row term
-// b = c0 + i2 c2 + i3 c3, formed once per group (two fma per atom): one fma and one add per
-// pair instead of three fma and one add.  The tile holds (i1, delta) of each point (16 B),
-// the rest of the record comes with scalar loads.  Groups, compensation and outputs are
-// those of bwd_split_kernel; the reduction is the fixed-point read with the per-tile range
-// check ((|x| + |y| + |z|) of the lane's atoms times the tile's bound, which covers the
-// row parts) and variant 3 for tiles out of range.
+// FP64-phase adjoint over a grid whose rows hold a multiple of 64 points: 64-point groups,
+// each one row's run of consecutive points (groups start at multiples of 64 from the
+// grid's start).  Per lane atom, c0 = o.r + arg f / 2 pi + kPhaseShift and c_d = e_d.r in
+// FP64, and w - 1 = exp(2 i pi c1) - 1 in FP32 (formed in FP64).  A group takes the phase
+// factor E = exp(2 i pi (S.r + arg f / 2 pi)) of its first point exactly (the FP64 phase
+// fma(i1, c1, c0 + i2 c2 + i3 c3), the fixed-point read under the per-tile range check or
+// variant 3, hardware cos and sin) and steps it along the row, E <- E + E (w - 1) (four
+// FP32 fma; the small w - 1 keeps the rounding of w out of the steps where step1.r is
+// small).  Per point: v = Im(conj(G) E) = Re G Im E - Im G Re E, a0 += v and a1 += u v
+// (u the point's place in the group); per group: T_d += S0_d a0 + e1_d a1 (S0 the
+// group's first point), Kahan-compensated across groups as in bwd_split_kernel.  The
+// point records (PointRow) come with scalar loads; no LDS.  Outputs as bwd_split_kernel.
 template <int Q, int FK>
-__global__ __launch_bounds__(kThreads) void bwd_grid_kernel(
-    const PointGrid* __restrict__ rec, int k_begin, int k_end, int per_split,
-    const float* __restrict__ xyz, const float* __restrict__ f, int64_t N, int blocks_n,
-    float* __restrict__ part, float* __restrict__ grad, int carry_in, int direct, GridDef g,
-    const float* __restrict__ bnd) {
-  constexpr int GRP = 64;
+__global__ __launch_bounds__(kThreads) void bwd_rows_kernel(
+    const PointRow* __restrict__ rec, const float4* __restrict__ grp, const float* __restrict__ bnd,
+    int k_begin, int k_end, int per_split, const float* __restrict__ xyz, const float* __restrict__ f,
+    int64_t N, int blocks_n, float* __restrict__ part, float* __restrict__ grad, int carry_in, int direct,
+    GridDef g) {
+  constexpr int GRP = kRowGroup;
   constexpr int NS = 3;
-  __shared__ double2 sd[kThreads];          // (i1, delta) of the tile's points
   const int lb = xcd_major_block(blockIdx.x, gridDim.x);
   const int nb = lb % blocks_n;
   const int sp = lb / blocks_n;
   const int64_t j0 = int64_t(nb) * (kThreads * Q) + threadIdx.x;
   double c0[Q], c1[Q], c2[Q], c3[Q];
+  float wr[Q], wi[Q];                       // w - 1
   float sum[Q][NS], cmp[Q][NS];
   float r1 = 0.f;
 #pragma unroll
@@ -556,10 +558,15 @@ __global__ __launch_bounds__(kThreads) void bwd_grid_kernel(
     const double x = xyz[3 * jj], y = xyz[3 * jj + 1], z = xyz[3 * jj + 2];
     r1 = fmaxf(r1, bound_abs(fabs(x) + fabs(y) + fabs(z)));
     const double al = (FK && f) ? arg_cycles(f[2 * jj], f[2 * jj + 1]) : 0.0;
-    c0[q] = __builtin_fma(g.o[2], z, __builtin_fma(g.o[1], y, __builtin_fma(g.o[0], x, al)));
+    c0[q] = __builtin_fma(g.o[2], z, __builtin_fma(g.o[1], y, __builtin_fma(g.o[0], x, al + kPhaseShift)));
     c1[q] = __builtin_fma(g.e1[2], z, __builtin_fma(g.e1[1], y, g.e1[0] * x));
     c2[q] = __builtin_fma(g.e2[2], z, __builtin_fma(g.e2[1], y, g.e2[0] * x));
     c3[q] = __builtin_fma(g.e3[2], z, __builtin_fma(g.e3[1], y, g.e3[0] * x));
+    // w - 1 = (cos 2 pi t - 1, sin 2 pi t), t = c1 mod 1, with cos 2 pi t - 1 = -2 sin^2 pi t
+    const double t = c1[q] - __builtin_rint(c1[q]);
+    const double h = sinpi(t);
+    wr[q] = static_cast<float>(-2.0 * h * h);
+    wi[q] = static_cast<float>(sinpi(2.0 * t));
 #pragma unroll
     for (int d = 0; d < NS; ++d) {
       if (carry_in && j < N) {
@@ -571,56 +578,59 @@ __global__ __launch_bounds__(kThreads) void bwd_grid_kernel(
       }
     }
   }
+  const float e1x = static_cast<float>(g.e1[0]), e1y = static_cast<float>(g.e1[1]),
+              e1z = static_cast<float>(g.e1[2]);
   auto run_tile = [&](auto red_c, int t0, int nt) {
     constexpr int R = decltype(red_c)::value;
     for (int u0 = 0; u0 < nt; u0 += GRP) {
       const int ue = (u0 + GRP <= nt) ? u0 + GRP : nt;
-      const uint32_t row = static_cast<uint32_t>(t0 + u0) / static_cast<uint32_t>(g.n1);
+      const uint32_t k = static_cast<uint32_t>(t0 + u0);     // the group's first point
+      const uint32_t row = k / static_cast<uint32_t>(g.n1);
+      const double d1 = static_cast<double>(k - row * static_cast<uint32_t>(g.n1));
       const double d2 = static_cast<double>(row % static_cast<uint32_t>(g.n2)),
                    d3 = static_cast<double>(row / static_cast<uint32_t>(g.n2));
-      double b[Q];
+      float er[Q], ei[Q], a0[Q], a1[Q];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) b[q] = __builtin_fma(d3, c3[q], __builtin_fma(d2, c2[q], c0[q]));
-      float gq[Q][NS];
-#pragma unroll
-      for (int q = 0; q < Q; ++q)
-#pragma unroll
-        for (int d = 0; d < NS; ++d) gq[q][d] = 0.f;
-      auto pair_step = [&](int u) {
-        const double2 pd = sd[u];
-        const uint4 w = reinterpret_cast<const uint4*>(rec + t0 + u)[1];
-        const float gsx = __uint_as_float(w.x), gsy = __uint_as_float(w.y), gsz = __uint_as_float(w.z);
+      for (int q = 0; q < Q; ++q) {
+        const double b = __builtin_fma(d3, c3[q], __builtin_fma(d2, c2[q], c0[q]));
+        cis_turn_pt<R>(__builtin_fma(d1, c1[q], b), er[q], ei[q]);
+        a0[q] = 0.f;
+        a1[q] = 0.f;
+      }
+      auto point = [&](int u, bool step) {
+        const PointRow r = rec[t0 + u];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-          float c, s;
-          cis_turn_pt<R>(__builtin_fma(pd.x, c1[q], b[q]) + pd.y, c, s);
-          gq[q][0] = __builtin_fmaf(s, gsx, gq[q][0]);
-          gq[q][1] = __builtin_fmaf(s, gsy, gq[q][1]);
-          gq[q][2] = __builtin_fmaf(s, gsz, gq[q][2]);
+          const float v = __builtin_fmaf(r.gr, ei[q], r.ngi * er[q]);
+          a0[q] += v;
+          a1[q] = __builtin_fmaf(r.u, v, a1[q]);
+          if (step) {
+            const float nr = __builtin_fmaf(er[q], wr[q], __builtin_fmaf(-ei[q], wi[q], er[q]));
+            const float ni = __builtin_fmaf(er[q], wi[q], __builtin_fmaf(ei[q], wr[q], ei[q]));
+            er[q] = nr;
+            ei[q] = ni;
+          }
         }
       };
       if (ue - u0 == GRP) {
 #pragma unroll
-        for (int u = 0; u < GRP; ++u) pair_step(u0 + u);
+        for (int u = 0; u < GRP; ++u) point(u0 + u, u + 1 < GRP);
       } else {
-        for (int u = u0; u < ue; ++u) pair_step(u);
+        for (int u = u0; u < ue; ++u) point(u, true);
       }
+      const float4 s0 = grp[k / GRP];
 #pragma unroll
-      for (int q = 0; q < Q; ++q)
-#pragma unroll
-        for (int d = 0; d < NS; ++d) kahan_acc(sum[q][d], cmp[q][d], gq[q][d]);
+      for (int q = 0; q < Q; ++q) {
+        kahan_acc(sum[q][0], cmp[q][0], __builtin_fmaf(s0.x, a0[q], e1x * a1[q]));
+        kahan_acc(sum[q][1], cmp[q][1], __builtin_fmaf(s0.y, a0[q], e1y * a1[q]));
+        kahan_acc(sum[q][2], cmp[q][2], __builtin_fmaf(s0.z, a0[q], e1z * a1[q]));
+      }
     }
   };
   const int k0 = k_begin + sp * per_split;
   const int k1 = min(k0 + per_split, k_end);
   for (int t0 = k0; t0 < k1; t0 += kThreads) {
     const int nt = min(kThreads, k1 - t0);
-    __syncthreads();                        // the previous tile is no longer read
-    if (int(threadIdx.x) < nt) {
-      const PointGrid r = rec[t0 + threadIdx.x];
-      sd[threadIdx.x] = make_double2(r.i1, r.delta);
-    }
-    __syncthreads();
     const float st = fmaxf(bnd[t0 / kThreads], bnd[(t0 + nt - 1) / kThreads]);
     if (__all(r1 * st < kFixedPhaseBound)) run_tile(std::integral_constant<int, 2>{}, t0, nt);
     else run_tile(std::integral_constant<int, 3>{}, t0, nt);
@@ -812,12 +822,8 @@ __global__ __launch_bounds__(kThreads) void pack_points_ph_kernel(const float* _
   }
 }
 
-// Point k of a grid with its seed: S (FP64, from the grid), the row part R = o + i2 e2 +
-// i3 e3, delta = -arg(G) / (2 pi) + kPhaseShift, |G|.
-struct GridPoint { double S[3], R[3], i1, delta, m; };
-__device__ __forceinline__ GridPoint grid_point_seed(const GridDef& g, const float* __restrict__ G,
-                                                    int64_t k) {
-  GridPoint p;
+// Point k of a grid: S (FP64) and the row part R = o + i2 e2 + i3 e3.
+__device__ __forceinline__ void grid_point_rows(const GridDef& g, int64_t k, double* S, double* R) {
   // (counts and indices stay below 2^30: 32-bit index arithmetic)
   const uint32_t ku = static_cast<uint32_t>(k), n1 = static_cast<uint32_t>(g.n1),
                  n2 = static_cast<uint32_t>(g.n2);
@@ -826,48 +832,50 @@ __device__ __forceinline__ GridPoint grid_point_seed(const GridDef& g, const flo
                d3 = static_cast<double>(row / n2);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    p.R[d] = __builtin_fma(d3, g.e3[d], __builtin_fma(d2, g.e2[d], g.o[d]));
-    p.S[d] = __builtin_fma(d1, g.e1[d], p.R[d]);
+    R[d] = __builtin_fma(d3, g.e3[d], __builtin_fma(d2, g.e2[d], g.o[d]));
+    S[d] = __builtin_fma(d1, g.e1[d], R[d]);
   }
-  const double gr = G[2 * k], gi = G[2 * k + 1];
-  p.m = sqrt(gr * gr + gi * gi);
-  p.delta = -atan2(gi, gr) * 0.15915494309189533577 + kPhaseShift;
-  p.i1 = d1;
-  return p;
 }
 
-// Point records of a grid, grid-stride over blocks of 256 points: PointGrid (ROWS, the grid
-// kernels) or PointPH (the general kernels, with the FP64 grid point), and each block's
-// bound in bnd[block]: the largest |S| component, for PointGrid also of the row part.
+// Point records of a grid, grid-stride over blocks of 256 points, and each block's bound
+// in bnd[block] (the largest |S| component, for the rows form also of the row part):
+// ROWS, the records of bwd_rows_kernel (PointRow, and the group's first point S0 in
+// grp[k / 64]); otherwise PointPH for the general kernels, with the FP64 grid point and
+// the seed's phase and modulus as pack_points_ph_kernel forms them.
 template <bool ROWS>
 __global__ __launch_bounds__(kThreads) void pack_points_grid_kernel(GridDef g, const float* __restrict__ G,
                                                                     int64_t n, void* __restrict__ rec_v,
+                                                                    float4* __restrict__ grp,
                                                                     float* __restrict__ bnd) {
   __shared__ float wmax[kThreads / 64];
   for (int64_t b = blockIdx.x; b * kThreads < n; b += gridDim.x) {
     const int64_t k = b * kThreads + threadIdx.x;
     float sm = 0.f;
     if (k < n) {
-      const GridPoint q = grid_point_seed(g, G, k);
-      sm = fmaxf(bound_abs(q.S[0]), fmaxf(bound_abs(q.S[1]), bound_abs(q.S[2])));
+      double S[3], R[3];
+      grid_point_rows(g, k, S, R);
+      sm = fmaxf(bound_abs(S[0]), fmaxf(bound_abs(S[1]), bound_abs(S[2])));
+      const float gr = G[2 * k], gi = G[2 * k + 1];
       if constexpr (ROWS) {
-        sm = fmaxf(sm, fmaxf(bound_abs(q.R[0]), fmaxf(bound_abs(q.R[1]), bound_abs(q.R[2]))));
-        PointGrid r;
-        r.i1 = q.i1;
-        r.delta = q.delta;
-        r.gsx = static_cast<float>(q.m * q.S[0]);
-        r.gsy = static_cast<float>(q.m * q.S[1]);
-        r.gsz = static_cast<float>(q.m * q.S[2]);
-        r.gmag = static_cast<float>(q.m);
-        static_cast<PointGrid*>(rec_v)[k] = r;
+        sm = fmaxf(sm, fmaxf(bound_abs(R[0]), fmaxf(bound_abs(R[1]), bound_abs(R[2]))));
+        PointRow r;
+        r.gr = gr;
+        r.ngi = -gi;
+        r.u = static_cast<float>(k % kRowGroup);
+        r.pad = 0.f;
+        static_cast<PointRow*>(rec_v)[k] = r;
+        if (k % kRowGroup == 0)
+          grp[k / kRowGroup] = make_float4(static_cast<float>(S[0]), static_cast<float>(S[1]),
+                                           static_cast<float>(S[2]), 0.f);
       } else {
+        const double m = sqrt(double(gr) * gr + double(gi) * gi);
         PointPH r;
-        r.sx = q.S[0]; r.sy = q.S[1]; r.sz = q.S[2];
-        r.delta = q.delta;
-        r.gsx = static_cast<float>(q.m * q.S[0]);
-        r.gsy = static_cast<float>(q.m * q.S[1]);
-        r.gsz = static_cast<float>(q.m * q.S[2]);
-        r.gmag = static_cast<float>(q.m);
+        r.sx = S[0]; r.sy = S[1]; r.sz = S[2];
+        r.delta = -atan2(double(gi), double(gr)) * 0.15915494309189533577 + kPhaseShift;
+        r.gsx = static_cast<float>(m * S[0]);
+        r.gsy = static_cast<float>(m * S[1]);
+        r.gsz = static_cast<float>(m * S[2]);
+        r.gmag = static_cast<float>(m);
         static_cast<PointPH*>(rec_v)[k] = r;
       }
     }
@@ -1058,25 +1066,29 @@ hipError_t launch_pack_points_grid(const Plan& p, const GridDef& g, const float*
                                    hipStream_t st) {
   const int64_t k = p.stream;
   if (k <= 0) return hipSuccess;
-  float* bnd = reinterpret_cast<float*>(static_cast<char*>(rec) + point_bound_offset(k, p.rec_size));
-  if (p.grid == 2) pack_points_grid_kernel<true><<<grid_for(k), kThreads, 0, st>>>(g, G, k, rec, bnd);
-  else pack_points_grid_kernel<false><<<grid_for(k), kThreads, 0, st>>>(g, G, k, rec, bnd);
+  char* base = static_cast<char*>(rec);
+  if (p.grid == 2)
+    pack_points_grid_kernel<true><<<grid_for(k), kThreads, 0, st>>>(
+        g, G, k, rec, reinterpret_cast<float4*>(base + row_group_offset(k)),
+        reinterpret_cast<float*>(base + row_bound_offset(k)));
+  else
+    pack_points_grid_kernel<false><<<grid_for(k), kThreads, 0, st>>>(
+        g, G, k, rec, nullptr, reinterpret_cast<float*>(base + point_bound_offset(k)));
   return hipGetLastError();
 }
 
 namespace {
 template <int Q, int FK>
-void bwd_grid_launch(const Plan& p, const void* rec, int64_t k_begin, int64_t k_end, int64_t per_split,
+void bwd_rows_launch(const Plan& p, const void* rec, int64_t k_begin, int64_t k_end, int64_t per_split,
                      const void* xyz, const void* f, void* partial, void* grad, int carry_in, int direct,
                      const GridDef& g, hipStream_t st) {
   const dim3 grid(static_cast<unsigned>(p.blocks * p.nsplit));
-  const auto* r = static_cast<const PointGrid*>(rec);
-  const float* bnd = reinterpret_cast<const float*>(static_cast<const char*>(rec) +
-                                                    point_bound_offset(p.stream, sizeof(PointGrid)));
-  bwd_grid_kernel<Q, FK><<<grid, kThreads, 0, st>>>(
-      r, int(k_begin), int(k_end), int(per_split), static_cast<const float*>(xyz),
-      static_cast<const float*>(f), p.lanes, int(p.blocks), static_cast<float*>(partial),
-      static_cast<float*>(grad), carry_in, direct, g, bnd);
+  const char* base = static_cast<const char*>(rec);
+  bwd_rows_kernel<Q, FK><<<grid, kThreads, 0, st>>>(
+      static_cast<const PointRow*>(rec), reinterpret_cast<const float4*>(base + row_group_offset(p.stream)),
+      reinterpret_cast<const float*>(base + row_bound_offset(p.stream)), int(k_begin), int(k_end),
+      int(per_split), static_cast<const float*>(xyz), static_cast<const float*>(f), p.lanes, int(p.blocks),
+      static_cast<float*>(partial), static_cast<float*>(grad), carry_in, direct, g);
 }
 }  // namespace
 
@@ -1086,7 +1098,7 @@ hipError_t launch_bwd_chunk(const Plan& p, const void* rec, int64_t k_begin, int
                             const void* S, const void* G, const GridDef* gd) {
   if (p.mode == kPH64 && p.grid == 2 && gd && !p.gf) {
 #define NX_GRID_BWD(Q, FK) \
-  bwd_grid_launch<Q, FK>(p, rec, k_begin, k_end, per_split, xyz, f, partial, grad, carry_in, direct, *gd, st)
+  bwd_rows_launch<Q, FK>(p, rec, k_begin, k_end, per_split, xyz, f, partial, grad, carry_in, direct, *gd, st)
     if (p.fk) {
       if (p.per_lane == 4) NX_GRID_BWD(4, 1);
       else if (p.per_lane == 2) NX_GRID_BWD(2, 1);

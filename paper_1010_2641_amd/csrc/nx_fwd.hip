@@ -92,6 +92,19 @@ __device__ __forceinline__ float round_unbiased(double m, int64_t j) {
   return u < t ? hi : lo;
 }
 
+// Any finite v to FP32 by unbiased rounding (round_unbiased of |v|, the sign put back),
+// drawn from mix64(key).
+__device__ __forceinline__ float round_unbiased_signed(double v, uint64_t key) {
+  const double a = fabs(v);
+  float lo = static_cast<float>(a);
+  if (static_cast<double>(lo) > a) lo = __uint_as_float(__float_as_uint(lo) - 1u);
+  const float hi = __uint_as_float(__float_as_uint(lo) + 1u);
+  const double t = (a - static_cast<double>(lo)) / (static_cast<double>(hi) - static_cast<double>(lo));
+  const double u = static_cast<double>(mix64(key) >> 11) * 0x1.0p-53;
+  const float r = u < t ? hi : lo;
+  return v < 0.0 ? -r : r;
+}
+
 // The FP64-phase record of atom j (indices counted from the first atom of a plan, which
 // starts the plan's first group):
 //   a  = arg f in cycles (0 for f = 1 or f = 0) + offset (kPhaseShift, plus 1/2 for the
@@ -514,8 +527,8 @@ __global__ __launch_bounds__(kThreads, INL ? 4 : 5) void fwd_lds_kernel(
 }
 
 // Grid atom records (AtomGrid): the AtomPH record of atom j (same addend, factor, turn
-// and rounding) with its position folded into c0 = o.r + a and c_d = e_d.r, in FP64; rmax
-// as in pack_atoms_ph_kernel.
+// and rounding) with its position folded into c0 = o.r + a and c_d = e_d.r, in FP64, and
+// the row step exp(2 i pi c1) - 1; rmax as in pack_atoms_ph_kernel.
 __global__ __launch_bounds__(kThreads) void pack_atoms_grid_kernel(const float* __restrict__ xyz,
                                                                    const float* __restrict__ f,
                                                                    int64_t n, AtomGrid* __restrict__ rec,
@@ -534,6 +547,15 @@ __global__ __launch_bounds__(kThreads) void pack_atoms_grid_kernel(const float* 
       r.m = a.m;
       r.ck = a.ck;
       r.sk = a.sk;
+      // exp(2 i pi c) - 1 = (-2 sin^2 pi t, sin 2 pi t), t = c mod 1, for c1 and c2,
+      // rounded without bias (keys of their own: j with a tag 1..4 in bits 60-62)
+      const uint64_t key = static_cast<uint64_t>(j);
+      const double t1 = r.c1 - __builtin_rint(r.c1), h1 = sinpi(t1);
+      const double t2 = r.c2 - __builtin_rint(r.c2), h2 = sinpi(t2);
+      r.wr = round_unbiased_signed(-2.0 * h1 * h1, key | (1ull << 60));
+      r.wi = round_unbiased_signed(sinpi(2.0 * t1), key | (2ull << 60));
+      r.vr = round_unbiased_signed(-2.0 * h2 * h2, key | (3ull << 60));
+      r.vi = round_unbiased_signed(sinpi(2.0 * t2), key | (4ull << 60));
       am = fmaxf(bound_abs(a.x), fmaxf(bound_abs(a.y), bound_abs(a.z)));
     }
     am = wave_max(am);
@@ -663,6 +685,276 @@ __global__ __launch_bounds__(kThreads, 8) void fwd_grid_kernel(
   if (k < K) {
     if (direct) A[k] = make_float2(sr + cr, si + ci);
     else part[int64_t(sp) * K + k] = make_float4(sr, si, cr, ci);
+  }
+}
+
+// The forward over rows of a multiple of 128 points with two consecutive points per
+// lane, i1 and i1 + 1 (each wave covers 128 points of one row): the first point's phase
+// factor E = exp(2 i pi psi) comes as in fwd_grid_kernel (FP64 phase, the fixed-point
+// read, hardware cos and sin), the second's is E + E (w - 1) with the atom's row step
+// w - 1 from its record (four FP32 fma in place of the phase, the reduction and two
+// transcendentals).  Groups, quads, eighth turns and compensation per point as in
+// fwd_grid_kernel; the range check covers both points.  Built for 6 waves per SIMD with
+// 16-atom groups (78 VGPRs, no spills; 8 would spill), 4 with 8-atom groups.
+template <int FK, int GRP>
+__global__ __launch_bounds__(kThreads, GRP == 16 ? 6 : 4) void fwd_rows2_kernel(
+    const AtomGrid* __restrict__ rec, int a_begin, int a_end, int per_split, GridDef g, int64_t K,
+    int blocks_k, float4* __restrict__ part, float2* __restrict__ A, int carry_in, int direct) {
+  static_assert(kThreads % GRP == 0, "tiles must hold whole groups");
+  struct Tile { double c1; float m, ck, sk, rmax, wr, wi; };   // 32 B
+  __shared__ Tile tile[kThreads];
+  __shared__ double rowb[kThreads / 64][kThreads];   // the row term per wave and atom
+  const int lb = xcd_major_block(blockIdx.x, gridDim.x);
+  const int kb = lb % blocks_k;
+  const int sp = lb / blocks_k;
+  const int wave = threadIdx.x >> 6;
+  // the lane's points k and k + 1 (K is a multiple of 128, so both exist or neither)
+  const int64_t kbase = int64_t(kb) * (2 * kThreads);
+  const int64_t k = kbase + 128 * wave + 2 * (threadIdx.x & 63);
+  const int64_t kk = k < K ? k : K - 2;
+  const double di1 = static_cast<double>(static_cast<uint32_t>(kk) % static_cast<uint32_t>(g.n1));
+  float s1;
+  {
+    double S3[3], R3[3], T3[3];
+    grid_point(g, kk, S3, R3);
+    grid_point(g, kk + 1, T3, R3);
+    s1 = fmaxf(fmaxf(bound_abs(fabs(S3[0]) + fabs(S3[1]) + fabs(S3[2])),
+                     bound_abs(fabs(T3[0]) + fabs(T3[1]) + fabs(T3[2]))),
+               bound_abs(fabs(R3[0]) + fabs(R3[1]) + fabs(R3[2])));
+  }
+  double d2w[kThreads / 64], d3w[kThreads / 64];
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) {
+    int64_t kw = kbase + 128 * w;
+    if (kw > K - 1) kw = K - 1;
+    const uint32_t row = static_cast<uint32_t>(kw) / static_cast<uint32_t>(g.n1);
+    d2w[w] = static_cast<double>(row % static_cast<uint32_t>(g.n2));
+    d3w[w] = static_cast<double>(row / static_cast<uint32_t>(g.n2));
+  }
+  float sr[2], si[2], cr[2], ci[2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    sr[p] = si[p] = cr[p] = ci[p] = 0.f;
+    if (carry_in && k < K) {
+      const float4 st = part[int64_t(sp) * K + k + p];
+      sr[p] = st.x; si[p] = st.y; cr[p] = st.z; ci[p] = st.w;
+    }
+  }
+  // one atom against both points: the first point's factor from the phase, the second's
+  // stepped; the terms (m-weighted for complex f) into (r0, i0) and (r1, i1)
+  auto pair2 = [&](auto red_c, int uu, float& r0, float& i0, float& r1, float& i1, bool first) {
+    constexpr int R = decltype(red_c)::value;
+    const double ph = __builtin_fma(di1, tile[uu].c1, rowb[wave][uu]);
+    float c, s;
+    cis_turn<R>(ph, c, s);
+    const float wr = tile[uu].wr, wi = tile[uu].wi;
+    const float c2 = __builtin_fmaf(c, wr, __builtin_fmaf(-s, wi, c));
+    const float s2 = __builtin_fmaf(c, wi, __builtin_fmaf(s, wr, s));
+    if constexpr (FK == 0) {
+      if (first) { r0 = c; i0 = s; r1 = c2; i1 = s2; }
+      else { r0 += c; i0 += s; r1 += c2; i1 += s2; }
+    } else {
+      const float m = tile[uu].m;
+      if (first) { r0 = m * c; i0 = m * s; r1 = m * c2; i1 = m * s2; }
+      else {
+        r0 = __builtin_fmaf(m, c, r0); i0 = __builtin_fmaf(m, s, i0);
+        r1 = __builtin_fmaf(m, c2, r1); i1 = __builtin_fmaf(m, s2, i1);
+      }
+    }
+  };
+  auto run_tile = [&](auto red_c, int nt) {
+    int u0 = 0;
+    for (; u0 + GRP <= nt; u0 += GRP) {
+      const float ck = tile[u0].ck, sk = tile[u0].sk;
+      float gr0 = 0.f, gi0 = 0.f, gr1 = 0.f, gi1 = 0.f;
+#pragma unroll
+      for (int q = 0; q < GRP / 4; ++q) {
+        float qr0, qi0, qr1, qi1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pair2(red_c, u0 + 4 * q + u, qr0, qi0, qr1, qi1, u == 0);
+        if (q == 0) { gr0 = qr0; gi0 = qi0; gr1 = qr1; gi1 = qi1; }
+        else { gr0 += qr0; gi0 += qi0; gr1 += qr1; gi1 += qi1; }
+      }
+      kahan_rot(sr[0], cr[0], si[0], ci[0], gr0, gi0, ck, sk);
+      kahan_rot(sr[1], cr[1], si[1], ci[1], gr1, gi1, ck, sk);
+    }
+    if (u0 < nt) {    // the split's last, partial group
+      const float ck = tile[u0].ck, sk = tile[u0].sk;
+      float gr0 = 0.f, gi0 = 0.f, gr1 = 0.f, gi1 = 0.f;
+      for (int uu = u0; uu < nt; ++uu) {
+        float r0, i0, r1, i1;
+        pair2(red_c, uu, r0, i0, r1, i1, true);
+        gr0 += r0; gi0 += i0; gr1 += r1; gi1 += i1;
+      }
+      kahan_rot(sr[0], cr[0], si[0], ci[0], gr0, gi0, ck, sk);
+      kahan_rot(sr[1], cr[1], si[1], ci[1], gr1, gi1, ck, sk);
+    }
+  };
+  const int j0 = a_begin + sp * per_split;
+  const int j1 = min(j0 + per_split, a_end);
+  for (int t0 = j0; t0 < j1; t0 += kThreads) {
+    const int nt = min(kThreads, j1 - t0);
+    __syncthreads();                        // the previous tile is no longer read
+    if (int(threadIdx.x) < nt) {
+      const AtomGrid a = rec[t0 + threadIdx.x];
+      tile[threadIdx.x] = Tile{a.c1, a.m, a.ck, a.sk, a.rmax, a.wr, a.wi};
+#pragma unroll
+      for (int w = 0; w < kThreads / 64; ++w)
+        rowb[w][threadIdx.x] = __builtin_fma(d3w[w], a.c3, __builtin_fma(d2w[w], a.c2, a.c0));
+    }
+    __syncthreads();
+    const float rt = fmaxf(tile[0].rmax, tile[nt - 1].rmax);
+    if (__all(s1 * rt < kFixedPhaseBound)) run_tile(std::integral_constant<int, 2>{}, nt);
+    else run_tile(std::integral_constant<int, 3>{}, nt);
+  }
+  if (k < K) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      if (direct) A[k + p] = make_float2(sr[p] + cr[p], si[p] + ci[p]);
+      else part[int64_t(sp) * K + k + p] = make_float4(sr[p], si[p], cr[p], ci[p]);
+    }
+  }
+}
+
+// The forward over rows of a multiple of 128 points taken in pairs (n2 even), a 2 x 2
+// block of points per lane: (i1, i2), (i1 + 1, i2), (i1, i2 + 1), (i1 + 1, i2 + 1) with i2
+// even; each wave covers 128 points of an even row and the same points of the next row.
+// The first point's phase factor E comes as in fwd_grid_kernel, the others' are stepped:
+// E w, E v and E w v, with the atom's steps w - 1 (along the row) and v - 1 (to the next
+// row) from its record, E + E (w - 1) etc. in FP32 (three steps of four fma in place of
+// three phases, reductions and six transcendentals).  Groups, quads, eighth turns and
+// compensation per point as in fwd_grid_kernel; the range check covers the four points.
+// Work of a wave: task t = 4 (work-group) + wave, segment t % (n1 / 128) of row pair
+// t / (n1 / 128); waves past the last task compute nothing that is written.
+template <int FK, int GRP>
+__global__ __launch_bounds__(kThreads, 4) void fwd_rows4_kernel(
+    const AtomGrid* __restrict__ rec, int a_begin, int a_end, int per_split, GridDef g, int64_t K,
+    int blocks_k, float4* __restrict__ part, float2* __restrict__ A, int carry_in, int direct) {
+  static_assert(kThreads % GRP == 0, "tiles must hold whole groups");
+  struct Tile { double c1; float m, ck, sk, rmax, wr, wi, vr, vi, pad0, pad1; };   // 48 B
+  __shared__ Tile tile[kThreads];
+  __shared__ double rowb[kThreads / 64][kThreads];   // the even row's term per wave and atom
+  const int lb = xcd_major_block(blockIdx.x, gridDim.x);
+  const int kb = lb % blocks_k;
+  const int sp = lb / blocks_k;
+  const int wave = threadIdx.x >> 6;
+  const uint32_t n1 = static_cast<uint32_t>(g.n1), n2 = static_cast<uint32_t>(g.n2);
+  const uint32_t segs = n1 / 128, ntask = static_cast<uint32_t>(K / 256);
+  // the tasks of the work-group's waves (the last task for waves past the end)
+  double d2w[kThreads / 64], d3w[kThreads / 64];
+  uint32_t k00 = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) {
+    uint32_t t = static_cast<uint32_t>(kb) * 4 + w;
+    if (t >= ntask) t = ntask - 1;
+    const uint32_t pair = t / segs, seg = t - pair * segs;
+    const uint32_t i3 = pair / (n2 / 2), i2 = 2 * (pair - i3 * (n2 / 2));
+    d2w[w] = static_cast<double>(i2);
+    d3w[w] = static_cast<double>(i3);
+    if (w == wave) k00 = seg * 128 + 2 * (threadIdx.x & 63) + n1 * (i2 + n2 * i3);
+  }
+  const bool live = static_cast<uint32_t>(kb) * 4 + wave < ntask;
+  const uint32_t kp[4] = {k00, k00 + 1, k00 + n1, k00 + n1 + 1};
+  const double di1 = static_cast<double>(k00 % n1);
+  float s1 = 0.f;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    double S3[3], R3[3];
+    grid_point(g, kp[p], S3, R3);
+    s1 = fmaxf(s1, fmaxf(bound_abs(fabs(S3[0]) + fabs(S3[1]) + fabs(S3[2])),
+                         bound_abs(fabs(R3[0]) + fabs(R3[1]) + fabs(R3[2]))));
+  }
+  float sr[4], si[4], cr[4], ci[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    sr[p] = si[p] = cr[p] = ci[p] = 0.f;
+    if (carry_in && live) {
+      const float4 st = part[int64_t(sp) * K + kp[p]];
+      sr[p] = st.x; si[p] = st.y; cr[p] = st.z; ci[p] = st.w;
+    }
+  }
+  // one atom against the four points; the terms (m-weighted for complex f) into (r[p], i[p])
+  auto quad4 = [&](auto red_c, int uu, float* r, float* im, bool first) {
+    constexpr int R = decltype(red_c)::value;
+    const double ph = __builtin_fma(di1, tile[uu].c1, rowb[wave][uu]);
+    float z[4][2];
+    cis_turn<R>(ph, z[0][0], z[0][1]);
+    const float wr = tile[uu].wr, wi = tile[uu].wi, vr = tile[uu].vr, vi = tile[uu].vi;
+    // z <- z + z (s - 1) for a step s - 1 = (sr_, si_)
+    auto step = [](const float* a, float sr_, float si_, float* b) {
+      b[0] = __builtin_fmaf(a[0], sr_, __builtin_fmaf(-a[1], si_, a[0]));
+      b[1] = __builtin_fmaf(a[0], si_, __builtin_fmaf(a[1], sr_, a[1]));
+    };
+    step(z[0], wr, wi, z[1]);
+    step(z[0], vr, vi, z[2]);
+    step(z[1], vr, vi, z[3]);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      if constexpr (FK == 0) {
+        if (first) { r[p] = z[p][0]; im[p] = z[p][1]; }
+        else { r[p] += z[p][0]; im[p] += z[p][1]; }
+      } else {
+        const float m = tile[uu].m;
+        if (first) { r[p] = m * z[p][0]; im[p] = m * z[p][1]; }
+        else { r[p] = __builtin_fmaf(m, z[p][0], r[p]); im[p] = __builtin_fmaf(m, z[p][1], im[p]); }
+      }
+    }
+  };
+  auto run_tile = [&](auto red_c, int nt) {
+    int u0 = 0;
+    for (; u0 + GRP <= nt; u0 += GRP) {
+      const float ck = tile[u0].ck, sk = tile[u0].sk;
+      float gr[4], gi[4];
+#pragma unroll
+      for (int q = 0; q < GRP / 4; ++q) {
+        float qr[4], qi[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) quad4(red_c, u0 + 4 * q + u, qr, qi, u == 0);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          if (q == 0) { gr[p] = qr[p]; gi[p] = qi[p]; }
+          else { gr[p] += qr[p]; gi[p] += qi[p]; }
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p) kahan_rot(sr[p], cr[p], si[p], ci[p], gr[p], gi[p], ck, sk);
+    }
+    if (u0 < nt) {    // the split's last, partial group
+      const float ck = tile[u0].ck, sk = tile[u0].sk;
+      float gr[4] = {0.f, 0.f, 0.f, 0.f}, gi[4] = {0.f, 0.f, 0.f, 0.f};
+      for (int uu = u0; uu < nt; ++uu) {
+        float r[4], im[4];
+        quad4(red_c, uu, r, im, true);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) { gr[p] += r[p]; gi[p] += im[p]; }
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p) kahan_rot(sr[p], cr[p], si[p], ci[p], gr[p], gi[p], ck, sk);
+    }
+  };
+  const int j0 = a_begin + sp * per_split;
+  const int j1 = min(j0 + per_split, a_end);
+  for (int t0 = j0; t0 < j1; t0 += kThreads) {
+    const int nt = min(kThreads, j1 - t0);
+    __syncthreads();                        // the previous tile is no longer read
+    if (int(threadIdx.x) < nt) {
+      const AtomGrid a = rec[t0 + threadIdx.x];
+      tile[threadIdx.x] = Tile{a.c1, a.m, a.ck, a.sk, a.rmax, a.wr, a.wi, a.vr, a.vi, 0.f, 0.f};
+#pragma unroll
+      for (int w = 0; w < kThreads / 64; ++w)
+        rowb[w][threadIdx.x] = __builtin_fma(d3w[w], a.c3, __builtin_fma(d2w[w], a.c2, a.c0));
+    }
+    __syncthreads();
+    const float rt = fmaxf(tile[0].rmax, tile[nt - 1].rmax);
+    if (__all(s1 * rt < kFixedPhaseBound)) run_tile(std::integral_constant<int, 2>{}, nt);
+    else run_tile(std::integral_constant<int, 3>{}, nt);
+  }
+  if (live) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      if (direct) A[kp[p]] = make_float2(sr[p] + cr[p], si[p] + ci[p]);
+      else part[int64_t(sp) * K + kp[p]] = make_float4(sr[p], si[p], cr[p], ci[p]);
+    }
   }
 }
 
@@ -981,17 +1273,34 @@ hipError_t launch_fwd_chunk(const Plan& p, const void* rec, int64_t a_begin, int
     const auto* r = static_cast<const AtomGrid*>(rec);
     auto* pa = static_cast<float4*>(partial);
     auto* a = static_cast<float2*>(A);
-#define NX_GRID_FWD(FK, GRP)                                                                    \
-  fwd_grid_kernel<FK, GRP><<<grid, kThreads, 0, st>>>(r, int(a_begin), int(a_end), int(per_split), \
-                                                      *gd, p.lanes, int(p.blocks), pa, a, carry_in, direct)
+    auto launch = [&](auto fk_c, auto grp_c) {
+      constexpr int FK = decltype(fk_c)::value, GRP = decltype(grp_c)::value;
+      if constexpr (GRP == 16) {    // (the 2 x 2 block exists with 16-atom groups only)
+        if (p.per_lane == 4) {
+          fwd_rows4_kernel<FK, GRP><<<grid, kThreads, 0, st>>>(r, int(a_begin), int(a_end), int(per_split),
+                                                               *gd, p.lanes, int(p.blocks), pa, a, carry_in,
+                                                               direct);
+          return;
+        }
+      }
+      if (p.per_lane == 2)
+        fwd_rows2_kernel<FK, GRP><<<grid, kThreads, 0, st>>>(r, int(a_begin), int(a_end), int(per_split), *gd,
+                                                             p.lanes, int(p.blocks), pa, a, carry_in, direct);
+      else
+        fwd_grid_kernel<FK, GRP><<<grid, kThreads, 0, st>>>(r, int(a_begin), int(a_end), int(per_split), *gd,
+                                                            p.lanes, int(p.blocks), pa, a, carry_in, direct);
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using G8 = std::integral_constant<int, 8>;
+    using G16 = std::integral_constant<int, 16>;
     if (p.fk) {
-      if (p.grp == 16) NX_GRID_FWD(1, 16);
-      else NX_GRID_FWD(1, 8);
+      if (p.grp == 16) launch(I1{}, G16{});
+      else launch(I1{}, G8{});
     } else {
-      if (p.grp == 16) NX_GRID_FWD(0, 16);
-      else NX_GRID_FWD(0, 8);
+      if (p.grp == 16) launch(I0{}, G16{});
+      else launch(I0{}, G8{});
     }
-#undef NX_GRID_FWD
     return hipGetLastError();
   }
   if (p.mode == kF64) {

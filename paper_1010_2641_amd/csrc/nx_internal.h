@@ -83,13 +83,28 @@ struct GridDef {
 // Forward atom record of the grid sums: with r the atom's position and a its FP64-phase
 // addend (as in AtomPH), c0 = o.r + a and c_d = e_d.r, so that the phase of point
 // (i1, i2, i3) is i1 c1 + (c0 + i2 c2 + i3 c3); the bracket is one value per atom and grid
-// row.  m, ck, sk, rmax as in AtomPH.
-struct alignas(16) AtomGrid { double c0, c1, c2, c3; float m, ck, sk, rmax; };      // 48 B
-// Adjoint point record of the grid sums: i1 (FP64, exact) and delta (the seed's phase plus
-// kPhaseShift) for the phase, |G| S and |G| in FP32 (S the FP64 grid point).
-struct alignas(16) PointGrid { double i1, delta; float gsx, gsy, gsz, gmag; };      // 32 B
-// (the plan sizes the forward's records as AtomPH for both)
-static_assert(sizeof(AtomGrid) == sizeof(AtomPH), "grid atom records replace AtomPH in place");
+// row.  m, ck, sk, rmax as in AtomPH.  (wr, wi) = exp(2 i pi c1) - 1, the step of the
+// phase factor from one point of a row to the next, and (vr, vi) = exp(2 i pi c2) - 1, from
+// one row to the next (i2 + 1), formed in FP64 and rounded to FP32 without bias
+// (stochastically, from a hash of the atom's index), so that the rounding errors of atoms
+// with equal c1 or c2 (a lattice plane) add up incoherently.
+struct alignas(16) AtomGrid { double c0, c1, c2, c3; float m, ck, sk, rmax, wr, wi, vr, vi; };  // 64 B
+// Adjoint over grid rows: along a row the phase factor of atom j steps by the constant
+// w_j = exp(2 i pi step1.r_j) from one point to the next, so each 64-point group (one
+// row's run) forms exp(2 i pi psi) exactly (FP64 phase, hardware cos and sin) at its first
+// point only and multiplies by w_j in FP32 for the others.  Per point the record holds the
+// seed as (Re G, -Im G) and the point's place u in its group (FP32); per group the
+// group's first point S0 (FP32).  The sums S.v are formed per group as S0 a0 + step1 a1
+// with a0 = sum v and a1 = sum u v.
+struct alignas(16) PointRow { float gr, ngi, u, pad; };                             // 16 B
+constexpr int kRowGroup = 64;
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+// group records (float4 S0 per 64 points) after the point records, then the tile bounds
+inline size_t row_group_offset(int64_t n) { return align256(static_cast<size_t>(n) * sizeof(PointRow)); }
+inline size_t row_group_bytes(int64_t n) {
+  return align256(static_cast<size_t>((n + kRowGroup - 1) / kRowGroup) * 16);
+}
+inline size_t row_bound_offset(int64_t n) { return row_group_offset(n) + row_group_bytes(n); }
 
 // Running state of one output lane item (a point for the forward, one component of
 // an atom's sum for the adjoint) kept between launches and across splits.
@@ -235,9 +250,11 @@ inline int reduce_lanes(int nsplit, int64_t outputs) {
 // Builds the plan of (op, mode) for the sizes; pure host code, no HIP call.  At most
 // max_split stream slices (kMaxSplit when omitted).
 // `grid`: 0 for a list of points; for a grid (FP64-phase mode), 2 asks for the grid kernels
-// and 1 for the general ones; the plan keeps 2 only where the grid kernels exist for it
-// (rows of n1 points, n1 a multiple of 64, the fixed-point reduction; one point per lane in
-// the forward, 64-point groups in the adjoint) and holds the kind it chose in p.grid.
+// (rows of n1 points, n1 a multiple of 64), 3 for them over rows of a multiple of 128
+// points (two points per lane in the forward), 4 over such rows in pairs (n2 even: a 2 x 2
+// block of points per lane in the forward), 1 for the general ones; the plan keeps the
+// grid kernels only where they exist for it (the fixed-point reduction; 64-point groups in
+// the adjoint) and holds the kind it chose in p.grid (2 or 1).
 Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_null,
                int64_t max_split = kMaxSplit, int grid = 0);
 
@@ -253,8 +270,8 @@ hipError_t launch_pack_atoms(int mode, int red, int grp, const void* xyz, const 
 hipError_t launch_pack_points(int mode, int red, const void* S, const void* G, int64_t k,
                               void* rec, hipStream_t st);
 // Grid records (FP64-phase mode): the atoms as AtomGrid (plan grid 2; grid 1 packs AtomPH
-// with launch_pack_atoms), the points of the grid with the seed G as PointGrid (grid 2) or
-// PointPH (grid 1), followed by the tile bounds as after launch_pack_points.
+// with launch_pack_atoms), the points of the grid with the seed G as PointRow with the
+// group records (grid 2) or PointPH (grid 1), followed by the tile bounds.
 hipError_t launch_pack_atoms_grid(const Plan& p, const float* xyz, const float* f, int64_t n,
                                   const GridDef& g, void* rec, hipStream_t st);
 hipError_t launch_pack_points_grid(const Plan& p, const GridDef& g, const float* G, void* rec,

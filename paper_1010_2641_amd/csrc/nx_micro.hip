@@ -254,84 +254,145 @@ __global__ __launch_bounds__(kThreads, 8) void mix_bwd_ph64_tile(int iters, floa
   cm.stop(clk);
 }
 
-// The grid kernels' sequences (a grid walked by rows), in the sums' shape.  Forward: the
-// phase is fma(i1, c1, b) (i1 the lane's point index along the row, c1 = step1.r and b the
-// atom's row term, both shared by the wave), then the fixed-point turn, cos, sin and the
-// accumulation as above.  The shared operands come from LDS in the kernel (vector
-// registers); here the tile's row terms b stay in registers and c1 is formed by the
-// scalar unit, which changes it every iteration (an addend from the scalar unit would
-// have to be copied to vector registers first: the accumulating form of the FP64 fma
-// overwrites its addend).
+// The grid kernels' sequences (a grid walked by rows), in their own shapes.
+//
+// Forward, a 2 x 2 block of points per lane: per atom, the first point's phase
+// fma(i1, c1, b) (i1 the lane's index along the row, c1 = step1.r and b the atom's row
+// term, both shared by the wave), the fixed-point turn, cos and sin; the other three
+// points' phase factors stepped from it with the atom's steps w - 1 and v - 1 (three steps
+// of four fma); the four terms accumulated (two fma or adds each).  The shared operands
+// come from LDS in the kernel (vector registers): here the tile's row terms and steps stay
+// in vector registers and c1 is formed by the scalar unit, which changes it every
+// iteration (an addend from the scalar unit would have to be copied to vector registers
+// first: the accumulating form of the FP64 fma overwrites its addend).  4 atoms per
+// iteration.
+constexpr int kTileGrid = 4;
+
 template <bool CF>
 __global__ __launch_bounds__(kThreads, 8) void mix_fwd_grid_tile(int iters, float* out, unsigned long long* clk) {
   ClockMark cm;
   cm.start();
   double di1 = static_cast<double>((threadIdx.x + blockIdx.x * kThreads) & 127);
-  double b[kTile];
+  double b[kTileGrid];
+  float wr[kTileGrid], wi[kTileGrid], vr[kTileGrid], vi[kTileGrid];
 #pragma unroll
-  for (int t = 0; t < kTile; ++t) {
+  for (int t = 0; t < kTileGrid; ++t) {
     b[t] = kShift + 12.5 + 0.125 * t;
+    wr[t] = -1e-3f * (t + 1);
+    wi[t] = 4e-2f * (t + 1);
+    vr[t] = -2e-3f * (t + 1);
+    vi[t] = 6e-2f * (t + 1);
     opaque(b[t]);
+    opaque(wr[t]);
+    opaque(wi[t]);
+    opaque(vr[t]);
+    opaque(vi[t]);
   }
   opaque(di1);
-  float ar = 0.f, ai = 0.f;
+  float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
   for (int j = 0; j < iters; ++j) {
 #pragma unroll
-    for (int t = 0; t < kTile; ++t) {
+    for (int t = 0; t < kTileGrid; ++t) {
       const double c1 = uniform_f64(0x3f340000u + (t << 8), 0x9999999au, j);   // ~3e-4
       const float m = uniform_f32(0x41f80000u + (t << 8), j);              // ~31
       const double ph = __builtin_fma(di1, c1, b[t]);
+      float z[4][2];
       const float tt = static_cast<float>(__double2loint(ph)) * 0x1.0p-32f;
-      const float c = __builtin_amdgcn_cosf(tt);
-      const float s = __builtin_amdgcn_sinf(tt);
-      if constexpr (CF) {
-        ar = __builtin_fmaf(m, c, ar);
-        ai = __builtin_fmaf(m, s, ai);
-      } else {
-        ar += c;
-        ai += s;
+      z[0][0] = __builtin_amdgcn_cosf(tt);
+      z[0][1] = __builtin_amdgcn_sinf(tt);
+      auto step = [](const float* a, float sr, float si, float* c) {
+        c[0] = __builtin_fmaf(a[0], sr, __builtin_fmaf(-a[1], si, a[0]));
+        c[1] = __builtin_fmaf(a[0], si, __builtin_fmaf(a[1], sr, a[1]));
+      };
+      step(z[0], wr[t], wi[t], z[1]);
+      step(z[0], vr[t], vi[t], z[2]);
+      step(z[1], vr[t], vi[t], z[3]);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        if constexpr (CF) {
+          ar[p] = __builtin_fmaf(m, z[p][0], ar[p]);
+          ai[p] = __builtin_fmaf(m, z[p][1], ai[p]);
+        } else {
+          ar[p] += z[p][0];
+          ai[p] += z[p][1];
+        }
       }
     }
   }
-  out[threadIdx.x + blockIdx.x * kThreads] = ar - ai;
+  out[threadIdx.x + blockIdx.x * kThreads] = ar[0] - ai[0] + ar[1] - ai[1] + ar[2] - ai[2] + ar[3] - ai[3];
   cm.stop(clk);
 }
 
-// Adjoint over grid rows: the phase is fma(i1, c1, b) + delta (c1 = step1.r and b the row
-// term of the lane's atom, the factor's angle folded into b; i1 and delta those of the
-// point, shared by the wave), then the fixed-point turn, sin and T_d += (|G| S_d) sin.  The
-// same sequence for complex f and f = 1.  Two atoms per lane, 16 points per iteration.
+// Adjoint over grid rows, one 64-point group per iteration, two atoms per lane: per atom
+// the group's first phase factor E (the row term b = c0 + i2 c2 + i3 c3 and the phase
+// fma(i1, c1, b), 3 FP64 fma; the fixed-point turn, cos and sin), then per point v =
+// Re G Im E - Im G Re E (mul, fma), a0 += v, a1 += u v and the step E + E (w - 1) (four fma;
+// none after the last point), and per group the three S0_d a0 + e1_d a1 (two each).  The
+// point's values (Re G, -Im G, u) are formed by the scalar unit, as the kernel loads them;
+// the same sequence for complex f and f = 1.
 template <bool CF>
 __global__ __launch_bounds__(kThreads, 8) void mix_bwd_grid_tile(int iters, float* out, unsigned long long* clk) {
   ClockMark cm;
   cm.start();
   const double lane = static_cast<double>(threadIdx.x + blockIdx.x * kThreads);
-  double c1[2], b[2];
-  float t0[2], t1[2], t2[2];
+  double c0[2], c1[2], c2[2], c3[2];
+  float wr[2], wi[2], t0[2], t1[2], t2[2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
+    c0[q] = kShift + 12.5 - 1e-6 * lane + 0.25 * q;
     c1[q] = 3e-4 + 1e-9 * lane + 1e-5 * q;
-    b[q] = 12.5 - 1e-6 * lane + 0.25 * q;
+    c2[q] = 5e-4 - 1e-9 * lane + 2e-5 * q;
+    c3[q] = 7e-4 + 2e-9 * lane - 1e-5 * q;
+    wr[q] = -1e-3f * (q + 1);
+    wi[q] = 4e-2f * (q + 1);
     t0[q] = t1[q] = t2[q] = 0.f;
+    opaque(c0[q]);
     opaque(c1[q]);
-    opaque(b[q]);
+    opaque(c2[q]);
+    opaque(c3[q]);
+    opaque(wr[q]);
+    opaque(wi[q]);
   }
   for (int j = 0; j < iters; ++j) {
+    const double d1 = uniform_f64(0x40500000u, 0x00000000u, j);           // ~64
+    const double d2 = uniform_f64(0x40400000u, 0x00000000u, j);           // ~32
+    const double d3 = uniform_f64(0x40300000u, 0x00000000u, j);           // ~16
+    const float s0x = uniform_f32(0x40800000u, j), s0y = uniform_f32(0x3d000000u, j),
+                s0z = uniform_f32(0x40800001u, j), e1x = uniform_f32(0x3a500000u, j),
+                e1y = uniform_f32(0x3a100000u, j), e1z = uniform_f32(0x39d00000u, j);
+    float er[2], ei[2], a0[2], a1[2];
 #pragma unroll
-    for (int t = 0; t < kTile; ++t) {
-      const double i1 = uniform_f64(0x40500000u + t, 0x00000000u, j);      // ~64
-      const double d0 = uniform_f64(0x41380000u + t, 0x33333333u, j);      // ~1.57e6
-      const float gx = uniform_f32(0x3f800000u + (t << 8), j), gy = uniform_f32(0x3f000000u + (t << 8), j),
-                  gz = uniform_f32(0x40800000u + (t << 8), j);
+    for (int q = 0; q < 2; ++q) {
+      const double b = __builtin_fma(d3, c3[q], __builtin_fma(d2, c2[q], c0[q]));
+      const double ph = __builtin_fma(d1, c1[q], b);
+      const float tt = static_cast<float>(__double2loint(ph)) * 0x1.0p-32f;
+      er[q] = __builtin_amdgcn_cosf(tt);
+      ei[q] = __builtin_amdgcn_sinf(tt);
+      a0[q] = 0.f;
+      a1[q] = 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 64; ++u) {
+      const float gr = uniform_f32(0x3f800000u + (u << 8), j), ngi = uniform_f32(0xbf000000u + (u << 8), j);
+      const float uf = uniform_f32(0x3f800000u + (u << 12), j);
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        const double ph = __builtin_fma(i1, c1[q], b[q]) + d0;
-        const float tt = static_cast<float>(__double2loint(ph)) * 0x1.0p-32f;
-        const float s = __builtin_amdgcn_sinf(tt);
-        t0[q] = __builtin_fmaf(s, gx, t0[q]);
-        t1[q] = __builtin_fmaf(s, gy, t1[q]);
-        t2[q] = __builtin_fmaf(s, gz, t2[q]);
+        const float v = __builtin_fmaf(gr, ei[q], ngi * er[q]);
+        a0[q] += v;
+        a1[q] = __builtin_fmaf(uf, v, a1[q]);
+        if (u + 1 < 64) {
+          const float nr = __builtin_fmaf(er[q], wr[q], __builtin_fmaf(-ei[q], wi[q], er[q]));
+          const float ni = __builtin_fmaf(er[q], wi[q], __builtin_fmaf(ei[q], wr[q], ei[q]));
+          er[q] = nr;
+          ei[q] = ni;
+        }
       }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      t0[q] = __builtin_fmaf(s0x, a0[q], __builtin_fmaf(e1x, a1[q], t0[q]));
+      t1[q] = __builtin_fmaf(s0y, a0[q], __builtin_fmaf(e1y, a1[q], t1[q]));
+      t2[q] = __builtin_fmaf(s0z, a0[q], __builtin_fmaf(e1z, a1[q], t2[q]));
     }
   }
   out[threadIdx.x + blockIdx.x * kThreads] = t0[0] - t1[0] + t2[0] + t0[1] - t1[1] + t2[1];
@@ -503,7 +564,7 @@ int nxm_pairs_per_lane_iter(int mix, int wide) {
   if (mix >= NXM_OP_FMA_F32 && mix <= NXM_OP_ADD_F32) return wide == 2 ? 0 : 4 * (wide ? 16 : 8);
   if (mix >= NXM_FWD_GRID_CF && mix <= NXM_BWD_GRID_F1) {    // the sums' shape only
     if (wide != 2) return 0;
-    return mix >= NXM_BWD_GRID_CF ? 2 * kTile : kTile;
+    return mix >= NXM_BWD_GRID_CF ? 2 * 64 : 4 * kTileGrid;
   }
   if (mix < NXM_FWD_PH64_CF || mix > NXM_BWD_F32_F1) return 0;
   const bool ph64 = mix >= NXM_FWD_PH64_CF && mix <= NXM_BWD_PH64_F1;

@@ -55,7 +55,7 @@ def test_micro_header_symbols_exported():
     assert micro.nxm_run(4, 2, 1, 1, FAKE, None, None) == -1
     assert micro.nxm_run(8, 2, 1, 1, FAKE, None, None) == -1
     # the mixes of the sums over grid rows: the sums' shape only
-    assert micro.nxm_pairs_per_lane_iter(21, 2) == 16 and micro.nxm_pairs_per_lane_iter(24, 2) == 32
+    assert micro.nxm_pairs_per_lane_iter(21, 2) == 16 and micro.nxm_pairs_per_lane_iter(24, 2) == 128
     assert micro.nxm_pairs_per_lane_iter(21, 0) == 0 and micro.nxm_pairs_per_lane_iter(23, 1) == 0
     assert micro.nxm_run(22, 0, 1, 1, FAKE, None, None) == -1
     assert micro.nxm_run(25, 2, 1, 1, FAKE, None, None) == -2
@@ -389,17 +389,18 @@ def test_grid_fit_step_checks_before_queueing():
 
 
 def test_grid_workspace(monkeypatch):
-    """Rows of a multiple of 64 points: 48-byte atom records (forward) and 32-byte point
-    records (i1, the phase addend, |G| S and |G|; adjoint), each followed as in the
-    point-list calls by the tiles' bounds; other grids take the point-list records (48 B).
-    Unknown ops are refused."""
+    """Rows of a multiple of 64 points: 64-byte atom records (forward); 16-byte point
+    records (the seed and the point's place in its 64-point group) and one 16-byte record
+    per group (its first point; adjoint), followed as in the point-list calls by the
+    tiles' bounds; other grids take the point-list records (48 B).  Unknown ops are
+    refused."""
     monkeypatch.delenv("NX_TUNE_GRID", raising=False)
     a256 = lambda b: -(-b // 256) * 256
     g = grid_struct(n1=128, n2=128, n3=128)          # 2,097,152 points
     n, k = 203_557, 128 ** 3
     bwd_rows = _lib.nx_workspace_bytes_grid(n, ctypes.byref(g), _lib.NX_OP_BWD, 0)
     bwd_list = _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_BWD, 0)
-    assert bwd_list - bwd_rows == a256(k * 48) - a256(k * 32)
+    assert bwd_list - bwd_rows == a256(k * 48) - a256(k * 16) - a256(k // 64 * 16)
     # the forward: one point per lane, same records as the list
     fw = _lib.nx_workspace_bytes_grid(n, ctypes.byref(g), _lib.NX_OP_FWD, 0)
     assert fw % 256 == 0 and fw >= a256(n * 48)
@@ -407,8 +408,14 @@ def test_grid_workspace(monkeypatch):
     g50 = grid_struct(n1=50, n2=40, n3=3)
     assert (_lib.nx_workspace_bytes_grid(1000, ctypes.byref(g50), _lib.NX_OP_BWD, 1)
             == _lib.nx_workspace_bytes(1000, 6000, 1, _lib.NX_OP_BWD, 1))
-    # and so does every grid under NX_TUNE_GRID=1
+    # the forward over rows takes 64-byte atom records (with the row step), also for few
+    # atoms (8-atom groups), against 48 bytes for the point-list kernels
+    small = grid_struct(n1=256, n2=3, n3=2)
+    rows_fw = _lib.nx_workspace_bytes_grid(5000, ctypes.byref(small), _lib.NX_OP_FWD, 0)
+    # and every grid takes the point-list kernels under NX_TUNE_GRID=1
     monkeypatch.setenv("NX_TUNE_GRID", "1")
+    list_fw = _lib.nx_workspace_bytes_grid(5000, ctypes.byref(small), _lib.NX_OP_FWD, 0)
+    assert rows_fw - list_fw == a256(5000 * 64) - a256(5000 * 48)
     assert _lib.nx_workspace_bytes_grid(n, ctypes.byref(g), _lib.NX_OP_BWD, 0) == bwd_list
     assert _lib.nx_workspace_bytes_grid(8, ctypes.byref(g), 3, 1) == 0
     assert "op must be" in _lib.last_error()

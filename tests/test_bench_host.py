@@ -27,7 +27,7 @@ def test_source_hash_is_stable_and_covers_the_kernel_sources():
 
 
 def test_every_kernel_has_an_operation_count():
-    for mode in ("ph64", "f32"):
+    for mode in ("ph64", "f32", "grid"):
         for dom in ("fwd", "bwd"):
             for fkind in ("complex", "unit"):
                 assert bench.ALG_SLOTS[(mode, dom, fkind)] > 0

@@ -85,10 +85,16 @@ def test_hot_kernels_occupancy(device_asm):
             "fwd_lds_kernelILi1ELi0ELi16ELi2ELb0E": 8,      # forward, f = 1
             "bwd_split_kernelILi2ELi1ELi64ELi2ELb0ELb0E": 6,    # adjoint, complex f
             "bwd_split_kernelILi2ELi0ELi64ELi2ELb0ELb0E": 6,    # adjoint, f = 1
-            "fwd_grid_kernelILi1ELi16E": 8,                      # grids walked by rows
+            # grids walked by rows: one point, two points, a 2 x 2 block per lane (forward);
+            # the stepped adjoint, two atoms per lane
+            "fwd_grid_kernelILi1ELi16E": 8,
             "fwd_grid_kernelILi0ELi16E": 8,
-            "bwd_grid_kernelILi2ELi1E": 6,
-            "bwd_grid_kernelILi2ELi0E": 6}
+            "fwd_rows2_kernelILi1ELi16E": 6,
+            "fwd_rows2_kernelILi0ELi16E": 6,
+            "fwd_rows4_kernelILi1ELi16E": 4,
+            "fwd_rows4_kernelILi0ELi16E": 4,
+            "bwd_rows_kernelILi2ELi1E": 7,
+            "bwd_rows_kernelILi2ELi0E": 7}
     for key, o in want.items():
         found = [v for k, v in occ.items() if key in k]
         assert found, key
@@ -158,19 +164,21 @@ def test_micro_loops_are_the_priced_instruction_mixes(device_asm):
         assert not any(k.startswith(("scratch_", "global_load", "buffer_load", "ds_")) for k in c)
         tiles += 1
     assert tiles == 4
-    # the sums over grid rows, same shape
+    # the sums over grid rows in their own shapes: forward, 4 atoms against a 2 x 2 block
+    # of points (one phase, cos and sin per atom); adjoint, one 64-point group against 2
+    # atoms (3 FP64 fma, cos and sin per atom)
     grids = 0
     for name, c in loops.items():
         m = re.search(r"mix_(fwd|bwd)_grid_tileILb([01])E", name)
         if not m:
             continue
         op, fkind = m.group(1), "complex" if m.group(2) == "1" else "unit"
-        pairs = 16 * (2 if op == "bwd" else 1)
+        pairs, atoms, fma64 = (128, 2, 6) if op == "bwd" else (16, 4, 4)
         valu = sum(v for k, v in c.items() if k.startswith("v_"))
         trans = c["v_sin_f32_e32"] + c["v_cos_f32_e32"]
-        assert valu == pairs * bench.ALG_SLOTS[("grid", op, fkind)], (name, dict(c))
-        assert trans == pairs * (1 if op == "bwd" else 2), (name, dict(c))
-        assert c["v_fma_f64"] + c["v_fmac_f64_e32"] == pairs, (name, dict(c))
+        assert valu == round(pairs * bench.ALG_SLOTS[("grid", op, fkind)]), (name, dict(c))
+        assert trans == 2 * atoms, (name, dict(c))
+        assert c["v_fma_f64"] + c["v_fmac_f64_e32"] == fma64, (name, dict(c))
         assert not any(k.startswith(("scratch_", "global_load", "buffer_load", "ds_", "v_mov")) for k in c)
         grids += 1
     assert grids == 4
