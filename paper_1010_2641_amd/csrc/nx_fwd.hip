@@ -694,16 +694,17 @@ __global__ __launch_bounds__(kThreads, 8) void fwd_grid_kernel(
 // read, hardware cos and sin), the second's is E + E (w - 1) with the atom's row step
 // w - 1 from its record (four FP32 fma in place of the phase, the reduction and two
 // transcendentals).  Groups, quads, eighth turns and compensation per point as in
-// fwd_grid_kernel; the range check covers both points.  Built for 6 waves per SIMD with
-// 16-atom groups (78 VGPRs, no spills; 8 would spill), 4 with 8-atom groups.
+// fwd_grid_kernel; the range check covers both points.  Built for 8 waves per SIMD with
+// 16-atom groups (62 VGPRs), 5 with 8-atom groups (88).
 template <int FK, int GRP>
-__global__ __launch_bounds__(kThreads, GRP == 16 ? 6 : 4) void fwd_rows2_kernel(
+__global__ __launch_bounds__(kThreads, GRP == 16 ? 8 : 5) void fwd_rows2_kernel(
     const AtomGrid* __restrict__ rec, int a_begin, int a_end, int per_split, GridDef g, int64_t K,
     int blocks_k, float4* __restrict__ part, float2* __restrict__ A, int carry_in, int direct) {
   static_assert(kThreads % GRP == 0, "tiles must hold whole groups");
   struct Tile { double c1; float m, ck, sk, rmax, wr, wi; };   // 32 B
   __shared__ Tile tile[kThreads];
   __shared__ double rowb[kThreads / 64][kThreads];   // the row term per wave and atom
+  __shared__ double rowd[kThreads / 64][2];          // (i2, i3) of the waves' rows
   const int lb = xcd_major_block(blockIdx.x, gridDim.x);
   const int kb = lb % blocks_k;
   const int sp = lb / blocks_k;
@@ -722,14 +723,13 @@ __global__ __launch_bounds__(kThreads, GRP == 16 ? 6 : 4) void fwd_rows2_kernel(
                      bound_abs(fabs(T3[0]) + fabs(T3[1]) + fabs(T3[2]))),
                bound_abs(fabs(R3[0]) + fabs(R3[1]) + fabs(R3[2])));
   }
-  double d2w[kThreads / 64], d3w[kThreads / 64];
-#pragma unroll
-  for (int w = 0; w < kThreads / 64; ++w) {
-    int64_t kw = kbase + 128 * w;
+  // the rows of the work-group's waves, to LDS (read where the tiles are staged)
+  if ((threadIdx.x & 63) == 0) {
+    int64_t kw = kbase + 128 * wave;
     if (kw > K - 1) kw = K - 1;
     const uint32_t row = static_cast<uint32_t>(kw) / static_cast<uint32_t>(g.n1);
-    d2w[w] = static_cast<double>(row % static_cast<uint32_t>(g.n2));
-    d3w[w] = static_cast<double>(row / static_cast<uint32_t>(g.n2));
+    rowd[wave][0] = static_cast<double>(row % static_cast<uint32_t>(g.n2));
+    rowd[wave][1] = static_cast<double>(row / static_cast<uint32_t>(g.n2));
   }
   float sr[2], si[2], cr[2], ci[2];
 #pragma unroll
@@ -800,7 +800,7 @@ __global__ __launch_bounds__(kThreads, GRP == 16 ? 6 : 4) void fwd_rows2_kernel(
       tile[threadIdx.x] = Tile{a.c1, a.m, a.ck, a.sk, a.rmax, a.wr, a.wi};
 #pragma unroll
       for (int w = 0; w < kThreads / 64; ++w)
-        rowb[w][threadIdx.x] = __builtin_fma(d3w[w], a.c3, __builtin_fma(d2w[w], a.c2, a.c0));
+        rowb[w][threadIdx.x] = __builtin_fma(rowd[w][1], a.c3, __builtin_fma(rowd[w][0], a.c2, a.c0));
     }
     __syncthreads();
     const float rt = fmaxf(tile[0].rmax, tile[nt - 1].rmax);
@@ -825,33 +825,37 @@ __global__ __launch_bounds__(kThreads, GRP == 16 ? 6 : 4) void fwd_rows2_kernel(
 // three phases, reductions and six transcendentals).  Groups, quads, eighth turns and
 // compensation per point as in fwd_grid_kernel; the range check covers the four points.
 // Work of a wave: task t = 4 (work-group) + wave, segment t % (n1 / 128) of row pair
-// t / (n1 / 128); waves past the last task compute nothing that is written.
+// t / (n1 / 128); waves past the last task compute nothing that is written.  Built for 5
+// waves per SIMD (85 VGPRs, no spills; 6 would spill).
 template <int FK, int GRP>
-__global__ __launch_bounds__(kThreads, 4) void fwd_rows4_kernel(
+__global__ __launch_bounds__(kThreads, 5) void fwd_rows4_kernel(
     const AtomGrid* __restrict__ rec, int a_begin, int a_end, int per_split, GridDef g, int64_t K,
     int blocks_k, float4* __restrict__ part, float2* __restrict__ A, int carry_in, int direct) {
   static_assert(kThreads % GRP == 0, "tiles must hold whole groups");
   struct Tile { double c1; float m, ck, sk, rmax, wr, wi, vr, vi, pad0, pad1; };   // 48 B
   __shared__ Tile tile[kThreads];
   __shared__ double rowb[kThreads / 64][kThreads];   // the even row's term per wave and atom
+  __shared__ double rowd[kThreads / 64][2];          // (i2, i3) of the waves' even rows
   const int lb = xcd_major_block(blockIdx.x, gridDim.x);
   const int kb = lb % blocks_k;
   const int sp = lb / blocks_k;
   const int wave = threadIdx.x >> 6;
   const uint32_t n1 = static_cast<uint32_t>(g.n1), n2 = static_cast<uint32_t>(g.n2);
   const uint32_t segs = n1 / 128, ntask = static_cast<uint32_t>(K / 256);
-  // the tasks of the work-group's waves (the last task for waves past the end)
-  double d2w[kThreads / 64], d3w[kThreads / 64];
-  uint32_t k00 = 0;
-#pragma unroll
-  for (int w = 0; w < kThreads / 64; ++w) {
-    uint32_t t = static_cast<uint32_t>(kb) * 4 + w;
+  // the wave's task (the last task for waves past the end); the rows of the work-group's
+  // waves go to LDS, read where the tiles are staged (in registers they would hold 16
+  // VGPRs through the loop)
+  uint32_t k00;
+  {
+    uint32_t t = static_cast<uint32_t>(kb) * 4 + wave;
     if (t >= ntask) t = ntask - 1;
     const uint32_t pair = t / segs, seg = t - pair * segs;
     const uint32_t i3 = pair / (n2 / 2), i2 = 2 * (pair - i3 * (n2 / 2));
-    d2w[w] = static_cast<double>(i2);
-    d3w[w] = static_cast<double>(i3);
-    if (w == wave) k00 = seg * 128 + 2 * (threadIdx.x & 63) + n1 * (i2 + n2 * i3);
+    k00 = seg * 128 + 2 * (threadIdx.x & 63) + n1 * (i2 + n2 * i3);
+    if ((threadIdx.x & 63) == 0) {
+      rowd[wave][0] = static_cast<double>(i2);
+      rowd[wave][1] = static_cast<double>(i3);
+    }
   }
   const bool live = static_cast<uint32_t>(kb) * 4 + wave < ntask;
   const uint32_t kp[4] = {k00, k00 + 1, k00 + n1, k00 + n1 + 1};
@@ -942,7 +946,7 @@ __global__ __launch_bounds__(kThreads, 4) void fwd_rows4_kernel(
       tile[threadIdx.x] = Tile{a.c1, a.m, a.ck, a.sk, a.rmax, a.wr, a.wi, a.vr, a.vi, 0.f, 0.f};
 #pragma unroll
       for (int w = 0; w < kThreads / 64; ++w)
-        rowb[w][threadIdx.x] = __builtin_fma(d3w[w], a.c3, __builtin_fma(d2w[w], a.c2, a.c0));
+        rowb[w][threadIdx.x] = __builtin_fma(rowd[w][1], a.c3, __builtin_fma(rowd[w][0], a.c2, a.c0));
     }
     __syncthreads();
     const float rt = fmaxf(tile[0].rmax, tile[nt - 1].rmax);

@@ -89,10 +89,10 @@ def test_hot_kernels_occupancy(device_asm):
             # the stepped adjoint, two atoms per lane
             "fwd_grid_kernelILi1ELi16E": 8,
             "fwd_grid_kernelILi0ELi16E": 8,
-            "fwd_rows2_kernelILi1ELi16E": 6,
-            "fwd_rows2_kernelILi0ELi16E": 6,
-            "fwd_rows4_kernelILi1ELi16E": 4,
-            "fwd_rows4_kernelILi0ELi16E": 4,
+            "fwd_rows2_kernelILi1ELi16E": 8,
+            "fwd_rows2_kernelILi0ELi16E": 8,
+            "fwd_rows4_kernelILi1ELi16E": 5,
+            "fwd_rows4_kernelILi0ELi16E": 5,
             "bwd_rows_kernelILi2ELi1E": 7,
             "bwd_rows_kernelILi2ELi0E": 7}
     for key, o in want.items():
