@@ -161,6 +161,8 @@ def parse():
                    help="time the steps as three calls (forward, misfit, adjoint) instead of one "
                         "nx_fit_step call (for one long step: the three calls also give the sums' "
                         "own times, so the step is not run twice)")
+    p.add_argument("--no-list", action="store_true",
+                   help="skip the point-list step timed beside a grid step (list_path)")
     p.add_argument("--no-micro", action="store_true",
                    help="skip the issue-ceiling microbenchmarks (the valu_issue fields)")
     p.add_argument("--copy-cal", type=int, default=0, metavar="BYTES",
@@ -685,7 +687,7 @@ def main():
             f"{'/'.join(key)} {v[0]:.3e} pairs/s" for key, v in sorted(ceilings.items())))
 
     head = measure(args.workload, args, args.steps, args.warmup, ceilings, want_graph=args.graph,
-                   want_species=not args.no_species, staged_only=args.staged, want_list=True)
+                   want_species=not args.no_species, staged_only=args.staged, want_list=not args.no_list)
     c5 = None
     if args.workload == "c2" and not args.no_c5:
         # the largest configuration, one timed step (its 39 s per step would take the
