@@ -144,21 +144,36 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
   // a grid walked by rows (its own kernels): every wave's points lie in one row; where its
   // kernels do not exist for the plan the general kernels take the grid's points
   // (NX_TUNE_GRID=1 sends every grid to the general kernels)
-  const int rows_lane = grid == 4 ? 4 : grid == 3 ? 2 : 1;   // points per lane over rows
-  if (grid >= 3) grid = 2;
+  const int shape_ok = grid >= 2 ? grid - 2 : 0;   // counts that allow a 2 along i1, i2, i3
+  if (grid >= 2) grid = 2;
   if (grid == 2 && env_i64("NX_TUNE_GRID", -1) == 1) grid = 1;
   // a grid's forward: LDS tiles and the fixed-point reduction, the forms built to walk
   // grid rows (grid 2) or to form each lane's FP64 grid point (grid 1), whatever the knobs
-  // say; over rows of a multiple of 128 points two consecutive points per lane, over such
-  // rows in pairs a 2 x 2 block (the others' phase factors stepped from the first's;
-  // NX_TUNE_P=1 or 2 caps the points per lane), else one
+  // say.  Over grid rows a block of points per lane, two along i1 where n1 is a multiple
+  // of 128, two along i2 where n2 is even, two along i3 where n3 is even too (the others'
+  // phase factors stepped from the first's): up to 2 x 2 x 2 with 16-atom groups, at most
+  // two points with 8-atom groups (the larger blocks exist with 16 only); NX_TUNE_P=1, 2 or
+  // 4 caps the points per lane (dropping i3, then i2, then i1)
   if (grid != 0 && fwd && p.mode == kPH64) {
-    const int64_t tp = env_i64("NX_TUNE_P", -1);
-    p.per_lane = grid == 2 ? ((tp == 1 || tp == 2) ? std::min<int>(int(tp), rows_lane) : rows_lane) : 1;
     p.red = 2;
     p.lds = 1;
     if (p.grp != 8) p.grp = 16;
-    if (p.per_lane == 4 && p.grp != 16) p.per_lane = 2;     // (the block form has 16-atom groups)
+    p.blk_a = p.blk_b = p.blk_c = 1;
+    if (grid == 2) {
+      p.blk_a = (shape_ok & 1) ? 2 : 1;
+      p.blk_b = (shape_ok & 2) ? 2 : 1;
+      p.blk_c = ((shape_ok & 4) && p.blk_b == 2) ? 2 : 1;
+      const int64_t tp = env_i64("NX_TUNE_P", -1);
+      const int cap = (tp == 1 || tp == 2 || tp == 4) ? int(tp) : 8;
+      const int limit = std::min(cap, p.grp == 16 ? 8 : 2);
+      while (p.blk_a * p.blk_b * p.blk_c > limit) {
+        if (p.blk_c == 2) p.blk_c = 1;
+        else if (p.blk_b == 2 && p.blk_a == 2) p.blk_b = 1;
+        else if (p.blk_a == 2) p.blk_a = 1;
+        else p.blk_b = 1;
+      }
+    }
+    p.per_lane = p.blk_a * p.blk_b * p.blk_c;
   }
   // the fixed-point reduction checks its range per LDS tile: the scalar-load forms (and
   // the forward's 32-atom groups, which have no LDS form) take the centred one, and so do
@@ -171,7 +186,10 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
     p.red = 0;
   if (grid == 2 && !(p.mode == kPH64 && p.red == 2 && p.lds && (fwd || p.grp == 64)))
     grid = 1;
-  if (grid == 1 && fwd) p.per_lane = 1;
+  if (grid == 1 && fwd) {
+    p.per_lane = 1;
+    p.blk_a = p.blk_b = p.blk_c = 1;
+  }
   p.grid = p.mode == kPH64 ? grid : 0;
   const int64_t per_block = int64_t(kThreads) * p.per_lane;
   p.blocks = p.lanes > 0 ? ceil_div(p.lanes, per_block) : 0;
@@ -340,11 +358,12 @@ nx::GridDef grid_def(const nx_grid* g) {
   return d;
 }
 
-// The grid kernels walk rows of n1 points; they need n1 to be a multiple of 64 (3: of 128,
-// where the forward takes two points per lane; 4: of 128 with n2 even, a 2 x 2 block).
+// The grid kernels walk rows of n1 points; they need n1 to be a multiple of 64.  The kind
+// passed to make_plan: 1 (general kernels) or 2 + the counts that allow two points per
+// lane along i1 (1: n1 a multiple of 128), i2 (2: n2 even) and i3 (4: n3 even).
 int grid_kind(const nx_grid* g) {
-  if (g->n1 % 128 == 0) return g->n2 % 2 == 0 ? 4 : 3;
-  return g->n1 % 64 == 0 ? 2 : 1;
+  if (g->n1 % 64 != 0) return 1;
+  return 2 + ((g->n1 % 128 == 0) ? 1 : 0) + ((g->n2 % 2 == 0) ? 2 : 0) + ((g->n3 % 2 == 0) ? 4 : 0);
 }
 
 // The launch sequence of run_sum over the points of a grid (FP64-phase mode): grid records

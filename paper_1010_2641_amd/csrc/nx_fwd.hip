@@ -547,8 +547,8 @@ __global__ __launch_bounds__(kThreads) void pack_atoms_grid_kernel(const float* 
       r.m = a.m;
       r.ck = a.ck;
       r.sk = a.sk;
-      // exp(2 i pi c) - 1 = (-2 sin^2 pi t, sin 2 pi t), t = c mod 1, for c1 and c2,
-      // rounded without bias (keys of their own: j with a tag 1..4 in bits 60-62)
+      // exp(2 i pi c) - 1 = (-2 sin^2 pi t, sin 2 pi t), t = c mod 1, for c1, c2 and c3,
+      // rounded without bias (keys of their own: j with a tag 1..6 in bits 60-62)
       const uint64_t key = static_cast<uint64_t>(j);
       const double t1 = r.c1 - __builtin_rint(r.c1), h1 = sinpi(t1);
       const double t2 = r.c2 - __builtin_rint(r.c2), h2 = sinpi(t2);
@@ -556,6 +556,11 @@ __global__ __launch_bounds__(kThreads) void pack_atoms_grid_kernel(const float* 
       r.wi = round_unbiased_signed(sinpi(2.0 * t1), key | (2ull << 60));
       r.vr = round_unbiased_signed(-2.0 * h2 * h2, key | (3ull << 60));
       r.vi = round_unbiased_signed(sinpi(2.0 * t2), key | (4ull << 60));
+      const double t3 = r.c3 - __builtin_rint(r.c3), h3 = sinpi(t3);
+      r.xr = round_unbiased_signed(-2.0 * h3 * h3, key | (5ull << 60));
+      r.xi = round_unbiased_signed(sinpi(2.0 * t3), key | (6ull << 60));
+      r.pad0 = 0.f;
+      r.pad1 = 0.f;
       am = fmaxf(bound_abs(a.x), fmaxf(bound_abs(a.y), bound_abs(a.z)));
     }
     am = wave_max(am);
@@ -572,328 +577,110 @@ __global__ __launch_bounds__(kThreads) void pack_atoms_grid_kernel(const float* 
   }
 }
 
-// FP64-phase forward over a grid whose rows hold a multiple of 64 points, one point per
-// lane: every wave's 64 points lie in one row (i2, i3), at i1 = i1_0 .. i1_0 + 63.  The phase
-// of atom j at point (i1, i2, i3) is i1 c1_j + b_j,row with the row term b = c0 + i2 c2 + i3 c3:
-// the thread that stages atom j into the LDS tile forms b for the rows of the work-group's
-// 4 waves (two fma each), and every pair then costs one FP64 fma instead of three.  Groups,
-// quads, eighth turns and compensation are those of fwd_lds_kernel; the reduction is the
-// fixed-point read, with the per-tile range check (the lane's |S|_1 and that of its row
-// part o + i2 e2 + i3 e3, so that the row term stays in range too) and variant 3 for tiles
-// out of range.  Built for 8 waves per SIMD (62 VGPRs, no spills).
-template <int FK, int GRP>
-__global__ __launch_bounds__(kThreads, 8) void fwd_grid_kernel(
-    const AtomGrid* __restrict__ rec, int a_begin, int a_end, int per_split, GridDef g, int64_t K,
-    int blocks_k, float4* __restrict__ part, float2* __restrict__ A, int carry_in, int direct) {
-  static_assert(kThreads % GRP == 0, "tiles must hold whole groups");
-  struct Tile { double c1; float m, ck, sk, rmax; };   // 24 B
-  __shared__ Tile tile[kThreads];
-  __shared__ double rowb[kThreads / 64][kThreads];   // the row term per wave and atom
-  const int lb = xcd_major_block(blockIdx.x, gridDim.x);
-  const int kb = lb % blocks_k;
-  const int sp = lb / blocks_k;
-  const int wave = threadIdx.x >> 6;
-  const int64_t k = int64_t(kb) * kThreads + threadIdx.x;
-  const int64_t kk = k < K ? k : K - 1;
-  const double di1 = static_cast<double>(static_cast<uint32_t>(kk) % static_cast<uint32_t>(g.n1));
-  float s1;
-  {
-    double S3[3], R3[3];
-    grid_point(g, kk, S3, R3);
-    s1 = fmaxf(bound_abs(fabs(S3[0]) + fabs(S3[1]) + fabs(S3[2])),
-               bound_abs(fabs(R3[0]) + fabs(R3[1]) + fabs(R3[2])));
-  }
-  // the rows of the work-group's waves (that of each wave's first point)
-  double d2w[kThreads / 64], d3w[kThreads / 64];
-#pragma unroll
-  for (int w = 0; w < kThreads / 64; ++w) {
-    int64_t kw = int64_t(kb) * kThreads + 64 * w;
-    if (kw > K - 1) kw = K - 1;
-    const uint32_t row = static_cast<uint32_t>(kw) / static_cast<uint32_t>(g.n1);
-    d2w[w] = static_cast<double>(row % static_cast<uint32_t>(g.n2));
-    d3w[w] = static_cast<double>(row / static_cast<uint32_t>(g.n2));
-  }
-  float sr = 0.f, si = 0.f, cr = 0.f, ci = 0.f;
-  if (carry_in && k < K) {
-    const float4 st = part[int64_t(sp) * K + k];
-    sr = st.x; si = st.y; cr = st.z; ci = st.w;
-  }
-  auto run_tile = [&](auto red_c, int nt) {
-    constexpr int R = decltype(red_c)::value;
-    const double* bw = rowb[wave];
-    int u0 = 0;
-    for (; u0 + GRP <= nt; u0 += GRP) {
-      const float ck = tile[u0].ck, sk = tile[u0].sk;
-      float gr = 0.f, gi = 0.f;
-#pragma unroll
-      for (int q = 0; q < GRP / 4; ++q) {
-        float qr = 0.f, qi = 0.f;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int uu = u0 + 4 * q + u;
-          const double ph = __builtin_fma(di1, tile[uu].c1, bw[uu]);
-          float c, s;
-          cis_turn<R>(ph, c, s);
-          const float m = tile[uu].m;
-          if constexpr (FK == 0) {
-            if (u == 0) { qr = c; qi = s; } else { qr += c; qi += s; }
-          } else {
-            if (u == 0) { qr = m * c; qi = m * s; }
-            else { qr = __builtin_fmaf(m, c, qr); qi = __builtin_fmaf(m, s, qi); }
-          }
-        }
-        if (q == 0) { gr = qr; gi = qi; } else { gr += qr; gi += qi; }
-      }
-      kahan_rot(sr, cr, si, ci, gr, gi, ck, sk);
-    }
-    if (u0 < nt) {    // the split's last, partial group
-      const float ck = tile[u0].ck, sk = tile[u0].sk;
-      float gr = 0.f, gi = 0.f;
-      for (int uu = u0; uu < nt; ++uu) {
-        const double ph = __builtin_fma(di1, tile[uu].c1, bw[uu]);
-        float c, s;
-        cis_turn<R>(ph, c, s);
-        if constexpr (FK == 0) {
-          gr += c;
-          gi += s;
-        } else {
-          const float m = tile[uu].m;
-          gr = __builtin_fmaf(m, c, gr);
-          gi = __builtin_fmaf(m, s, gi);
-        }
-      }
-      kahan_rot(sr, cr, si, ci, gr, gi, ck, sk);
-    }
-  };
-  const int j0 = a_begin + sp * per_split;
-  const int j1 = min(j0 + per_split, a_end);
-  for (int t0 = j0; t0 < j1; t0 += kThreads) {
-    const int nt = min(kThreads, j1 - t0);
-    __syncthreads();                        // the previous tile is no longer read
-    if (int(threadIdx.x) < nt) {
-      const AtomGrid a = rec[t0 + threadIdx.x];
-      tile[threadIdx.x] = Tile{a.c1, a.m, a.ck, a.sk, a.rmax};
-#pragma unroll
-      for (int w = 0; w < kThreads / 64; ++w)
-        rowb[w][threadIdx.x] = __builtin_fma(d3w[w], a.c3, __builtin_fma(d2w[w], a.c2, a.c0));
-    }
-    __syncthreads();
-    const float rt = fmaxf(tile[0].rmax, tile[nt - 1].rmax);
-    if (__all(s1 * rt < kFixedPhaseBound)) run_tile(std::integral_constant<int, 2>{}, nt);
-    else run_tile(std::integral_constant<int, 3>{}, nt);
-  }
-  if (k < K) {
-    if (direct) A[k] = make_float2(sr + cr, si + ci);
-    else part[int64_t(sp) * K + k] = make_float4(sr, si, cr, ci);
-  }
+// FP64-phase forward over a grid whose rows hold a multiple of 64 points, a block of
+// BA x BB x BC points per lane: (i1 + a, i2 + b, i3 + c), 0 <= a < BA, 0 <= b < BB,
+// 0 <= c < BC (each 1 or 2), with i1 a multiple of BA, i2 of BB and i3 of BC.  Each wave
+// covers 64 BA consecutive points of BB x BC rows (task t = 4 (work-group) + wave: segment
+// t % (n1 / (64 BA)) of row block t / (n1 / (64 BA)); waves past the last task compute
+// nothing that is written).
+//
+// The phase of atom j at point (i1, i2, i3) is i1 c1_j + b_j with the base row's term
+// b = c0 + i2 c2 + i3 c3: the thread that stages atom j into the LDS tile forms b for the
+// base rows of the work-group's 4 waves (two fma each; the rows' indices sit in LDS, not in
+// registers), so the first point's phase is one FP64 fma instead of three.  Its phase
+// factor E comes from the fixed-point read and hardware cos and sin; the block's other
+// points take theirs by steps, E + E (s - 1) in FP32 (four fma) with the atom's steps
+// w - 1, v - 1, x - 1 (along the row, to i2 + 1, to i3 + 1) from its record: (a, b, c) from
+// (a, b, c - 1) by x, else from (a, b - 1, 0) by v, else from (a - 1, 0, 0) by w, at most
+// three steps from E.  Groups, quads, eighth turns and compensation per point are those of
+// fwd_lds_kernel; the range check covers every point of the block (its |S|_1 and that of
+// its row parts o + i2 e2 + i3 e3, so that the row term stays in range too) and takes
+// variant 3 for tiles out of range.  Built for 8 waves per SIMD with one point per lane or
+// two with 16-atom groups, 5 for two with 8-atom groups or four, 3 for eight (no spills).
+constexpr int block_waves(int grp, int p) {
+  return p == 1 ? 8 : p == 2 ? (grp == 16 ? 8 : 5) : p == 4 ? 5 : 3;
 }
 
-// The forward over rows of a multiple of 128 points with two consecutive points per
-// lane, i1 and i1 + 1 (each wave covers 128 points of one row): the first point's phase
-// factor E = exp(2 i pi psi) comes as in fwd_grid_kernel (FP64 phase, the fixed-point
-// read, hardware cos and sin), the second's is E + E (w - 1) with the atom's row step
-// w - 1 from its record (four FP32 fma in place of the phase, the reduction and two
-// transcendentals).  Groups, quads, eighth turns and compensation per point as in
-// fwd_grid_kernel; the range check covers both points.  Built for 8 waves per SIMD with
-// 16-atom groups (62 VGPRs), 5 with 8-atom groups (88).
-template <int FK, int GRP>
-__global__ __launch_bounds__(kThreads, GRP == 16 ? 8 : 5) void fwd_rows2_kernel(
+template <int FK, int GRP, int BA, int BB, int BC>
+__global__ __launch_bounds__(kThreads, block_waves(GRP, BA * BB * BC)) void fwd_block_kernel(
     const AtomGrid* __restrict__ rec, int a_begin, int a_end, int per_split, GridDef g, int64_t K,
     int blocks_k, float4* __restrict__ part, float2* __restrict__ A, int carry_in, int direct) {
   static_assert(kThreads % GRP == 0, "tiles must hold whole groups");
-  struct Tile { double c1; float m, ck, sk, rmax, wr, wi; };   // 32 B
+  constexpr int P = BA * BB * BC;
+  // the tile holds the steps the shape uses, in the order w, v, x (32 or 48 B per atom:
+  // with every step in every shape's record the compiler kept up to twice the registers)
+  constexpr int NS = (BA == 2) + (BB == 2) + (BC == 2);
+  // (the index of a step the shape does not take is 0: those branches never run)
+  constexpr int IW = 0, IV = BB == 2 ? (BA == 2) : 0, IX = BC == 2 ? (BA == 2) + (BB == 2) : 0;
+  struct alignas(16) Tile { double c1; float m, ck, sk, rmax; float st[NS > 0 ? NS : 1][2]; };
   __shared__ Tile tile[kThreads];
-  __shared__ double rowb[kThreads / 64][kThreads];   // the row term per wave and atom
-  __shared__ double rowd[kThreads / 64][2];          // (i2, i3) of the waves' rows
-  const int lb = xcd_major_block(blockIdx.x, gridDim.x);
-  const int kb = lb % blocks_k;
-  const int sp = lb / blocks_k;
-  const int wave = threadIdx.x >> 6;
-  // the lane's points k and k + 1 (K is a multiple of 128, so both exist or neither)
-  const int64_t kbase = int64_t(kb) * (2 * kThreads);
-  const int64_t k = kbase + 128 * wave + 2 * (threadIdx.x & 63);
-  const int64_t kk = k < K ? k : K - 2;
-  const double di1 = static_cast<double>(static_cast<uint32_t>(kk) % static_cast<uint32_t>(g.n1));
-  float s1;
-  {
-    double S3[3], R3[3], T3[3];
-    grid_point(g, kk, S3, R3);
-    grid_point(g, kk + 1, T3, R3);
-    s1 = fmaxf(fmaxf(bound_abs(fabs(S3[0]) + fabs(S3[1]) + fabs(S3[2])),
-                     bound_abs(fabs(T3[0]) + fabs(T3[1]) + fabs(T3[2]))),
-               bound_abs(fabs(R3[0]) + fabs(R3[1]) + fabs(R3[2])));
-  }
-  // the rows of the work-group's waves, to LDS (read where the tiles are staged)
-  if ((threadIdx.x & 63) == 0) {
-    int64_t kw = kbase + 128 * wave;
-    if (kw > K - 1) kw = K - 1;
-    const uint32_t row = static_cast<uint32_t>(kw) / static_cast<uint32_t>(g.n1);
-    rowd[wave][0] = static_cast<double>(row % static_cast<uint32_t>(g.n2));
-    rowd[wave][1] = static_cast<double>(row / static_cast<uint32_t>(g.n2));
-  }
-  float sr[2], si[2], cr[2], ci[2];
-#pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    sr[p] = si[p] = cr[p] = ci[p] = 0.f;
-    if (carry_in && k < K) {
-      const float4 st = part[int64_t(sp) * K + k + p];
-      sr[p] = st.x; si[p] = st.y; cr[p] = st.z; ci[p] = st.w;
-    }
-  }
-  // one atom against both points: the first point's factor from the phase, the second's
-  // stepped; the terms (m-weighted for complex f) into (r0, i0) and (r1, i1)
-  auto pair2 = [&](auto red_c, int uu, float& r0, float& i0, float& r1, float& i1, bool first) {
-    constexpr int R = decltype(red_c)::value;
-    const double ph = __builtin_fma(di1, tile[uu].c1, rowb[wave][uu]);
-    float c, s;
-    cis_turn<R>(ph, c, s);
-    const float wr = tile[uu].wr, wi = tile[uu].wi;
-    const float c2 = __builtin_fmaf(c, wr, __builtin_fmaf(-s, wi, c));
-    const float s2 = __builtin_fmaf(c, wi, __builtin_fmaf(s, wr, s));
-    if constexpr (FK == 0) {
-      if (first) { r0 = c; i0 = s; r1 = c2; i1 = s2; }
-      else { r0 += c; i0 += s; r1 += c2; i1 += s2; }
-    } else {
-      const float m = tile[uu].m;
-      if (first) { r0 = m * c; i0 = m * s; r1 = m * c2; i1 = m * s2; }
-      else {
-        r0 = __builtin_fmaf(m, c, r0); i0 = __builtin_fmaf(m, s, i0);
-        r1 = __builtin_fmaf(m, c2, r1); i1 = __builtin_fmaf(m, s2, i1);
-      }
-    }
-  };
-  auto run_tile = [&](auto red_c, int nt) {
-    int u0 = 0;
-    for (; u0 + GRP <= nt; u0 += GRP) {
-      const float ck = tile[u0].ck, sk = tile[u0].sk;
-      float gr0 = 0.f, gi0 = 0.f, gr1 = 0.f, gi1 = 0.f;
-#pragma unroll
-      for (int q = 0; q < GRP / 4; ++q) {
-        float qr0, qi0, qr1, qi1;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) pair2(red_c, u0 + 4 * q + u, qr0, qi0, qr1, qi1, u == 0);
-        if (q == 0) { gr0 = qr0; gi0 = qi0; gr1 = qr1; gi1 = qi1; }
-        else { gr0 += qr0; gi0 += qi0; gr1 += qr1; gi1 += qi1; }
-      }
-      kahan_rot(sr[0], cr[0], si[0], ci[0], gr0, gi0, ck, sk);
-      kahan_rot(sr[1], cr[1], si[1], ci[1], gr1, gi1, ck, sk);
-    }
-    if (u0 < nt) {    // the split's last, partial group
-      const float ck = tile[u0].ck, sk = tile[u0].sk;
-      float gr0 = 0.f, gi0 = 0.f, gr1 = 0.f, gi1 = 0.f;
-      for (int uu = u0; uu < nt; ++uu) {
-        float r0, i0, r1, i1;
-        pair2(red_c, uu, r0, i0, r1, i1, true);
-        gr0 += r0; gi0 += i0; gr1 += r1; gi1 += i1;
-      }
-      kahan_rot(sr[0], cr[0], si[0], ci[0], gr0, gi0, ck, sk);
-      kahan_rot(sr[1], cr[1], si[1], ci[1], gr1, gi1, ck, sk);
-    }
-  };
-  const int j0 = a_begin + sp * per_split;
-  const int j1 = min(j0 + per_split, a_end);
-  for (int t0 = j0; t0 < j1; t0 += kThreads) {
-    const int nt = min(kThreads, j1 - t0);
-    __syncthreads();                        // the previous tile is no longer read
-    if (int(threadIdx.x) < nt) {
-      const AtomGrid a = rec[t0 + threadIdx.x];
-      tile[threadIdx.x] = Tile{a.c1, a.m, a.ck, a.sk, a.rmax, a.wr, a.wi};
-#pragma unroll
-      for (int w = 0; w < kThreads / 64; ++w)
-        rowb[w][threadIdx.x] = __builtin_fma(rowd[w][1], a.c3, __builtin_fma(rowd[w][0], a.c2, a.c0));
-    }
-    __syncthreads();
-    const float rt = fmaxf(tile[0].rmax, tile[nt - 1].rmax);
-    if (__all(s1 * rt < kFixedPhaseBound)) run_tile(std::integral_constant<int, 2>{}, nt);
-    else run_tile(std::integral_constant<int, 3>{}, nt);
-  }
-  if (k < K) {
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      if (direct) A[k + p] = make_float2(sr[p] + cr[p], si[p] + ci[p]);
-      else part[int64_t(sp) * K + k + p] = make_float4(sr[p], si[p], cr[p], ci[p]);
-    }
-  }
-}
-
-// The forward over rows of a multiple of 128 points taken in pairs (n2 even), a 2 x 2
-// block of points per lane: (i1, i2), (i1 + 1, i2), (i1, i2 + 1), (i1 + 1, i2 + 1) with i2
-// even; each wave covers 128 points of an even row and the same points of the next row.
-// The first point's phase factor E comes as in fwd_grid_kernel, the others' are stepped:
-// E w, E v and E w v, with the atom's steps w - 1 (along the row) and v - 1 (to the next
-// row) from its record, E + E (w - 1) etc. in FP32 (three steps of four fma in place of
-// three phases, reductions and six transcendentals).  Groups, quads, eighth turns and
-// compensation per point as in fwd_grid_kernel; the range check covers the four points.
-// Work of a wave: task t = 4 (work-group) + wave, segment t % (n1 / 128) of row pair
-// t / (n1 / 128); waves past the last task compute nothing that is written.  Built for 5
-// waves per SIMD (85 VGPRs, no spills; 6 would spill).
-template <int FK, int GRP>
-__global__ __launch_bounds__(kThreads, 5) void fwd_rows4_kernel(
-    const AtomGrid* __restrict__ rec, int a_begin, int a_end, int per_split, GridDef g, int64_t K,
-    int blocks_k, float4* __restrict__ part, float2* __restrict__ A, int carry_in, int direct) {
-  static_assert(kThreads % GRP == 0, "tiles must hold whole groups");
-  struct Tile { double c1; float m, ck, sk, rmax, wr, wi, vr, vi, pad0, pad1; };   // 48 B
-  __shared__ Tile tile[kThreads];
-  __shared__ double rowb[kThreads / 64][kThreads];   // the even row's term per wave and atom
-  __shared__ double rowd[kThreads / 64][2];          // (i2, i3) of the waves' even rows
+  __shared__ double rowb[kThreads / 64][kThreads];   // the base row's term per wave and atom
+  __shared__ double rowd[kThreads / 64][2];          // (i2, i3) of the waves' base rows
   const int lb = xcd_major_block(blockIdx.x, gridDim.x);
   const int kb = lb % blocks_k;
   const int sp = lb / blocks_k;
   const int wave = threadIdx.x >> 6;
   const uint32_t n1 = static_cast<uint32_t>(g.n1), n2 = static_cast<uint32_t>(g.n2);
-  const uint32_t segs = n1 / 128, ntask = static_cast<uint32_t>(K / 256);
-  // the wave's task (the last task for waves past the end); the rows of the work-group's
-  // waves go to LDS, read where the tiles are staged (in registers they would hold 16
-  // VGPRs through the loop)
-  uint32_t k00;
+  const uint32_t segs = n1 / (64 * BA), ntask = static_cast<uint32_t>(K / (64 * P));
+  uint32_t k0;
   {
     uint32_t t = static_cast<uint32_t>(kb) * 4 + wave;
     if (t >= ntask) t = ntask - 1;
-    const uint32_t pair = t / segs, seg = t - pair * segs;
-    const uint32_t i3 = pair / (n2 / 2), i2 = 2 * (pair - i3 * (n2 / 2));
-    k00 = seg * 128 + 2 * (threadIdx.x & 63) + n1 * (i2 + n2 * i3);
+    const uint32_t rb = t / segs, seg = t - rb * segs;
+    const uint32_t nb2 = n2 / BB;
+    const uint32_t i3 = BC * (rb / nb2), i2 = BB * (rb - (rb / nb2) * nb2);
+    k0 = seg * (64 * BA) + BA * (threadIdx.x & 63) + n1 * (i2 + n2 * i3);
     if ((threadIdx.x & 63) == 0) {
       rowd[wave][0] = static_cast<double>(i2);
       rowd[wave][1] = static_cast<double>(i3);
     }
   }
   const bool live = static_cast<uint32_t>(kb) * 4 + wave < ntask;
-  const uint32_t kp[4] = {k00, k00 + 1, k00 + n1, k00 + n1 + 1};
-  const double di1 = static_cast<double>(k00 % n1);
+  uint32_t kp[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int a = p % BA, b = (p / BA) % BB, c = p / (BA * BB);
+    kp[p] = k0 + a + n1 * (b + n2 * c);
+  }
+  const double di1 = static_cast<double>(k0 % n1);
   float s1 = 0.f;
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
+  for (int p = 0; p < P; ++p) {
     double S3[3], R3[3];
     grid_point(g, kp[p], S3, R3);
     s1 = fmaxf(s1, fmaxf(bound_abs(fabs(S3[0]) + fabs(S3[1]) + fabs(S3[2])),
                          bound_abs(fabs(R3[0]) + fabs(R3[1]) + fabs(R3[2]))));
   }
-  float sr[4], si[4], cr[4], ci[4];
+  float sr[P], si[P], cr[P], ci[P];
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
+  for (int p = 0; p < P; ++p) {
     sr[p] = si[p] = cr[p] = ci[p] = 0.f;
     if (carry_in && live) {
       const float4 st = part[int64_t(sp) * K + kp[p]];
       sr[p] = st.x; si[p] = st.y; cr[p] = st.z; ci[p] = st.w;
     }
   }
-  // one atom against the four points; the terms (m-weighted for complex f) into (r[p], i[p])
-  auto quad4 = [&](auto red_c, int uu, float* r, float* im, bool first) {
+  // one atom against the block's points; the terms (m-weighted for complex f) into
+  // (r[p], im[p])
+  auto block_terms = [&](auto red_c, int uu, float* r, float* im, bool first) {
     constexpr int R = decltype(red_c)::value;
     const double ph = __builtin_fma(di1, tile[uu].c1, rowb[wave][uu]);
-    float z[4][2];
+    float z[P][2];
     cis_turn<R>(ph, z[0][0], z[0][1]);
-    const float wr = tile[uu].wr, wi = tile[uu].wi, vr = tile[uu].vr, vi = tile[uu].vi;
     // z <- z + z (s - 1) for a step s - 1 = (sr_, si_)
-    auto step = [](const float* a, float sr_, float si_, float* b) {
-      b[0] = __builtin_fmaf(a[0], sr_, __builtin_fmaf(-a[1], si_, a[0]));
-      b[1] = __builtin_fmaf(a[0], si_, __builtin_fmaf(a[1], sr_, a[1]));
+    auto step = [](const float* q, float sr_, float si_, float* o) {
+      o[0] = __builtin_fmaf(q[0], sr_, __builtin_fmaf(-q[1], si_, q[0]));
+      o[1] = __builtin_fmaf(q[0], si_, __builtin_fmaf(q[1], sr_, q[1]));
     };
-    step(z[0], wr, wi, z[1]);
-    step(z[0], vr, vi, z[2]);
-    step(z[1], vr, vi, z[3]);
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 1; p < P; ++p) {
+      const int a = p % BA, b = (p / BA) % BB, c = p / (BA * BB);
+      if (c > 0) step(z[p - BA * BB], tile[uu].st[IX][0], tile[uu].st[IX][1], z[p]);
+      else if (b > 0) step(z[p - BA], tile[uu].st[IV][0], tile[uu].st[IV][1], z[p]);
+      else if (a > 0) step(z[p - 1], tile[uu].st[IW][0], tile[uu].st[IW][1], z[p]);
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
       if constexpr (FK == 0) {
         if (first) { r[p] = z[p][0]; im[p] = z[p][1]; }
         else { r[p] += z[p][0]; im[p] += z[p][1]; }
@@ -908,32 +695,34 @@ __global__ __launch_bounds__(kThreads, 5) void fwd_rows4_kernel(
     int u0 = 0;
     for (; u0 + GRP <= nt; u0 += GRP) {
       const float ck = tile[u0].ck, sk = tile[u0].sk;
-      float gr[4], gi[4];
+      float gr[P], gi[P];
 #pragma unroll
       for (int q = 0; q < GRP / 4; ++q) {
-        float qr[4], qi[4];
+        float qr[P], qi[P];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) quad4(red_c, u0 + 4 * q + u, qr, qi, u == 0);
+        for (int u = 0; u < 4; ++u) block_terms(red_c, u0 + 4 * q + u, qr, qi, u == 0);
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
+        for (int p = 0; p < P; ++p) {
           if (q == 0) { gr[p] = qr[p]; gi[p] = qi[p]; }
           else { gr[p] += qr[p]; gi[p] += qi[p]; }
         }
       }
 #pragma unroll
-      for (int p = 0; p < 4; ++p) kahan_rot(sr[p], cr[p], si[p], ci[p], gr[p], gi[p], ck, sk);
+      for (int p = 0; p < P; ++p) kahan_rot(sr[p], cr[p], si[p], ci[p], gr[p], gi[p], ck, sk);
     }
     if (u0 < nt) {    // the split's last, partial group
       const float ck = tile[u0].ck, sk = tile[u0].sk;
-      float gr[4] = {0.f, 0.f, 0.f, 0.f}, gi[4] = {0.f, 0.f, 0.f, 0.f};
-      for (int uu = u0; uu < nt; ++uu) {
-        float r[4], im[4];
-        quad4(red_c, uu, r, im, true);
+      float gr[P], gi[P];
 #pragma unroll
-        for (int p = 0; p < 4; ++p) { gr[p] += r[p]; gi[p] += im[p]; }
+      for (int p = 0; p < P; ++p) { gr[p] = 0.f; gi[p] = 0.f; }
+      for (int uu = u0; uu < nt; ++uu) {
+        float r[P], im[P];
+        block_terms(red_c, uu, r, im, true);
+#pragma unroll
+        for (int p = 0; p < P; ++p) { gr[p] += r[p]; gi[p] += im[p]; }
       }
 #pragma unroll
-      for (int p = 0; p < 4; ++p) kahan_rot(sr[p], cr[p], si[p], ci[p], gr[p], gi[p], ck, sk);
+      for (int p = 0; p < P; ++p) kahan_rot(sr[p], cr[p], si[p], ci[p], gr[p], gi[p], ck, sk);
     }
   };
   const int j0 = a_begin + sp * per_split;
@@ -943,7 +732,17 @@ __global__ __launch_bounds__(kThreads, 5) void fwd_rows4_kernel(
     __syncthreads();                        // the previous tile is no longer read
     if (int(threadIdx.x) < nt) {
       const AtomGrid a = rec[t0 + threadIdx.x];
-      tile[threadIdx.x] = Tile{a.c1, a.m, a.ck, a.sk, a.rmax, a.wr, a.wi, a.vr, a.vi, 0.f, 0.f};
+      Tile t;
+      t.c1 = a.c1;
+      t.m = a.m;
+      t.ck = a.ck;
+      t.sk = a.sk;
+      t.rmax = a.rmax;
+      if constexpr (BA == 2) { t.st[IW][0] = a.wr; t.st[IW][1] = a.wi; }
+      if constexpr (BB == 2) { t.st[IV][0] = a.vr; t.st[IV][1] = a.vi; }
+      if constexpr (BC == 2) { t.st[IX][0] = a.xr; t.st[IX][1] = a.xi; }
+      if constexpr (NS == 0) { t.st[0][0] = 0.f; t.st[0][1] = 0.f; }
+      tile[threadIdx.x] = t;
 #pragma unroll
       for (int w = 0; w < kThreads / 64; ++w)
         rowb[w][threadIdx.x] = __builtin_fma(rowd[w][1], a.c3, __builtin_fma(rowd[w][0], a.c2, a.c0));
@@ -955,7 +754,7 @@ __global__ __launch_bounds__(kThreads, 5) void fwd_rows4_kernel(
   }
   if (live) {
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < P; ++p) {
       if (direct) A[kp[p]] = make_float2(sr[p] + cr[p], si[p] + ci[p]);
       else part[int64_t(sp) * K + kp[p]] = make_float4(sr[p], si[p], cr[p], ci[p]);
     }
@@ -1277,22 +1076,32 @@ hipError_t launch_fwd_chunk(const Plan& p, const void* rec, int64_t a_begin, int
     const auto* r = static_cast<const AtomGrid*>(rec);
     auto* pa = static_cast<float4*>(partial);
     auto* a = static_cast<float2*>(A);
+    // the block shape (p.blk_a, p.blk_b, p.blk_c); with 8-atom groups only the shapes of
+    // at most two points exist
     auto launch = [&](auto fk_c, auto grp_c) {
       constexpr int FK = decltype(fk_c)::value, GRP = decltype(grp_c)::value;
-      if constexpr (GRP == 16) {    // (the 2 x 2 block exists with 16-atom groups only)
-        if (p.per_lane == 4) {
-          fwd_rows4_kernel<FK, GRP><<<grid, kThreads, 0, st>>>(r, int(a_begin), int(a_end), int(per_split),
-                                                               *gd, p.lanes, int(p.blocks), pa, a, carry_in,
-                                                               direct);
-          return;
+      const int shape = (p.blk_a - 1) | ((p.blk_b - 1) << 1) | ((p.blk_c - 1) << 2);
+#define NX_BLOCK(BA, BB, BC)                                                                         \
+  fwd_block_kernel<FK, GRP, BA, BB, BC><<<grid, kThreads, 0, st>>>(r, int(a_begin), int(a_end),      \
+                                                                  int(per_split), *gd, p.lanes,      \
+                                                                  int(p.blocks), pa, a, carry_in, direct)
+      if constexpr (GRP == 16) {
+        switch (shape) {
+          case 1: NX_BLOCK(2, 1, 1); return;
+          case 2: NX_BLOCK(1, 2, 1); return;
+          case 3: NX_BLOCK(2, 2, 1); return;
+          case 6: NX_BLOCK(1, 2, 2); return;
+          case 7: NX_BLOCK(2, 2, 2); return;
+          default: NX_BLOCK(1, 1, 1); return;
+        }
+      } else {
+        switch (shape) {
+          case 1: NX_BLOCK(2, 1, 1); return;
+          case 2: NX_BLOCK(1, 2, 1); return;
+          default: NX_BLOCK(1, 1, 1); return;
         }
       }
-      if (p.per_lane == 2)
-        fwd_rows2_kernel<FK, GRP><<<grid, kThreads, 0, st>>>(r, int(a_begin), int(a_end), int(per_split), *gd,
-                                                             p.lanes, int(p.blocks), pa, a, carry_in, direct);
-      else
-        fwd_grid_kernel<FK, GRP><<<grid, kThreads, 0, st>>>(r, int(a_begin), int(a_end), int(per_split), *gd,
-                                                            p.lanes, int(p.blocks), pa, a, carry_in, direct);
+#undef NX_BLOCK
     };
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;

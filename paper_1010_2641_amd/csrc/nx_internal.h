@@ -84,11 +84,15 @@ struct GridDef {
 // addend (as in AtomPH), c0 = o.r + a and c_d = e_d.r, so that the phase of point
 // (i1, i2, i3) is i1 c1 + (c0 + i2 c2 + i3 c3); the bracket is one value per atom and grid
 // row.  m, ck, sk, rmax as in AtomPH.  (wr, wi) = exp(2 i pi c1) - 1, the step of the
-// phase factor from one point of a row to the next, and (vr, vi) = exp(2 i pi c2) - 1, from
-// one row to the next (i2 + 1), formed in FP64 and rounded to FP32 without bias
-// (stochastically, from a hash of the atom's index), so that the rounding errors of atoms
-// with equal c1 or c2 (a lattice plane) add up incoherently.
-struct alignas(16) AtomGrid { double c0, c1, c2, c3; float m, ck, sk, rmax, wr, wi, vr, vi; };  // 64 B
+// phase factor from one point of a row to the next, (vr, vi) = exp(2 i pi c2) - 1, from one
+// row to the next (i2 + 1), and (xr, xi) = exp(2 i pi c3) - 1 (i3 + 1), formed in FP64 and
+// rounded to FP32 without bias (stochastically, from a hash of the atom's index), so that
+// the rounding errors of atoms with equal c1, c2 or c3 (a lattice plane) add up
+// incoherently.
+struct alignas(16) AtomGrid {
+  double c0, c1, c2, c3;
+  float m, ck, sk, rmax, wr, wi, vr, vi, xr, xi, pad0, pad1;
+};  // 80 B
 // Adjoint over grid rows: along a row the phase factor of atom j steps by the constant
 // w_j = exp(2 i pi step1.r_j) from one point to the next, so each 64-point group (one
 // row's run) forms exp(2 i pi psi) exactly (FP64 phase, hardware cos and sin) at its first
@@ -182,6 +186,8 @@ struct Plan {
   int inl = 0;           // small calls: records formed in the sum kernel, no pack dispatch
   int grid = 0;          // points: 0 a list, 1 a grid (general kernels, FP64 points from the
                          // grid), 2 a grid walked by rows (the grid kernels)
+  int blk_a = 1, blk_b = 1, blk_c = 1;   // forward over grid rows: points per lane along
+                                         // i1, i2, i3 (per_lane = their product)
   int64_t lanes = 0;     // number of lane items
   int64_t stream = 0;    // number of stream items
   int64_t blocks = 0;    // work-groups over lane items
@@ -249,12 +255,13 @@ inline int reduce_lanes(int nsplit, int64_t outputs) {
 
 // Builds the plan of (op, mode) for the sizes; pure host code, no HIP call.  At most
 // max_split stream slices (kMaxSplit when omitted).
-// `grid`: 0 for a list of points; for a grid (FP64-phase mode), 2 asks for the grid kernels
-// (rows of n1 points, n1 a multiple of 64), 3 for them over rows of a multiple of 128
-// points (two points per lane in the forward), 4 over such rows in pairs (n2 even: a 2 x 2
-// block of points per lane in the forward), 1 for the general ones; the plan keeps the
-// grid kernels only where they exist for it (the fixed-point reduction; 64-point groups in
-// the adjoint) and holds the kind it chose in p.grid (2 or 1).
+// `grid`: 0 for a list of points; for a grid (FP64-phase mode), 1 asks for the general
+// kernels and 2 + s for the grid kernels over rows of n1 points (n1 a multiple of 64), where
+// the bits of s say which counts allow two points per lane in the forward's block: 1 for
+// n1 a multiple of 128, 2 for n2 even, 4 for n3 even.  The plan keeps the grid kernels
+// only where they exist for it (the fixed-point reduction; 64-point groups in the
+// adjoint), holds the kind it chose in p.grid (2 or 1) and the forward's block shape in
+// p.blk_a, p.blk_b, p.blk_c.
 Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_null,
                int64_t max_split = kMaxSplit, int grid = 0);
 

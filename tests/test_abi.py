@@ -389,7 +389,7 @@ def test_grid_fit_step_checks_before_queueing():
 
 
 def test_grid_workspace(monkeypatch):
-    """Rows of a multiple of 64 points: 64-byte atom records (forward); 16-byte point
+    """Rows of a multiple of 64 points: 80-byte atom records (forward); 16-byte point
     records (the seed and the point's place in its 64-point group) and one 16-byte record
     per group (its first point; adjoint), followed as in the point-list calls by the
     tiles' bounds; other grids take the point-list records (48 B).  Unknown ops are
@@ -401,21 +401,21 @@ def test_grid_workspace(monkeypatch):
     bwd_rows = _lib.nx_workspace_bytes_grid(n, ctypes.byref(g), _lib.NX_OP_BWD, 0)
     bwd_list = _lib.nx_workspace_bytes(n, k, 1, _lib.NX_OP_BWD, 0)
     assert bwd_list - bwd_rows == a256(k * 48) - a256(k * 16) - a256(k // 64 * 16)
-    # the forward: one point per lane, same records as the list
+    # the forward: 2 x 2 x 2 blocks of points per lane
     fw = _lib.nx_workspace_bytes_grid(n, ctypes.byref(g), _lib.NX_OP_FWD, 0)
-    assert fw % 256 == 0 and fw >= a256(n * 48)
+    assert fw % 256 == 0 and fw >= a256(n * 80)
     # a row of 50 points takes the general kernels and their records
     g50 = grid_struct(n1=50, n2=40, n3=3)
     assert (_lib.nx_workspace_bytes_grid(1000, ctypes.byref(g50), _lib.NX_OP_BWD, 1)
             == _lib.nx_workspace_bytes(1000, 6000, 1, _lib.NX_OP_BWD, 1))
-    # the forward over rows takes 64-byte atom records (with the row step), also for few
+    # the forward over rows takes 80-byte atom records (with the three steps), also for few
     # atoms (8-atom groups), against 48 bytes for the point-list kernels
     small = grid_struct(n1=256, n2=3, n3=2)
     rows_fw = _lib.nx_workspace_bytes_grid(5000, ctypes.byref(small), _lib.NX_OP_FWD, 0)
     # and every grid takes the point-list kernels under NX_TUNE_GRID=1
     monkeypatch.setenv("NX_TUNE_GRID", "1")
     list_fw = _lib.nx_workspace_bytes_grid(5000, ctypes.byref(small), _lib.NX_OP_FWD, 0)
-    assert rows_fw - list_fw == a256(5000 * 64) - a256(5000 * 48)
+    assert rows_fw - list_fw == a256(5000 * 80) - a256(5000 * 48)
     assert _lib.nx_workspace_bytes_grid(n, ctypes.byref(g), _lib.NX_OP_BWD, 0) == bwd_list
     assert _lib.nx_workspace_bytes_grid(8, ctypes.byref(g), 3, 1) == 0
     assert "op must be" in _lib.last_error()

@@ -85,14 +85,16 @@ def test_hot_kernels_occupancy(device_asm):
             "fwd_lds_kernelILi1ELi0ELi16ELi2ELb0E": 8,      # forward, f = 1
             "bwd_split_kernelILi2ELi1ELi64ELi2ELb0ELb0E": 6,    # adjoint, complex f
             "bwd_split_kernelILi2ELi0ELi64ELi2ELb0ELb0E": 6,    # adjoint, f = 1
-            # grids walked by rows: one point, two points, a 2 x 2 block per lane (forward);
-            # the stepped adjoint, two atoms per lane
-            "fwd_grid_kernelILi1ELi16E": 8,
-            "fwd_grid_kernelILi0ELi16E": 8,
-            "fwd_rows2_kernelILi1ELi16E": 8,
-            "fwd_rows2_kernelILi0ELi16E": 8,
-            "fwd_rows4_kernelILi1ELi16E": 5,
-            "fwd_rows4_kernelILi0ELi16E": 5,
+            # grids walked by rows: blocks of 1, 2, 4 and 8 points per lane (forward); the
+            # stepped adjoint, two atoms per lane
+            "fwd_block_kernelILi1ELi16ELi1ELi1ELi1E": 8,
+            "fwd_block_kernelILi1ELi16ELi2ELi1ELi1E": 8,
+            "fwd_block_kernelILi1ELi16ELi1ELi2ELi1E": 8,
+            "fwd_block_kernelILi1ELi16ELi2ELi2ELi1E": 5,
+            "fwd_block_kernelILi1ELi16ELi1ELi2ELi2E": 5,
+            "fwd_block_kernelILi1ELi16ELi2ELi2ELi2E": 3,
+            "fwd_block_kernelILi0ELi16ELi2ELi2ELi2E": 3,
+            "fwd_block_kernelILi1ELi8ELi2ELi1ELi1E": 5,
             "bwd_rows_kernelILi2ELi1E": 7,
             "bwd_rows_kernelILi2ELi0E": 7}
     for key, o in want.items():

@@ -46,8 +46,12 @@ def bwd(xyz, f, grid, G):
 
 
 SHAPES = [((128, 5, 3), 3001, True),      # rows of 128, n2 odd: two points per lane
-          ((128, 2, 3), 900, True),       # rows in pairs: 2 x 2 blocks; 3 of 4 waves busy
-          ((256, 4, 1), 20_000, False),   # 2 x 2 blocks, 16-atom groups
+          ((128, 2, 3), 900, True),       # rows in pairs (8-atom groups: two points per lane)
+          ((256, 4, 1), 20_000, False),   # 8-atom groups: two points per lane
+          ((128, 2, 2), 70_000, True),    # 16-atom groups, 2 x 2 x 2 blocks; 1 of 4 waves busy
+          ((256, 2, 3), 70_000, False),   # 2 x 2 blocks
+          ((64, 4, 2), 70_000, True),     # rows of 64: 1 x 2 x 2 blocks
+          ((64, 2, 3), 66_000, False),    # 1 x 2 blocks
           ((64, 5, 1), 777, False),       # 320 points: a partly filled last work-group
           ((64, 1, 1), 70_000, True),     # one row, many atoms: stream splits
           ((50, 7, 3), 2500, True),       # rows of 50: the point-list kernels
@@ -225,17 +229,18 @@ def test_c2_grid_fit_step_at_full_size():
 @pytest.mark.parametrize("step,n1,n2,atoms", [(0.0005, 128, 4, 24), (0.004, 128, 3, 24), (0.004, 128, 4, 24),
                                                (0.02, 256, 2, 24), (0.004, 128, 4, 44)])
 def test_lattice_maps_pointwise(step, n1, n2, atoms, monkeypatch):
-    """Perfect simple-cubic lattices (every atom of a plane shares step1.r and step2.r),
-    the case where a systematic rounding of the row steps would add up coherently: T1
-    against the oracle at the FP64 grid points with the stepped forms (2 x 2 blocks for n2
-    even, two points per lane for n2 odd) and with one point per lane (NX_TUNE_P=1), over
-    fine and coarse maps through (0, 0, 4); 44^3 atoms take 16-atom groups."""
+    """Perfect simple-cubic lattices (every atom of a plane shares step1.r, step2.r and
+    step3.r), the case where a systematic rounding of the steps would add up coherently: T1
+    against the oracle at the FP64 grid points with the stepped blocks (16-atom groups:
+    2 x 2 x 2 for n2 even, two points per lane for n2 odd) and with one point per lane
+    (NX_TUNE_P=1), over fine and coarse maps through (0, 0, 4)."""
     xyz = wl.cubic_sites(atoms, atoms, atoms).astype(np.float32)
     n = xyz.shape[0]
     grid = wl.RegularGrid((-0.5 * step * n1, 0.013, 3.98), (step, 0.0, 0.0), (0.0, 0.004, 0.0),
                           (0.0, 0.0, 0.01), n1, n2, 2)
     print(f"case lattice map: {n} atoms, step {step}, {n1} x {n2} x 2", flush=True)
     ref = oracle.forward(xyz, None, grid.points())
+    monkeypatch.setenv("NX_TUNE_GRP", "16")       # (few atoms would take 8-atom groups)
     A2 = fwd(xyz, None, grid)
     monkeypatch.setenv("NX_TUNE_P", "1")
     A1 = fwd(xyz, None, grid)
