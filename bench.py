@@ -71,16 +71,16 @@ ALG_SLOTS = {
     ("f32", "bwd", "complex"): 3 + 1 + 2 + 4 + 2 + 3,
     ("f32", "bwd", "unit"): 3 + 1 + 2 + 2 + 3,
     # grids walked by rows (FP64-phase mode), per pair on average:
-    #   forward, a 2 x 2 block of points per lane: per atom the first point's phase
+    #   forward, a 2 x 2 x 2 block of points per lane: per atom the first point's phase
     #     fma(i1, step1.r, b) (b the atom's row term, formed once per atom and row), the
-    #     fixed-point turn (2), cos and sin; the three other points' phase factors stepped
-    #     from it (3 steps of 4 fma); the four terms accumulated (2 each): 25 per 4 pairs
+    #     fixed-point turn (2), cos and sin; the seven other points' phase factors stepped
+    #     from it (7 steps of 4 fma); the eight terms accumulated (2 each): 49 per 8 pairs
     #   adjoint, 64-point groups, the phase factor stepped along the row: per atom and group
     #     the first point's factor (3 FP64 fma, 2, cos, sin) and the three S0 a0 + e1 a1 (2
     #     each); per pair v = Im(conj(G) E) (2), a0 and a1 (2) and the step (4, none after
     #     the group's last point): (7 + 6 + 64 * 4 + 63 * 4) / 64 per pair
-    ("grid", "fwd", "complex"): 25 / 4,
-    ("grid", "fwd", "unit"): 25 / 4,
+    ("grid", "fwd", "complex"): 49 / 8,
+    ("grid", "fwd", "unit"): 49 / 8,
     ("grid", "bwd", "complex"): (7 + 6 + 64 * 4 + 63 * 4) / 64,
     ("grid", "bwd", "unit"): (7 + 6 + 64 * 4 + 63 * 4) / 64,
 }

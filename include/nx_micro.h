@@ -52,8 +52,9 @@ typedef enum {
   NXM_OP_MUL_F32 = 18,   /*   v_mul_f32_e32 */
   NXM_OP_FMA_F32_V = 19, /*   FP32 fma, vector operands, three-operand encoding (v_fma_f32) */
   NXM_OP_ADD_F32 = 20,   /*   v_add_f32_e32 */
-  NXM_FWD_GRID_CF = 21,  /* forward over grid rows, complex f: 1 fma64, cvt_i32, mul, cos, sin, 2 fma */
-  NXM_FWD_GRID_F1 = 22,  /* forward over grid rows, f = 1: the same with 2 adds */
+  NXM_FWD_GRID_CF = 21,  /* forward over grid rows, 2 x 2 x 2 points: per atom 1 fma64, cvt_i32, mul, cos,
+                            sin, 7 steps (4 fma each), 8 x 2 fma */
+  NXM_FWD_GRID_F1 = 22,  /* the same for f = 1, 8 x 2 adds */
   NXM_BWD_GRID_CF = 23,  /* adjoint over grid rows: 1 fma64, add64, cvt_i32, mul, sin, 3 fma */
   NXM_BWD_GRID_F1 = 24   /* adjoint over grid rows, f = 1: the same sequence */
 } nxm_mix;

@@ -151,9 +151,11 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
   // grid rows (grid 2) or to form each lane's FP64 grid point (grid 1), whatever the knobs
   // say.  Over grid rows a block of points per lane, two along i1 where n1 is a multiple
   // of 128, two along i2 where n2 is even, two along i3 where n3 is even too (the others'
-  // phase factors stepped from the first's): up to 2 x 2 x 2 with 16-atom groups, at most
-  // two points with 8-atom groups (the larger blocks exist with 16 only); NX_TUNE_P=1, 2 or
-  // 4 caps the points per lane (dropping i3, then i2, then i1)
+  // phase factors stepped from the first's), with 16-atom groups; calls with few atoms
+  // (8-atom groups) are bound by latency, not issue, and keep one point per lane, where
+  // the steps would only add their rounding (C1: forward no faster with two points, T1
+  // 7.4e-6 against 6.6e-6).  NX_TUNE_P=1, 2 or 4 caps the points per lane (dropping i3,
+  // then i2, then i1)
   if (grid != 0 && fwd && p.mode == kPH64) {
     p.red = 2;
     p.lds = 1;
@@ -165,7 +167,7 @@ Plan make_plan(int op, int mode, int64_t n_atoms, int64_t n_points, int f_is_nul
       p.blk_c = ((shape_ok & 4) && p.blk_b == 2) ? 2 : 1;
       const int64_t tp = env_i64("NX_TUNE_P", -1);
       const int cap = (tp == 1 || tp == 2 || tp == 4) ? int(tp) : 8;
-      const int limit = std::min(cap, p.grp == 16 ? 8 : 2);
+      const int limit = std::min(cap, p.grp == 16 ? 8 : 1);
       while (p.blk_a * p.blk_b * p.blk_c > limit) {
         if (p.blk_c == 2) p.blk_c = 1;
         else if (p.blk_b == 2 && p.blk_a == 2) p.blk_b = 1;

@@ -595,14 +595,12 @@ __global__ __launch_bounds__(kThreads) void pack_atoms_grid_kernel(const float* 
 // three steps from E.  Groups, quads, eighth turns and compensation per point are those of
 // fwd_lds_kernel; the range check covers every point of the block (its |S|_1 and that of
 // its row parts o + i2 e2 + i3 e3, so that the row term stays in range too) and takes
-// variant 3 for tiles out of range.  Built for 8 waves per SIMD with one point per lane or
-// two with 16-atom groups, 5 for two with 8-atom groups or four, 3 for eight (no spills).
-constexpr int block_waves(int grp, int p) {
-  return p == 1 ? 8 : p == 2 ? (grp == 16 ? 8 : 5) : p == 4 ? 5 : 3;
-}
+// variant 3 for tiles out of range.  Built for 8 waves per SIMD with one or two points per
+// lane, 5 with four, 3 with eight (no spills).
+constexpr int block_waves(int p) { return p <= 2 ? 8 : p == 4 ? 5 : 3; }
 
 template <int FK, int GRP, int BA, int BB, int BC>
-__global__ __launch_bounds__(kThreads, block_waves(GRP, BA * BB * BC)) void fwd_block_kernel(
+__global__ __launch_bounds__(kThreads, block_waves(BA * BB * BC)) void fwd_block_kernel(
     const AtomGrid* __restrict__ rec, int a_begin, int a_end, int per_split, GridDef g, int64_t K,
     int blocks_k, float4* __restrict__ part, float2* __restrict__ A, int carry_in, int direct) {
   static_assert(kThreads % GRP == 0, "tiles must hold whole groups");
@@ -1076,8 +1074,7 @@ hipError_t launch_fwd_chunk(const Plan& p, const void* rec, int64_t a_begin, int
     const auto* r = static_cast<const AtomGrid*>(rec);
     auto* pa = static_cast<float4*>(partial);
     auto* a = static_cast<float2*>(A);
-    // the block shape (p.blk_a, p.blk_b, p.blk_c); with 8-atom groups only the shapes of
-    // at most two points exist
+    // the block shape (p.blk_a, p.blk_b, p.blk_c); with 8-atom groups one point per lane
     auto launch = [&](auto fk_c, auto grp_c) {
       constexpr int FK = decltype(fk_c)::value, GRP = decltype(grp_c)::value;
       const int shape = (p.blk_a - 1) | ((p.blk_b - 1) << 1) | ((p.blk_c - 1) << 2);
@@ -1095,11 +1092,9 @@ hipError_t launch_fwd_chunk(const Plan& p, const void* rec, int64_t a_begin, int
           default: NX_BLOCK(1, 1, 1); return;
         }
       } else {
-        switch (shape) {
-          case 1: NX_BLOCK(2, 1, 1); return;
-          case 2: NX_BLOCK(1, 2, 1); return;
-          default: NX_BLOCK(1, 1, 1); return;
-        }
+        (void)shape;
+        NX_BLOCK(1, 1, 1);
+        return;
       }
 #undef NX_BLOCK
     };

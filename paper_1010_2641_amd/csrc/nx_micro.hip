@@ -256,17 +256,17 @@ __global__ __launch_bounds__(kThreads, 8) void mix_bwd_ph64_tile(int iters, floa
 
 // The grid kernels' sequences (a grid walked by rows), in their own shapes.
 //
-// Forward, a 2 x 2 block of points per lane: per atom, the first point's phase
+// Forward, a 2 x 2 x 2 block of points per lane: per atom, the first point's phase
 // fma(i1, c1, b) (i1 the lane's index along the row, c1 = step1.r and b the atom's row
-// term, both shared by the wave), the fixed-point turn, cos and sin; the other three
-// points' phase factors stepped from it with the atom's steps w - 1 and v - 1 (three steps
-// of four fma); the four terms accumulated (two fma or adds each).  The shared operands
-// come from LDS in the kernel (vector registers): here the tile's row terms and steps stay
-// in vector registers and c1 is formed by the scalar unit, which changes it every
-// iteration (an addend from the scalar unit would have to be copied to vector registers
-// first: the accumulating form of the FP64 fma overwrites its addend).  4 atoms per
-// iteration.
-constexpr int kTileGrid = 4;
+// term, both shared by the wave), the fixed-point turn, cos and sin; the other seven
+// points' phase factors stepped from it with the atom's steps w - 1, v - 1 and x - 1
+// (seven steps of four fma); the eight terms accumulated (two fma or adds each).  The
+// shared operands come from LDS in the kernel (vector registers): here the tile's row
+// terms and steps stay in vector registers and c1 is formed by the scalar unit, which
+// changes it every iteration (an addend from the scalar unit would have to be copied to
+// vector registers first: the accumulating form of the FP64 fma overwrites its addend).
+// 2 atoms per iteration.
+constexpr int kTileGrid = 2;
 
 template <bool CF>
 __global__ __launch_bounds__(kThreads, 8) void mix_fwd_grid_tile(int iters, float* out, unsigned long long* clk) {
@@ -274,41 +274,44 @@ __global__ __launch_bounds__(kThreads, 8) void mix_fwd_grid_tile(int iters, floa
   cm.start();
   double di1 = static_cast<double>((threadIdx.x + blockIdx.x * kThreads) & 127);
   double b[kTileGrid];
-  float wr[kTileGrid], wi[kTileGrid], vr[kTileGrid], vi[kTileGrid];
+  float st[kTileGrid][3][2];
 #pragma unroll
   for (int t = 0; t < kTileGrid; ++t) {
     b[t] = kShift + 12.5 + 0.125 * t;
-    wr[t] = -1e-3f * (t + 1);
-    wi[t] = 4e-2f * (t + 1);
-    vr[t] = -2e-3f * (t + 1);
-    vi[t] = 6e-2f * (t + 1);
     opaque(b[t]);
-    opaque(wr[t]);
-    opaque(wi[t]);
-    opaque(vr[t]);
-    opaque(vi[t]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      st[t][d][0] = -1e-3f * (t + 1) * (d + 1);
+      st[t][d][1] = 4e-2f * (t + 1) + 1e-2f * d;
+      opaque(st[t][d][0]);
+      opaque(st[t][d][1]);
+    }
   }
   opaque(di1);
-  float ar[4] = {0.f, 0.f, 0.f, 0.f}, ai[4] = {0.f, 0.f, 0.f, 0.f};
+  float ar[8], ai[8];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) ar[p] = ai[p] = 0.f;
   for (int j = 0; j < iters; ++j) {
 #pragma unroll
     for (int t = 0; t < kTileGrid; ++t) {
       const double c1 = uniform_f64(0x3f340000u + (t << 8), 0x9999999au, j);   // ~3e-4
       const float m = uniform_f32(0x41f80000u + (t << 8), j);              // ~31
       const double ph = __builtin_fma(di1, c1, b[t]);
-      float z[4][2];
+      float z[8][2];
       const float tt = static_cast<float>(__double2loint(ph)) * 0x1.0p-32f;
       z[0][0] = __builtin_amdgcn_cosf(tt);
       z[0][1] = __builtin_amdgcn_sinf(tt);
-      auto step = [](const float* a, float sr, float si, float* c) {
-        c[0] = __builtin_fmaf(a[0], sr, __builtin_fmaf(-a[1], si, a[0]));
-        c[1] = __builtin_fmaf(a[0], si, __builtin_fmaf(a[1], sr, a[1]));
+      auto step = [](const float* a, const float* s, float* c) {
+        c[0] = __builtin_fmaf(a[0], s[0], __builtin_fmaf(-a[1], s[1], a[0]));
+        c[1] = __builtin_fmaf(a[0], s[1], __builtin_fmaf(a[1], s[0], a[1]));
       };
-      step(z[0], wr[t], wi[t], z[1]);
-      step(z[0], vr[t], vi[t], z[2]);
-      step(z[1], vr[t], vi[t], z[3]);
+      step(z[0], st[t][0], z[1]);
+      step(z[0], st[t][1], z[2]);
+      step(z[1], st[t][1], z[3]);
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
+      for (int p = 0; p < 4; ++p) step(z[p], st[t][2], z[p + 4]);
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
         if constexpr (CF) {
           ar[p] = __builtin_fmaf(m, z[p][0], ar[p]);
           ai[p] = __builtin_fmaf(m, z[p][1], ai[p]);
@@ -319,7 +322,10 @@ __global__ __launch_bounds__(kThreads, 8) void mix_fwd_grid_tile(int iters, floa
       }
     }
   }
-  out[threadIdx.x + blockIdx.x * kThreads] = ar[0] - ai[0] + ar[1] - ai[1] + ar[2] - ai[2] + ar[3] - ai[3];
+  float acc = 0.f;
+#pragma unroll
+  for (int p = 0; p < 8; ++p) acc += ar[p] - ai[p];
+  out[threadIdx.x + blockIdx.x * kThreads] = acc;
   cm.stop(clk);
 }
 
@@ -564,7 +570,7 @@ int nxm_pairs_per_lane_iter(int mix, int wide) {
   if (mix >= NXM_OP_FMA_F32 && mix <= NXM_OP_ADD_F32) return wide == 2 ? 0 : 4 * (wide ? 16 : 8);
   if (mix >= NXM_FWD_GRID_CF && mix <= NXM_BWD_GRID_F1) {    // the sums' shape only
     if (wide != 2) return 0;
-    return mix >= NXM_BWD_GRID_CF ? 2 * 64 : 4 * kTileGrid;
+    return mix >= NXM_BWD_GRID_CF ? 2 * 64 : 8 * kTileGrid;
   }
   if (mix < NXM_FWD_PH64_CF || mix > NXM_BWD_F32_F1) return 0;
   const bool ph64 = mix >= NXM_FWD_PH64_CF && mix <= NXM_BWD_PH64_F1;

@@ -45,9 +45,9 @@ def bwd(xyz, f, grid, G):
     return g.cpu().numpy().astype(np.float64)
 
 
-SHAPES = [((128, 5, 3), 3001, True),      # rows of 128, n2 odd: two points per lane
-          ((128, 2, 3), 900, True),       # rows in pairs (8-atom groups: two points per lane)
-          ((256, 4, 1), 20_000, False),   # 8-atom groups: two points per lane
+SHAPES = [((128, 5, 3), 70_000, True),    # rows of 128, n2 odd: two points per lane
+          ((128, 2, 3), 900, True),       # few atoms (8-atom groups): one point per lane
+          ((256, 4, 1), 20_000, False),   # the same
           ((128, 2, 2), 70_000, True),    # 16-atom groups, 2 x 2 x 2 blocks; 1 of 4 waves busy
           ((256, 2, 3), 70_000, False),   # 2 x 2 blocks
           ((64, 4, 2), 70_000, True),     # rows of 64: 1 x 2 x 2 blocks
