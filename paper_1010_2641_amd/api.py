@@ -14,7 +14,8 @@ library (include/nx.h), which does all the arithmetic.
 * ``scatter``, ``scatter_species``          -- differentiable forwards (autograd.Function);
 * ``fit_step``, ``fit_step_species``        -- forward, misfit and adjoint in one call;
 * ``Grid``, ``scatter_fwd_grid``, ``scatter_bwd_grid``, ``fit_step_grid`` -- the same sums
-  over a regular grid of points given exactly (FP64 origin and steps), walked by rows.
+  over a regular grid of points given exactly (FP64 origin and steps), walked by rows;
+  ``scatter_grid`` is differentiable with respect to the positions.
 """
 from __future__ import annotations
 
@@ -518,3 +519,36 @@ def fit_step_grid(xyz: torch.Tensor, f: Optional[torch.Tensor], grid: Grid, I: t
     _lib.check(_lib.nx_fit_step_grid(_ptr(xyz), _ptr(f), n, ctypes.byref(g), _ptr(I), _ptr(A), _ptr(L),
                                      _ptr(G), _ptr(grad), _lib.NX_F32_PH64, _ptr(ws), wsb, _stream(dev)))
     return (L, A, grad, G) if return_seed else (L, A, grad)
+
+
+class ScatterGridFn(torch.autograd.Function):
+    """Differentiable Eq. 2 over a grid with respect to the positions (the grid and f are
+    constants).  Backward receives torch's complex gradient dL/dRe A + i dL/dIm A and calls
+    the grid adjoint kernel."""
+
+    @staticmethod
+    def forward(ctx, xyz, f, grid):
+        ctx.save_for_backward(xyz, f) if f is not None else ctx.save_for_backward(xyz)
+        ctx.has_f = f is not None
+        ctx.grid = grid
+        return scatter_fwd_grid(xyz, f, grid)
+
+    @staticmethod
+    def backward(ctx, gA):
+        if ctx.has_f:
+            xyz, f = ctx.saved_tensors
+        else:
+            (xyz,), f = ctx.saved_tensors, None
+        if not ctx.needs_input_grad[0]:
+            return None, None, None
+        return scatter_bwd_grid(xyz, f, ctx.grid, _seed_arg(gA, torch.complex64)), None, None
+
+
+def scatter_grid(xyz: torch.Tensor, f: Optional[torch.Tensor], grid: Grid):
+    """Differentiable forward sum over the points of ``grid`` (gradients with respect to
+    xyz; the grid adjoint has no factor gradient: take dL/df through ``scatter`` with the
+    grid's points as a list)."""
+    if f is not None and f.requires_grad:
+        raise NotImplementedError("scatter_grid: no gradient with respect to f over a grid; use "
+                                  "scatter() with the grid's points for dL/df")
+    return ScatterGridFn.apply(xyz, f, grid)

@@ -74,3 +74,29 @@ def test_conjugate_views():
         assert not seed.is_conj() and seed.is_contiguous() and seed.dtype == dtype
         assert torch.equal(torch.view_as_real(seed),
                            torch.view_as_real(g.to(dtype)) * torch.tensor([1.0, -1.0], dtype=seed.real.dtype))
+
+
+def test_grid_wrappers_are_checked():
+    """The grid calls: the grid's fields and counts, the sizes of G, I and out against
+    n1 n2 n3, the refusal of a factor gradient over a grid."""
+    g = api.Grid((0.0, 0.0, 4.0), (0.01, 0.0, 0.0), (0.0, 0.01, 0.0), (0.0, 0.0, 0.01), 64, 2, 3)
+    x = z(5, 3)
+    with pytest.raises(TypeError, match="grid must be a Grid"):
+        api.scatter_fwd_grid(x, None, object())
+    with pytest.raises(ValueError, match="3 components"):
+        api.scatter_fwd_grid(x, None, api.Grid((0.0, 0.0), (0.01, 0.0, 0.0), (0.0, 0.01, 0.0),
+                                               (0.0, 0.0, 0.01), 64))
+    with pytest.raises(ValueError, match="counts must be >= 0"):
+        api.scatter_fwd_grid(x, None, api.Grid((0.0,) * 3, (0.01, 0.0, 0.0), (0.0,) * 3, (0.0,) * 3, -1))
+    with pytest.raises(ValueError, match=r"out must have shape \(384,\)"):
+        api.scatter_fwd_grid(x, None, g, out=z(383, dtype=torch.complex64))
+    with pytest.raises(ValueError, match=r"G must have shape \(384,\)"):
+        api.scatter_bwd_grid(x, None, g, z(100, dtype=torch.complex64))
+    with pytest.raises(ValueError, match=r"I must have shape \(384,\)"):
+        api.fit_step_grid(x, None, g, z(100))
+    with pytest.raises(ValueError, match="must be on the GPU"):
+        api.scatter_fwd_grid(x, None, g)
+    f = torch.zeros(5, dtype=torch.complex64, requires_grad=True)
+    with pytest.raises(NotImplementedError, match="no gradient with respect to f"):
+        api.scatter_grid(x, f, g)
+    assert g.size == 384

@@ -247,3 +247,29 @@ def test_lattice_maps_pointwise(step, n1, n2, atoms, monkeypatch):
     e2, e1 = M.t1(A2, ref), M.t1(A1, ref)
     print(f"  T1 stepped {e2:.3e}, one point per lane {e1:.3e}", flush=True)
     assert e2 <= M.T1_TOL and e1 <= M.T1_TOL
+
+
+@pytest.mark.parametrize("cplx", [True, False])
+def test_autograd_over_a_grid(cplx):
+    """scatter_grid under torch autograd: L = sum (|A|^2 - I)^2 computed in torch, its
+    gradient with respect to the positions through the grid adjoint, against the oracle's
+    adjoint fed the oracle's own seed (T3), and against the one-call fit step."""
+    grid = oblique(128, 2, 2)
+    n = 3000
+    xyz, f, _ = wl.random_problem(n, 1, seed=91, extent=30.0, s_range=1.0, complex_f=cplx)
+    P = grid.points()
+    I = (np.abs(oracle.forward(xyz, f, P)) ** 2 * 1.05).astype(np.float32)
+    x = dev(xyz).requires_grad_(True)
+    print(f"case autograd over a grid complex={cplx}", flush=True)
+    A = api.scatter_grid(x, dev(f), grid)
+    L = ((A.abs() ** 2 - dev(I)) ** 2).sum()
+    L.backward()
+    g = x.grad.cpu().numpy().astype(np.float64)
+    _, G_ref = oracle.loss(oracle.forward(xyz, f, P), I)
+    en, em = M.t3(g, oracle.adjoint(xyz, f, P, G_ref))
+    print(f"  T3 norm={en:.3e} max={em:.3e}", flush=True)
+    assert en <= M.T3_NORM_TOL and em <= M.T3_MAX_TOL
+    _, _, g_step = api.fit_step_grid(dev(xyz), dev(f), grid, dev(I))
+    torch.cuda.synchronize()
+    en2, _ = M.t3(g, g_step.cpu().numpy())
+    assert en2 <= M.T3_NORM_TOL
