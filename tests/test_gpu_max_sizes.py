@@ -102,6 +102,58 @@ def test_forward_max_points_sampled():
     assert err <= 3 * M.INC_TOL * np.sqrt(3)
 
 
+def max_grid():
+    """1024^3 = 2^30 points with dyadic steps around (0, 0, 4): the grid kernels' 32-bit
+    index arithmetic, row and plane decomposition and 2 x 2 x 2 blocks at the largest
+    count."""
+    from paper_1010_2641_amd import workloads as wl
+    h = 1.0 / 1024.0
+    return wl.RegularGrid((-0.5, -0.5, 3.5), (h, 0.0, 0.0), (0.0, h, 0.0), (0.0, 0.0, h), 1024, 1024, 1024)
+
+
+def test_grid_forward_max_points_sampled(monkeypatch):
+    """The grid forward over 2^30 points (64 atoms, 16-atom groups forced so that the
+    2 x 2 x 2 blocks run): sampled amplitudes, the corners included, against the oracle."""
+    from paper_1010_2641_amd import workloads as wl
+    grid = max_grid()
+    assert grid.size == MAX
+    xyz, f, _ = wl.random_problem(64, 1, seed=93, extent=20.0, s_range=1.0)
+    monkeypatch.setenv("NX_TUNE_GRP", "16")
+    print(f"case grid max points: 64 atoms x {MAX} points", flush=True)
+    A = api.scatter_fwd_grid(torch.from_numpy(xyz).cuda(), torch.from_numpy(f).cuda(), grid)
+    rng = np.random.default_rng(94)
+    idx = np.unique(np.concatenate([[0, 1, 1023, 1024, MAX // 2, MAX - 1025, MAX - 2, MAX - 1],
+                                    rng.integers(0, MAX, size=4088)]))
+    A_s = A[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.complex128)
+    del A
+    torch.cuda.empty_cache()
+    e = M.incoherent(A_s, oracle.forward(xyz, f, grid.points(idx)), f, 64)
+    print(f"grid max points sampled: pointwise/sqrt(sum|f|^2) = {e:.3e}", flush=True)
+    assert e <= M.INC_TOL
+
+
+def test_grid_adjoint_max_points_sampled():
+    """The grid adjoint over 2^30 points (256 atoms, the stepped 64-point runs): the seed is
+    zero except at 4,096 seeded points, whose contributions the oracle sums."""
+    from paper_1010_2641_amd import workloads as wl
+    grid = max_grid()
+    xyz, f, _ = wl.random_problem(256, 1, seed=95, extent=20.0, s_range=1.0)
+    rng = np.random.default_rng(96)
+    idx = np.unique(np.concatenate([[0, 63, 64, MAX - 64, MAX - 1], rng.integers(0, MAX, size=4091)]))
+    Gs = (rng.normal(size=len(idx)) + 1j * rng.normal(size=len(idx))).astype(np.complex64)
+    G = torch.zeros(MAX, dtype=torch.complex64, device="cuda")
+    G[torch.from_numpy(idx).cuda()] = torch.from_numpy(Gs).cuda()
+    print(f"case grid max points adjoint: 256 atoms x {MAX} points", flush=True)
+    g = api.scatter_bwd_grid(torch.from_numpy(xyz).cuda(), torch.from_numpy(f).cuda(), grid, G)
+    del G
+    g_np = g.cpu().numpy().astype(np.float64)
+    del g
+    torch.cuda.empty_cache()
+    en, em = M.t3(g_np, oracle.adjoint(xyz, f, grid.points(idx), Gs))
+    print(f"grid max points adjoint: T3 norm={en:.3e} max={em:.3e}", flush=True)
+    assert en <= M.T3_NORM_TOL and em <= M.T3_MAX_TOL
+
+
 def test_counts_above_the_maximum_are_rejected():
     x = torch.zeros((4, 3), dtype=torch.float32, device="cuda")
     assert _lib.nx_scatter_fwd(x.data_ptr(), None, MAX + 1, x.data_ptr(), 4, x.data_ptr(), 1, None, 0,
