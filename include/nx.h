@@ -282,6 +282,32 @@ int nx_scatter_bwd_species(const float* xyz, int64_t n_atoms, const int64_t* spe
 size_t nx_workspace_bytes_species(const int64_t* species_start, int n_species, int64_t n_points,
                                   int mode, int op);
 
+/* The species-factorised sum of Section 4.2 over the points of `grid` (host pointer; the
+ * maps of Section 4 are such grids, their atoms of a few types): nx_scatter_fwd_species
+ * with S_k the grid's k-th point, each species' unit-factor sum walked over the grid as
+ * nx_scatter_fwd_grid walks it.  fs, A, A_species as for nx_scatter_fwd_species with
+ * n_points = n1 n2 n3 (points in the grid's order); mode NX_F32_PH64 only (else
+ * NX_ERR_MODE).  Workspace: nx_workspace_bytes_species_grid(..., op = 0).  Errors as for
+ * nx_scatter_fwd_species and nx_scatter_fwd_grid. */
+int nx_scatter_fwd_species_grid(const float* xyz, int64_t n_atoms, const int64_t* species_start,
+                                int n_species, const float* fs, const nx_grid* grid, float* A,
+                                float* A_species, int mode, void* ws, size_t ws_bytes,
+                                void* stream);
+
+/* Adjoint of nx_scatter_fwd_species_grid for the seed G (float[n1 n2 n3 * 2], device):
+ * grad_xyz and grad_fs as for nx_scatter_bwd_species (each species' seed G conj(fs[s])
+ * drives the grid adjoint over that species' atoms; grad_xyz is zero for an empty grid).
+ * Workspace: nx_workspace_bytes_species_grid(..., op = 1) (only when grad_xyz is wanted). */
+int nx_scatter_bwd_species_grid(const float* xyz, int64_t n_atoms, const int64_t* species_start,
+                                int n_species, const float* fs, const nx_grid* grid, const float* G,
+                                const float* A_species, float* grad_xyz, float* grad_fs, int mode,
+                                void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes of the species-factorised calls over a grid: op 0 forward, op 1 adjoint.
+ * Returns 0 and sets the last error on invalid arguments. */
+size_t nx_workspace_bytes_species_grid(const int64_t* species_start, int n_species,
+                                       const nx_grid* grid, int op);
+
 /* Message of the calling thread's last error ("" if none).  The pointer stays valid
  * until the thread's next call into the library. */
 const char* nx_last_error(void);

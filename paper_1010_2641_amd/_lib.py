@@ -52,6 +52,10 @@ SIGNATURES = {
     "nx_scatter_fwd_grid": ([_VP, _VP, _I64, _GP, _VP, _I, _VP, _SZ, _VP], _I),
     "nx_scatter_bwd_grid": ([_VP, _VP, _I64, _GP, _VP, _VP, _I, _VP, _SZ, _VP], _I),
     "nx_fit_step_grid": ([_VP, _VP, _I64, _GP, _VP, _VP, _VP, _VP, _VP, _I, _VP, _SZ, _VP], _I),
+    "nx_scatter_fwd_species_grid": ([_VP, _I64, _VP, _I, _VP, _GP, _VP, _VP, _I, _VP, _SZ, _VP], _I),
+    "nx_scatter_bwd_species_grid": ([_VP, _I64, _VP, _I, _VP, _GP, _VP, _VP, _VP, _VP, _I, _VP, _SZ,
+                                     _VP], _I),
+    "nx_workspace_bytes_species_grid": ([_VP, _I, _GP, _I], _SZ),
 }
 
 
@@ -122,3 +126,6 @@ nx_workspace_bytes_grid = lib.nx_workspace_bytes_grid
 nx_scatter_fwd_grid = lib.nx_scatter_fwd_grid
 nx_scatter_bwd_grid = lib.nx_scatter_bwd_grid
 nx_fit_step_grid = lib.nx_fit_step_grid
+nx_scatter_fwd_species_grid = lib.nx_scatter_fwd_species_grid
+nx_scatter_bwd_species_grid = lib.nx_scatter_bwd_species_grid
+nx_workspace_bytes_species_grid = lib.nx_workspace_bytes_species_grid

@@ -15,7 +15,9 @@ library (include/nx.h), which does all the arithmetic.
 * ``fit_step``, ``fit_step_species``        -- forward, misfit and adjoint in one call;
 * ``Grid``, ``scatter_fwd_grid``, ``scatter_bwd_grid``, ``fit_step_grid`` -- the same sums
   over a regular grid of points given exactly (FP64 origin and steps), walked by rows;
-  ``scatter_grid`` is differentiable with respect to the positions.
+  ``scatter_grid`` is differentiable with respect to the positions;
+  ``scatter_fwd_species_grid`` / ``scatter_bwd_species_grid`` the species-factorised sum
+  over such a grid.
 """
 from __future__ import annotations
 
@@ -519,6 +521,63 @@ def fit_step_grid(xyz: torch.Tensor, f: Optional[torch.Tensor], grid: Grid, I: t
     _lib.check(_lib.nx_fit_step_grid(_ptr(xyz), _ptr(f), n, ctypes.byref(g), _ptr(I), _ptr(A), _ptr(L),
                                      _ptr(G), _ptr(grad), _lib.NX_F32_PH64, _ptr(ws), wsb, _stream(dev)))
     return (L, A, grad, G) if return_seed else (L, A, grad)
+
+
+def workspace_bytes_species_grid(species_start: Sequence[int], grid: Grid, op: int = 0) -> int:
+    """Workspace bytes of the species-factorised calls over a grid (op 0 forward, 1 adjoint)."""
+    g, _ = _grid_arg(grid)
+    start, ns = _species_array(species_start, int(species_start[-1]) if len(species_start) else -1)
+    n = _lib.nx_workspace_bytes_species_grid(start, ns, ctypes.byref(g), op)
+    msg = _lib.last_error()
+    if msg:
+        raise _lib.NxError(_lib.NX_ERR_ARG, msg)
+    return int(n)
+
+
+def scatter_fwd_species_grid(xyz: torch.Tensor, species_start: Sequence[int], fs: Optional[torch.Tensor],
+                             grid: Grid, return_species: bool = False):
+    """``scatter_fwd_species`` over the points of ``grid`` (FP64-phase mode): fs
+    (n_species, grid.size) complex64 or None.  Returns A (grid.size,) complex64, and the
+    per-species sums (n_species, grid.size) when return_species."""
+    _need(xyz, "xyz", torch.float32, (None, 3))
+    g, k = _grid_arg(grid)
+    n = xyz.shape[0]
+    start, ns = _species_array(species_start, n)
+    _fs_arg(fs, ns, k)
+    _on_gpu(xyz=xyz, fs=fs)
+    nbytes = workspace_bytes_species_grid(species_start, grid, 0)
+    A = torch.empty(k, dtype=torch.complex64, device=xyz.device)
+    As = torch.empty((ns, k), dtype=torch.complex64, device=xyz.device) if return_species else None
+    ws, wsb = _workspace(nbytes, xyz.device)
+    _lib.check(_lib.nx_scatter_fwd_species_grid(_ptr(xyz), n, start, ns, _ptr(_real(fs)), ctypes.byref(g),
+                                                _ptr(_real(A)), _ptr(_real(As)), _lib.NX_F32_PH64,
+                                                _ptr(ws), wsb, _stream(xyz.device)))
+    return (A, As) if return_species else A
+
+
+def scatter_bwd_species_grid(xyz: torch.Tensor, species_start: Sequence[int], fs: Optional[torch.Tensor],
+                             grid: Grid, G: torch.Tensor, A_species: Optional[torch.Tensor] = None,
+                             want_xyz: bool = True):
+    """Adjoint of ``scatter_fwd_species_grid``: (dL/dxyz (N,3) float32 or None, dL/dfs
+    (n_species, grid.size) complex64 or None -- the latter when A_species is given)."""
+    _need(xyz, "xyz", torch.float32, (None, 3))
+    g, k = _grid_arg(grid)
+    n = xyz.shape[0]
+    _need(G, "G", torch.complex64, (k,))
+    start, ns = _species_array(species_start, n)
+    _fs_arg(fs, ns, k)
+    if A_species is not None:
+        _need(A_species, "A_species", torch.complex64, (ns, k))
+    _on_gpu(xyz=xyz, G=G, fs=fs, A_species=A_species)
+    nbytes = workspace_bytes_species_grid(species_start, grid, 1)
+    grad = torch.empty((n, 3), dtype=torch.float32, device=xyz.device) if want_xyz else None
+    gfs = torch.empty((ns, k), dtype=torch.complex64, device=xyz.device) if A_species is not None else None
+    ws, wsb = _workspace(nbytes, xyz.device)
+    _lib.check(_lib.nx_scatter_bwd_species_grid(_ptr(xyz), n, start, ns, _ptr(_real(fs)), ctypes.byref(g),
+                                                _ptr(_real(G)), _ptr(_real(A_species)), _ptr(grad),
+                                                _ptr(_real(gfs)), _lib.NX_F32_PH64, _ptr(ws), wsb,
+                                                _stream(xyz.device)))
+    return grad, gfs
 
 
 class ScatterGridFn(torch.autograd.Function):

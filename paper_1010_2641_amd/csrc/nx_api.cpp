@@ -442,6 +442,35 @@ size_t species_ws(int op, int mode, int64_t n_points, const int64_t* start, int 
   return total;
 }
 
+// Workspace of the species-factorised calls over a grid of k points (grid kind g, the
+// FP64-phase mode): forward, every species' grid atom records at its atoms' place, then one
+// (sum, comp) state per species; adjoint, the per-species seed, then the largest of the
+// species' grid adjoint workspaces (point records and partials).
+size_t species_grid_ws(int op, int64_t k, int g, const int64_t* start, int n_species,
+                       size_t* state_off) {
+  size_t total = 0;
+  if (op == 0) {
+    for (int s = 0; s < n_species; ++s) {
+      const nx::Plan ps = nx::make_plan(nx::kOpFwd, NX_F32_PH64, start[s + 1] - start[s], k, 1,
+                                        nx::kMaxSplit, g);
+      total = std::max(total, align_up(size_t(start[s + 1]) * ps.rec_size, 256));
+    }
+    for (int s = 0; s < n_species; ++s) {
+      const nx::Plan ps = nx::make_plan(nx::kOpFwd, NX_F32_PH64, start[s + 1] - start[s], k, 1,
+                                        nx::kMaxSplit, g);
+      if (state_off) state_off[s] = total;
+      total += align_up(size_t(ps.nsplit) * size_t(k) * 16, 256);
+    }
+  } else {
+    size_t most = 0;
+    for (int s = 0; s < n_species; ++s)
+      most = std::max(most, nx::make_plan(nx::kOpBwd, NX_F32_PH64, start[s + 1] - start[s], k, 1,
+                                          nx::kMaxSplit, g).total());
+    total = align_up(size_t(k) * 8, 256) + most;
+  }
+  return total;
+}
+
 }  // namespace
 
 namespace {
@@ -899,6 +928,129 @@ int nx_scatter_bwd_species(const float* xyz, int64_t n_atoms, const int64_t* spe
     const nx::Plan ps = nx::make_plan(nx::kOpBwd, mode, ns, n_points, 1);
     const int r = run_sum(fn, ps, false, xyz + 3 * a0, nullptr, S, seed, grad_xyz + 3 * a0, nullptr,
                           rest, st);
+    if (r != NX_OK) return r;
+  }
+  return ok();
+}
+
+size_t nx_workspace_bytes_species_grid(const int64_t* species_start, int n_species,
+                                       const nx_grid* grid, int op) {
+  const char* fn = "nx_workspace_bytes_species_grid";
+  const int64_t k = grid_points(fn, grid);
+  if (k < 0) return 0;
+  if (n_species < 1 || n_species > nx::kMaxSpecies || !species_start) {
+    fail(NX_ERR_ARG, "%s: n_species %d outside [1, %d] or NULL species_start", fn, n_species,
+         nx::kMaxSpecies);
+    return 0;
+  }
+  const int64_t n_atoms = species_start[n_species];
+  if (check_counts(fn, n_atoms, k) != NX_OK) return 0;
+  if (check_species(fn, n_atoms, species_start, n_species) != NX_OK) return 0;
+  if (op != 0 && op != 1) {
+    fail(NX_ERR_MODE, "%s: op must be 0 (forward) or 1 (adjoint), got %d", fn, op);
+    return 0;
+  }
+  ok();
+  return species_grid_ws(op, k, grid_kind(grid), species_start, n_species, nullptr);
+}
+
+int nx_scatter_fwd_species_grid(const float* xyz, int64_t n_atoms, const int64_t* species_start,
+                                int n_species, const float* fs, const nx_grid* grid, float* A,
+                                float* A_species, int mode, void* ws, size_t ws_bytes,
+                                void* stream) {
+  const char* fn = "nx_scatter_fwd_species_grid";
+  const int64_t k = grid_points(fn, grid);
+  if (k < 0) return NX_ERR_ARG;
+  if (int r = check_counts(fn, n_atoms, k)) return r;
+  if (int r = check_species(fn, n_atoms, species_start, n_species)) return r;
+  if (mode != NX_F32_PH64)
+    return fail(NX_ERR_MODE, "%s: mode %d: grids take the FP64-phase mode (NX_F32_PH64)", fn, mode);
+  if (k == 0) return ok();
+  if (!A || (n_atoms > 0 && !xyz))
+    return fail(NX_ERR_ARG, "%s: NULL pointer (xyz=%p A=%p)", fn, (const void*)xyz, (void*)A);
+  if (!aligned(A, 8) || (fs && !aligned(fs, 8)) || (A_species && !aligned(A_species, 8)))
+    return fail(NX_ERR_ARG, "%s: A, fs and A_species must be 8-byte aligned (complex64)", fn);
+  const int g = grid_kind(grid);
+  size_t off[nx::kMaxSpecies];
+  const size_t need = species_grid_ws(0, k, g, species_start, n_species, off);
+  if (ws == nullptr || ws_bytes < need || !aligned(ws, 16))
+    return fail(NX_ERR_WORKSPACE, "%s: workspace of %zu bytes (16-byte aligned) needed, %zu given", fn,
+                need, ws_bytes);
+  const nx::GridDef gd = grid_def(grid);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  hipError_t e;
+  nx::SpeciesStates ss{};
+  ss.n = n_species;
+  for (int s = 0; s < n_species; ++s) {
+    const int64_t a0 = species_start[s], ns = species_start[s + 1] - a0;
+    const nx::Plan ps = nx::make_plan(nx::kOpFwd, mode, ns, k, 1, nx::kMaxSplit, g);
+    // each species' grid records, packed with its own plan, at its atoms' place (its groups
+    // counted from its first atom); the chunks write its (sum, comp) state, never A
+    e = nx::launch_pack_atoms_grid(ps, xyz + 3 * a0, nullptr, ns, gd, base + a0 * ps.rec_size, st);
+    if (e != hipSuccess) return device_error(fn, e);
+    void* state = base + off[s];
+    ss.state[s] = state;
+    ss.nsplit[s] = ps.nsplit;
+    for (int64_t c = 0; c < ps.nchunks; ++c) {
+      int64_t b, en, per;
+      nx::chunk_range(ps, c, &b, &en, &per);
+      e = nx::launch_fwd_chunk(ps, base, a0 + b, a0 + en, per, nullptr, state, nullptr, c > 0 ? 1 : 0,
+                               0, st, nullptr, nullptr, &gd);
+      if (e != hipSuccess) return device_error(fn, e);
+    }
+  }
+  e = nx::launch_species_combine(ss, fs, k, A, A_species, st);
+  if (e != hipSuccess) return device_error(fn, e);
+  return ok();
+}
+
+int nx_scatter_bwd_species_grid(const float* xyz, int64_t n_atoms, const int64_t* species_start,
+                                int n_species, const float* fs, const nx_grid* grid, const float* G,
+                                const float* A_species, float* grad_xyz, float* grad_fs, int mode,
+                                void* ws, size_t ws_bytes, void* stream) {
+  const char* fn = "nx_scatter_bwd_species_grid";
+  const int64_t k = grid_points(fn, grid);
+  if (k < 0) return NX_ERR_ARG;
+  if (int r = check_counts(fn, n_atoms, k)) return r;
+  if (int r = check_species(fn, n_atoms, species_start, n_species)) return r;
+  if (mode != NX_F32_PH64)
+    return fail(NX_ERR_MODE, "%s: mode %d: grids take the FP64-phase mode (NX_F32_PH64)", fn, mode);
+  if (!grad_xyz && !grad_fs) return ok();
+  if (k > 0 && !G) return fail(NX_ERR_ARG, "%s: NULL G", fn);
+  if (grad_xyz && n_atoms > 0 && !xyz) return fail(NX_ERR_ARG, "%s: NULL xyz", fn);
+  if (grad_fs && k > 0 && !A_species)
+    return fail(NX_ERR_ARG, "%s: grad_fs needs the per-species sums A_species", fn);
+  if ((G && !aligned(G, 8)) || (fs && !aligned(fs, 8)) || (grad_fs && !aligned(grad_fs, 8)) ||
+      (A_species && !aligned(A_species, 8)))
+    return fail(NX_ERR_ARG, "%s: G, fs, A_species and grad_fs must be 8-byte aligned", fn);
+  const int g = grid_kind(grid);
+  const size_t need = species_grid_ws(1, k, g, species_start, n_species, nullptr);
+  if (grad_xyz && n_atoms > 0 && need > 0 && (ws == nullptr || ws_bytes < need || !aligned(ws, 16)))
+    return fail(NX_ERR_WORKSPACE, "%s: workspace of %zu bytes (16-byte aligned) needed, %zu given", fn,
+                need, ws_bytes);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (grad_fs) {
+    for (int s = 0; s < n_species; ++s) {
+      e = nx::launch_species_gradf(G, A_species + 2 * int64_t(s) * k, k, grad_fs + 2 * int64_t(s) * k, st);
+      if (e != hipSuccess) return device_error(fn, e);
+    }
+  }
+  if (!grad_xyz || n_atoms == 0) return ok();
+  const nx::GridDef gd = grid_def(grid);
+  char* base = static_cast<char*>(ws);
+  float* seed = reinterpret_cast<float*>(base);
+  char* rest = base + align_up(size_t(k) * 8, 256);
+  for (int s = 0; s < n_species; ++s) {
+    const int64_t a0 = species_start[s], ns = species_start[s + 1] - a0;
+    if (ns == 0) continue;
+    e = nx::launch_species_seed(G, fs ? fs + 2 * int64_t(s) * k : nullptr, k, seed, st);
+    if (e != hipSuccess) return device_error(fn, e);
+    // (no points: the grid adjoint runs over an empty range and writes a zero gradient)
+    const nx::Plan ps = nx::make_plan(nx::kOpBwd, mode, ns, k, 1, nx::kMaxSplit, g);
+    const int r = run_sum_grid(fn, ps, false, xyz + 3 * a0, nullptr, gd, seed, grad_xyz + 3 * a0,
+                               rest, st);
     if (r != NX_OK) return r;
   }
   return ok();

@@ -420,3 +420,70 @@ def test_grid_workspace(monkeypatch):
     assert _lib.nx_workspace_bytes_grid(8, ctypes.byref(g), 3, 1) == 0
     assert "op must be" in _lib.last_error()
     assert _lib.nx_workspace_bytes_grid(8, None, _lib.NX_OP_FWD, 1) == 0
+
+
+def fwd_sp_grid(g, start, ns, n_atoms=8, xyz=FAKE, fs=None, A=FAKE, As=None, mode=1, ws=FAKE,
+                wsb=1 << 40):
+    return _lib.nx_scatter_fwd_species_grid(xyz, n_atoms, start, ns, fs,
+                                            ctypes.byref(g) if g is not None else None, A, As, mode,
+                                            ws, wsb, None)
+
+
+def bwd_sp_grid(g, start, ns, n_atoms=8, xyz=FAKE, fs=None, G=FAKE, As=None, grad=FAKE, gfs=None,
+                mode=1, ws=FAKE, wsb=1 << 40):
+    return _lib.nx_scatter_bwd_species_grid(xyz, n_atoms, start, ns, fs,
+                                            ctypes.byref(g) if g is not None else None, G, As, grad,
+                                            gfs, mode, ws, wsb, None)
+
+
+def test_species_grid_argument_checks():
+    """The species-factorised calls over a grid check the grid, the partition, the mode,
+    pointers, alignment and workspace before queueing anything."""
+    g = grid_struct()
+    assert fwd_sp_grid(None, starts(0, 8), 1) == _lib.NX_ERR_ARG and "NULL grid" in _lib.last_error()
+    assert bwd_sp_grid(None, starts(0, 8), 1) == _lib.NX_ERR_ARG
+    assert fwd_sp_grid(grid_struct(n1=-2), starts(0, 8), 1) == _lib.NX_ERR_ARG
+    assert fwd_sp_grid(g, starts(0, 3, 7), 2) == _lib.NX_ERR_ARG            # must end at n_atoms
+    assert fwd_sp_grid(g, starts(0, 5, 3, 8), 3) == _lib.NX_ERR_ARG         # decreasing
+    assert "decreases" in _lib.last_error()
+    assert fwd_sp_grid(g, starts(*range(0, 18)), 17, n_atoms=17) == _lib.NX_ERR_ARG
+    assert fwd_sp_grid(g, starts(0, 8), 1, mode=0) == _lib.NX_ERR_MODE
+    assert "NX_F32_PH64" in _lib.last_error()
+    assert bwd_sp_grid(g, starts(0, 8), 1, mode=0) == _lib.NX_ERR_MODE
+    assert fwd_sp_grid(g, starts(0, 8), 1, A=None) == _lib.NX_ERR_ARG
+    assert fwd_sp_grid(g, starts(0, 8), 1, xyz=None) == _lib.NX_ERR_ARG
+    assert fwd_sp_grid(g, starts(0, 8), 1, A=FAKE + 4) == _lib.NX_ERR_ARG
+    assert fwd_sp_grid(g, starts(0, 8), 1, As=FAKE + 4) == _lib.NX_ERR_ARG
+    assert fwd_sp_grid(g, starts(0, 3, 8), 2, wsb=0) == _lib.NX_ERR_WORKSPACE
+    assert bwd_sp_grid(g, starts(0, 8), 1, G=None) == _lib.NX_ERR_ARG
+    assert bwd_sp_grid(g, starts(0, 8), 1, xyz=None) == _lib.NX_ERR_ARG
+    assert bwd_sp_grid(g, starts(0, 8), 1, grad=None, gfs=FAKE) == _lib.NX_ERR_ARG   # needs A_species
+    assert "A_species" in _lib.last_error()
+    assert bwd_sp_grid(g, starts(0, 8), 1, wsb=16) == _lib.NX_ERR_WORKSPACE
+    # nothing asked for; an empty grid forward; no atoms
+    assert bwd_sp_grid(g, starts(0, 8), 1, grad=None, gfs=None, ws=None, wsb=0) == _lib.NX_OK
+    assert fwd_sp_grid(grid_struct(n2=0), starts(0, 8), 1, A=None, xyz=None, ws=None, wsb=0) == _lib.NX_OK
+    assert bwd_sp_grid(g, starts(0, 0), 1, n_atoms=0, xyz=None, grad=FAKE, ws=None, wsb=0) == _lib.NX_OK
+
+
+def test_species_grid_workspace(monkeypatch):
+    """Forward: every atom's grid record (80 B over rows), then one 16-byte (sum, comp) state
+    per point, split and species; adjoint: the per-species seed (8 B per point), then the
+    largest species' grid adjoint workspace."""
+    monkeypatch.delenv("NX_TUNE_GRID", raising=False)
+    a256 = lambda b: -(-b // 256) * 256
+    g = grid_struct(n1=128, n2=128, n3=128)
+    k, st = 128 ** 3, starts(0, 100_000, 203_557)
+    fw = _lib.nx_workspace_bytes_species_grid(st, 2, ctypes.byref(g), 0)
+    assert fw >= a256(203_557 * 80) + 2 * k * 16
+    bw = _lib.nx_workspace_bytes_species_grid(st, 2, ctypes.byref(g), 1)
+    most = max(_lib.nx_workspace_bytes_grid(n, ctypes.byref(g), _lib.NX_OP_BWD, 1) for n in (100_000, 103_557))
+    assert bw == a256(k * 8) + most
+    # the point-list species call over the same points needs 48-byte point records
+    assert bw < _lib.nx_workspace_bytes_species(st, 2, k, 1, 1)
+    assert _lib.nx_workspace_bytes_species_grid(st, 2, ctypes.byref(g), 2) == 0
+    assert "op must be" in _lib.last_error()
+    assert _lib.nx_workspace_bytes_species_grid(st, 2, None, 0) == 0
+    assert _lib.nx_workspace_bytes_species_grid(None, 2, ctypes.byref(g), 0) == 0
+    assert fwd_sp_grid(grid_struct(n1=128, n2=2, n3=2), starts(0, 4096), 1, n_atoms=4096,
+                       wsb=100) == _lib.NX_ERR_WORKSPACE
