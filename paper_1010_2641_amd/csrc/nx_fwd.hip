@@ -528,11 +528,14 @@ __global__ __launch_bounds__(kThreads, INL ? 4 : 5) void fwd_lds_kernel(
 
 // Grid atom records (AtomGrid): the AtomPH record of atom j (same addend, factor, turn
 // and rounding) with its position folded into c0 = o.r + a and c_d = e_d.r, in FP64, and
-// the row step exp(2 i pi c1) - 1; rmax as in pack_atoms_ph_kernel.
+// the steps exp(2 i pi c_d) - 1 that the plan's block shape takes (bit d - 1 of `steps`;
+// the others are written as 0 and never read: each costs two FP64 sinpi and two
+// roundings, most of the pack's time when the block has one point); rmax as in
+// pack_atoms_ph_kernel.
 __global__ __launch_bounds__(kThreads) void pack_atoms_grid_kernel(const float* __restrict__ xyz,
                                                                    const float* __restrict__ f,
                                                                    int64_t n, AtomGrid* __restrict__ rec,
-                                                                   GridDef g, int grp) {
+                                                                   GridDef g, int grp, int steps) {
   __shared__ float wmax[kThreads / 64];
   for (int64_t b = blockIdx.x; b * kThreads < n; b += gridDim.x) {
     const int64_t j = b * kThreads + threadIdx.x;
@@ -550,15 +553,22 @@ __global__ __launch_bounds__(kThreads) void pack_atoms_grid_kernel(const float* 
       // exp(2 i pi c) - 1 = (-2 sin^2 pi t, sin 2 pi t), t = c mod 1, for c1, c2 and c3,
       // rounded without bias (keys of their own: j with a tag 1..6 in bits 60-62)
       const uint64_t key = static_cast<uint64_t>(j);
-      const double t1 = r.c1 - __builtin_rint(r.c1), h1 = sinpi(t1);
-      const double t2 = r.c2 - __builtin_rint(r.c2), h2 = sinpi(t2);
-      r.wr = round_unbiased_signed(-2.0 * h1 * h1, key | (1ull << 60));
-      r.wi = round_unbiased_signed(sinpi(2.0 * t1), key | (2ull << 60));
-      r.vr = round_unbiased_signed(-2.0 * h2 * h2, key | (3ull << 60));
-      r.vi = round_unbiased_signed(sinpi(2.0 * t2), key | (4ull << 60));
-      const double t3 = r.c3 - __builtin_rint(r.c3), h3 = sinpi(t3);
-      r.xr = round_unbiased_signed(-2.0 * h3 * h3, key | (5ull << 60));
-      r.xi = round_unbiased_signed(sinpi(2.0 * t3), key | (6ull << 60));
+      r.wr = r.wi = r.vr = r.vi = r.xr = r.xi = 0.f;
+      if (steps & 1) {
+        const double t1 = r.c1 - __builtin_rint(r.c1), h1 = sinpi(t1);
+        r.wr = round_unbiased_signed(-2.0 * h1 * h1, key | (1ull << 60));
+        r.wi = round_unbiased_signed(sinpi(2.0 * t1), key | (2ull << 60));
+      }
+      if (steps & 2) {
+        const double t2 = r.c2 - __builtin_rint(r.c2), h2 = sinpi(t2);
+        r.vr = round_unbiased_signed(-2.0 * h2 * h2, key | (3ull << 60));
+        r.vi = round_unbiased_signed(sinpi(2.0 * t2), key | (4ull << 60));
+      }
+      if (steps & 4) {
+        const double t3 = r.c3 - __builtin_rint(r.c3), h3 = sinpi(t3);
+        r.xr = round_unbiased_signed(-2.0 * h3 * h3, key | (5ull << 60));
+        r.xi = round_unbiased_signed(sinpi(2.0 * t3), key | (6ull << 60));
+      }
       r.pad0 = 0.f;
       r.pad1 = 0.f;
       am = fmaxf(bound_abs(a.x), fmaxf(bound_abs(a.y), bound_abs(a.z)));
@@ -1060,8 +1070,9 @@ hipError_t launch_pack_atoms_grid(const Plan& p, const float* xyz, const float* 
                                   const GridDef& g, void* rec, hipStream_t st) {
   if (p.grid != 2) return launch_pack_atoms(p.mode, p.red, p.grp, xyz, f, n, rec, st);
   if (n <= 0) return hipSuccess;
+  const int steps = (p.blk_a == 2 ? 1 : 0) | (p.blk_b == 2 ? 2 : 0) | (p.blk_c == 2 ? 4 : 0);
   pack_atoms_grid_kernel<<<grid_for(n), kThreads, 0, st>>>(xyz, f, n, static_cast<AtomGrid*>(rec), g,
-                                                           p.grp);
+                                                           p.grp, steps);
   return hipGetLastError();
 }
 

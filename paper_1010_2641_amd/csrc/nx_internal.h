@@ -88,7 +88,7 @@ struct GridDef {
 // row to the next (i2 + 1), and (xr, xi) = exp(2 i pi c3) - 1 (i3 + 1), formed in FP64 and
 // rounded to FP32 without bias (stochastically, from a hash of the atom's index), so that
 // the rounding errors of atoms with equal c1, c2 or c3 (a lattice plane) add up
-// incoherently.
+// incoherently.  Only the steps the plan's block shape takes are formed; the others hold 0.
 struct alignas(16) AtomGrid {
   double c0, c1, c2, c3;
   float m, ck, sk, rmax, wr, wi, vr, vi, xr, xi, pad0, pad1;
