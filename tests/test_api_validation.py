@@ -100,3 +100,25 @@ def test_grid_wrappers_are_checked():
     with pytest.raises(NotImplementedError, match="no gradient with respect to f"):
         api.scatter_grid(x, f, g)
     assert g.size == 384
+
+
+def test_species_grid_wrappers_are_checked():
+    """The species-factorised calls over a grid: the partition, the factor table, the seed
+    and the per-species sums against n_species x (n1 n2 n3)."""
+    g = api.Grid((0.0, 0.0, 4.0), (0.01, 0.0, 0.0), (0.0, 0.01, 0.0), (0.0, 0.0, 0.01), 64, 2, 3)
+    x = z(5, 3)
+    with pytest.raises(ValueError, match="species_start"):
+        api.scatter_fwd_species_grid(x, [0, 4], None, g)
+    with pytest.raises(ValueError, match=r"fs must have shape \(2, 384\)"):
+        api.scatter_fwd_species_grid(x, [0, 2, 5], z(2, 383, dtype=torch.complex64), g)
+    with pytest.raises(TypeError, match="grid must be a Grid"):
+        api.scatter_fwd_species_grid(x, [0, 5], None, object())
+    with pytest.raises(ValueError, match=r"G must have shape \(384,\)"):
+        api.scatter_bwd_species_grid(x, [0, 5], None, g, z(100, dtype=torch.complex64))
+    with pytest.raises(ValueError, match=r"A_species must have shape \(2, 384\)"):
+        api.scatter_bwd_species_grid(x, [0, 2, 5], None, g, z(384, dtype=torch.complex64),
+                                     z(1, 384, dtype=torch.complex64))
+    with pytest.raises(ValueError, match="must be on the GPU"):
+        api.scatter_fwd_species_grid(x, [0, 2, 5], z(2, 384, dtype=torch.complex64), g)
+    with pytest.raises(ValueError, match="must be on the GPU"):
+        api.scatter_bwd_species_grid(x, [0, 5], None, g, z(384, dtype=torch.complex64))
