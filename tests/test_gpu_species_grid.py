@@ -112,3 +112,16 @@ def test_species_grid_empty():
     G = torch.zeros(0, dtype=torch.complex64, device="cuda:0")
     gx, gfs = api.scatter_bwd_species_grid(dev(xyz), start, dev(fs), grid, G, As)
     assert np.all(host(gx) == 0) and gfs.shape == (2, 0)
+
+
+def test_species_grid_no_atoms():
+    """Every species empty: A is zero at every point; the adjoint has no atoms to write and
+    the factor gradient is G conj(0) = 0."""
+    grid = oblique(128, 2, 2)
+    xyz = np.zeros((0, 3), np.float32)
+    fs = wl.species_factor_table(grid.points(), [complex(31, 1), complex(8, 0.2)], b_iso=(1.2, 0.6))
+    A, As = api.scatter_fwd_species_grid(dev(xyz), [0, 0, 0], dev(fs), grid, return_species=True)
+    assert host(A).shape == (grid.size,) and np.all(host(A) == 0) and np.all(host(As) == 0)
+    G = dev(wl.random_seed_field(grid.size, seed=66).astype(np.complex64))
+    gx, gfs = api.scatter_bwd_species_grid(dev(xyz), [0, 0, 0], dev(fs), grid, G, As)
+    assert host(gx).shape == (0, 3) and np.all(host(gfs) == 0)
