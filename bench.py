@@ -605,8 +605,9 @@ def measure(name, args, steps, warmup, ceilings, want_graph=False, want_species=
         progress(f"{name}: all-FP64 path timed on {res['f64_path']['points_timed']} points")
 
     # the same step with the species factored out of the sum (Section 4.2): one
-    # unit-factor sum per species, atoms regrouped by species once, outside the timing
-    if want_species and w.f is not None and grid is None:
+    # unit-factor sum per species, atoms regrouped by species once, outside the timing;
+    # over the grid when the step takes it
+    if want_species and w.f is not None:
         xs, start, vals, _ = wl.group_by_species(w.xyz, w.f)
         if len(vals) <= 16:
             txs = torch.from_numpy(xs).to(dev)
@@ -614,11 +615,17 @@ def measure(name, args, steps, warmup, ceilings, want_graph=False, want_species=
 
             def sstep(rec):
                 rec[0].record(stream)
-                As = api.scatter_fwd_species(txs, start, fs, tS, args.mode)
+                if grid is not None:
+                    As = api.scatter_fwd_species_grid(txs, start, fs, grid)
+                else:
+                    As = api.scatter_fwd_species(txs, start, fs, tS, args.mode)
                 rec[1].record(stream)
                 _, Gs = api.loss_grad(As, I)
                 rec[2].record(stream)
-                api.scatter_bwd_species(txs, start, fs, tS, Gs, None, args.mode)
+                if grid is not None:
+                    api.scatter_bwd_species_grid(txs, start, fs, grid, Gs)
+                else:
+                    api.scatter_bwd_species(txs, start, fs, tS, Gs, None, args.mode)
                 rec[3].record(stream)
                 return As
 
@@ -634,7 +641,11 @@ def measure(name, args, steps, warmup, ceilings, want_graph=False, want_species=
             As_ = A_sp.cpu().numpy().astype(np.complex128)
             progress(f"{name}: species-factorised step timed")
             res["species_path"] = {
-                "n_species": len(vals), "fwd_pairs_per_s": pairs / ts[0],
+                "n_species": len(vals),
+                "entry_points": ("nx_scatter_fwd_species_grid, nx_loss_grad, nx_scatter_bwd_species_grid"
+                                 if grid is not None else
+                                 "nx_scatter_fwd_species, nx_loss_grad, nx_scatter_bwd_species"),
+                "fwd_pairs_per_s": pairs / ts[0],
                 "bwd_pairs_per_s": pairs / ts[1], "step_pairs_per_s": pairs / ts[2],
                 "t2_vs_per_atom_step": float(np.linalg.norm(As_ - Ad) / np.linalg.norm(Ad))}
             del txs, fs
