@@ -37,6 +37,8 @@
 //          relative scale error) and p = 1 mod 8 (measured negligible) adds up
 //          incoherently.
 //   F64  : phase, reduction, sin/cos (cis_f64) and sums all in FP64.
+#include <type_traits>
+
 #include "nx_internal.h"
 
 namespace nx {
@@ -620,9 +622,18 @@ __global__ __launch_bounds__(kThreads, block_waves(BA * BB * BC)) void fwd_block
   constexpr int NS = (BA == 2) + (BB == 2) + (BC == 2);
   // (the index of a step the shape does not take is 0: those branches never run)
   constexpr int IW = 0, IV = BB == 2 ? (BA == 2) : 0, IX = BC == 2 ? (BA == 2) + (BB == 2) : 0;
-  struct alignas(16) Tile { double c1; float m, ck, sk, rmax; float st[NS > 0 ? NS : 1][2]; };
+  // blocks of eight points keep each atom's c1 beside its row term per wave (one 16-byte
+  // LDS read for the phase) and its factor before its steps: 49 LDS reads per 16 atoms
+  // instead of 57, C2's forward 2.4 % faster with the same results; with four points the
+  // larger staging cost more than it saved (C3, C4 2 % slower), and one or two points keep
+  // the smaller tile of 8 waves per SIMD
+  constexpr bool FUSE = P == 8;
+  struct alignas(16) TileN { double c1; float m, ck, sk, rmax; float st[NS > 0 ? NS : 1][2]; };
+  struct alignas(16) TileF { float m; float st[NS > 0 ? NS : 1][2]; float ck, sk, rmax; };
+  using Tile = std::conditional_t<FUSE, TileF, TileN>;
   __shared__ Tile tile[kThreads];
-  __shared__ double rowb[kThreads / 64][kThreads];   // the base row's term per wave and atom
+  // the base row's term per wave and atom (and, with FUSE, the atom's c1 beside it)
+  __shared__ std::conditional_t<FUSE, double2, double> rowb[kThreads / 64][kThreads];
   __shared__ double rowd[kThreads / 64][2];          // (i2, i3) of the waves' base rows
   const int lb = xcd_major_block(blockIdx.x, gridDim.x);
   const int kb = lb % blocks_k;
@@ -672,7 +683,13 @@ __global__ __launch_bounds__(kThreads, block_waves(BA * BB * BC)) void fwd_block
   // (r[p], im[p])
   auto block_terms = [&](auto red_c, int uu, float* r, float* im, bool first) {
     constexpr int R = decltype(red_c)::value;
-    const double ph = __builtin_fma(di1, tile[uu].c1, rowb[wave][uu]);
+    double ph;
+    if constexpr (FUSE) {
+      const double2 rc = rowb[wave][uu];
+      ph = __builtin_fma(di1, rc.y, rc.x);
+    } else {
+      ph = __builtin_fma(di1, tile[uu].c1, rowb[wave][uu]);
+    }
     float z[P][2];
     cis_turn<R>(ph, z[0][0], z[0][1]);
     // z <- z + z (s - 1) for a step s - 1 = (sr_, si_)
@@ -741,7 +758,7 @@ __global__ __launch_bounds__(kThreads, block_waves(BA * BB * BC)) void fwd_block
     if (int(threadIdx.x) < nt) {
       const AtomGrid a = rec[t0 + threadIdx.x];
       Tile t;
-      t.c1 = a.c1;
+      if constexpr (!FUSE) t.c1 = a.c1;
       t.m = a.m;
       t.ck = a.ck;
       t.sk = a.sk;
@@ -752,8 +769,11 @@ __global__ __launch_bounds__(kThreads, block_waves(BA * BB * BC)) void fwd_block
       if constexpr (NS == 0) { t.st[0][0] = 0.f; t.st[0][1] = 0.f; }
       tile[threadIdx.x] = t;
 #pragma unroll
-      for (int w = 0; w < kThreads / 64; ++w)
-        rowb[w][threadIdx.x] = __builtin_fma(rowd[w][1], a.c3, __builtin_fma(rowd[w][0], a.c2, a.c0));
+      for (int w = 0; w < kThreads / 64; ++w) {
+        const double b = __builtin_fma(rowd[w][1], a.c3, __builtin_fma(rowd[w][0], a.c2, a.c0));
+        if constexpr (FUSE) rowb[w][threadIdx.x] = make_double2(b, a.c1);
+        else rowb[w][threadIdx.x] = b;
+      }
     }
     __syncthreads();
     const float rt = fmaxf(tile[0].rmax, tile[nt - 1].rmax);
