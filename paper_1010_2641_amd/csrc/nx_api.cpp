@@ -52,7 +52,8 @@ bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 //   NX_TUNE_FILL_BLOCKS   small problems: work-groups the slices may be shortened to reach
 //                         (default 1024); NX_TUNE_MIN_SLICE their shortest slice (32)
 //   NX_TUNE_INLINE        0: always pack the records in their own dispatch; 1: form them in
-//                         the sum kernel wherever that form exists (default: small calls)
+//                         the sum kernel wherever that form exists (default: small calls;
+//                         a grid's small forward then takes the general grid form)
 int64_t env_i64(const char* name, int64_t def) {
   const char* v = std::getenv(name);
   if (!v || !*v) return def;
@@ -366,6 +367,23 @@ nx::GridDef grid_def(const nx_grid* g) {
 int grid_kind(const nx_grid* g) {
   if (g->n1 % 64 != 0) return 1;
   return 2 + ((g->n1 % 128 == 0) ? 1 : 0) + ((g->n2 % 2 == 0) ? 2 : 0) + ((g->n3 % 2 == 0) ? 4 : 0);
+}
+
+// A grid's forward with few records to form (one point per lane, 8- or 16-atom groups,
+// blocks x atoms within the inline bound of the point lists): the general grid form, each
+// lane forming its FP64 grid point, with the atom records formed while staging, saves the
+// pack dispatch (C1, 4,096 atoms over 64 x 64 points: the grid rows' pack, 4 us, and its
+// launch, against a sum kernel 3 us slower).  The workspace stays the one the plan sized
+// (its record part unused).  NX_TUNE_INLINE=0 keeps the rows and their packed records.
+void inline_small_grid_fwd(nx::Plan& p) {
+  if (p.mode != nx::kPH64 || p.grid != 2 || p.per_lane != 1 || p.red != 2 || !p.lds ||
+      (p.grp != 8 && p.grp != 16))
+    return;
+  const int64_t ti = env_i64("NX_TUNE_INLINE", -1);
+  if (ti == 1 || (ti != 0 && p.blocks * p.stream <= nx::kInlineMaxRecords)) {
+    p.grid = 1;
+    p.inl = 1;
+  }
 }
 
 // The launch sequence of run_sum over the points of a grid (FP64-phase mode): grid records
@@ -763,8 +781,9 @@ int nx_scatter_fwd_grid(const float* xyz, const float* f, int64_t n_atoms, const
     return fail(NX_ERR_ARG, "%s: NULL pointer (xyz=%p A=%p)", fn, (const void*)xyz, (void*)A);
   if (!aligned(A, 8) || (f && !aligned(f, 8)))
     return fail(NX_ERR_ARG, "%s: A and f must be 8-byte aligned (complex64)", fn);
-  const nx::Plan p = nx::make_plan(nx::kOpFwd, mode, n_atoms, k, f == nullptr, nx::kMaxSplit, grid_kind(grid));
+  nx::Plan p = nx::make_plan(nx::kOpFwd, mode, n_atoms, k, f == nullptr, nx::kMaxSplit, grid_kind(grid));
   if (int r = check_ws(fn, p, ws, ws_bytes)) return r;
+  inline_small_grid_fwd(p);
   return run_sum_grid(fn, p, true, xyz, f, grid_def(grid), nullptr, A, ws, static_cast<hipStream_t>(stream));
 }
 

@@ -953,6 +953,17 @@ hipError_t fwd_dispatch_red(const Plan& p, const void* rec, int64_t a_begin, int
   if constexpr (MODE == kPH64) {
     if (gd) {       // grid points: the plan takes one point per lane, LDS tiles, RED 2
       if constexpr (P == 1) {
+        if (p.inl && red == 2) {    // small calls: atom records formed while staging
+          if (p.grp == 16)
+            fwd_lds_kernel<1, FK, 16, 2, true, true><<<grid, kThreads, 0, st>>>(
+                nullptr, int(a_begin), int(a_end), int(per_split), nullptr, p.lanes, int(p.blocks), pa,
+                a, carry_in, direct, xyz, f, *gd);
+          else
+            fwd_lds_kernel<1, FK, 8, 2, true, true><<<grid, kThreads, 0, st>>>(
+                nullptr, int(a_begin), int(a_end), int(per_split), nullptr, p.lanes, int(p.blocks), pa,
+                a, carry_in, direct, xyz, f, *gd);
+          return hipGetLastError();
+        }
         if (p.grp == 16)
           fwd_lds_kernel<1, FK, 16, 2, false, true><<<grid, kThreads, 0, st>>>(
               r, int(a_begin), int(a_end), int(per_split), nullptr, p.lanes, int(p.blocks), pa, a,

@@ -83,6 +83,27 @@ def test_bwd_grid_vs_oracle(shape, n, cplx):
     assert en <= M.T3_NORM_TOL and em <= M.T3_MAX_TOL
 
 
+@pytest.mark.parametrize("inline", ["0", "1"])
+@pytest.mark.parametrize("shape,n,cplx", [((128, 2, 3), 900, True), ((256, 4, 1), 20_000, False),
+                                          ((64, 5, 1), 777, True), ((192, 2, 2), 1, False)])
+def test_small_grid_forward_inline_and_packed(shape, n, cplx, inline, monkeypatch):
+    """Few records (one point per lane): by default the forward forms each lane's FP64 grid
+    point and the atom records while staging (no pack dispatch); NX_TUNE_INLINE=0 keeps the
+    row kernel and its packed records.  Both against the oracle, and against each other to
+    rounding (their phases round differently)."""
+    grid = oblique(*shape)
+    xyz, f, _ = wl.random_problem(n, 1, seed=3 * n + shape[0], extent=60.0, s_range=1.0, complex_f=cplx)
+    print(f"case small grid fwd {shape} N={n} complex={cplx} inline={inline}", flush=True)
+    monkeypatch.setenv("NX_TUNE_INLINE", inline)
+    A = fwd(xyz, f, grid)
+    monkeypatch.setenv("NX_TUNE_INLINE", "1" if inline == "0" else "0")
+    B = fwd(xyz, f, grid)
+    ref = oracle.forward(xyz, f, grid.points())
+    e, eb = M.incoherent(A, ref, f, n), M.incoherent(A, B, f, n)
+    print(f"  pointwise/sqrt(sum|f|^2) = {e:.3e}, against the other form {eb:.3e}", flush=True)
+    assert e <= M.INC_TOL and eb <= 2 * M.INC_TOL
+
+
 @pytest.mark.parametrize("cplx", [True, False])
 def test_row_kernels_agree_with_point_list_kernels(cplx, monkeypatch):
     """The same grid through the row kernels and (NX_TUNE_GRID=1) through the point-list
@@ -155,18 +176,21 @@ def test_fit_step_grid_one_call_equals_three(n, cplx):
     assert float(L) == float(L3)
 
 
-def test_tiles_beyond_the_fixed_point_range():
+@pytest.mark.parametrize("inline", ["0", "1"])
+def test_tiles_beyond_the_fixed_point_range(inline, monkeypatch):
     """Every other block of 700 atoms 300,000 lattice units out (their tiles exceed the
     fixed-point range: 300,000 x |S|_1 > 2^19) and every other group of points with
     |S_x| near 30,000 (the adjoint's tiles beyond the range for atoms within 40 units):
-    those tiles reduce with rint and still meet the tolerances."""
+    those tiles reduce with rint and still meet the tolerances; the forward with its atom
+    records formed while staging (the tile's bound from its own records) and packed."""
+    monkeypatch.setenv("NX_TUNE_INLINE", inline)
     n = 3000
     xyz, f, _ = wl.random_problem(n, 1, seed=77, extent=40.0, s_range=1.0)
     far = (np.arange(n) // 700) % 2 == 1
     xyz = xyz.copy()
     xyz[far, 0] += np.float32(300_000.0)
     grid = oblique(128, 4, 2, origin=(3.0, 0.0, 0.0))
-    print("case grid forward, out-of-range atom tiles", flush=True)
+    print(f"case grid forward, out-of-range atom tiles, inline={inline}", flush=True)
     A = fwd(xyz, f, grid)
     assert M.incoherent(A, oracle.forward(xyz, f, grid.points()), f, n) <= M.INC_TOL
     # points: the second half of the grid's rows far out along x
